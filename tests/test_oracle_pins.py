@@ -1,0 +1,339 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these re-types the oracle's formula: each compares it with a brute
+force, a closed form, an invariant or a special case that reduces to
+something simpler, chosen so that a dropped term, a wrong sign, a wrong index
+or a transposed operand fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import erfc
+
+import oracle
+from paper_2501_03061_amd import inputs
+
+
+def _rand_block(rng, n_orb, n):
+    n0, n1, n2 = n
+    return rng.standard_normal((n_orb, n2, n1, n0)) + 1j * rng.standard_normal((n_orb, n2, n1, n0))
+
+
+def _relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ---------------------------------------------------------------- P1 brute force
+def _brute_vx(psi, occ, phi, K):
+    """Vx by explicit sums: real-space kernel k(d) = (1/N_g) sum_m K[m] e^{+2 pi i m.d/n}
+    built from explicit exponentials, then the circular convolution
+    v(r) = sum_r' k(r - r') rho(r') as a dense matrix, then -sum_j f_j psi_j v."""
+    n2, n1, n0 = K.shape
+    ng = n0 * n1 * n2
+    z, y, x = np.meshgrid(np.arange(n2), np.arange(n1), np.arange(n0), indexing="ij")
+    coords = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)      # [ng][3]
+    kflat = K.ravel()
+    # k(d) for every displacement d on the grid
+    phase = 2j * math.pi * (np.outer(coords[:, 0], coords[:, 0]) / n0
+                            + np.outer(coords[:, 1], coords[:, 1]) / n1
+                            + np.outer(coords[:, 2], coords[:, 2]) / n2)  # [d][m]
+    kd = (np.exp(phase) @ kflat) / ng
+    # convolution matrix C[r][r'] = k((r - r') mod n)
+    diff = (coords[:, None, :] - coords[None, :, :]) % np.array([n0, n1, n2])
+    didx = diff[..., 2] * n1 * n0 + diff[..., 1] * n0 + diff[..., 0]
+    C = kd[didx]
+    out = np.zeros(phi.shape, dtype=complex)
+    for i in range(phi.shape[0]):
+        for j in range(psi.shape[0]):
+            rho = (np.conj(psi[j]) * phi[i]).ravel()
+            v = (C @ rho).reshape(K.shape)
+            out[i] -= occ[j] * psi[j] * v
+    return out
+
+
+@pytest.mark.parametrize("n", [(4, 6, 5), (6, 6, 6), (8, 4, 3)])
+def test_p1_brute_force_arbitrary_kernel(rng, n):
+    """Arbitrary (not even) complex kernel: pins FFT sign, normalisation and
+    index layout all at once."""
+    psi = _rand_block(rng, 3, n)
+    phi = _rand_block(rng, 2, n)
+    occ = rng.uniform(0, 1, 3)
+    K = rng.standard_normal(psi.shape[1:]) + 1j * rng.standard_normal(psi.shape[1:])
+    assert _relerr(oracle.exchange_apply(psi, occ, phi, K), _brute_vx(psi, occ, phi, K)) < 1e-13
+
+
+def test_p1_brute_force_hse(rng):
+    n, L = (4, 6, 5), (3.0, 4.5, 3.7)
+    psi = _rand_block(rng, 3, n)
+    occ = rng.uniform(0, 1, 3)
+    K = oracle.kernel_hse(n, L, 0.106)
+    assert _relerr(oracle.exchange_apply(psi, occ, psi, K), _brute_vx(psi, occ, psi, K)) < 1e-13
+
+
+# ---------------------------------------------------------------- P2 / P3 special kernels
+def test_p2_constant_kernel_is_local_potential(rng):
+    n = (6, 5, 4)
+    psi, phi = _rand_block(rng, 4, n), _rand_block(rng, 3, n)
+    occ = rng.uniform(0, 1, 4)
+    c = 2.75
+    K = np.full(psi.shape[1:], c)
+    dens = np.einsum("j,jzyx->zyx", occ, np.abs(psi) ** 2)
+    expect = -c * dens[None] * phi
+    assert _relerr(oracle.exchange_apply(psi, occ, phi, K), expect) < 1e-14
+
+
+def test_p3_g0_kernel_is_projector(rng):
+    n, L = (6, 4, 5), (5.0, 4.0, 6.0)
+    omega = L[0] * L[1] * L[2]
+    dV = omega / (n[0] * n[1] * n[2])
+    psi, phi = _rand_block(rng, 3, n), _rand_block(rng, 2, n)
+    occ = rng.uniform(0, 1, 3)
+    K0 = 279.6
+    K = np.zeros(psi.shape[1:])
+    K[0, 0, 0] = K0
+    expect = np.zeros(phi.shape, dtype=complex)
+    for i in range(phi.shape[0]):
+        for j in range(psi.shape[0]):
+            ov = dV * np.vdot(psi[j], phi[i])
+            expect[i] -= (K0 / omega) * occ[j] * ov * psi[j]
+    assert _relerr(oracle.exchange_apply(psi, occ, phi, K), expect) < 1e-14
+
+
+# ---------------------------------------------------------------- kernel pins
+@pytest.mark.parametrize("G", [0.05, 0.3, 1.0, 3.0])
+def test_hse_kernel_is_fourier_transform_of_erfc(G):
+    """K(G) = (4 pi/G) int_0^inf erfc(mu r) sin(G r) dr, by quadrature."""
+    mu = 0.106
+    val, _ = integrate.quad(lambda r: erfc(mu * r), 0, np.inf, weight="sin", wvar=G)
+    quad_K = 4 * math.pi / G * val
+    # one grid point with |G| = G: cubic cell with L chosen so that m = (1,0,0) has |G| = G
+    L = 2 * math.pi / G
+    K = oracle.kernel_hse((4, 4, 4), (L, L, L), mu)
+    assert abs(K[0, 0, 1] - quad_K) / quad_K < 1e-8
+
+
+def test_hse_kernel_g0_limit():
+    mu = 0.106
+    val, _ = integrate.quad(lambda r: r * erfc(mu * r), 0, np.inf)
+    K = oracle.kernel_hse((4, 4, 4), (10.0, 10.0, 10.0), mu)
+    assert abs(K[0, 0, 0] - 4 * math.pi * val) / K[0, 0, 0] < 1e-10
+    assert abs(K[0, 0, 0] - 279.6) < 0.05
+
+
+def test_signed_freq_nyquist():
+    assert list(oracle.signed_freq(6)) == [0, 1, 2, -3, -2, -1]
+    assert list(oracle.signed_freq(5)) == [0, 1, 2, -2, -1]
+
+
+# ---------------------------------------------------------------- P4 / P5 plane waves
+def _wrap(m, n):
+    m = np.mod(m, n)
+    return np.where(m < n / 2.0, m, m - n)
+
+
+def _K_closed(q, L, mu):
+    g2 = sum((2 * math.pi * q[a] / L) ** 2 for a in range(3))
+    if g2 == 0:
+        return math.pi / mu ** 2
+    return 4 * math.pi * (1 - math.exp(-g2 / (4 * mu ** 2))) / g2
+
+
+def test_p4_plane_wave_closed_form():
+    n, L, mu = 24, 10.0, 0.106
+    ms = [(0, 0, 0), (1, -2, 3), (11, 0, 0), (-7, 5, 2)]
+    occ = np.array([1.0, 0.7, 0.25, 0.05])
+    psi = inputs.plane_wave_orbitals(n, L, ms)
+    K = oracle.kernel_hse((n, n, n), (L, L, L), mu)
+    omega = L ** 3
+    # phi_k: a plane wave whose difference with m=(11,0,0) wraps around the grid
+    mk = (-11, 3, 0)
+    phi = inputs.plane_wave_orbitals(n, L, [mk])
+    lam = 0.0
+    for j, mj in enumerate(ms):
+        q = [int(_wrap(mk[a] - mj[a], n)) for a in range(3)]
+        lam -= occ[j] * _K_closed(q, L, mu) / omega
+    out = oracle.exchange_apply(psi, occ, phi, K)
+    assert _relerr(out, lam * phi) < 1e-13
+
+
+def test_p5_plane_wave_energy_and_ace():
+    n, L, mu = 16, 8.0, 0.2
+    ms = [(0, 0, 0), (1, 0, 0), (0, -2, 1), (3, 1, -1), (-8, 2, 0)]
+    occ = np.array([0.95, 0.8, 0.5, 0.2, 0.01])
+    psi = inputs.plane_wave_orbitals(n, L, ms)
+    K = oracle.kernel_hse((n, n, n), (L, L, L), mu)
+    omega = L ** 3
+    dV = omega / n ** 3
+    lam = np.zeros(len(ms))
+    ex = 0.0
+    for i, mi in enumerate(ms):
+        for j, mj in enumerate(ms):
+            q = [int(_wrap(mi[a] - mj[a], n)) for a in range(3)]
+            kq = _K_closed(q, L, mu) / omega
+            lam[i] -= occ[j] * kq
+            ex -= 0.5 * occ[i] * occ[j] * kq
+    assert abs(oracle.exchange_energy_gspace(psi, occ, K, omega) - ex) < 1e-12 * abs(ex)
+    r = oracle.ace_build(psi, occ, K, dV)
+    assert np.allclose(r["M"], np.diag(lam), atol=1e-12 * abs(lam).max())
+    xi_expect = np.stack([r["W"][i] / math.sqrt(-lam[i]) for i in range(len(ms))])
+    assert _relerr(r["xi"], xi_expect) < 1e-12
+    assert _relerr(r["W"], lam[:, None, None, None] * psi) < 1e-13
+
+
+# ---------------------------------------------------------------- P6 / P7 operator properties
+@pytest.fixture(scope="module")
+def toy():
+    inst = inputs.make_instance(12, 6.0, 6, kT=0.05, seed=3, ecut=6.0)
+    K = oracle.kernel_hse(inst.n, inst.L, 0.106)
+    return inst, K
+
+
+def test_p6_hermitian_and_negative_semidefinite(rng, toy):
+    inst, K = toy
+    dV = inst.omega / inst.ng
+    phi = _rand_block(rng, 5, inst.n)
+    vphi = oracle.exchange_apply(inst.psi, inst.occ, phi, K)
+    A = dV * np.conj(phi.reshape(5, -1)) @ vphi.reshape(5, -1).T
+    assert np.linalg.norm(A - A.conj().T) / np.linalg.norm(A) < 1e-14
+    assert np.linalg.eigvalsh(0.5 * (A + A.conj().T)).max() < 0
+
+
+def test_p7_energy_real_space_equals_gspace(toy):
+    inst, K = toy
+    dV = inst.omega / inst.ng
+    vx = oracle.exchange_apply(inst.psi, inst.occ, inst.psi, K)
+    e1 = oracle.exchange_energy_real(inst.psi, inst.occ, vx, dV)
+    e2 = oracle.exchange_energy_gspace(inst.psi, inst.occ, K, inst.omega)
+    assert e1 < 0
+    assert abs(e1 - e2) < 1e-13 * abs(e2)
+
+
+# ---------------------------------------------------------------- P8 symmetries
+def test_p8_linear_in_occupations(rng, toy):
+    inst, K = toy
+    phi = _rand_block(rng, 2, inst.n)
+    f1, f2 = rng.uniform(0, 1, inst.n_orb), rng.uniform(0, 1, inst.n_orb)
+    a = oracle.exchange_apply(inst.psi, f1 + 3 * f2, phi, K)
+    b = oracle.exchange_apply(inst.psi, f1, phi, K) + 3 * oracle.exchange_apply(inst.psi, f2, phi, K)
+    assert _relerr(a, b) < 1e-14
+
+
+def test_p8_phase_invariance(rng, toy):
+    inst, K = toy
+    phi = _rand_block(rng, 2, inst.n)
+    th = rng.uniform(0, 2 * math.pi, inst.n_orb)
+    psi2 = inst.psi * np.exp(1j * th)[:, None, None, None]
+    a = oracle.exchange_apply(inst.psi, inst.occ, phi, K)
+    b = oracle.exchange_apply(psi2, inst.occ, phi, K)
+    assert _relerr(b, a) < 1e-14
+
+
+def test_p8_translation_covariance(rng, toy):
+    inst, K = toy
+    phi = _rand_block(rng, 2, inst.n)
+    sh = (2, -3, 5)
+    roll = lambda a: np.roll(a, sh, axis=(1, 2, 3))
+    a = roll(oracle.exchange_apply(inst.psi, inst.occ, phi, K))
+    b = oracle.exchange_apply(roll(inst.psi), inst.occ, roll(phi), K)
+    assert _relerr(b, a) < 1e-14
+
+
+# ---------------------------------------------------------------- P9 sigma form
+def test_p9_sigma_form_equals_diagonalised_form(rng):
+    n, L = (6, 5, 4), (4.0, 3.5, 3.0)
+    N = 3
+    Phi = _rand_block(rng, N, n)
+    phi = _rand_block(rng, 2, n)
+    K = oracle.kernel_hse(n, L, 0.3)
+    # random Hermitian sigma with spectrum in [0, 1]
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    Q, _ = np.linalg.qr(X)
+    d = rng.uniform(0, 1, N)
+    sigma = Q @ np.diag(d) @ Q.conj().T
+    a = oracle.exchange_apply_sigma(Phi, sigma, phi, K)
+    # Eq. (11)-(13): varphi = Phi Q (columns), occupations d
+    varphi = np.einsum("izyx,il->lzyx", Phi, Q)
+    b = oracle.exchange_apply(varphi, d, phi, K)
+    assert _relerr(a, b) < 1e-13
+
+
+# ---------------------------------------------------------------- P10 / P11 ACE
+def test_p10_ace_reproduces_vx_on_span(rng, toy):
+    inst, K = toy
+    dV = inst.omega / inst.ng
+    r = oracle.ace_build(inst.psi, inst.occ, K, dV)
+    assert r["herm_defect"] < 1e-13
+    Y = oracle.ace_apply(r["xi"], inst.psi, dV)
+    assert _relerr(Y, r["W"]) < 1e-13
+    # V_ACE on a random block: Hermitian, NSD, rank N
+    phi = _rand_block(rng, 8, inst.n)
+    A = dV * np.conj(phi.reshape(8, -1)) @ oracle.ace_apply(r["xi"], phi, dV).reshape(8, -1).T
+    assert np.linalg.norm(A - A.conj().T) / np.linalg.norm(A) < 1e-14
+    ev = np.linalg.eigvalsh(0.5 * (A + A.conj().T))
+    assert ev.max() < 1e-12 * abs(ev).max()
+    assert np.sum(ev < -1e-10 * abs(ev).max()) == inst.n_orb
+    # energy through the compressed operator
+    xf = r["xi"].reshape(inst.n_orb, -1)
+    proj = np.conj(xf) @ inst.psi.reshape(inst.n_orb, -1).T        # [k][i]
+    e_ace = -0.5 * dV ** 2 * float(np.dot(inst.occ, np.sum(np.abs(proj) ** 2, axis=0)))
+    e_ref = oracle.exchange_energy_gspace(inst.psi, inst.occ, K, inst.omega)
+    assert abs(e_ace - e_ref) < 1e-13 * abs(e_ref)
+
+
+def test_p11_cholesky_factor(toy):
+    inst, K = toy
+    dV = inst.omega / inst.ng
+    r = oracle.ace_build(inst.psi, inst.occ, K, dV)
+    L = r["L"]
+    assert np.allclose(L, np.tril(L))
+    assert np.all(np.abs(L.diagonal().imag) == 0) and np.all(L.diagonal().real > 0)
+    assert _relerr(L @ L.conj().T, -r["M"]) < 1e-14
+
+
+# ---------------------------------------------------------------- loop pins
+def test_loop_plane_wave_scalar_recursion():
+    """On a plane-wave basis V_ACE is diagonal, so each column follows the
+    scalar recursion c <- 1 - i dt a lam (1 + c)/2; many iterations reach the
+    Cayley factor (1 - i dt a lam/2)/(1 + i dt a lam/2) of the implicit midpoint rule."""
+    n, L, mu = 12, 7.0, 0.15
+    ms = [(0, 0, 0), (1, 1, 0), (-2, 0, 3)]
+    occ = np.array([1.0, 0.6, 0.3])
+    psi = inputs.plane_wave_orbitals(n, L, ms)
+    K = oracle.kernel_hse((n, n, n), (L, L, L), mu)
+    dV = L ** 3 / n ** 3
+    r = oracle.ace_build(psi, occ, K, dV)
+    lam = np.real(np.diag(r["M"]))
+    dt, a = oracle.DT_50AS, oracle.ALPHA
+    for iters in (4, 60):
+        out, res = oracle.ptim_exchange_loop(r["xi"], psi, dV, n_iter=iters)
+        c = np.ones(3, dtype=complex)
+        rs = []
+        for _ in range(iters):
+            cn = 1 - 1j * dt * a * lam * (1 + c) / 2
+            rs.append(np.linalg.norm(cn - c) / np.linalg.norm(cn))
+            c = cn
+        assert _relerr(out, c[:, None, None, None] * psi) < 1e-13
+        assert np.allclose(res, rs, rtol=1e-9, atol=1e-13)
+    cay = (1 - 0.5j * dt * a * lam) / (1 + 0.5j * dt * a * lam)
+    assert np.allclose(c, cay, atol=1e-12)
+
+
+# ---------------------------------------------------------------- generator sanity
+def test_generator_orthonormal_and_band_limited():
+    inst = inputs.make_instance(24, 10.0, 16, kT=0.01, seed=0)
+    dV = inst.omega / inst.ng
+    S = dV * np.conj(inst.psi.reshape(16, -1)) @ inst.psi.reshape(16, -1).T
+    assert np.abs(S - np.eye(16)).max() < 1e-13
+    spec = np.fft.fftn(inst.psi, axes=(1, 2, 3)).reshape(16, -1)
+    idx = inputs.sphere_indices(inst.n, inst.L, 10.0)
+    mask = np.ones(inst.ng, bool)
+    mask[idx] = False
+    assert np.abs(spec[:, mask]).max() < 1e-10 * np.abs(spec).max()
+    assert len(idx) == 1503
+    assert np.all((inst.occ >= 0) & (inst.occ <= 1))
+
+
+def test_generator_sphere_size_mid72():
+    assert len(inputs.sphere_indices((72, 72, 72), (20.0, 20.0, 20.0), 10.0)) == 12053
