@@ -1,0 +1,180 @@
+/* px.h -- C ABI of libpx: the Fock exchange operator with fractional
+ * occupations and its adaptively compressed (ACE) form on AMD MI355X (gfx950).
+ *
+ * Problem statement (arXiv 2501.03061):
+ *   Sec. II-B, Eq. (8)-(10): the exchange operator Vx[P](r,r') = -P(r,r') K(r,r')
+ *     with a (possibly screened) interaction kernel K.
+ *   Sec. IV-A-1, Eq. (11)-(13): once the occupation matrix is diagonalised,
+ *     P = sum_j f_j psi_j psi_j^*, and
+ *       (Vx phi_i)(r) = -sum_j f_j psi_j(r) IFFT[ K(G) FFT(conj(psi_j) phi_i) ](r),
+ *     N_phi * N_psi pair solves.
+ *   Sec. IV-A-2, Eq. (14): ACE, W = Vx Psi reproduced exactly by
+ *     V_ACE = -xi xi^H on span(Psi).
+ *
+ * Conventions shared by every entry point
+ *   Grid and cell: orthorhombic cell of edge lengths L[0..2] (bohr), grid
+ *     n[0] x n[1] x n[2]; Omega = L0 L1 L2, N_g = n0 n1 n2, dV = Omega/N_g.
+ *   Layout: every orbital block is orbital-major and C-ordered
+ *     [orbital][n2][n1][n0] (x = n0 fastest), interleaved complex (re, im):
+ *     complex128 for PX_PREC_FP64, complex64 for PX_PREC_FP32.
+ *     occ is float64 [n_psi]; kernel_G is float64 [n2][n1][n0] in FFT index
+ *     order (index m has frequency m if m < n/2, else m - n).
+ *     Small matrices (M) are complex128, row-major, n x n.
+ *   Units: atomic units.  The hybrid mixing fraction alpha of Eq. (8) is NOT
+ *     applied (the library returns Vx); there is no spin factor.
+ *   FFT convention: forward exp(-iG.r) unnormalised, inverse exp(+iG.r) with
+ *     1/N_g; for a real even kernel the result does not depend on the sign.
+ *   Memory: all array arguments are DEVICE pointers owned by the caller.  The
+ *     library never allocates or frees device memory; scratch space comes from
+ *     the workspace the caller attaches with px_set_workspace, sized by
+ *     px_workspace_bytes.  Outputs must not alias inputs.
+ *   Streams: every compute call only enqueues work on `stream` (a
+ *     hipStream_t; NULL = default stream) and returns; no host synchronisation
+ *     except in px_sync.
+ *   Errors: arguments are validated on the host before anything is enqueued;
+ *     a non-PX_OK return means nothing was enqueued.  px_last_error gives a
+ *     message.  Device-side failures (Cholesky breakdown) are reported through
+ *     the caller's status word and surfaced by px_sync.
+ *   Precision forms: PX_PREC_FP64 runs everything in FP64.  PX_PREC_FP32 runs
+ *     pair products, FFTs and contractions in FP32 (FP32 MFMA accumulation)
+ *     while the G = 0 coefficient, the exchange energy sums, the reductions of
+ *     contraction partials, the Cholesky factorisation and the triangular
+ *     inverse stay FP64.
+ */
+#ifndef PX_H_
+#define PX_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PX_ABI_VERSION 1
+
+typedef enum {
+  PX_OK = 0,
+  PX_ERR_INVALID_ARG = 1,           /* null pointer, bad size, bad aliasing      */
+  PX_ERR_UNSUPPORTED_GRID = 2,      /* grid shape without a compiled FFT plan    */
+  PX_ERR_WORKSPACE = 3,             /* no workspace attached or too small        */
+  PX_ERR_DEVICE = 4,                /* a HIP runtime call failed                 */
+  PX_ERR_NOT_POSITIVE_DEFINITE = 5  /* -M is not positive definite (px_sync)     */
+} px_status;
+
+typedef enum { PX_PREC_FP64 = 0, PX_PREC_FP32 = 1 } px_precision;
+
+typedef enum {
+  PX_OP_EXCHANGE = 0,
+  PX_OP_ACE_BUILD = 1,
+  PX_OP_ACE_APPLY = 2,
+  PX_OP_PTIM_LOOP = 3
+} px_op;
+
+/* Orthorhombic cell: edge lengths in bohr and the real-space grid, n[0] = x. */
+typedef struct {
+  double L[3];
+  int32_t n[3];
+} px_cell;
+
+typedef struct px_context px_context;
+
+/* Returns PX_ABI_VERSION of the loaded library. */
+int32_t px_abi_version(void);
+
+/* Creates a context bound to HIP device `device` (host state only: tuning
+ * table, latched errors, attached workspace).  *ctx receives the handle. */
+px_status px_create(int32_t device, px_context** ctx);
+
+/* Destroys a context; NULL is accepted.  Does not free the workspace. */
+void px_destroy(px_context* ctx);
+
+/* Message of the last failure on this context (never NULL). */
+const char* px_last_error(const px_context* ctx);
+
+/* Whether the grid of `cell` has compiled FFT plans in precision `prec`
+ * (1 = yes).  Supported: cubic n in {16,24,32,40,48,60,64,72,80,96}. */
+int32_t px_grid_supported(const px_cell* cell, px_precision prec);
+
+/* Bytes of workspace that `op` needs for this problem with the context's
+ * current tuning; 0 if the arguments are invalid.  n_phi is ignored for
+ * PX_OP_ACE_BUILD (Phi = Psi). */
+size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, px_precision prec,
+                          int32_t n_psi, int32_t n_phi);
+
+/* Attaches caller-owned device memory as the workspace (256-byte aligned).
+ * The same buffer serves every later call on the context; calls that overlap
+ * in time on different streams must not share a context. */
+px_status px_set_workspace(px_context* ctx, void* dev_ptr, size_t bytes);
+
+/* Pair-chunk tuning: a chunk is ic output orbitals x jc density orbitals whose
+ * pair slabs are in flight together (Sec. III-B(b) batches 16 pairs on its
+ * GPU).  0 restores the default.  Changes px_workspace_bytes. */
+px_status px_set_tuning(px_context* ctx, const px_cell* cell, px_precision prec, int32_t ic,
+                        int32_t jc);
+
+/* Fills kernel_G (device, float64 [n2][n1][n0], FFT order) with the HSE06
+ * screened interaction K(G) = 4 pi (1 - exp(-G^2/(4 mu^2)))/G^2, K(0) = pi/mu^2
+ * (Sec. II-B: "possibly screened" kernel; Sec. VI: HSE06). */
+px_status px_kernel_hse(px_context* ctx, const px_cell* cell, double mu, double* kernel_G,
+                        hipStream_t stream);
+
+/* Rounds n_elems complex128 values to complex64 (round to nearest even):
+ * the staging step of the FP32 form.  src and dst are device pointers. */
+px_status px_convert_c128_to_c64(px_context* ctx, size_t n_elems, const void* src, void* dst,
+                                 hipStream_t stream);
+
+/* Exchange operator applied to a block, Eq. (13) with occupations f_j:
+ *   vx_phi[i] = (Vx phi_i) = -sum_j occ[j] psi_j IFFT[K FFT(conj(psi_j) phi_i)]
+ * psi [n_psi][N_g], phi [n_phi][N_g], vx_phi [n_phi][N_g] in the element type
+ * of `prec`; occ, kernel_G FP64.  e_x (nullable, device, one float64) receives
+ *   E_x = 1/2 sum_i f_i <psi_i|Vx psi_i> = -Omega/(2 N_g^2) sum_ij f_i f_j sum_G K |FFT(conj(psi_j) psi_i)|^2,
+ * accumulated in FP64; it requires phi == psi and n_phi == n_psi. */
+px_status px_exchange_apply(px_context* ctx, const px_cell* cell, px_precision prec,
+                            int32_t n_psi, const void* psi, const double* occ, int32_t n_phi,
+                            const void* phi, const double* kernel_G, void* vx_phi, double* e_x,
+                            hipStream_t stream);
+
+/* ACE construction (Eq. 14; steps: W = Vx Psi, M = dV Psi^H W, M <- (M+M^H)/2,
+ * -M = L L^H with L lower and real positive diagonal, xi = W L^{-H}).
+ * psi [n][N_g] (element type of prec), occ FP64 [n], kernel_G FP64.
+ * Outputs: xi [n][N_g] (element type of prec); M (nullable) complex128 [n][n]
+ * after Hermitisation; e_x (nullable) as in px_exchange_apply; status (device
+ * int32, required): 0 on success, else the 1-based column where the Cholesky
+ * factorisation of -M broke down (xi is then undefined). */
+px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                       const void* psi, const double* occ, const double* kernel_G, void* xi,
+                       double* M, double* e_x, int32_t* status, hipStream_t stream);
+
+/* ACE application (Eq. 14): out = V_ACE phi = -xi (dV xi^H phi).
+ * xi [n][N_g], phi and out [n_phi][N_g], element type of prec. */
+px_status px_ace_apply(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                       const void* xi, int32_t n_phi, const void* phi, void* out,
+                       hipStream_t stream);
+
+/* Exchange-only implicit-midpoint fixed point with the ACE operator (the
+ * orbital update of Eq. 6 at the midpoint of Eq. 4, keeping only alpha*Vx of
+ * Eq. 8 and no projector, iterated as x = T(x) of Eq. 7):
+ *   Phi^(k+1) = Phi_n - i*dt_alpha * V_ACE (Phi_n + Phi^(k))/2,  Phi^(0) = Phi_n,
+ * for k = 0 .. n_iter-1, with residual R_k = ||Phi^(k+1) - Phi^(k)||_F / ||Phi^(k+1)||_F
+ * accumulated in FP64.  dt_alpha = dt * alpha (e.g. 50 as * 0.25).
+ * xi [n][N_g], phi_n and phi_out [n_phi][N_g] (element type of prec),
+ * residuals: device float64 [n_iter]. */
+px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                                const void* xi, int32_t n_phi, const void* phi_n, int32_t n_iter,
+                                double dt_alpha, void* phi_out, double* residuals,
+                                hipStream_t stream);
+
+/* Synchronises `stream`, then reads the status word of the last px_ace_build
+ * on this context: PX_ERR_NOT_POSITIVE_DEFINITE if it reported a breakdown
+ * (the error stays latched until px_clear_error), PX_ERR_DEVICE on a HIP error. */
+px_status px_sync(px_context* ctx, hipStream_t stream);
+
+/* Clears a latched error. */
+void px_clear_error(px_context* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PX_H_ */

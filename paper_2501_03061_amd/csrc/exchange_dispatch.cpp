@@ -1,0 +1,28 @@
+// Size dispatch of the pair pipeline: the cubic grids with compiled plans.
+#include "px_internal.hpp"
+
+namespace px {
+
+template <int N>
+hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hipStream_t s);
+
+#define PX_SIZES(X) X(16) X(24) X(32) X(40) X(48) X(60) X(64) X(72) X(80) X(96)
+
+bool grid_supported(int n0, int n1, int n2) {
+  if (n0 != n1 || n1 != n2) return false;
+#define PX_CASE(N) if (n0 == N) return true;
+  PX_SIZES(PX_CASE)
+#undef PX_CASE
+  return false;
+}
+
+hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool g0, bool ex,
+                        hipStream_t s) {
+  (void)g0;
+#define PX_CASE(N) if (n == N) return launch_chunk_n<N>(fp32, a, npairs, ex, s);
+  PX_SIZES(PX_CASE)
+#undef PX_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace px

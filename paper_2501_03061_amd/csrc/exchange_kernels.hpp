@@ -1,0 +1,383 @@
+// The fused pair pipeline of the exchange operator (Eq. 13 with occupations f_j):
+//
+//   (Vx phi_i)(r) = -sum_j f_j psi_j(r) * IFFT[ K(G) * FFT(conj(psi_j) * phi_i) ](r)
+//
+// split into three passes over a chunk of orbital pairs (i, j), each pass a
+// kernel that keeps one 2D section of the grid in LDS:
+//
+//   pass 1  (z-slab, i) : pair product conj(psi_j)*phi_i, forward x and y
+//                         transforms, slab written to the pair buffer T.
+//   pass 2  (y-plane, pair): forward z transform, multiply by K(G) (and, in
+//                         FP32 form, the G = 0 coefficient taken from FP64
+//                         slab sums), FP64 partial of sum_G K |rho(G)|^2 for
+//                         the exchange energy, inverse z transform; in place.
+//   pass 3  (z-slab, i) : inverse x and y transforms, then the weighted sum
+//                         over the chunk's j of f_j/N_g * psi_j * v_ij kept in
+//                         registers and subtracted from the output slab once.
+//
+// Layout of every grid array: [n2][n1][n0] with x = n0 fastest; orbital blocks
+// are orbital-major.  T is float (complex64 data) or double (complex128).
+#pragma once
+#include "fft_core.hpp"
+#include "px_internal.hpp"
+
+namespace px {
+
+typedef double vd2 __attribute__((ext_vector_type(2)));
+typedef float vf2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec;
+template <> struct Vec<double> { using t = vd2; };
+template <> struct Vec<float> { using t = vf2; };
+
+template <typename T> __device__ __forceinline__ cpx<T> ldg(const cpx<T>* p) {
+  using V = typename Vec<T>::t;
+  V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  return {v.x, v.y};
+}
+template <typename T> __device__ __forceinline__ cpx<T> ldc(const cpx<T>* p) {  // cached load
+  using V = typename Vec<T>::t;
+  V v = *reinterpret_cast<const V*>(p);
+  return {v.x, v.y};
+}
+template <typename T> __device__ __forceinline__ void stg(cpx<T>* p, cpx<T> a) {
+  using V = typename Vec<T>::t;
+  V v;
+  v.x = a.x;
+  v.y = a.y;
+  *reinterpret_cast<V*>(p) = v;
+}
+
+// Twiddle table: tw[m] = exp(-2 pi i m / N), FP64 sincospi rounded to T.
+template <typename T, int N, int NT> __device__ __forceinline__ void fill_twiddles(cpx<T>* tw) {
+  for (int m = threadIdx.x; m < N; m += NT) {
+    double s, c;
+    sincospi(2.0 * double(m) / double(N), &s, &c);
+    tw[m] = {T(c), T(-s)};
+  }
+}
+
+// Block-wide FP64 sum; result valid in thread 0.  red must hold NT/64 doubles.
+template <int NT> __device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) s += red[k];
+  }
+  __syncthreads();
+  return s;
+}
+
+// ============================================================== pass 1
+template <typename T, int N0, int N1, int NT, bool G0>
+__global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
+  __shared__ cpx<T> lds[N0 * N1];
+  __shared__ cpx<T> tw0[N0];
+  __shared__ cpx<T> tw1[N1];
+  __shared__ double red[2 * (NT / 64)];
+  using GX = Lines<N0, N1, N0, 1, false>;  // rows: contiguous lines
+  using GY = Lines<N1, N0, 1, N0, true>;   // columns: strided lines
+  constexpr int NSX = Plan<N0>::nst, NSY = Plan<N1>::nst;
+  using X0 = StageOf<N0, 0, false>;
+  using YL = StageOf<N1, NSY - 1, false>;
+  constexpr int NB0 = N1 * (N0 / X0::R), BPT0 = (NB0 + NT - 1) / NT;
+  constexpr int NBL = N0 * (N1 / YL::R), BPTL = (NBL + NT - 1) / NT;
+
+  fill_twiddles<T, N0, NT>(tw0);
+  fill_twiddles<T, N1, NT>(tw1);
+  const int z = blockIdx.x, ii = blockIdx.y;
+  const size_t slab = size_t(N0) * N1;
+  const size_t ng = slab * a.n2;
+  const cpx<T>* phi = reinterpret_cast<const cpx<T>*>(a.phi) + size_t(a.i0 + ii) * ng + z * slab;
+  const int tid = threadIdx.x;
+  __syncthreads();
+
+  for (int jj = 0; jj < a.jc; ++jj) {
+    const cpx<T>* psi = reinterpret_cast<const cpx<T>*>(a.psi) + size_t(a.j0 + jj) * ng + z * slab;
+    const int p = ii * a.jc + jj;
+    double sre = 0.0, sim = 0.0;
+    // first x stage straight from global memory: product, radix butterfly, LDS
+#pragma unroll
+    for (int k = 0; k < BPT0; ++k) {
+      const int b = tid + k * NT;
+      if (NB0 % NT == 0 || b < NB0) {
+        int line, j;
+        decode<GX, X0::R>(b, line, j);
+        cpx<T> v[X0::R];
+#pragma unroll
+        for (int r = 0; r < X0::R; ++r) {
+          const int off = line * N0 + j + r * (N0 / X0::R);
+          cpx<T> ps = ldc(psi + off), ph = ldc(phi + off);
+          if constexpr (G0) {
+            sre += double(ps.x) * double(ph.x) + double(ps.y) * double(ph.y);
+            sim += double(ps.x) * double(ph.y) - double(ps.y) * double(ph.x);
+          }
+          v[r] = cmulc(ps, ph);
+        }
+        dft<T, X0::R, false>(v);
+#pragma unroll
+        for (int r = 0; r < X0::R; ++r) lds[line * N0 + out_pos<X0::R, 1>(j, r)] = v[r];
+      }
+    }
+    if constexpr (G0) {
+      double s0 = block_sum<NT>(sre, red);
+      double s1 = block_sum<NT>(sim, red + NT / 64);
+      if (tid == 0) a.g0[size_t(p) * a.n2 + z] = make_double2(s0, s1);
+    } else {
+      __syncthreads();
+    }
+    stages_lds<T, GX, false, NT, 1, NSX>(lds, tw0);
+    stages_lds<T, GY, false, NT, 0, NSY - 1>(lds, tw1);
+    // last y stage: LDS -> global pair buffer
+    cpx<T>* out = reinterpret_cast<cpx<T>*>(a.t) + size_t(p) * ng + z * slab;
+#pragma unroll
+    for (int k = 0; k < BPTL; ++k) {
+      const int b = tid + k * NT;
+      if (NBL % NT == 0 || b < NBL) {
+        int line, j;
+        decode<GY, YL::R>(b, line, j);
+        cpx<T> v[YL::R];
+#pragma unroll
+        for (int r = 0; r < YL::R; ++r) v[r] = lds[line + (j + r * (N1 / YL::R)) * N0];
+        twiddle<T, N1, YL::R, YL::NS, false>(v, j, tw1);
+        dft<T, YL::R, false>(v);
+#pragma unroll
+        for (int r = 0; r < YL::R; ++r) stg(out + line + (j + r * (N1 / YL::R)) * N0, v[r]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ============================================================== pass 2
+template <typename T, int N0, int N1, int N2, int NT, bool G0, bool EX>
+__global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
+  __shared__ cpx<T> lds[N2 * N0];
+  __shared__ cpx<T> tw2[N2];
+  __shared__ double red[NT / 64];
+  using GZ = Lines<N2, N0, 1, N0, true>;  // plane [z][x], lines along z
+  constexpr int NS = Plan<N2>::nst;
+  using F0 = StageOf<N2, 0, false>;
+  using FL = StageOf<N2, NS - 1, false>;
+  using I0 = StageOf<N2, 0, true>;
+  using IL = StageOf<N2, NS - 1, true>;
+  static_assert(I0::R == FL::R, "inverse must start with the forward's last radix");
+  constexpr int NB0 = N0 * (N2 / F0::R), BPT0 = (NB0 + NT - 1) / NT;
+  constexpr int NBL = N0 * (N2 / FL::R), BPTL = (NBL + NT - 1) / NT;
+  constexpr int NBI = N0 * (N2 / IL::R), BPTI = (NBI + NT - 1) / NT;
+
+  fill_twiddles<T, N2, NT>(tw2);
+  const int y = blockIdx.x, p = blockIdx.y;
+  const size_t slab = size_t(N0) * N1;
+  const size_t ng = slab * N2;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(a.t) + size_t(p) * ng + size_t(y) * N0;
+  const double* kern = a.kern + size_t(y) * N0;
+  const int tid = threadIdx.x;
+  __syncthreads();
+
+  // forward stage 0 from global
+#pragma unroll
+  for (int k = 0; k < BPT0; ++k) {
+    const int b = tid + k * NT;
+    if (NB0 % NT == 0 || b < NB0) {
+      int line, j;
+      decode<GZ, F0::R>(b, line, j);
+      cpx<T> v[F0::R];
+#pragma unroll
+      for (int r = 0; r < F0::R; ++r) v[r] = ldc(buf + size_t(j + r * (N2 / F0::R)) * slab + line);
+      dft<T, F0::R, false>(v);
+#pragma unroll
+      for (int r = 0; r < F0::R; ++r) lds[out_pos<F0::R, 1>(j, r) * N0 + line] = v[r];
+    }
+  }
+  __syncthreads();
+  stages_lds<T, GZ, false, NT, 1, NS - 1>(lds, tw2);
+  // last forward stage into registers, kernel multiply, first inverse stage
+  cpx<T> v[BPTL][FL::R];
+  double ex = 0.0;
+#pragma unroll
+  for (int k = 0; k < BPTL; ++k) {
+    const int b = tid + k * NT;
+    if (NBL % NT == 0 || b < NBL) {
+      int line, j;
+      decode<GZ, FL::R>(b, line, j);
+#pragma unroll
+      for (int r = 0; r < FL::R; ++r) v[k][r] = lds[(j + r * (N2 / FL::R)) * N0 + line];
+      twiddle<T, N2, FL::R, FL::NS, false>(v[k], j, tw2);
+      dft<T, FL::R, false>(v[k]);
+#pragma unroll
+      for (int r = 0; r < FL::R; ++r) {
+        const int kz = j + r * (N2 / FL::R);
+        const double kg = kern[size_t(kz) * slab + line];
+        cpx<T> c = v[k][r];
+        if (G0 && y == 0 && line == 0 && kz == 0) {
+          // G = 0 from the FP64 slab sums of pass 1
+          double s0 = 0.0, s1 = 0.0;
+          const double2* g = a.g0 + size_t(p) * N2;
+          for (int zz = 0; zz < N2; ++zz) {
+            double2 t = g[zz];
+            s0 += t.x;
+            s1 += t.y;
+          }
+          if (EX) ex += kg * (s0 * s0 + s1 * s1);
+          v[k][r] = {T(kg * s0), T(kg * s1)};
+        } else {
+          if (EX) ex += kg * (double(c.x) * double(c.x) + double(c.y) * double(c.y));
+          v[k][r] = {T(kg * double(c.x)), T(kg * double(c.y))};
+        }
+      }
+    }
+  }
+  if constexpr (EX) {
+    double s = block_sum<NT>(ex, red);
+    if (tid == 0) a.expart[size_t(p) * N1 + y] = s;
+  } else {
+    __syncthreads();  // every thread is done reading LDS before it is overwritten
+  }
+#pragma unroll
+  for (int k = 0; k < BPTL; ++k) {
+    const int b = tid + k * NT;
+    if (NBL % NT == 0 || b < NBL) {
+      int line, j;
+      decode<GZ, I0::R>(b, line, j);
+      dft<T, I0::R, true>(v[k]);
+#pragma unroll
+      for (int r = 0; r < I0::R; ++r) lds[out_pos<I0::R, 1>(j, r) * N0 + line] = v[k][r];
+    }
+  }
+  __syncthreads();
+  stages_lds<T, GZ, true, NT, 1, NS - 1>(lds, tw2);
+  // last inverse stage back to global, in place
+#pragma unroll
+  for (int k = 0; k < BPTI; ++k) {
+    const int b = tid + k * NT;
+    if (NBI % NT == 0 || b < NBI) {
+      int line, j;
+      decode<GZ, IL::R>(b, line, j);
+      cpx<T> w[IL::R];
+#pragma unroll
+      for (int r = 0; r < IL::R; ++r) w[r] = lds[(j + r * (N2 / IL::R)) * N0 + line];
+      twiddle<T, N2, IL::R, IL::NS, true>(w, j, tw2);
+      dft<T, IL::R, true>(w);
+#pragma unroll
+      for (int r = 0; r < IL::R; ++r) stg(buf + size_t(j + r * (N2 / IL::R)) * slab + line, w[r]);
+    }
+  }
+}
+
+// ============================================================== pass 3
+template <typename T, int N0, int N1, int NT>
+__global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
+  __shared__ cpx<T> lds[N0 * N1];
+  __shared__ cpx<T> tw0[N0];
+  __shared__ cpx<T> tw1[N1];
+  using GX = Lines<N0, N1, N0, 1, false>;
+  using GY = Lines<N1, N0, 1, N0, true>;
+  constexpr int NSX = Plan<N0>::nst, NSY = Plan<N1>::nst;
+  using X0 = StageOf<N0, 0, true>;
+  using YL = StageOf<N1, NSY - 1, true>;
+  constexpr int NB0 = N1 * (N0 / X0::R), BPT0 = (NB0 + NT - 1) / NT;
+  constexpr int NBL = N0 * (N1 / YL::R), BPTL = (NBL + NT - 1) / NT;
+
+  fill_twiddles<T, N0, NT>(tw0);
+  fill_twiddles<T, N1, NT>(tw1);
+  const int z = blockIdx.x, ii = blockIdx.y;
+  const size_t slab = size_t(N0) * N1;
+  const size_t ng = slab * a.n2;
+  const int tid = threadIdx.x;
+  cpx<T> acc[BPTL][YL::R];
+#pragma unroll
+  for (int k = 0; k < BPTL; ++k)
+#pragma unroll
+    for (int r = 0; r < YL::R; ++r) acc[k][r] = {T(0), T(0)};
+  __syncthreads();
+
+  for (int jj = 0; jj < a.jc; ++jj) {
+    const int p = ii * a.jc + jj;
+    const cpx<T>* tin = reinterpret_cast<const cpx<T>*>(a.t) + size_t(p) * ng + z * slab;
+    const cpx<T>* psi = reinterpret_cast<const cpx<T>*>(a.psi) + size_t(a.j0 + jj) * ng + z * slab;
+    const T wj = T(a.occ[a.j0 + jj] * a.inv_ng);
+#pragma unroll
+    for (int k = 0; k < BPT0; ++k) {
+      const int b = tid + k * NT;
+      if (NB0 % NT == 0 || b < NB0) {
+        int line, j;
+        decode<GX, X0::R>(b, line, j);
+        cpx<T> v[X0::R];
+#pragma unroll
+        for (int r = 0; r < X0::R; ++r) v[r] = ldg(tin + line * N0 + j + r * (N0 / X0::R));
+        dft<T, X0::R, true>(v);
+#pragma unroll
+        for (int r = 0; r < X0::R; ++r) lds[line * N0 + out_pos<X0::R, 1>(j, r)] = v[r];
+      }
+    }
+    __syncthreads();
+    stages_lds<T, GX, true, NT, 1, NSX>(lds, tw0);
+    stages_lds<T, GY, true, NT, 0, NSY - 1>(lds, tw1);
+#pragma unroll
+    for (int k = 0; k < BPTL; ++k) {
+      const int b = tid + k * NT;
+      if (NBL % NT == 0 || b < NBL) {
+        int line, j;
+        decode<GY, YL::R>(b, line, j);
+        cpx<T> v[YL::R];
+#pragma unroll
+        for (int r = 0; r < YL::R; ++r) v[r] = lds[line + (j + r * (N1 / YL::R)) * N0];
+        twiddle<T, N1, YL::R, YL::NS, true>(v, j, tw1);
+        dft<T, YL::R, true>(v);
+#pragma unroll
+        for (int r = 0; r < YL::R; ++r) {
+          cpx<T> ps = ldc(psi + line + (j + r * (N1 / YL::R)) * N0);
+          cpx<T> t = cmul(ps, v[r]);
+          acc[k][r].x += wj * t.x;
+          acc[k][r].y += wj * t.y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  cpx<T>* out = reinterpret_cast<cpx<T>*>(a.out) + size_t(a.i0 + ii) * ng + z * slab;
+#pragma unroll
+  for (int k = 0; k < BPTL; ++k) {
+    const int b = tid + k * NT;
+    if (NBL % NT == 0 || b < NBL) {
+      int line, j;
+      decode<GY, YL::R>(b, line, j);
+#pragma unroll
+      for (int r = 0; r < YL::R; ++r) {
+        cpx<T>* o = out + line + (j + r * (N1 / YL::R)) * N0;
+        cpx<T> prev = a.first ? cpx<T>{T(0), T(0)} : ldc(o);
+        stg(o, csub(prev, acc[k][r]));
+      }
+    }
+  }
+}
+
+// ============================================================== host launcher
+template <int N> constexpr int threads_for() { return N >= 72 ? 512 : 256; }
+
+// Pass 1, 2, 3 of one chunk for the cubic grid N^3.  The FP32 form always
+// takes the G = 0 coefficient from FP64 slab sums.
+template <int N>
+hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hipStream_t s) {
+  constexpr int NT = threads_for<N>();
+  dim3 g1(N, a.ic), g2(N, npairs), g3(N, a.ic);
+  if (fp32) {
+    hipLaunchKernelGGL((pass1_fwd_xy<float, N, N, NT, true>), g1, dim3(NT), 0, s, a);
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, true>), g2, dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, false>), g2, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT>), g3, dim3(NT), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((pass1_fwd_xy<double, N, N, NT, false>), g1, dim3(NT), 0, s, a);
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, true>), g2, dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, false>), g2, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT>), g3, dim3(NT), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace px

@@ -1,0 +1,309 @@
+// Complex contractions of the ACE construction and application on MFMA
+// (gfx950 matrix cores):
+//
+//   xhy:  M[a][b] = scale * sum_r conj(X[a][r]) Y[b][r]     (M = dV Psi^H W,
+//                                                           C = dV xi^H Phi)
+//   xc :  Z[b][r] = alpha * sum_a X[a][r] C[a][b]           (xi = W U,
+//                                                           Y = -xi C)
+//
+// X, Y, Z are orbital blocks [orb][N_g] (complex128 or complex64), C and M are
+// small complex128 matrices.  A complex product is four real MFMAs:
+//   re += xr*yr + xi*yi, im += xr*yi - xi*yr   (xhy, conjugated left operand)
+//   re += xr*cr - xi*ci, im += xr*ci + xi*cr   (xc)
+// using v_mfma_f64_16x16x4f64 (FP64 form) or v_mfma_f32_16x16x4f32 (FP32
+// form).  Operand layout of both 16x16x4 instructions: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16].  The result layouts differ: item t of lane
+// l holds D[4*(l/16)+t][l%16] for f32 but D[l/16+4*t][l%16] for f64 (checked
+// on gfx950 with a one-hot B operand).
+//
+// xhy splits the long r sum across workgroups; each writes FP64 partials that
+// a second kernel adds in a fixed order (deterministic).  In the FP32 form
+// the MFMA accumulators cover at most 1024 consecutive r before they are
+// added into FP64 registers, which keeps the contraction error near 1e-8.
+#include "fft_core.hpp"
+#include "px_internal.hpp"
+
+namespace px {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double vd2g __attribute__((ext_vector_type(2)));
+typedef float vf2g __attribute__((ext_vector_type(2)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { using t = d4; };
+template <> struct Acc<float> { using t = f4; };
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ __forceinline__ cpx<T> load_c(const cpx<T>* p) {
+  if constexpr (sizeof(T) == 8) {
+    vd2g v = *reinterpret_cast<const vd2g*>(p);
+    return {v.x, v.y};
+  } else {
+    vf2g v = *reinterpret_cast<const vf2g*>(p);
+    return {v.x, v.y};
+  }
+}
+
+// Row of the 16x16 result held in item t of a lane with l/16 = q.
+template <typename T> __device__ __forceinline__ int drow(int q, int t) {
+  return sizeof(T) == 8 ? q + 4 * t : 4 * q + t;
+}
+
+constexpr int XHY_SUB = 1024;  // FP32 form: r-span of one FP32 accumulation
+constexpr int XHY_KU = 4;      // k-steps of 4 per unrolled iteration (16 r)
+
+// ---------------------------------------------------------------- xhy
+// grid (ceil(na/64), ceil(nb/64), nsplit), 256 threads; wave w covers the
+// 32x32 sub-block (w&1, w>>1) as 2x2 MFMA tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_xhy_k(int na, int nb, size_t ng, const cpx<T>* X,
+                                                  const cpx<T>* Y, double* part, size_t kchunk) {
+  using A = typename Acc<T>::t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a_base = blockIdx.x * 64 + (w & 1) * 32;
+  const int b_base = blockIdx.y * 64 + (w >> 1) * 32;
+  const size_t r_begin = size_t(blockIdx.z) * kchunk;
+  const size_t r_end = (r_begin + kchunk < ng) ? r_begin + kchunk : ng;
+  const int q = lane >> 4, m = lane & 15;
+
+  const cpx<T>* xrow[2];
+  const cpx<T>* yrow[2];
+  bool xv[2], yv[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int a = a_base + 16 * t + m, b = b_base + 16 * t + m;
+    xv[t] = a < na;
+    yv[t] = b < nb;
+    xrow[t] = X + size_t(xv[t] ? a : 0) * ng;
+    yrow[t] = Y + size_t(yv[t] ? b : 0) * ng;
+  }
+  A are[2][2], aim[2][2];
+  double dre[2][2][4], dim[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      are[i][j] = A{0, 0, 0, 0};
+      aim[i][j] = A{0, 0, 0, 0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) dre[i][j][t] = dim[i][j][t] = 0.0;
+    }
+
+  size_t r0 = r_begin;
+  while (r0 < r_end) {
+    const size_t sub_end = (sizeof(T) == 4) ? ((r0 + XHY_SUB < r_end) ? r0 + XHY_SUB : r_end) : r_end;
+    for (; r0 < sub_end; r0 += 4 * XHY_KU) {
+      // lane (m, q) reads r = r0 + 4q + s, s = 0..3 for each of its rows
+      cpx<T> xa[2][XHY_KU], yb[2][XHY_KU];
+      const size_t rl = r0 + 4 * q;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int s = 0; s < XHY_KU; ++s) {
+          const bool in = rl + s < sub_end;
+          xa[t][s] = (in && xv[t]) ? load_c(xrow[t] + rl + s) : cpx<T>{T(0), T(0)};
+          yb[t][s] = (in && yv[t]) ? load_c(yrow[t] + rl + s) : cpx<T>{T(0), T(0)};
+        }
+#pragma unroll
+      for (int s = 0; s < XHY_KU; ++s)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            are[i][j] = mfma(xa[i][s].x, yb[j][s].x, are[i][j]);
+            are[i][j] = mfma(xa[i][s].y, yb[j][s].y, are[i][j]);
+            aim[i][j] = mfma(xa[i][s].x, yb[j][s].y, aim[i][j]);
+            aim[i][j] = mfma(-xa[i][s].y, yb[j][s].x, aim[i][j]);
+          }
+    }
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            dre[i][j][t] += double(are[i][j][t]);
+            dim[i][j][t] += double(aim[i][j][t]);
+          }
+          are[i][j] = A{0, 0, 0, 0};
+          aim[i][j] = A{0, 0, 0, 0};
+        }
+    }
+  }
+  double* out = part + size_t(blockIdx.z) * na * nb * 2;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int a = a_base + 16 * i + drow<T>(q, t), b = b_base + 16 * j + m;
+        if (a < na && b < nb) {
+          double re, im;
+          if constexpr (sizeof(T) == 4) {
+            re = dre[i][j][t];
+            im = dim[i][j][t];
+          } else {
+            re = are[i][j][t];
+            im = aim[i][j][t];
+          }
+          out[(size_t(a) * nb + b) * 2] = re;
+          out[(size_t(a) * nb + b) * 2 + 1] = im;
+        }
+      }
+}
+
+__global__ void xhy_reduce_k(int na, int nb, const double* part, int nsplit, double scale,
+                             double* M, int ldm) {
+  const size_t n = size_t(na) * nb;
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+       e += size_t(gridDim.x) * blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+      re += part[(size_t(s) * n + e) * 2];
+      im += part[(size_t(s) * n + e) * 2 + 1];
+    }
+    const size_t a = e / nb, b = e % nb;
+    M[(a * ldm + b) * 2] = scale * re;
+    M[(a * ldm + b) * 2 + 1] = scale * im;
+  }
+}
+
+static size_t xhy_kchunk(int na, int nb, size_t ng, int* nsplit) {
+  const size_t tiles = size_t((na + 63) / 64) * ((nb + 63) / 64);
+  size_t want = (2048 + tiles - 1) / tiles;  // aim at ~2048 workgroups
+  size_t kchunk = (ng + want - 1) / want;
+  if (kchunk < 1024) kchunk = 1024;
+  kchunk = (kchunk + 15) / 16 * 16;
+  *nsplit = int((ng + kchunk - 1) / kchunk);
+  return kchunk;
+}
+
+size_t gemm_xhy_part_elems(int na, int nb, size_t ng, int* nsplit) {
+  xhy_kchunk(na, nb, ng, nsplit);
+  return size_t(*nsplit) * na * nb;
+}
+
+hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, const void* Y,
+                           double scale, double* M, int ldm, double* part, int nsplit_avail,
+                           hipStream_t s) {
+  int nsplit;
+  const size_t kchunk = xhy_kchunk(na, nb, ng, &nsplit);
+  if (nsplit > nsplit_avail) return hipErrorInvalidValue;
+  dim3 grid((na + 63) / 64, (nb + 63) / 64, nsplit);
+  if (fp32)
+    hipLaunchKernelGGL(gemm_xhy_k<float>, grid, dim3(256), 0, s, na, nb, ng,
+                       static_cast<const cpx<float>*>(X), static_cast<const cpx<float>*>(Y), part,
+                       kchunk);
+  else
+    hipLaunchKernelGGL(gemm_xhy_k<double>, grid, dim3(256), 0, s, na, nb, ng,
+                       static_cast<const cpx<double>*>(X), static_cast<const cpx<double>*>(Y),
+                       part, kchunk);
+  const size_t n = size_t(na) * nb;
+  const int blocks = int((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(xhy_reduce_k, dim3(blocks), dim3(256), 0, s, na, nb, part, nsplit, scale, M,
+                     ldm);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- xc
+// grid (ceil(ng/64), ceil(nb/64)), 256 threads; wave w covers r-block (w&1)
+// and b-block (w>>1) of 32 each, as 2x2 MFMA tiles (i: r, j: b).
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_xc_k(int na, int nb, size_t ng, const cpx<T>* X,
+                                                 const double* C, int ldc, double alpha,
+                                                 cpx<T>* Z, int upper) {
+  using A = typename Acc<T>::t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const size_t r_base = size_t(blockIdx.x) * 64 + (w & 1) * 32;
+  const int b_base = blockIdx.y * 64 + (w >> 1) * 32;
+  const int q = lane >> 4, m = lane & 15;
+  int a_end = na;
+  if (upper) {
+    const int lim = blockIdx.y * 64 + 64;
+    a_end = lim < na ? lim : na;
+  }
+  bool rv[2], bv[2];
+  size_t rr[2];
+  int bb[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    rr[t] = r_base + 16 * t + m;
+    rv[t] = rr[t] < ng;
+    bb[t] = b_base + 16 * t + m;
+    bv[t] = bb[t] < nb;
+  }
+  A zre[2][2], zim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      zre[i][j] = A{0, 0, 0, 0};
+      zim[i][j] = A{0, 0, 0, 0};
+    }
+  for (int a0 = 0; a0 < a_end; a0 += 4) {
+    const int a = a0 + q;
+    const bool av = a < a_end;
+    cpx<T> xa[2], cb[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      xa[t] = (av && rv[t]) ? load_c(X + size_t(a) * ng + rr[t]) : cpx<T>{T(0), T(0)};
+      if (av && bv[t]) {
+        const double* c = C + (size_t(a) * ldc + bb[t]) * 2;
+        cb[t] = {T(c[0]), T(c[1])};
+      } else {
+        cb[t] = {T(0), T(0)};
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        zre[i][j] = mfma(xa[i].x, cb[j].x, zre[i][j]);
+        zre[i][j] = mfma(-xa[i].y, cb[j].y, zre[i][j]);
+        zim[i][j] = mfma(xa[i].x, cb[j].y, zim[i][j]);
+        zim[i][j] = mfma(xa[i].y, cb[j].x, zim[i][j]);
+      }
+  }
+  const T al = T(alpha);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int b = b_base + 16 * j + m;
+      if (b >= nb) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const size_t r = r_base + 16 * i + drow<T>(q, t);
+        if (r < ng) {
+          cpx<T>* o = Z + size_t(b) * ng + r;
+          o->x = al * zre[i][j][t];
+          o->y = al * zim[i][j][t];
+        }
+      }
+    }
+}
+
+hipError_t launch_gemm_xc(bool fp32, int na, int nb, size_t ng, const void* X, const double* C,
+                          int ldc, double alpha, void* Z, bool upper, hipStream_t s) {
+  dim3 grid(unsigned((ng + 63) / 64), (nb + 63) / 64);
+  if (fp32)
+    hipLaunchKernelGGL(gemm_xc_k<float>, grid, dim3(256), 0, s, na, nb, ng,
+                       static_cast<const cpx<float>*>(X), C, ldc, alpha,
+                       static_cast<cpx<float>*>(Z), int(upper));
+  else
+    hipLaunchKernelGGL(gemm_xc_k<double>, grid, dim3(256), 0, s, na, nb, ng,
+                       static_cast<const cpx<double>*>(X), C, ldc, alpha,
+                       static_cast<cpx<double>*>(Z), int(upper));
+  return hipGetLastError();
+}
+
+}  // namespace px

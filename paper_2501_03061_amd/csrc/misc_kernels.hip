@@ -1,0 +1,208 @@
+// Small kernels around the pair pipeline: the screened kernel table, FP64 ->
+// FP32 staging, and the fixed-order FP64 reductions of the exchange energy.
+#include "px_internal.hpp"
+
+namespace px {
+
+// K(G) of the HSE06 screened interaction (Fourier transform of erfc(mu r)/r):
+// 4 pi (1 - exp(-G^2/(4 mu^2))) / G^2 for G != 0 via expm1, pi/mu^2 at G = 0.
+// G = 2 pi m / L per axis, m the signed frequency of the FFT index.
+__global__ void kernel_hse_k(int n0, int n1, int n2, double L0, double L1, double L2, double mu,
+                             double* kern) {
+  const size_t ng = size_t(n0) * n1 * n2;
+  for (size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < ng;
+       idx += size_t(gridDim.x) * blockDim.x) {
+    const int x = int(idx % n0), y = int((idx / n0) % n1), z = int(idx / (size_t(n0) * n1));
+    const int mx = (2 * x < n0) ? x : x - n0;
+    const int my = (2 * y < n1) ? y : y - n1;
+    const int mz = (2 * z < n2) ? z : z - n2;
+    const double tp = 6.283185307179586476925286766559;
+    const double gx = tp * mx / L0, gy = tp * my / L1, gz = tp * mz / L2;
+    const double g2 = gx * gx + gy * gy + gz * gz;
+    double k;
+    if (g2 > 0.0) k = 4.0 * 3.14159265358979323846264338328 * (-expm1(-g2 / (4.0 * mu * mu))) / g2;
+    else k = 3.14159265358979323846264338328 / (mu * mu);
+    kern[idx] = k;
+  }
+}
+
+hipError_t launch_kernel_hse(int n0, int n1, int n2, double L0, double L1, double L2, double mu,
+                             double* kern, hipStream_t s) {
+  const size_t ng = size_t(n0) * n1 * n2;
+  const int blocks = int((ng + 255) / 256 < 65536 ? (ng + 255) / 256 : 65536);
+  hipLaunchKernelGGL(kernel_hse_k, dim3(blocks), dim3(256), 0, s, n0, n1, n2, L0, L1, L2, mu, kern);
+  return hipGetLastError();
+}
+
+typedef double vd4 __attribute__((ext_vector_type(4)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+// complex128 -> complex64, round to nearest even; two complex values per thread step
+__global__ void convert_k(size_t n, const double* src, float* dst) {
+  const size_t npair = n / 2;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < npair;
+       i += size_t(gridDim.x) * blockDim.x) {
+    vd4 v = __builtin_nontemporal_load(reinterpret_cast<const vd4*>(src) + i);
+    vf4 o = {float(v.x), float(v.y), float(v.z), float(v.w)};
+    reinterpret_cast<vf4*>(dst)[i] = o;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) {
+    dst[2 * (n - 1)] = float(src[2 * (n - 1)]);
+    dst[2 * (n - 1) + 1] = float(src[2 * (n - 1) + 1]);
+  }
+}
+
+hipError_t launch_convert_c128_c64(size_t n, const void* src, void* dst, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t work = (n / 2 + 255) / 256;
+  const int blocks = int(work < 8192 ? (work > 0 ? work : 1) : 8192);
+  hipLaunchKernelGGL(convert_k, dim3(blocks), dim3(256), 0, s, n,
+                     static_cast<const double*>(src), static_cast<float*>(dst));
+  return hipGetLastError();
+}
+
+__global__ void expart_reduce_k(const double* expart, int n1, int i0, int ic, int j0, int jc,
+                                double* S, int lds) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ic * jc) return;
+  const int ii = p / jc, jj = p % jc;
+  double s = 0.0;
+  for (int y = 0; y < n1; ++y) s += expart[size_t(p) * n1 + y];
+  S[size_t(i0 + ii) * lds + (j0 + jj)] = s;
+}
+
+hipError_t launch_expart_reduce(const double* expart, int n1, int i0, int ic, int j0, int jc,
+                                double* S, int lds, hipStream_t s) {
+  const int np = ic * jc;
+  hipLaunchKernelGGL(expart_reduce_k, dim3((np + 255) / 256), dim3(256), 0, s, expart, n1, i0, ic,
+                     j0, jc, S, lds);
+  return hipGetLastError();
+}
+
+// e_x = scale * sum_i f_i sum_j f_j S[i][j]; one block, fixed summation order.
+__global__ __launch_bounds__(256) void energy_k(const double* S, const double* occ, int n,
+                                                double scale, double* e_x) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    double row = 0.0;
+    for (int j = 0; j < n; ++j) row += occ[j] * S[size_t(i) * n + j];
+    acc += occ[i] * row;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *e_x = scale * red[0];
+}
+
+hipError_t launch_energy(const double* S, const double* occ, int n, double scale, double* e_x,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(energy_k, dim3(1), dim3(256), 0, s, S, occ, n, scale, e_x);
+  return hipGetLastError();
+}
+
+}  // namespace px
+
+// ---------------------------------------------------------------- PT-IM-style loop
+namespace px {
+
+template <typename T> struct V2;
+template <> struct V2<double> { typedef double t __attribute__((ext_vector_type(2))); };
+template <> struct V2<float> { typedef float t __attribute__((ext_vector_type(2))); };
+
+// mid = (a + b)/2 over n complex values
+template <typename T>
+__global__ void midpoint_k(size_t n, const T* a, const T* b, T* mid) {
+  using V = typename V2<T>::t;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    V x = reinterpret_cast<const V*>(a)[i], y = reinterpret_cast<const V*>(b)[i];
+    V m = {T(0.5) * (x.x + y.x), T(0.5) * (x.y + y.y)};
+    reinterpret_cast<V*>(mid)[i] = m;
+  }
+}
+
+// nxt = phi_n - i*c*y; per-block FP64 partials of |nxt - cur|^2 and |nxt|^2
+template <typename T>
+__global__ __launch_bounds__(256) void ptim_update_k(size_t n, const T* phi_n, const T* y,
+                                                     const T* cur, T* nxt, double c,
+                                                     double* partial) {
+  using V = typename V2<T>::t;
+  __shared__ double red[2][256];
+  double dd = 0.0, nn = 0.0;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += size_t(gridDim.x) * blockDim.x) {
+    V p = reinterpret_cast<const V*>(phi_n)[i], v = reinterpret_cast<const V*>(y)[i];
+    V q = reinterpret_cast<const V*>(cur)[i];
+    // -i c (vr + i vi) = c vi - i c vr
+    const double nr = double(p.x) + c * double(v.y), ni = double(p.y) - c * double(v.x);
+    V o = {T(nr), T(ni)};
+    reinterpret_cast<V*>(nxt)[i] = o;
+    const double dr = double(o.x) - double(q.x), di = double(o.y) - double(q.y);
+    dd += dr * dr + di * di;
+    nn += double(o.x) * double(o.x) + double(o.y) * double(o.y);
+  }
+  red[0][threadIdx.x] = dd;
+  red[1][threadIdx.x] = nn;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = red[0][0];
+    partial[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+// res = sqrt(sum dd / sum nn) over nblocks partials, fixed order
+__global__ void residual_k(const double* partial, int nblocks, double* res) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < nblocks; ++k) {
+    a += partial[2 * k];
+    b += partial[2 * k + 1];
+  }
+  *res = sqrt(a / b);
+}
+
+constexpr int kUpdateBlocks = 1024;
+
+int ptim_update_blocks() { return kUpdateBlocks; }
+
+hipError_t launch_midpoint(bool fp32, size_t n, const void* a, const void* b, void* mid,
+                           hipStream_t s) {
+  const int blocks = int((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+  if (fp32)
+    hipLaunchKernelGGL(midpoint_k<float>, dim3(blocks), dim3(256), 0, s, n,
+                       static_cast<const float*>(a), static_cast<const float*>(b),
+                       static_cast<float*>(mid));
+  else
+    hipLaunchKernelGGL(midpoint_k<double>, dim3(blocks), dim3(256), 0, s, n,
+                       static_cast<const double*>(a), static_cast<const double*>(b),
+                       static_cast<double*>(mid));
+  return hipGetLastError();
+}
+
+hipError_t launch_ptim_update(bool fp32, size_t n, const void* phi_n, const void* y,
+                              const void* cur, void* nxt, double c, double* partial,
+                              double* res, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(ptim_update_k<float>, dim3(kUpdateBlocks), dim3(256), 0, s, n,
+                       static_cast<const float*>(phi_n), static_cast<const float*>(y),
+                       static_cast<const float*>(cur), static_cast<float*>(nxt), c, partial);
+  else
+    hipLaunchKernelGGL(ptim_update_k<double>, dim3(kUpdateBlocks), dim3(256), 0, s, n,
+                       static_cast<const double*>(phi_n), static_cast<const double*>(y),
+                       static_cast<const double*>(cur), static_cast<double*>(nxt), c, partial);
+  hipLaunchKernelGGL(residual_k, dim3(1), dim3(64), 0, s, partial, kUpdateBlocks, res);
+  return hipGetLastError();
+}
+
+}  // namespace px

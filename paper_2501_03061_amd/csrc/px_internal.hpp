@@ -1,0 +1,70 @@
+// Internal interfaces between the host orchestration (px_api.cpp) and the
+// kernel translation units.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace px {
+
+// One chunk of orbital pairs: i in [i0, i0+ic) (output orbitals phi_i) times
+// j in [j0, j0+jc) (density orbitals psi_j).  Pair p = (i-i0)*jc + (j-j0)
+// owns slab p of the pair buffer t ([pairs][n2][n1][n0]).
+struct ChunkArgs {
+  const void* psi;      // [n_psi][N_g] complex (precision of the call)
+  const void* phi;      // [n_phi][N_g]
+  void* t;              // pair buffer, >= ic*jc*N_g complex
+  void* out;            // [n_phi][N_g]
+  const double* occ;    // [n_psi]
+  const double* kern;   // [N_g] FP64, FFT order
+  double2* g0;          // [ic*jc][n2] FP64 slab sums (FP32 form)
+  double* expart;       // [ic*jc][n1] FP64 partial sums of K |rho(G)|^2
+  int n2;
+  int i0, ic, j0, jc;
+  int first;            // pass 3 overwrites the output instead of accumulating
+  double inv_ng;
+};
+
+bool grid_supported(int n0, int n1, int n2);
+hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool g0, bool ex,
+                        hipStream_t s);
+
+// misc_kernels.hip
+hipError_t launch_kernel_hse(int n0, int n1, int n2, double L0, double L1, double L2, double mu,
+                             double* kern, hipStream_t s);
+hipError_t launch_convert_c128_c64(size_t n, const void* src, void* dst, hipStream_t s);
+// S[i][j] (row stride lds) = sum_y expart[(ii*jc+jj)*n1 + y] for the chunk
+hipError_t launch_expart_reduce(const double* expart, int n1, int i0, int ic, int j0, int jc,
+                                double* S, int lds, hipStream_t s);
+// e_x = scale * sum_i sum_j f_i f_j S[i][j]
+hipError_t launch_energy(const double* S, const double* occ, int n, double scale, double* e_x,
+                         hipStream_t s);
+
+// PT-IM-style loop pieces (n = complex element count)
+hipError_t launch_midpoint(bool fp32, size_t n, const void* a, const void* b, void* mid,
+                           hipStream_t s);
+// nxt = phi_n - i*c*y; res = ||nxt - cur|| / ||nxt|| accumulated in FP64
+hipError_t launch_ptim_update(bool fp32, size_t n, const void* phi_n, const void* y,
+                              const void* cur, void* nxt, double c, double* partial,
+                              double* res, hipStream_t s);
+int ptim_update_blocks();
+
+// gemm_kernels.hip: complex GEMMs on MFMA
+// M[a][b] (a < na, b < nb, row-major ldm) = scale * sum_r conj(X[a][r]) Y[b][r]
+//   X: [na][ng], Y: [nb][ng]; FP64 result.  part: workspace of nsplit*na*nb complex128.
+hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, const void* Y,
+                           double scale, double* M, int ldm, double* part, int nsplit,
+                           hipStream_t s);
+size_t gemm_xhy_part_elems(int na, int nb, size_t ng, int* nsplit);
+// Z[b][r] = alpha * sum_a X[a][r] C[a][b]  (+ beta * Z[b][r] if accumulate)
+//   X: [na][ng], C: complex128 [na][ldc] row-major, Z: [nb][ng]; upper: C upper triangular
+hipError_t launch_gemm_xc(bool fp32, int na, int nb, size_t ng, const void* X, const double* C,
+                          int ldc, double alpha, void* Z, bool upper, hipStream_t s);
+
+// chol_kernels.hip: FP64 Hermitian tools on an n x n complex128 matrix (row-major)
+hipError_t launch_hermitize(double* M, int n, hipStream_t s);
+// U = L^{-H} where -M = L L^H; status[0] = 0 on success or the 1-based failing column
+hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t* status,
+                           hipStream_t s);
+
+}  // namespace px

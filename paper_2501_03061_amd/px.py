@@ -1,0 +1,267 @@
+"""Thin ctypes binding of libpx (include/px.h).
+
+Argument marshalling only: every array argument is a torch tensor that lives
+on the GPU (device memory and the current stream come from PyTorch); its data
+pointer, sizes and the stream handle are passed to the C entry point of the
+same name.  Nothing here computes any part of the method, and there is no
+fallback: if libpx.so is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpx.so")
+
+PX_OK, PX_ERR_INVALID_ARG, PX_ERR_UNSUPPORTED_GRID, PX_ERR_WORKSPACE, PX_ERR_DEVICE, \
+    PX_ERR_NOT_POSITIVE_DEFINITE = range(6)
+PX_PREC_FP64, PX_PREC_FP32 = 0, 1
+PX_OP_EXCHANGE, PX_OP_ACE_BUILD, PX_OP_ACE_APPLY, PX_OP_PTIM_LOOP = 0, 1, 2, 3
+
+STATUS_NAMES = {0: "PX_OK", 1: "PX_ERR_INVALID_ARG", 2: "PX_ERR_UNSUPPORTED_GRID",
+                3: "PX_ERR_WORKSPACE", 4: "PX_ERR_DEVICE", 5: "PX_ERR_NOT_POSITIVE_DEFINITE"}
+
+# Every function declared in include/px.h, with its ctypes signature.
+_vp, _i32, _sz, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t, ctypes.c_double
+
+
+class PxCell(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double * 3), ("n", ctypes.c_int32 * 3)]
+
+
+_cellp = ctypes.POINTER(PxCell)
+SIGNATURES = {
+    "px_abi_version": (_i32, []),
+    "px_create": (_i32, [_i32, ctypes.POINTER(_vp)]),
+    "px_destroy": (None, [_vp]),
+    "px_last_error": (ctypes.c_char_p, [_vp]),
+    "px_grid_supported": (_i32, [_cellp, _i32]),
+    "px_workspace_bytes": (_sz, [_vp, _i32, _cellp, _i32, _i32, _i32]),
+    "px_set_workspace": (_i32, [_vp, _vp, _sz]),
+    "px_set_tuning": (_i32, [_vp, _cellp, _i32, _i32, _i32]),
+    "px_kernel_hse": (_i32, [_vp, _cellp, _dbl, _vp, _vp]),
+    "px_convert_c128_to_c64": (_i32, [_vp, _sz, _vp, _vp, _vp]),
+    "px_exchange_apply": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "px_ace_build": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "px_ace_apply": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
+    "px_ptim_exchange_loop": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _i32, _dbl, _vp, _vp, _vp]),
+    "px_sync": (_i32, [_vp, _vp]),
+    "px_clear_error": (None, [_vp]),
+}
+
+_lib = None
+
+
+class PxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libpx.so once; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libpx.so not found at {path}: run __graft_entry__.build() "
+                          "(or python -m paper_2501_03061_amd.csrc.build) first")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+@dataclass(frozen=True)
+class Cell:
+    """Orthorhombic cell: edge lengths L (bohr) and grid n = (n0, n1, n2), n0 = x."""
+    L: tuple
+    n: tuple
+
+    @staticmethod
+    def cubic(n: int, L: float) -> "Cell":
+        return Cell((float(L),) * 3, (int(n),) * 3)
+
+    def c(self) -> PxCell:
+        return PxCell((ctypes.c_double * 3)(*self.L), (ctypes.c_int32 * 3)(*self.n))
+
+    @property
+    def ng(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def omega(self) -> float:
+        return self.L[0] * self.L[1] * self.L[2]
+
+    @property
+    def dV(self) -> float:
+        return self.omega / self.ng
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _prec(dtype) -> int:
+    import torch
+    if dtype == torch.complex128:
+        return PX_PREC_FP64
+    if dtype == torch.complex64:
+        return PX_PREC_FP32
+    raise TypeError(f"orbital blocks must be complex128 or complex64, got {dtype}")
+
+
+def _check_block(name, t, cell: Cell, dtype=None):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous device tensor")
+    if t.dim() != 4 or tuple(t.shape[1:]) != (cell.n[2], cell.n[1], cell.n[0]):
+        raise ValueError(f"{name} must have shape [orb][n2][n1][n0], got {tuple(t.shape)}")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+class Context:
+    """A px_context plus a caller-owned workspace tensor grown on demand."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        st = self.lib.px_create(int(device), ctypes.byref(h))
+        if st != PX_OK:
+            raise PxError(st, "px_create failed")
+        self.h = h
+        self.device = device
+        self.ws = None
+
+    def close(self):
+        if self.h:
+            self.lib.px_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != PX_OK:
+            raise PxError(st, self.lib.px_last_error(self.h).decode())
+
+    def last_error(self) -> str:
+        return self.lib.px_last_error(self.h).decode()
+
+    # ------------------------------------------------------------ workspace
+    def workspace_bytes(self, op, cell: Cell, prec, n_psi, n_phi=0) -> int:
+        return int(self.lib.px_workspace_bytes(self.h, op, ctypes.byref(cell.c()), prec, n_psi, n_phi))
+
+    def ensure_workspace(self, nbytes: int):
+        import torch
+        if nbytes <= 0:
+            raise PxError(PX_ERR_INVALID_ARG, "invalid problem for workspace sizing")
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = None
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._check(self.lib.px_set_workspace(self.h, _ptr(self.ws), self.ws.numel()))
+
+    def set_tuning(self, cell: Cell, prec, ic: int, jc: int):
+        self._check(self.lib.px_set_tuning(self.h, ctypes.byref(cell.c()), prec, ic, jc))
+
+    # ------------------------------------------------------------ entry points
+    def px_kernel_hse(self, cell: Cell, mu: float, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((cell.n[2], cell.n[1], cell.n[0]), dtype=torch.float64,
+                              device=f"cuda:{self.device}")
+        self._check(self.lib.px_kernel_hse(self.h, ctypes.byref(cell.c()), float(mu), _ptr(out),
+                                           _stream(stream)))
+        return out
+
+    def px_convert_c128_to_c64(self, src, dst=None, stream=None):
+        import torch
+        if src.dtype != torch.complex128 or not src.is_contiguous():
+            raise TypeError("src must be a contiguous complex128 tensor")
+        if dst is None:
+            dst = torch.empty(src.shape, dtype=torch.complex64, device=src.device)
+        self._check(self.lib.px_convert_c128_to_c64(self.h, src.numel(), _ptr(src), _ptr(dst),
+                                                    _stream(stream)))
+        return dst
+
+    def px_exchange_apply(self, cell: Cell, psi, occ, phi, kern, out=None, e_x=None,
+                          stream=None):
+        import torch
+        prec = _prec(psi.dtype)
+        _check_block("psi", psi, cell)
+        _check_block("phi", phi, cell, psi.dtype)
+        if out is None:
+            out = torch.empty_like(phi)
+        self.ensure_workspace(self.workspace_bytes(PX_OP_EXCHANGE, cell, prec, psi.shape[0], phi.shape[0]))
+        self._check(self.lib.px_exchange_apply(
+            self.h, ctypes.byref(cell.c()), prec, psi.shape[0], _ptr(psi), _ptr(occ),
+            phi.shape[0], _ptr(phi), _ptr(kern), _ptr(out), _ptr(e_x), _stream(stream)))
+        return out
+
+    def px_ace_build(self, cell: Cell, psi, occ, kern, xi=None, M=None, e_x=None, status=None,
+                     stream=None):
+        import torch
+        prec = _prec(psi.dtype)
+        _check_block("psi", psi, cell)
+        dev = psi.device
+        if xi is None:
+            xi = torch.empty_like(psi)
+        if status is None:
+            status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ensure_workspace(self.workspace_bytes(PX_OP_ACE_BUILD, cell, prec, psi.shape[0]))
+        self._check(self.lib.px_ace_build(
+            self.h, ctypes.byref(cell.c()), prec, psi.shape[0], _ptr(psi), _ptr(occ), _ptr(kern),
+            _ptr(xi), _ptr(M), _ptr(e_x), _ptr(status), _stream(stream)))
+        return xi, status
+
+    def px_ace_apply(self, cell: Cell, xi, phi, out=None, stream=None):
+        import torch
+        prec = _prec(xi.dtype)
+        _check_block("xi", xi, cell)
+        _check_block("phi", phi, cell, xi.dtype)
+        if out is None:
+            out = torch.empty_like(phi)
+        self.ensure_workspace(self.workspace_bytes(PX_OP_ACE_APPLY, cell, prec, xi.shape[0], phi.shape[0]))
+        self._check(self.lib.px_ace_apply(
+            self.h, ctypes.byref(cell.c()), prec, xi.shape[0], _ptr(xi), phi.shape[0], _ptr(phi),
+            _ptr(out), _stream(stream)))
+        return out
+
+    def px_ptim_exchange_loop(self, cell: Cell, xi, phi_n, n_iter: int, dt_alpha: float,
+                              out=None, residuals=None, stream=None):
+        import torch
+        prec = _prec(xi.dtype)
+        _check_block("xi", xi, cell)
+        _check_block("phi_n", phi_n, cell, xi.dtype)
+        if out is None:
+            out = torch.empty_like(phi_n)
+        if residuals is None:
+            residuals = torch.zeros(n_iter, dtype=torch.float64, device=phi_n.device)
+        self.ensure_workspace(self.workspace_bytes(PX_OP_PTIM_LOOP, cell, prec, xi.shape[0], phi_n.shape[0]))
+        self._check(self.lib.px_ptim_exchange_loop(
+            self.h, ctypes.byref(cell.c()), prec, xi.shape[0], _ptr(xi), phi_n.shape[0],
+            _ptr(phi_n), int(n_iter), float(dt_alpha), _ptr(out), _ptr(residuals), _stream(stream)))
+        return out, residuals
+
+    def px_sync(self, stream=None):
+        """Raises PxError(PX_ERR_NOT_POSITIVE_DEFINITE) after a failed ACE build."""
+        self._check(self.lib.px_sync(self.h, _stream(stream)))
+
+    def px_clear_error(self):
+        self.lib.px_clear_error(self.h)

@@ -17,3 +17,16 @@ def pytest_configure(config):
 def rng():
     import numpy as np
     return np.random.default_rng(12345)
+
+
+@pytest.fixture(scope="session")
+def px_ctx():
+    """One library context on cuda:0 for all GPU tests (workspace reused)."""
+    import torch
+    from paper_2501_03061_amd import px
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    ctx = px.Context(0)
+    yield ctx
+    torch.cuda.synchronize()
+    ctx.ws = None
+    ctx.close()

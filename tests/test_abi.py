@@ -1,0 +1,143 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/px.h, and rejects bad arguments before enqueuing work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2501_03061_amd import px
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "px.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(px_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return px.load_library()
+
+
+def test_header_declares_the_three_entry_points():
+    names = _declared_functions()
+    for n in ("px_exchange_apply", "px_ace_build", "px_ace_apply"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert names, "no declarations parsed"
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding marshals exactly the declared set
+    assert sorted(px.SIGNATURES) == names
+
+
+def test_abi_version(lib):
+    assert lib.px_abi_version() == 1
+
+
+@pytest.fixture()
+def ctx(lib):
+    h = ctypes.c_void_p()
+    assert lib.px_create(0, ctypes.byref(h)) == px.PX_OK
+    yield h
+    lib.px_destroy(h)
+
+
+def _cell(n=24, L=10.0):
+    return px.Cell.cubic(n, L).c()
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+def test_grid_support(lib):
+    for n in (16, 24, 32, 40, 48, 60, 64, 72, 80, 96):
+        assert lib.px_grid_supported(ctypes.byref(_cell(n)), 0) == 1
+    for n in (7, 11, 25, 100):
+        assert lib.px_grid_supported(ctypes.byref(_cell(n)), 0) == 0
+    noncubic = px.Cell((1.0, 1.0, 1.0), (24, 24, 32)).c()
+    assert lib.px_grid_supported(ctypes.byref(noncubic), 0) == 0
+
+
+def test_create_rejects_negative_device(lib):
+    h = ctypes.c_void_p()
+    assert lib.px_create(-1, ctypes.byref(h)) == px.PX_ERR_INVALID_ARG
+
+
+def _exchange(lib, ctx, cell, n_psi=4, n_phi=4, psi=FAKE, occ=FAKE, phi=FAKE, kern=FAKE,
+              out=ctypes.c_void_p(0x2000), e_x=None, prec=0):
+    return lib.px_exchange_apply(ctx, ctypes.byref(cell), prec, n_psi, psi, occ, n_phi, phi,
+                                 kern, out, e_x, None)
+
+
+def test_exchange_validation(lib, ctx):
+    c = _cell()
+    assert _exchange(lib, ctx, c, psi=None) == px.PX_ERR_INVALID_ARG
+    assert _exchange(lib, ctx, c, n_psi=0) == px.PX_ERR_INVALID_ARG
+    assert _exchange(lib, ctx, c, n_phi=-3) == px.PX_ERR_INVALID_ARG
+    assert _exchange(lib, ctx, c, prec=7) == px.PX_ERR_INVALID_ARG
+    assert _exchange(lib, ctx, c, out=FAKE) == px.PX_ERR_INVALID_ARG        # aliases psi
+    assert _exchange(lib, ctx, _cell(7)) == px.PX_ERR_UNSUPPORTED_GRID
+    bad = px.Cell((10.0, -1.0, 10.0), (24, 24, 24)).c()
+    assert _exchange(lib, ctx, bad) == px.PX_ERR_INVALID_ARG
+    # energy needs phi == psi and equal counts
+    ex = ctypes.c_void_p(0x3000)
+    assert _exchange(lib, ctx, c, phi=ctypes.c_void_p(0x4000), e_x=ex) == px.PX_ERR_INVALID_ARG
+    assert _exchange(lib, ctx, c, n_phi=3, e_x=ex) == px.PX_ERR_INVALID_ARG
+    # no workspace attached
+    assert _exchange(lib, ctx, c) == px.PX_ERR_WORKSPACE
+    assert b"workspace" in lib.px_last_error(ctx)
+
+
+def test_workspace_sizes(lib, ctx):
+    c = _cell(72, 20.0)
+    ng = 72 ** 3
+    b64 = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 0, 512, 512)
+    b32 = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 1, 512, 512)
+    # default chunk: 32 x 8 pair slabs dominate
+    assert b64 >= 256 * ng * 16 and b32 >= 256 * ng * 8 and b32 < b64
+    ace = lib.px_workspace_bytes(ctx, px.PX_OP_ACE_BUILD, ctypes.byref(c), 0, 512, 0)
+    assert ace >= b64 + 512 * ng * 16             # plus W
+    assert lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 0, 0, 4) == 0
+    # tuning changes the chunk
+    assert lib.px_set_tuning(ctx, ctypes.byref(c), 0, 8, 4) == px.PX_OK
+    small = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 0, 512, 512)
+    assert small < b64
+    assert lib.px_set_tuning(ctx, ctypes.byref(c), 0, 0, 0) == px.PX_OK
+    assert lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 0, 512, 512) == b64
+    assert lib.px_set_tuning(ctx, ctypes.byref(c), 0, -1, 4) == px.PX_ERR_INVALID_ARG
+
+
+def test_set_workspace_alignment(lib, ctx):
+    assert lib.px_set_workspace(ctx, ctypes.c_void_p(0x1001), 1024) == px.PX_ERR_INVALID_ARG
+    assert lib.px_set_workspace(ctx, ctypes.c_void_p(0x10000), 1024) == px.PX_OK
+
+
+def test_ace_validation(lib, ctx):
+    c = _cell()
+    st = ctypes.c_void_p(0x5000)
+    f = lib.px_ace_build
+    assert f(ctx, ctypes.byref(c), 0, 0, FAKE, FAKE, FAKE, ctypes.c_void_p(0x6000), None, None, st, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, ctypes.byref(c), 0, 4, FAKE, FAKE, FAKE, ctypes.c_void_p(0x6000), None, None, None, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, ctypes.byref(c), 0, 4, FAKE, FAKE, FAKE, FAKE, None, None, st, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, ctypes.byref(_cell(7)), 0, 4, FAKE, FAKE, FAKE, ctypes.c_void_p(0x6000), None, None, st, None) == px.PX_ERR_UNSUPPORTED_GRID
+    assert f(ctx, ctypes.byref(c), 0, 4, FAKE, FAKE, FAKE, ctypes.c_void_p(0x6000), None, None, st, None) == px.PX_ERR_WORKSPACE
+    g = lib.px_ace_apply
+    assert g(ctx, ctypes.byref(c), 0, 4, FAKE, 2, ctypes.c_void_p(0x7000), ctypes.c_void_p(0x7000), None) == px.PX_ERR_INVALID_ARG
+    assert g(ctx, ctypes.byref(c), 0, 4, None, 2, ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000), None) == px.PX_ERR_INVALID_ARG
+    assert g(ctx, ctypes.byref(c), 0, 4, FAKE, 2, ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000), None) == px.PX_ERR_WORKSPACE
+
+
+def test_kernel_and_convert_validation(lib, ctx):
+    c = _cell()
+    assert lib.px_kernel_hse(ctx, ctypes.byref(c), 0.0, FAKE, None) == px.PX_ERR_INVALID_ARG
+    assert lib.px_kernel_hse(ctx, ctypes.byref(c), 0.106, None, None) == px.PX_ERR_INVALID_ARG
+    assert lib.px_convert_c128_to_c64(ctx, 10, None, FAKE, None) == px.PX_ERR_INVALID_ARG
+    assert lib.px_convert_c128_to_c64(ctx, 10, ctypes.c_void_p(0x1010), ctypes.c_void_p(0x2000), None) == px.PX_ERR_INVALID_ARG

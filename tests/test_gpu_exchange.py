@@ -1,0 +1,196 @@
+"""GPU parity of px_exchange_apply and px_kernel_hse against the CPU oracle.
+
+Tolerances: FP64 form <= 1e-11 relative Frobenius on Vx Phi and on E_x; FP32
+form <= 2e-5 on Vx Phi and <= 1e-7 relative on E_x.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_03061_amd import inputs, px
+from _gpu import banner, relerr, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL, FP32_TOL, FP32_EX_TOL = 1e-11, 2e-5, 1e-7
+
+
+def _cell(inst):
+    return px.Cell(inst.L, inst.n)
+
+
+def _rand(rng, n_orb, n):
+    return rng.standard_normal((n_orb, n, n, n)) + 1j * rng.standard_normal((n_orb, n, n, n))
+
+
+def _run(ctx, cell, psi, occ, phi, kern, fp32=False, energy=False):
+    import torch
+    dt = torch.complex64 if fp32 else torch.complex128
+    psi_d = to_dev(psi)
+    phi_d = psi_d if phi is psi else to_dev(phi)
+    if fp32:
+        psi_d32 = ctx.px_convert_c128_to_c64(psi_d)
+        phi_d = psi_d32 if phi is psi else ctx.px_convert_c128_to_c64(phi_d)
+        psi_d = psi_d32
+    occ_d = to_dev(occ)
+    k_d = to_dev(kern) if isinstance(kern, np.ndarray) else kern
+    e = torch.zeros(1, dtype=torch.float64, device="cuda") if energy else None
+    out = ctx.px_exchange_apply(cell, psi_d, occ_d, phi_d, k_d, e_x=e)
+    torch.cuda.synchronize()
+    assert out.dtype == dt
+    return to_host(out), (float(e.item()) if energy else None)
+
+
+@pytest.mark.parametrize("n,L", [(24, 10.0), (72, 20.0)])
+def test_kernel_hse_matches_oracle(px_ctx, n, L):
+    banner(f"kernel_hse n={n}")
+    cell = px.Cell.cubic(n, L)
+    k = to_host(px_ctx.px_kernel_hse(cell, 0.106))
+    ref = oracle.kernel_hse((n, n, n), (L, L, L), 0.106)
+    assert np.abs(k - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+@pytest.fixture(scope="module")
+def toy24():
+    c = inputs.CONFIGS["toy24"]
+    inst = inputs.make_instance(c["n"], c["L"], c["n_orb"], c["kT"], seed=c["seed"])
+    K = oracle.kernel_hse(inst.n, inst.L, c["mu"])
+    vx = oracle.exchange_apply(inst.psi, inst.occ, inst.psi, K)
+    ex = oracle.exchange_energy_gspace(inst.psi, inst.occ, K, inst.omega)
+    return inst, K, vx, ex
+
+
+def test_exchange_fp64_toy24(px_ctx, toy24):
+    inst, K, vx, ex = toy24
+    banner("exchange fp64 toy24")
+    cell = _cell(inst)
+    kd = px_ctx.px_kernel_hse(cell, 0.106)
+    out, e = _run(px_ctx, cell, inst.psi, inst.occ, inst.psi, kd, energy=True)
+    assert relerr(out, vx) < FP64_TOL
+    assert abs(e - ex) < FP64_TOL * abs(ex)
+
+
+def test_exchange_fp32_toy24(px_ctx, toy24):
+    inst, K, vx, ex = toy24
+    banner("exchange fp32 toy24")
+    cell = _cell(inst)
+    kd = px_ctx.px_kernel_hse(cell, 0.106)
+    out, e = _run(px_ctx, cell, inst.psi, inst.occ, inst.psi, kd, fp32=True, energy=True)
+    err = relerr(out, vx)
+    print(f"fp32 toy24: vx err {err:.3e}, ex err {abs(e - ex) / abs(ex):.3e}")
+    assert err < FP32_TOL
+    assert abs(e - ex) < FP32_EX_TOL * abs(ex)
+
+
+@pytest.mark.parametrize("n", [16, 24, 32, 40, 48, 60, 64, 72, 80, 96])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_exchange_sizes_ragged_chunks(px_ctx, n, fp32):
+    """Every compiled grid, unstructured random orbitals, a non-even random
+    kernel (pins the transform sign convention too), ragged pair chunks."""
+    banner(f"exchange sizes n={n} fp32={fp32}")
+    rng = np.random.default_rng(100 + n)
+    L = 0.3 * n
+    cell = px.Cell.cubic(n, L)
+    n_psi, n_phi = 7, 5
+    psi, phi = _rand(rng, n_psi, n), _rand(rng, n_phi, n)
+    occ = rng.uniform(0, 1, n_psi)
+    K = rng.uniform(0.1, 2.0, (n, n, n))
+    prec = px.PX_PREC_FP32 if fp32 else px.PX_PREC_FP64
+    px_ctx.set_tuning(cell, prec, 2, 3)      # 3 i-chunks (2,2,1) x 3 j-chunks (3,3,1)
+    try:
+        out, _ = _run(px_ctx, cell, psi, occ, phi, K, fp32=fp32)
+    finally:
+        px_ctx.set_tuning(cell, prec, 0, 0)
+    ref = oracle.exchange_apply(psi, occ, phi, K)
+    err = relerr(out, ref)
+    print(f"n={n} fp32={fp32}: err {err:.3e}")
+    assert err < (FP32_TOL if fp32 else FP64_TOL)
+
+
+def test_exchange_constant_kernel_is_local(px_ctx):
+    banner("exchange constant kernel")
+    rng = np.random.default_rng(7)
+    n = 32
+    cell = px.Cell.cubic(n, 9.0)
+    psi, phi = _rand(rng, 4, n), _rand(rng, 3, n)
+    occ = rng.uniform(0, 1, 4)
+    c = 1.75
+    out, _ = _run(px_ctx, cell, psi, occ, phi, np.full((n, n, n), c))
+    dens = np.einsum("j,jzyx->zyx", occ, np.abs(psi) ** 2)
+    assert relerr(out, -c * dens[None] * phi) < FP64_TOL
+
+
+def test_exchange_g0_kernel_is_projector(px_ctx):
+    banner("exchange G=0 kernel")
+    rng = np.random.default_rng(8)
+    n, L = 24, 7.0
+    cell = px.Cell.cubic(n, L)
+    dV = L ** 3 / n ** 3
+    psi, phi = _rand(rng, 3, n), _rand(rng, 2, n)
+    occ = rng.uniform(0, 1, 3)
+    K = np.zeros((n, n, n))
+    K[0, 0, 0] = 279.6
+    out, _ = _run(px_ctx, cell, psi, occ, phi, K)
+    expect = np.zeros_like(phi)
+    for i in range(2):
+        for j in range(3):
+            expect[i] -= (279.6 / L ** 3) * occ[j] * dV * np.vdot(psi[j], phi[i]) * psi[j]
+    assert relerr(out, expect) < FP64_TOL
+
+
+def test_exchange_plane_wave_closed_form_72(px_ctx):
+    """Closed form at the full 72^3 grid: Vx e^{ik.r} = -sum_j f_j K(k-k_j)/Omega e^{ik.r}."""
+    banner("exchange plane waves 72")
+    n, L, mu = 72, 20.0, 0.106
+    ms = [(0, 0, 0), (3, -1, 2), (35, 0, 0), (-20, 7, 1), (1, 1, 1)]
+    occ = np.array([1.0, 0.9, 0.3, 0.05, 1e-6])
+    psi = inputs.plane_wave_orbitals(n, L, ms)
+    mk = (-36, 2, 5)
+    phi = inputs.plane_wave_orbitals(n, L, [mk, (0, 0, 1)])
+    cell = px.Cell.cubic(n, L)
+    kd = px_ctx.px_kernel_hse(cell, mu)
+    out, _ = _run(px_ctx, cell, psi, occ, phi, kd)
+
+    def wrap(m):
+        m %= n
+        return m if m < n / 2 else m - n
+
+    for c, kv in enumerate([mk, (0, 0, 1)]):
+        lam = 0.0
+        for j, mj in enumerate(ms):
+            q = [wrap(kv[a] - mj[a]) for a in range(3)]
+            g2 = sum((2 * math.pi * q[a] / L) ** 2 for a in range(3))
+            kq = math.pi / mu ** 2 if g2 == 0 else 4 * math.pi * (-math.expm1(-g2 / (4 * mu * mu))) / g2
+            lam -= occ[j] * kq / L ** 3
+        assert relerr(out[c], lam * phi[c]) < FP64_TOL
+
+
+def test_exchange_tuning_invariance(px_ctx, toy24):
+    inst, K, vx, ex = toy24
+    banner("exchange tuning invariance")
+    cell = _cell(inst)
+    kd = to_dev(K)
+    res = []
+    for ic, jc in [(1, 1), (16, 16), (5, 7), (32, 8)]:
+        px_ctx.set_tuning(cell, px.PX_PREC_FP64, ic, jc)
+        out, e = _run(px_ctx, cell, inst.psi, inst.occ, inst.psi, kd, energy=True)
+        res.append((out, e))
+    px_ctx.set_tuning(cell, px.PX_PREC_FP64, 0, 0)
+    for out, e in res:
+        assert relerr(out, vx) < FP64_TOL
+        assert abs(e - ex) < FP64_TOL * abs(ex)
+
+
+def test_exchange_single_orbital_and_zero_occupation(px_ctx):
+    banner("exchange degenerate cases")
+    rng = np.random.default_rng(9)
+    n = 16
+    cell = px.Cell.cubic(n, 5.0)
+    psi = _rand(rng, 1, n)
+    K = rng.uniform(0.1, 1.0, (n, n, n))
+    out, _ = _run(px_ctx, cell, psi, np.array([0.0]), psi, K)
+    assert np.abs(out).max() == 0.0
+    out, _ = _run(px_ctx, cell, psi, np.array([0.5]), psi, K)
+    assert relerr(out, oracle.exchange_apply(psi, np.array([0.5]), psi, K)) < FP64_TOL
