@@ -166,6 +166,21 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
                                 double dt_alpha, void* phi_out, double* residuals,
                                 hipStream_t stream);
 
+/* Measurement mode.  When enabled, px_exchange_apply and px_ace_build record
+ * HIP events on their stream around pass 1 (pair product + forward xy
+ * transforms), pass 2 (z transforms + kernel multiply) and pass 3 (inverse xy
+ * transforms + weighted accumulation) of every pair chunk, and synchronise on
+ * the last event before returning (the only host synchronisation outside
+ * px_sync).  Off by default. */
+px_status px_set_profiling(px_context* ctx, int32_t enable);
+
+/* Totals since the last reset, per pass k = 0, 1, 2: ms[k] summed event time,
+ * bytes[k] algorithmic HBM bytes (2 * N_g * element size per pair: pass 1 reads
+ * psi_j and writes the pair slab, pass 2 reads and rewrites it, pass 3 reads it
+ * and psi_j), launches[k] kernel launches.  reset != 0 zeroes the totals. */
+px_status px_profile_read(px_context* ctx, double* ms, double* bytes, int64_t* launches,
+                          int32_t reset);
+
 /* Synchronises `stream`, then reads the status word of the last px_ace_build
  * on this context: PX_ERR_NOT_POSITIVE_DEFINITE if it reported a breakdown
  * (the error stays latched until px_clear_error), PX_ERR_DEVICE on a HIP error. */

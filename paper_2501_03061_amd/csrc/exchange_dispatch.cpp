@@ -4,7 +4,8 @@
 namespace px {
 
 template <int N>
-hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hipStream_t s);
+hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
+                          hipEvent_t* ev);
 
 #define PX_SIZES(X) X(16) X(24) X(32) X(40) X(48) X(60) X(64) X(72) X(80) X(96)
 
@@ -16,10 +17,9 @@ bool grid_supported(int n0, int n1, int n2) {
   return false;
 }
 
-hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool g0, bool ex,
-                        hipStream_t s) {
-  (void)g0;
-#define PX_CASE(N) if (n == N) return launch_chunk_n<N>(fp32, a, npairs, ex, s);
+hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
+                        hipEvent_t* ev) {
+#define PX_CASE(N) if (n == N) return launch_chunk_n<N>(fp32, a, npairs, ex, s, ev);
   PX_SIZES(PX_CASE)
 #undef PX_CASE
   return hipErrorInvalidValue;

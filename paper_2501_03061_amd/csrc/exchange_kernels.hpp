@@ -72,8 +72,28 @@ template <int NT> __device__ __forceinline__ double block_sum(double v, double* 
   return s;
 }
 
+// Branch-free gather of the R inputs of every butterfly slot of a stage whose
+// reads are x[j + r*N/R] along the lines of geometry G: slot indices past the
+// last butterfly are clamped to it (loaded, never stored), so all loads of a
+// slab issue back to back and stay in flight across the LDS stages that follow.
+template <typename T, class G, int R, int NT, int BPT, class F>
+__device__ __forceinline__ void gather(cpx<T> (&v)[BPT][R], F&& load) {
+  constexpr int NB = G::nl * (G::n / R);
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    int b = threadIdx.x + k * NT;
+    if (NB % NT != 0) b = b < NB ? b : NB - 1;
+    int line, j;
+    decode<G, R>(b, line, j);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[k][r] = load(line, j + r * (G::n / R));
+  }
+}
+
 // ============================================================== pass 1
-template <typename T, int N0, int N1, int NT, bool G0>
+// PF: prefetch the next density orbital's slab while the current one is
+// transformed.
+template <typename T, int N0, int N1, int NT, bool G0, bool PF>
 __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
   __shared__ cpx<T> lds[N0 * N1];
   __shared__ cpx<T> tw0[N0];
@@ -93,32 +113,53 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
   const size_t slab = size_t(N0) * N1;
   const size_t ng = slab * a.n2;
   const cpx<T>* phi = reinterpret_cast<const cpx<T>*>(a.phi) + size_t(a.i0 + ii) * ng + z * slab;
+  const cpx<T>* psi0 = reinterpret_cast<const cpx<T>*>(a.psi) + size_t(a.j0) * ng + z * slab;
   const int tid = threadIdx.x;
+
+  cpx<T> ph[BPT0][X0::R], nx[BPT0][X0::R];
+  if constexpr (PF) {
+    gather<T, GX, X0::R, NT>(ph, [&](int line, int e) { return ldc(phi + line * N0 + e); });
+    gather<T, GX, X0::R, NT>(nx, [&](int line, int e) { return ldc(psi0 + line * N0 + e); });
+  }
   __syncthreads();
 
   for (int jj = 0; jj < a.jc; ++jj) {
-    const cpx<T>* psi = reinterpret_cast<const cpx<T>*>(a.psi) + size_t(a.j0 + jj) * ng + z * slab;
+    cpx<T> cu[BPT0][X0::R];
+    if constexpr (PF) {
+#pragma unroll
+      for (int k = 0; k < BPT0; ++k)
+#pragma unroll
+        for (int r = 0; r < X0::R; ++r) cu[k][r] = nx[k][r];
+      if (jj + 1 < a.jc) {
+        const cpx<T>* pn = psi0 + size_t(jj + 1) * ng;
+        gather<T, GX, X0::R, NT>(nx, [&](int line, int e) { return ldc(pn + line * N0 + e); });
+      }
+    } else {
+      const cpx<T>* pc = psi0 + size_t(jj) * ng;
+      gather<T, GX, X0::R, NT>(cu, [&](int line, int e) { return ldc(pc + line * N0 + e); });
+      gather<T, GX, X0::R, NT>(ph, [&](int line, int e) { return ldc(phi + line * N0 + e); });
+    }
     const int p = ii * a.jc + jj;
     double sre = 0.0, sim = 0.0;
-    // first x stage straight from global memory: product, radix butterfly, LDS
+    // first x stage from registers: product, radix butterfly, LDS
 #pragma unroll
     for (int k = 0; k < BPT0; ++k) {
       const int b = tid + k * NT;
-      if (NB0 % NT == 0 || b < NB0) {
-        int line, j;
-        decode<GX, X0::R>(b, line, j);
-        cpx<T> v[X0::R];
+      const bool valid = NB0 % NT == 0 || b < NB0;
+      int line, j;
+      decode<GX, X0::R>(valid ? b : 0, line, j);
+      cpx<T> v[X0::R];
 #pragma unroll
-        for (int r = 0; r < X0::R; ++r) {
-          const int off = line * N0 + j + r * (N0 / X0::R);
-          cpx<T> ps = ldc(psi + off), ph = ldc(phi + off);
-          if constexpr (G0) {
-            sre += double(ps.x) * double(ph.x) + double(ps.y) * double(ph.y);
-            sim += double(ps.x) * double(ph.y) - double(ps.y) * double(ph.x);
-          }
-          v[r] = cmulc(ps, ph);
+      for (int r = 0; r < X0::R; ++r) {
+        const cpx<T> ps = cu[k][r], ph_ = ph[k][r];
+        if (G0 && valid) {
+          sre += double(ps.x) * double(ph_.x) + double(ps.y) * double(ph_.y);
+          sim += double(ps.x) * double(ph_.y) - double(ps.y) * double(ph_.x);
         }
-        dft<T, X0::R, false>(v);
+        v[r] = cmulc(ps, ph_);
+      }
+      dft<T, X0::R, false>(v);
+      if (valid) {
 #pragma unroll
         for (int r = 0; r < X0::R; ++r) lds[line * N0 + out_pos<X0::R, 1>(j, r)] = v[r];
       }
@@ -170,28 +211,36 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
   constexpr int NBL = N0 * (N2 / FL::R), BPTL = (NBL + NT - 1) / NT;
   constexpr int NBI = N0 * (N2 / IL::R), BPTI = (NBI + NT - 1) / NT;
 
-  fill_twiddles<T, N2, NT>(tw2);
   const int y = blockIdx.x, p = blockIdx.y;
   const size_t slab = size_t(N0) * N1;
-  const size_t ng = slab * N2;
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(a.t) + size_t(p) * ng + size_t(y) * N0;
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(a.t) + size_t(p) * slab * N2 + size_t(y) * N0;
   const double* kern = a.kern + size_t(y) * N0;
   const int tid = threadIdx.x;
-  __syncthreads();
 
-  // forward stage 0 from global
+  // all global loads first: the plane (at stage-0 positions) and the kernel
+  // values at the positions the last forward stage produces
+  cpx<T> v0[BPT0][F0::R];
+  gather<T, GZ, F0::R, NT>(v0, [&](int line, int e) { return ldc(buf + size_t(e) * slab + line); });
+  double kv[BPTL][FL::R];
+#pragma unroll
+  for (int k = 0; k < BPTL; ++k) {
+    int b = tid + k * NT;
+    if (NBL % NT != 0) b = b < NBL ? b : NBL - 1;
+    int line, j;
+    decode<GZ, FL::R>(b, line, j);
+#pragma unroll
+    for (int r = 0; r < FL::R; ++r) kv[k][r] = kern[size_t(j + r * (N2 / FL::R)) * slab + line];
+  }
+  fill_twiddles<T, N2, NT>(tw2);
 #pragma unroll
   for (int k = 0; k < BPT0; ++k) {
     const int b = tid + k * NT;
     if (NB0 % NT == 0 || b < NB0) {
       int line, j;
       decode<GZ, F0::R>(b, line, j);
-      cpx<T> v[F0::R];
+      dft<T, F0::R, false>(v0[k]);
 #pragma unroll
-      for (int r = 0; r < F0::R; ++r) v[r] = ldc(buf + size_t(j + r * (N2 / F0::R)) * slab + line);
-      dft<T, F0::R, false>(v);
-#pragma unroll
-      for (int r = 0; r < F0::R; ++r) lds[out_pos<F0::R, 1>(j, r) * N0 + line] = v[r];
+      for (int r = 0; r < F0::R; ++r) lds[out_pos<F0::R, 1>(j, r) * N0 + line] = v0[k][r];
     }
   }
   __syncthreads();
@@ -212,7 +261,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
 #pragma unroll
       for (int r = 0; r < FL::R; ++r) {
         const int kz = j + r * (N2 / FL::R);
-        const double kg = kern[size_t(kz) * slab + line];
+        const double kg = kv[k][r];
         cpx<T> c = v[k][r];
         if (G0 && y == 0 && line == 0 && kz == 0) {
           // G = 0 from the FP64 slab sums of pass 1
@@ -270,7 +319,8 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
 }
 
 // ============================================================== pass 3
-template <typename T, int N0, int N1, int NT>
+// PF: prefetch the next pair slab and the next psi_j slab during the transform.
+template <typename T, int N0, int N1, int NT, bool PF>
 __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
   __shared__ cpx<T> lds[N0 * N1];
   __shared__ cpx<T> tw0[N0];
@@ -289,17 +339,44 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
   const size_t slab = size_t(N0) * N1;
   const size_t ng = slab * a.n2;
   const int tid = threadIdx.x;
+  const cpx<T>* t0 = reinterpret_cast<const cpx<T>*>(a.t) + size_t(ii * a.jc) * ng + z * slab;
+  const cpx<T>* psi0 = reinterpret_cast<const cpx<T>*>(a.psi) + size_t(a.j0) * ng + z * slab;
+  auto tload = [](const cpx<T>* base) {
+    return [base](int line, int e) { return ldg(base + line * N0 + e); };
+  };
+  auto pload = [](const cpx<T>* base) {
+    return [base](int line, int e) { return ldc(base + line + e * N0); };
+  };
   cpx<T> acc[BPTL][YL::R];
 #pragma unroll
   for (int k = 0; k < BPTL; ++k)
 #pragma unroll
     for (int r = 0; r < YL::R; ++r) acc[k][r] = {T(0), T(0)};
+  cpx<T> tn[BPT0][X0::R], pn[BPTL][YL::R];
+  if constexpr (PF) {
+    gather<T, GX, X0::R, NT>(tn, tload(t0));
+    gather<T, GY, YL::R, NT>(pn, pload(psi0));
+  }
   __syncthreads();
 
   for (int jj = 0; jj < a.jc; ++jj) {
-    const int p = ii * a.jc + jj;
-    const cpx<T>* tin = reinterpret_cast<const cpx<T>*>(a.t) + size_t(p) * ng + z * slab;
-    const cpx<T>* psi = reinterpret_cast<const cpx<T>*>(a.psi) + size_t(a.j0 + jj) * ng + z * slab;
+    cpx<T> tc[BPT0][X0::R], pc[BPTL][YL::R];
+    if constexpr (PF) {
+#pragma unroll
+      for (int k = 0; k < BPT0; ++k)
+#pragma unroll
+        for (int r = 0; r < X0::R; ++r) tc[k][r] = tn[k][r];
+#pragma unroll
+      for (int k = 0; k < BPTL; ++k)
+#pragma unroll
+        for (int r = 0; r < YL::R; ++r) pc[k][r] = pn[k][r];
+      if (jj + 1 < a.jc) {
+        gather<T, GX, X0::R, NT>(tn, tload(t0 + size_t(jj + 1) * ng));
+        gather<T, GY, YL::R, NT>(pn, pload(psi0 + size_t(jj + 1) * ng));
+      }
+    } else {
+      gather<T, GX, X0::R, NT>(tc, tload(t0 + size_t(jj) * ng));
+    }
     const T wj = T(a.occ[a.j0 + jj] * a.inv_ng);
 #pragma unroll
     for (int k = 0; k < BPT0; ++k) {
@@ -307,12 +384,9 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
       if (NB0 % NT == 0 || b < NB0) {
         int line, j;
         decode<GX, X0::R>(b, line, j);
-        cpx<T> v[X0::R];
+        dft<T, X0::R, true>(tc[k]);
 #pragma unroll
-        for (int r = 0; r < X0::R; ++r) v[r] = ldg(tin + line * N0 + j + r * (N0 / X0::R));
-        dft<T, X0::R, true>(v);
-#pragma unroll
-        for (int r = 0; r < X0::R; ++r) lds[line * N0 + out_pos<X0::R, 1>(j, r)] = v[r];
+        for (int r = 0; r < X0::R; ++r) lds[line * N0 + out_pos<X0::R, 1>(j, r)] = tc[k][r];
       }
     }
     __syncthreads();
@@ -324,6 +398,11 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
       if (NBL % NT == 0 || b < NBL) {
         int line, j;
         decode<GY, YL::R>(b, line, j);
+        if constexpr (!PF) {
+          const cpx<T>* pj = psi0 + size_t(jj) * ng;
+#pragma unroll
+          for (int r = 0; r < YL::R; ++r) pc[k][r] = ldc(pj + line + (j + r * (N1 / YL::R)) * N0);
+        }
         cpx<T> v[YL::R];
 #pragma unroll
         for (int r = 0; r < YL::R; ++r) v[r] = lds[line + (j + r * (N1 / YL::R)) * N0];
@@ -331,8 +410,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
         dft<T, YL::R, true>(v);
 #pragma unroll
         for (int r = 0; r < YL::R; ++r) {
-          cpx<T> ps = ldc(psi + line + (j + r * (N1 / YL::R)) * N0);
-          cpx<T> t = cmul(ps, v[r]);
+          cpx<T> t = cmul(pc[k][r], v[r]);
           acc[k][r].x += wj * t.x;
           acc[k][r].y += wj * t.y;
         }
@@ -358,25 +436,48 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
 }
 
 // ============================================================== host launcher
-template <int N> constexpr int threads_for() { return N >= 72 ? 512 : 256; }
+// Threads per workgroup: close to the butterfly count of each stage of a slab
+// (N * N / R), so that most stages take one butterfly per thread.
+template <int N> constexpr int threads_for() {
+  return N == 16 ? 64 : N == 24 ? 192 : N == 32 ? 256 : N == 40 ? 320 : N == 48 ? 384
+       : N == 60 ? 640 : N == 64 ? 512 : N == 72 ? 704 : N == 80 ? 832 : 768;
+}
+// Prefetch across pair iterations where the doubled register set fits
+// without spilling (checked with the compiler's resource report).
+template <typename T, int N> constexpr bool prefetch1_for() {
+  return sizeof(T) == 4 ? N <= 80 : N <= 72;
+}
+template <typename T, int N> constexpr bool prefetch3_for() {
+  return sizeof(T) == 4 ? N <= 80 : N <= 48;
+}
 
 // Pass 1, 2, 3 of one chunk for the cubic grid N^3.  The FP32 form always
 // takes the G = 0 coefficient from FP64 slab sums.
+// ev (optional, 4 events) brackets the passes: ev[0] | pass 1 | ev[1] | pass 2 | ev[2] | pass 3 | ev[3].
 template <int N>
-hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hipStream_t s) {
+hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
+                          hipEvent_t* ev) {
   constexpr int NT = threads_for<N>();
   dim3 g1(N, a.ic), g2(N, npairs), g3(N, a.ic);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  if (fp32)
+    hipLaunchKernelGGL((pass1_fwd_xy<float, N, N, NT, true, prefetch1_for<float, N>()>), g1, dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((pass1_fwd_xy<double, N, N, NT, false, prefetch1_for<double, N>()>), g1, dim3(NT), 0, s, a);
+  if (ev) (void)hipEventRecord(ev[1], s);
   if (fp32) {
-    hipLaunchKernelGGL((pass1_fwd_xy<float, N, N, NT, true>), g1, dim3(NT), 0, s, a);
     if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, true>), g2, dim3(NT), 0, s, a);
     else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, false>), g2, dim3(NT), 0, s, a);
-    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT>), g3, dim3(NT), 0, s, a);
   } else {
-    hipLaunchKernelGGL((pass1_fwd_xy<double, N, N, NT, false>), g1, dim3(NT), 0, s, a);
     if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, true>), g2, dim3(NT), 0, s, a);
     else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, false>), g2, dim3(NT), 0, s, a);
-    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT>), g3, dim3(NT), 0, s, a);
   }
+  if (ev) (void)hipEventRecord(ev[2], s);
+  if (fp32)
+    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT, prefetch3_for<float, N>()>), g3, dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT, prefetch3_for<double, N>()>), g3, dim3(NT), 0, s, a);
+  if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // Device-side building blocks of the LDS-staged mixed-radix FFT (gfx950).
 //
 // A 1D transform of compile-time length N is a sequence of Stockham
-// autosort stages with radices taken from {2, 3, 4, 5, 8}.  Stage s with radix
+// autosort stages with radices taken from {2, 3, 4, 5, 6, 8, 9, 10, 12}.  Stage s with radix
 // R and span NS (the product of the radices before it) maps butterfly j of a
 // line (0 <= j < N/R) as
 //     in :  x[j + r*N/R],                          r = 0..R-1
@@ -14,9 +14,10 @@
 // registers.
 //
 // Forward transforms use exp(-i...), inverse exp(+i...), both unnormalised.
-// Twiddles come from a table of the N-th roots of unity (computed on the host
-// in FP64, rounded for FP32), held in LDS; powers w^r are formed by repeated
-// complex multiplication.
+// Twiddles come from a table of the N-th roots of unity (FP64 sincospi,
+// rounded for FP32), held in LDS; powers w^r are formed by repeated complex
+// multiplication.  Composite radices (6, 9, 10, 12) are Cooley-Tukey in
+// registers with compile-time twiddles.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -110,18 +111,83 @@ template <typename T, bool INV> __device__ __forceinline__ void dft8(cpx<T>* v) 
   v[7] = csub(e[3], o3);
 }
 
+// cos and sin of 2 pi m / R for the twiddles inside composite radices
+// (R = 6, 9, 10, 12 and the products a*q that occur there).
+__host__ __device__ constexpr double tcos(int R, int m) {
+  return R == 6   ? (m == 1 ? 0.5 : m == 2 ? -0.5 : 1.0)
+       : R == 9   ? (m == 1 ? 0.76604444311897803520 : m == 2 ? 0.17364817766693034885
+                   : m == 4 ? -0.93969262078590838405 : 1.0)
+       : R == 10  ? (m == 1 ? 0.80901699437494742410 : m == 2 ? 0.30901699437494742410
+                   : m == 3 ? -0.30901699437494742410 : m == 4 ? -0.80901699437494742410 : 1.0)
+       : R == 12  ? (m == 1 ? 0.86602540378443864676 : m == 2 ? 0.5 : m == 3 ? 0.0
+                   : m == 4 ? -0.5 : m == 6 ? -1.0 : 1.0)
+       : 1.0;
+}
+__host__ __device__ constexpr double tsin(int R, int m) {
+  return R == 6   ? (m == 1 || m == 2 ? 0.86602540378443864676 : 0.0)
+       : R == 9   ? (m == 1 ? 0.64278760968653932632 : m == 2 ? 0.98480775301220805936
+                   : m == 4 ? 0.34202014332566873304 : 0.0)
+       : R == 10  ? (m == 1 || m == 4 ? 0.58778525229247312917 : m == 2 || m == 3 ? 0.95105651629515357212 : 0.0)
+       : R == 12  ? (m == 1 || m == 5 ? 0.5 : m == 2 || m == 4 ? 0.86602540378443864676
+                   : m == 3 ? 1.0 : 0.0)
+       : 0.0;
+}
+
+template <typename T, int R, bool INV> __device__ __forceinline__ void dft(cpx<T>* v);
+
+// Composite radix R = A*B (Cooley-Tukey in registers): B-point transforms of
+// the A decimated subsequences, twiddles w_R^(a*q), then A-point transforms;
+// input index a + A*b, output index q + B*p.
+template <typename T, int A, int B, bool INV> __device__ __forceinline__ void dft_ct(cpx<T>* v) {
+  constexpr int R = A * B;
+  cpx<T> u[A][B];
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    cpx<T> s[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) s[b] = v[a + A * b];
+    dft<T, B, INV>(s);
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (a == 0 || q == 0) {
+        u[a][q] = s[q];
+      } else {
+        const T c = T(tcos(R, a * q)), sn = T(INV ? tsin(R, a * q) : -tsin(R, a * q));
+        u[a][q] = {s[q].x * c - s[q].y * sn, s[q].x * sn + s[q].y * c};
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    cpx<T> s[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) s[a] = u[a][q];
+    dft<T, A, INV>(s);
+#pragma unroll
+    for (int p = 0; p < A; ++p) v[q + B * p] = s[p];
+  }
+}
+
 template <typename T, int R, bool INV> __device__ __forceinline__ void dft(cpx<T>* v) {
-  static_assert(R == 2 || R == 3 || R == 4 || R == 5 || R == 8, "radix");
+  static_assert(R == 2 || R == 3 || R == 4 || R == 5 || R == 6 || R == 8 || R == 9 || R == 10 ||
+                    R == 12,
+                "radix");
   if constexpr (R == 2) dft2<T, INV>(v);
   else if constexpr (R == 3) dft3<T, INV>(v);
   else if constexpr (R == 4) dft4<T, INV>(v);
   else if constexpr (R == 5) dft5<T, INV>(v);
+  else if constexpr (R == 6) dft_ct<T, 2, 3, INV>(v);
+  else if constexpr (R == 9) dft_ct<T, 3, 3, INV>(v);
+  else if constexpr (R == 10) dft_ct<T, 2, 5, INV>(v);
+  else if constexpr (R == 12) dft_ct<T, 4, 3, INV>(v);
   else dft8<T, INV>(v);
 }
 
 // ---------------------------------------------------------------- plans
-// Radix sequence per supported length.  The inverse transform uses the
-// reversed sequence so that its first radix equals the forward's last.
+// Radix sequence per supported length: two stages everywhere, so a 2D
+// transform in LDS needs one transposing round trip per axis.  The inverse
+// transform uses the reversed sequence so that its first radix equals the
+// forward's last.
 template <int N> struct Plan;
 #define PX_PLAN(N_, NST_, R0_, R1_, R2_) \
   template <> struct Plan<N_> { static constexpr int nst = NST_; static constexpr int rad[3] = {R0_, R1_, R2_}; };
@@ -129,12 +195,12 @@ PX_PLAN(16, 2, 4, 4, 1)
 PX_PLAN(24, 2, 8, 3, 1)
 PX_PLAN(32, 2, 8, 4, 1)
 PX_PLAN(40, 2, 8, 5, 1)
-PX_PLAN(48, 3, 4, 4, 3)
-PX_PLAN(60, 3, 4, 3, 5)
+PX_PLAN(48, 2, 8, 6, 1)
+PX_PLAN(60, 2, 6, 10, 1)
 PX_PLAN(64, 2, 8, 8, 1)
-PX_PLAN(72, 3, 8, 3, 3)
-PX_PLAN(80, 3, 4, 4, 5)
-PX_PLAN(96, 3, 8, 4, 3)
+PX_PLAN(72, 2, 8, 9, 1)
+PX_PLAN(80, 2, 8, 10, 1)
+PX_PLAN(96, 2, 8, 12, 1)
 #undef PX_PLAN
 
 // Radix and span of stage S of the forward (INV=false) or inverse sequence.

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "../../include/px.h"
 #include "px_internal.hpp"
@@ -22,6 +23,15 @@ struct px_context {
   int32_t* last_status = nullptr;  // device status word of the last ACE build
   int latched = PX_OK;
   std::map<std::tuple<int, int, int, int>, std::pair<int, int>> tuning;  // (n0,n1,n2,prec) -> (ic, jc)
+  // measurement mode: HIP events around each pass of each chunk
+  bool profiling = false;
+  std::vector<hipEvent_t> events;
+  double prof_ms[3] = {0, 0, 0};
+  double prof_bytes[3] = {0, 0, 0};
+  int64_t prof_launches[3] = {0, 0, 0};
+  ~px_context() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -203,6 +213,16 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
   a.n2 = cell->n[2];
   a.inv_ng = 1.0 / double(ngrid(cell));
   double* S = reinterpret_cast<double*>(c->ws + l.S);
+  size_t nchunks = 0;
+  if (c->profiling) {
+    const size_t need = size_t((n_phi + ic - 1) / ic) * ((n_psi + jc - 1) / jc) * 4;
+    while (c->events.size() < need) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return fail(c, PX_ERR_DEVICE, "hipEventCreate failed");
+      c->events.push_back(e);
+    }
+  }
+  const size_t pair_bytes = ngrid(cell) * elem_bytes(prec);
   for (int i0 = 0; i0 < n_phi; i0 += ic) {
     a.i0 = i0;
     a.ic = (n_phi - i0) < ic ? (n_phi - i0) : ic;
@@ -210,9 +230,19 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       a.j0 = j0;
       a.jc = (n_psi - j0) < jc ? (n_psi - j0) : jc;
       a.first = j0 == 0;
+      hipEvent_t* ev = c->profiling ? &c->events[4 * nchunks] : nullptr;
       px_status st = hip_check(
-          c, px::launch_chunk(fp32, cell->n[0], a, a.ic * a.jc, fp32, energy, s), "pair pipeline");
+          c, px::launch_chunk(fp32, cell->n[0], a, a.ic * a.jc, energy, s, ev), "pair pipeline");
       if (st != PX_OK) return st;
+      if (c->profiling) {
+        // algorithmic bytes of each pass: 2 N_g b per pair (pass 1: read psi_j,
+        // write the pair slab; pass 2: read and write it; pass 3: read it and psi_j)
+        for (int k = 0; k < 3; ++k) {
+          c->prof_bytes[k] += 2.0 * double(pair_bytes) * a.ic * a.jc;
+          c->prof_launches[k] += 1;
+        }
+      }
+      ++nchunks;
       if (energy) {
         st = hip_check(c, px::launch_expart_reduce(a.expart, cell->n[1], i0, a.ic, j0, a.jc, S,
                                                    n_psi, s),
@@ -220,6 +250,17 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
         if (st != PX_OK) return st;
       }
     }
+  }
+  if (c->profiling && nchunks > 0) {
+    hipError_t e = hipEventSynchronize(c->events[4 * nchunks - 1]);
+    if (e != hipSuccess) return hip_check(c, e, "profiling sync");
+    for (size_t k = 0; k < nchunks; ++k)
+      for (int p = 0; p < 3; ++p) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, c->events[4 * k + p], c->events[4 * k + p + 1]);
+        if (e != hipSuccess) return hip_check(c, e, "hipEventElapsedTime");
+        c->prof_ms[p] += ms;
+      }
   }
   return PX_OK;
 }
@@ -491,6 +532,24 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
                    "update");
     if (st != PX_OK) return st;
     cur = nxt;
+  }
+  return PX_OK;
+}
+
+px_status px_set_profiling(px_context* ctx, int32_t enable) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  ctx->profiling = enable != 0;
+  return PX_OK;
+}
+
+px_status px_profile_read(px_context* ctx, double* ms, double* bytes, int64_t* launches,
+                          int32_t reset) {
+  if (!ctx || !ms || !bytes || !launches) return PX_ERR_INVALID_ARG;
+  for (int k = 0; k < 3; ++k) {
+    ms[k] = ctx->prof_ms[k];
+    bytes[k] = ctx->prof_bytes[k];
+    launches[k] = ctx->prof_launches[k];
+    if (reset) ctx->prof_ms[k] = ctx->prof_bytes[k] = 0.0, ctx->prof_launches[k] = 0;
   }
   return PX_OK;
 }

@@ -26,8 +26,10 @@ struct ChunkArgs {
 };
 
 bool grid_supported(int n0, int n1, int n2);
-hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool g0, bool ex,
-                        hipStream_t s);
+// Launches pass 1, 2, 3 of one chunk; ev (nullable) = 4 events recorded
+// before pass 1, between the passes and after pass 3.
+hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
+                        hipEvent_t* ev);
 
 // misc_kernels.hip
 hipError_t launch_kernel_hse(int n0, int n1, int n2, double L0, double L1, double L2, double mu,

@@ -146,9 +146,10 @@ def plane_wave_orbitals(n, L, ms) -> np.ndarray:
     return out
 
 
-def noise_block(n, L, n_orb, seed, ecut=10.0) -> np.ndarray:
+def noise_block(n, L, n_orb, seed, ecut=10.0, chunk=64) -> np.ndarray:
     """Band-limited random fields (same sphere as the orbitals), each column
-    scaled to dV-norm 1, not orthogonalised."""
+    scaled to dV-norm 1, not orthogonalised.  Coefficients are drawn orbital
+    by orbital (real parts, then imaginary parts) from one generator."""
     if isinstance(n, int):
         n = (n, n, n)
     if isinstance(L, (int, float)):
@@ -159,12 +160,14 @@ def noise_block(n, L, n_orb, seed, ecut=10.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     idx = sphere_indices(n, L, ecut)
     out = np.empty((n_orb, n2, n1, n0), dtype=np.complex128)
-    for a in range(n_orb):
-        g = np.zeros(ng, dtype=np.complex128)
-        g[idx] = rng.standard_normal(len(idx)) + 1j * rng.standard_normal(len(idx))
-        f = _sfft.ifftn(g.reshape(n2, n1, n0), workers=_workers())
-        f /= math.sqrt(dv * np.vdot(f, f).real)
-        out[a] = f
+    for a in range(0, n_orb, chunk):
+        b = min(n_orb, a + chunk)
+        g = np.zeros((b - a, ng), dtype=np.complex128)
+        for k in range(b - a):
+            g[k, idx] = rng.standard_normal(len(idx)) + 1j * rng.standard_normal(len(idx))
+        f = _sfft.ifftn(g.reshape(b - a, n2, n1, n0), axes=(1, 2, 3), workers=_workers())
+        norms = np.sqrt(dv * np.einsum("kzyx,kzyx->k", f.conj(), f).real)
+        out[a:b] = f / norms[:, None, None, None]
     return out
 
 
