@@ -100,6 +100,23 @@ def run_steps(step, k):
     return (time.perf_counter() - t0) / k
 
 
+def copy_bandwidth(ctx, nbytes=2 << 30, reps=5):
+    """Plain copy of nbytes (read + write = 2*nbytes moved) with the library's copy kernel."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    ctx.px_stream_copy(src, dst)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.px_stream_copy(src, dst)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del src, dst
+    return dict(copy_bytes=nbytes, copy_GBps=2 * nbytes / dt / 1e9, copy_ms=dt * 1e3)
+
+
 def cpu_baseline(inst, kern_np, seconds):
     """The oracle as it stands on a bounded sample: a few output columns of
     W = Vx Psi against all orbitals."""
@@ -131,6 +148,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the plain copy kernel (2 GiB, 5 launches) and print its bandwidth")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -142,6 +161,11 @@ def main():
     import torch
     from paper_2501_03061_amd import inputs, px
 
+    if args.calibrate_copy:
+        ctx = px.Context(0)
+        print(json.dumps(copy_bandwidth(ctx, reps=5)), flush=True)
+        return
+
     cfg = inputs.CONFIGS["mid72"]
     inst, psi64, phi64, occ = build_inputs(cfg)
     n = inst.n_orb
@@ -149,6 +173,8 @@ def main():
     ctx = px.Context(0)
     kern = ctx.px_kernel_hse(cell, cfg["mu"])
 
+    copy = copy_bandwidth(ctx)
+    log(f"copy kernel: {copy['copy_GBps']:.0f} GB/s")
     step32 = Step(ctx, cell, psi64, phi64, occ, kern, fp32=True)
     for _ in range(args.warmup):
         step32()
@@ -180,6 +206,7 @@ def main():
     pipe_gbps = sum(p["bytes"] for p in prof) / (pipe_ms * 1e-3) / 1e9
 
     extra = dict(
+        copy_kernel_GBps=copy["copy_GBps"],
         ace_build_s_fp32=ace_s32,
         pair_pipeline_ms_per_step=pipe_ms / args.steps,
         pair_pipeline_model_GBps=pipe_gbps,

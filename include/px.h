@@ -125,6 +125,12 @@ px_status px_kernel_hse(px_context* ctx, const px_cell* cell, double mu, double*
 px_status px_convert_c128_to_c64(px_context* ctx, size_t n_elems, const void* src, void* dst,
                                  hipStream_t stream);
 
+/* Plain device-to-device copy of `bytes` (a multiple of 16; 16-byte aligned
+ * pointers).  Not part of the method: it is the reference kernel whose
+ * measured bandwidth and HBM counters calibrate the roofline figures. */
+px_status px_stream_copy(px_context* ctx, const void* src, void* dst, size_t bytes,
+                         hipStream_t stream);
+
 /* Exchange operator applied to a block, Eq. (13) with occupations f_j:
  *   vx_phi[i] = (Vx phi_i) = -sum_j occ[j] psi_j IFFT[K FFT(conj(psi_j) phi_i)]
  * psi [n_psi][N_g], phi [n_phi][N_g], vx_phi [n_phi][N_g] in the element type

@@ -72,6 +72,18 @@ template <int NT> __device__ __forceinline__ double block_sum(double v, double* 
   return s;
 }
 
+// FP64 sum over the 64 lanes of a wave (valid in every lane).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Whether two slab buffers (ping-pong) fit in LDS next to the small tables.
+template <typename T, int N0, int N1> constexpr bool pingpong_fits() {
+  return 2 * N1 * (N0 + 1) * int(sizeof(cpx<T>)) <= 150 * 1024;
+}
+
 // Branch-free gather of the R inputs of every butterfly slot of a stage whose
 // reads are x[j + r*N/R] along the lines of geometry G: slot indices past the
 // last butterfly are clamped to it (loaded, never stored), so all loads of a
@@ -92,17 +104,25 @@ __device__ __forceinline__ void gather(cpx<T> (&v)[BPT][R], F&& load) {
 
 // ============================================================== pass 1
 // PF: prefetch the next density orbital's slab while the current one is
-// transformed.
+// transformed.  With two slab buffers in LDS (ping-pong, PP) every stage is
+// out of place and the buffers swap roles each pair, so a slab costs three
+// barriers; otherwise the middle stages run in place (two barriers each).
 template <typename T, int N0, int N1, int NT, bool G0, bool PF>
 __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
-  __shared__ cpx<T> lds[N0 * N1];
+  constexpr bool PP = pingpong_fits<T, N0, N1>();
+  constexpr int P0 = N0 + 1;  // odd row pitch: no bank conflicts on stride-R writes
+  constexpr int SL = N1 * P0;
+  __shared__ cpx<T> lds[PP ? 2 * SL : SL];
   __shared__ cpx<T> tw0[N0];
   __shared__ cpx<T> tw1[N1];
-  __shared__ double red[2 * (NT / 64)];
-  using GX = Lines<N0, N1, N0, 1, false>;  // rows: contiguous lines
-  using GY = Lines<N1, N0, 1, N0, true>;   // columns: strided lines
+  __shared__ double red[2][NT / 64];
+  using GX = Lines<N0, N1, P0, 1, false>;  // rows: contiguous lines
+  using GY = Lines<N1, N0, 1, P0, true>;   // columns: strided lines
   constexpr int NSX = Plan<N0>::nst, NSY = Plan<N1>::nst;
+  static_assert(!PP || (NSX == 2 && NSY == 2), "ping-pong path assumes two-stage plans");
   using X0 = StageOf<N0, 0, false>;
+  using X1 = StageOf<N0, 1, false>;
+  using Y0 = StageOf<N1, 0, false>;
   using YL = StageOf<N1, NSY - 1, false>;
   constexpr int NB0 = N1 * (N0 / X0::R), BPT0 = (NB0 + NT - 1) / NT;
   constexpr int NBL = N0 * (N1 / YL::R), BPTL = (NBL + NT - 1) / NT;
@@ -124,6 +144,8 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
   __syncthreads();
 
   for (int jj = 0; jj < a.jc; ++jj) {
+    cpx<T>* A = lds + (PP ? (jj & 1) * SL : 0);
+    cpx<T>* B = lds + (PP ? (1 - (jj & 1)) * SL : 0);
     cpx<T> cu[BPT0][X0::R];
     if constexpr (PF) {
 #pragma unroll
@@ -161,18 +183,38 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
       dft<T, X0::R, false>(v);
       if (valid) {
 #pragma unroll
-        for (int r = 0; r < X0::R; ++r) lds[line * N0 + out_pos<X0::R, 1>(j, r)] = v[r];
+        for (int r = 0; r < X0::R; ++r) A[line * P0 + out_pos<X0::R, 1>(j, r)] = v[r];
       }
     }
     if constexpr (G0) {
-      double s0 = block_sum<NT>(sre, red);
-      double s1 = block_sum<NT>(sim, red + NT / 64);
-      if (tid == 0) a.g0[size_t(p) * a.n2 + z] = make_double2(s0, s1);
-    } else {
-      __syncthreads();
+      sre = wave_sum(sre);
+      sim = wave_sum(sim);
+      if ((tid & 63) == 0) {
+        red[0][tid >> 6] = sre;
+        red[1][tid >> 6] = sim;
+      }
     }
-    stages_lds<T, GX, false, NT, 1, NSX>(lds, tw0);
-    stages_lds<T, GY, false, NT, 0, NSY - 1>(lds, tw1);
+    __syncthreads();
+    if constexpr (G0) {
+      if (tid == 0) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) {
+          s0 += red[0][w];
+          s1 += red[1][w];
+        }
+        a.g0[size_t(p) * a.n2 + z] = make_double2(s0, s1);
+      }
+    }
+    if constexpr (PP) {
+      stage_pp<T, GX, X1::R, X1::NS, false, NT>(A, B, tw0);
+      __syncthreads();
+      stage_pp<T, GY, Y0::R, Y0::NS, false, NT>(B, A, tw1);
+      __syncthreads();
+    } else {
+      stages_lds<T, GX, false, NT, 1, NSX>(A, tw0);
+      stages_lds<T, GY, false, NT, 0, NSY - 1>(A, tw1);
+    }
     // last y stage: LDS -> global pair buffer
     cpx<T>* out = reinterpret_cast<cpx<T>*>(a.t) + size_t(p) * ng + z * slab;
 #pragma unroll
@@ -183,24 +225,25 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
         decode<GY, YL::R>(b, line, j);
         cpx<T> v[YL::R];
 #pragma unroll
-        for (int r = 0; r < YL::R; ++r) v[r] = lds[line + (j + r * (N1 / YL::R)) * N0];
+        for (int r = 0; r < YL::R; ++r) v[r] = A[line + (j + r * (N1 / YL::R)) * P0];
         twiddle<T, N1, YL::R, YL::NS, false>(v, j, tw1);
         dft<T, YL::R, false>(v);
 #pragma unroll
         for (int r = 0; r < YL::R; ++r) stg(out + line + (j + r * (N1 / YL::R)) * N0, v[r]);
       }
     }
-    __syncthreads();
+    if constexpr (!PP) __syncthreads();
   }
 }
 
 // ============================================================== pass 2
 template <typename T, int N0, int N1, int N2, int NT, bool G0, bool EX>
 __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
-  __shared__ cpx<T> lds[N2 * N0];
+  constexpr int P0 = N0 + 1;
+  __shared__ cpx<T> lds[N2 * P0];
   __shared__ cpx<T> tw2[N2];
   __shared__ double red[NT / 64];
-  using GZ = Lines<N2, N0, 1, N0, true>;  // plane [z][x], lines along z
+  using GZ = Lines<N2, N0, 1, P0, true>;  // plane [z][x], lines along z
   constexpr int NS = Plan<N2>::nst;
   using F0 = StageOf<N2, 0, false>;
   using FL = StageOf<N2, NS - 1, false>;
@@ -240,7 +283,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
       decode<GZ, F0::R>(b, line, j);
       dft<T, F0::R, false>(v0[k]);
 #pragma unroll
-      for (int r = 0; r < F0::R; ++r) lds[out_pos<F0::R, 1>(j, r) * N0 + line] = v0[k][r];
+      for (int r = 0; r < F0::R; ++r) lds[out_pos<F0::R, 1>(j, r) * P0 + line] = v0[k][r];
     }
   }
   __syncthreads();
@@ -255,7 +298,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
       int line, j;
       decode<GZ, FL::R>(b, line, j);
 #pragma unroll
-      for (int r = 0; r < FL::R; ++r) v[k][r] = lds[(j + r * (N2 / FL::R)) * N0 + line];
+      for (int r = 0; r < FL::R; ++r) v[k][r] = lds[(j + r * (N2 / FL::R)) * P0 + line];
       twiddle<T, N2, FL::R, FL::NS, false>(v[k], j, tw2);
       dft<T, FL::R, false>(v[k]);
 #pragma unroll
@@ -282,11 +325,10 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
     }
   }
   if constexpr (EX) {
-    double s = block_sum<NT>(ex, red);
-    if (tid == 0) a.expart[size_t(p) * N1 + y] = s;
-  } else {
-    __syncthreads();  // every thread is done reading LDS before it is overwritten
+    ex = wave_sum(ex);
+    if ((tid & 63) == 0) red[tid >> 6] = ex;
   }
+  __syncthreads();  // every thread is done reading LDS before it is overwritten
 #pragma unroll
   for (int k = 0; k < BPTL; ++k) {
     const int b = tid + k * NT;
@@ -295,10 +337,18 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
       decode<GZ, I0::R>(b, line, j);
       dft<T, I0::R, true>(v[k]);
 #pragma unroll
-      for (int r = 0; r < I0::R; ++r) lds[out_pos<I0::R, 1>(j, r) * N0 + line] = v[k][r];
+      for (int r = 0; r < I0::R; ++r) lds[out_pos<I0::R, 1>(j, r) * P0 + line] = v[k][r];
     }
   }
   __syncthreads();
+  if constexpr (EX) {
+    if (tid == 0) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) s2 += red[w];
+      a.expart[size_t(p) * N1 + y] = s2;
+    }
+  }
   stages_lds<T, GZ, true, NT, 1, NS - 1>(lds, tw2);
   // last inverse stage back to global, in place
 #pragma unroll
@@ -309,7 +359,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
       decode<GZ, IL::R>(b, line, j);
       cpx<T> w[IL::R];
 #pragma unroll
-      for (int r = 0; r < IL::R; ++r) w[r] = lds[(j + r * (N2 / IL::R)) * N0 + line];
+      for (int r = 0; r < IL::R; ++r) w[r] = lds[(j + r * (N2 / IL::R)) * P0 + line];
       twiddle<T, N2, IL::R, IL::NS, true>(w, j, tw2);
       dft<T, IL::R, true>(w);
 #pragma unroll
@@ -320,15 +370,22 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
 
 // ============================================================== pass 3
 // PF: prefetch the next pair slab and the next psi_j slab during the transform.
+// PP as in pass 1.
 template <typename T, int N0, int N1, int NT, bool PF>
 __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
-  __shared__ cpx<T> lds[N0 * N1];
+  constexpr bool PP = pingpong_fits<T, N0, N1>();
+  constexpr int P0 = N0 + 1;
+  constexpr int SL = N1 * P0;
+  __shared__ cpx<T> lds[PP ? 2 * SL : SL];
   __shared__ cpx<T> tw0[N0];
   __shared__ cpx<T> tw1[N1];
-  using GX = Lines<N0, N1, N0, 1, false>;
-  using GY = Lines<N1, N0, 1, N0, true>;
+  using GX = Lines<N0, N1, P0, 1, false>;
+  using GY = Lines<N1, N0, 1, P0, true>;
   constexpr int NSX = Plan<N0>::nst, NSY = Plan<N1>::nst;
+  static_assert(!PP || (NSX == 2 && NSY == 2), "ping-pong path assumes two-stage plans");
   using X0 = StageOf<N0, 0, true>;
+  using X1 = StageOf<N0, 1, true>;
+  using Y0 = StageOf<N1, 0, true>;
   using YL = StageOf<N1, NSY - 1, true>;
   constexpr int NB0 = N1 * (N0 / X0::R), BPT0 = (NB0 + NT - 1) / NT;
   constexpr int NBL = N0 * (N1 / YL::R), BPTL = (NBL + NT - 1) / NT;
@@ -360,6 +417,8 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
   __syncthreads();
 
   for (int jj = 0; jj < a.jc; ++jj) {
+    cpx<T>* A = lds + (PP ? (jj & 1) * SL : 0);
+    cpx<T>* B = lds + (PP ? (1 - (jj & 1)) * SL : 0);
     cpx<T> tc[BPT0][X0::R], pc[BPTL][YL::R];
     if constexpr (PF) {
 #pragma unroll
@@ -386,12 +445,19 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
         decode<GX, X0::R>(b, line, j);
         dft<T, X0::R, true>(tc[k]);
 #pragma unroll
-        for (int r = 0; r < X0::R; ++r) lds[line * N0 + out_pos<X0::R, 1>(j, r)] = tc[k][r];
+        for (int r = 0; r < X0::R; ++r) A[line * P0 + out_pos<X0::R, 1>(j, r)] = tc[k][r];
       }
     }
     __syncthreads();
-    stages_lds<T, GX, true, NT, 1, NSX>(lds, tw0);
-    stages_lds<T, GY, true, NT, 0, NSY - 1>(lds, tw1);
+    if constexpr (PP) {
+      stage_pp<T, GX, X1::R, X1::NS, true, NT>(A, B, tw0);
+      __syncthreads();
+      stage_pp<T, GY, Y0::R, Y0::NS, true, NT>(B, A, tw1);
+      __syncthreads();
+    } else {
+      stages_lds<T, GX, true, NT, 1, NSX>(A, tw0);
+      stages_lds<T, GY, true, NT, 0, NSY - 1>(A, tw1);
+    }
 #pragma unroll
     for (int k = 0; k < BPTL; ++k) {
       const int b = tid + k * NT;
@@ -405,7 +471,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
         }
         cpx<T> v[YL::R];
 #pragma unroll
-        for (int r = 0; r < YL::R; ++r) v[r] = lds[line + (j + r * (N1 / YL::R)) * N0];
+        for (int r = 0; r < YL::R; ++r) v[r] = A[line + (j + r * (N1 / YL::R)) * P0];
         twiddle<T, N1, YL::R, YL::NS, true>(v, j, tw1);
         dft<T, YL::R, true>(v);
 #pragma unroll
@@ -416,7 +482,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
         }
       }
     }
-    __syncthreads();
+    if constexpr (!PP) __syncthreads();
   }
   cpx<T>* out = reinterpret_cast<cpx<T>*>(a.out) + size_t(a.i0 + ii) * ng + z * slab;
 #pragma unroll

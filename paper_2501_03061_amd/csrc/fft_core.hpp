@@ -111,27 +111,50 @@ template <typename T, bool INV> __device__ __forceinline__ void dft8(cpx<T>* v) 
   v[7] = csub(e[3], o3);
 }
 
-// cos and sin of 2 pi m / R for the twiddles inside composite radices
-// (R = 6, 9, 10, 12 and the products a*q that occur there).
-__host__ __device__ constexpr double tcos(int R, int m) {
-  return R == 6   ? (m == 1 ? 0.5 : m == 2 ? -0.5 : 1.0)
-       : R == 9   ? (m == 1 ? 0.76604444311897803520 : m == 2 ? 0.17364817766693034885
-                   : m == 4 ? -0.93969262078590838405 : 1.0)
-       : R == 10  ? (m == 1 ? 0.80901699437494742410 : m == 2 ? 0.30901699437494742410
-                   : m == 3 ? -0.30901699437494742410 : m == 4 ? -0.80901699437494742410 : 1.0)
-       : R == 12  ? (m == 1 ? 0.86602540378443864676 : m == 2 ? 0.5 : m == 3 ? 0.0
-                   : m == 4 ? -0.5 : m == 6 ? -1.0 : 1.0)
-       : 1.0;
+// Compile-time roots of unity: cos and sin of 2 pi m / R, evaluated by
+// constexpr Taylor series after exact reduction of the angle to [-pi/4, pi/4]
+// (accurate to about one ulp in double precision).
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double cx_sin_small(double t) {  // |t| <= pi/4
+  double term = t, sum = t;
+  for (int k = 1; k < 14; ++k) {
+    term *= -t * t / double((2 * k) * (2 * k + 1));
+    sum += term;
+  }
+  return sum;
 }
-__host__ __device__ constexpr double tsin(int R, int m) {
-  return R == 6   ? (m == 1 || m == 2 ? 0.86602540378443864676 : 0.0)
-       : R == 9   ? (m == 1 ? 0.64278760968653932632 : m == 2 ? 0.98480775301220805936
-                   : m == 4 ? 0.34202014332566873304 : 0.0)
-       : R == 10  ? (m == 1 || m == 4 ? 0.58778525229247312917 : m == 2 || m == 3 ? 0.95105651629515357212 : 0.0)
-       : R == 12  ? (m == 1 || m == 5 ? 0.5 : m == 2 || m == 4 ? 0.86602540378443864676
-                   : m == 3 ? 1.0 : 0.0)
-       : 0.0;
+constexpr double cx_cos_small(double t) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -t * t / double((2 * k - 1) * (2 * k));
+    sum += term;
+  }
+  return sum;
 }
+// angle 2 pi m / R with exact quadrant reduction on the integer 4 m mod 4 R
+constexpr void cx_root(int R, int m, double& c, double& s) {
+  m %= R;
+  if (m < 0) m += R;
+  const long num = 4L * m;             // angle = (num / R) * (pi / 2)
+  const long quad = (2 * num + R) / (2 * R);  // nearest multiple of pi/2, 0..4
+  const double rem = double(num - quad * R) / double(R) * (kPi / 2.0);  // |rem| <= pi/4
+  const double sr = cx_sin_small(rem), cr = cx_cos_small(rem);
+  switch (int(quad % 4)) {
+    case 0: c = cr; s = sr; break;
+    case 1: c = -sr; s = cr; break;
+    case 2: c = -cr; s = -sr; break;
+    default: c = sr; s = -cr; break;
+  }
+}
+
+template <int R> struct RootTable {
+  double c[R], s[R];
+  constexpr RootTable() : c(), s() {
+    for (int m = 0; m < R; ++m) cx_root(R, m, c[m], s[m]);
+  }
+};
+template <int R> inline constexpr RootTable<R> kRoots{};
 
 template <typename T, int R, bool INV> __device__ __forceinline__ void dft(cpx<T>* v);
 
@@ -152,7 +175,9 @@ template <typename T, int A, int B, bool INV> __device__ __forceinline__ void df
       if (a == 0 || q == 0) {
         u[a][q] = s[q];
       } else {
-        const T c = T(tcos(R, a * q)), sn = T(INV ? tsin(R, a * q) : -tsin(R, a * q));
+        constexpr const RootTable<R>& tab = kRoots<R>;
+        const T c = T(tab.c[(a * q) % R]);
+        const T sn = T(INV ? tab.s[(a * q) % R] : -tab.s[(a * q) % R]);
         u[a][q] = {s[q].x * c - s[q].y * sn, s[q].x * sn + s[q].y * c};
       }
     }
@@ -168,10 +193,13 @@ template <typename T, int A, int B, bool INV> __device__ __forceinline__ void df
   }
 }
 
+// Factor A of a composite length handled by dft_ct<A, R/A>.
+template <int R> constexpr int first_factor() {
+  return R % 8 == 0 && R > 8 ? 8 : R % 6 == 0 && R > 6 ? 6 : R % 4 == 0 && R > 4 ? 4
+       : R % 3 == 0 && R > 3 ? 3 : R % 2 == 0 && R > 2 ? 2 : R % 5 == 0 && R > 5 ? 5 : 1;
+}
+
 template <typename T, int R, bool INV> __device__ __forceinline__ void dft(cpx<T>* v) {
-  static_assert(R == 2 || R == 3 || R == 4 || R == 5 || R == 6 || R == 8 || R == 9 || R == 10 ||
-                    R == 12,
-                "radix");
   if constexpr (R == 2) dft2<T, INV>(v);
   else if constexpr (R == 3) dft3<T, INV>(v);
   else if constexpr (R == 4) dft4<T, INV>(v);
@@ -180,7 +208,13 @@ template <typename T, int R, bool INV> __device__ __forceinline__ void dft(cpx<T
   else if constexpr (R == 9) dft_ct<T, 3, 3, INV>(v);
   else if constexpr (R == 10) dft_ct<T, 2, 5, INV>(v);
   else if constexpr (R == 12) dft_ct<T, 4, 3, INV>(v);
-  else dft8<T, INV>(v);
+  else if constexpr (R == 8) dft8<T, INV>(v);
+  else {
+    // whole-line transforms (e.g. 72 = 8 x 9) for the register-resident pencils
+    constexpr int A = first_factor<R>();
+    static_assert(A > 1 && R % A == 0, "length must factor into 2, 3, 5");
+    dft_ct<T, A, R / A, INV>(v);
+  }
 }
 
 // ---------------------------------------------------------------- plans
@@ -294,6 +328,29 @@ __device__ __forceinline__ void stage_lds(cpx<T>* lds, const cpx<T>* tw) {
     }
   }
   __syncthreads();
+}
+
+// One out-of-place Stockham stage, src -> dst (both LDS, same geometry).  No
+// barrier inside: the caller separates stages that depend on each other.
+template <typename T, class G, int R, int NS, bool INV, int NT>
+__device__ __forceinline__ void stage_pp(const cpx<T>* src, cpx<T>* dst, const cpx<T>* tw) {
+  constexpr int NB = G::nl * (G::n / R);
+  constexpr int BPT = (NB + NT - 1) / NT;
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int b = threadIdx.x + k * NT;
+    if (NB % NT == 0 || b < NB) {
+      int line, j;
+      decode<G, R>(b, line, j);
+      cpx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = src[line * G::ls + (j + r * (G::n / R)) * G::es];
+      twiddle<T, G::n, R, NS, INV>(v, j, tw);
+      dft<T, R, INV>(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[line * G::ls + out_pos<R, NS>(j, r) * G::es] = v[r];
+    }
+  }
 }
 
 // Run stages [S0, S1) of the length-N transform over geometry G, LDS -> LDS.

@@ -35,18 +35,36 @@ hipError_t launch_kernel_hse(int n0, int n1, int n2, double L0, double L1, doubl
 }
 
 typedef double vd4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+// Plain device copy, 16 bytes per thread step: the reference kernel for HBM
+// counter calibration and the copy-bandwidth ceiling.
+__global__ __launch_bounds__(256) void stream_copy_k(size_t n16, const u4* src, u4* dst) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_stream_copy(size_t bytes, const void* src, void* dst, hipStream_t s) {
+  const size_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  const size_t blocks = (n16 + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(stream_copy_k, dim3(unsigned(blocks)), dim3(256), 0, s, n16,
+                     static_cast<const u4*>(src), static_cast<u4*>(dst));
+  return hipGetLastError();
+}
+
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
-// complex128 -> complex64, round to nearest even; two complex values per thread step
-__global__ void convert_k(size_t n, const double* src, float* dst) {
-  const size_t npair = n / 2;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < npair;
-       i += size_t(gridDim.x) * blockDim.x) {
+// complex128 -> complex64, round to nearest even; two complex values per
+// thread, one thread per pair (no grid-stride loop: streams at copy speed)
+__global__ __launch_bounds__(256) void convert_k(size_t n, const double* src, float* dst) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n / 2) {
     vd4 v = __builtin_nontemporal_load(reinterpret_cast<const vd4*>(src) + i);
     vf4 o = {float(v.x), float(v.y), float(v.z), float(v.w)};
     reinterpret_cast<vf4*>(dst)[i] = o;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) {
+  } else if (i == n / 2 && (n & 1)) {
     dst[2 * (n - 1)] = float(src[2 * (n - 1)]);
     dst[2 * (n - 1) + 1] = float(src[2 * (n - 1) + 1]);
   }
@@ -54,9 +72,9 @@ __global__ void convert_k(size_t n, const double* src, float* dst) {
 
 hipError_t launch_convert_c128_c64(size_t n, const void* src, void* dst, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const size_t work = (n / 2 + 255) / 256;
-  const int blocks = int(work < 8192 ? (work > 0 ? work : 1) : 8192);
-  hipLaunchKernelGGL(convert_k, dim3(blocks), dim3(256), 0, s, n,
+  const size_t blocks = (n / 2 + 1 + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(convert_k, dim3(unsigned(blocks)), dim3(256), 0, s, n,
                      static_cast<const double*>(src), static_cast<float*>(dst));
   return hipGetLastError();
 }

@@ -35,6 +35,7 @@ hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool e
 hipError_t launch_kernel_hse(int n0, int n1, int n2, double L0, double L1, double L2, double mu,
                              double* kern, hipStream_t s);
 hipError_t launch_convert_c128_c64(size_t n, const void* src, void* dst, hipStream_t s);
+hipError_t launch_stream_copy(size_t bytes, const void* src, void* dst, hipStream_t s);
 // S[i][j] (row stride lds) = sum_y expart[(ii*jc+jj)*n1 + y] for the chunk
 hipError_t launch_expart_reduce(const double* expart, int n1, int i0, int ic, int j0, int jc,
                                 double* S, int lds, hipStream_t s);

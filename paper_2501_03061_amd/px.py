@@ -43,6 +43,7 @@ SIGNATURES = {
     "px_set_tuning": (_i32, [_vp, _cellp, _i32, _i32, _i32]),
     "px_kernel_hse": (_i32, [_vp, _cellp, _dbl, _vp, _vp]),
     "px_convert_c128_to_c64": (_i32, [_vp, _sz, _vp, _vp, _vp]),
+    "px_stream_copy": (_i32, [_vp, _vp, _vp, _sz, _vp]),
     "px_exchange_apply": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "px_ace_build": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "px_ace_apply": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
@@ -201,6 +202,13 @@ class Context:
             dst = torch.empty(src.shape, dtype=torch.complex64, device=src.device)
         self._check(self.lib.px_convert_c128_to_c64(self.h, src.numel(), _ptr(src), _ptr(dst),
                                                     _stream(stream)))
+        return dst
+
+    def px_stream_copy(self, src, dst, stream=None):
+        nbytes = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() < nbytes:
+            raise ValueError("dst smaller than src")
+        self._check(self.lib.px_stream_copy(self.h, _ptr(src), _ptr(dst), nbytes, _stream(stream)))
         return dst
 
     def px_exchange_apply(self, cell: Cell, psi, occ, phi, kern, out=None, e_x=None,
