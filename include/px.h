@@ -172,6 +172,13 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
                                 double dt_alpha, void* phi_out, double* residuals,
                                 hipStream_t stream);
 
+/* Hermitian pair symmetry of the ACE build (default on).  With Phi = Psi and a
+ * real even kernel, v_ji = conj(v_ij): the orbitals are cut into square blocks
+ * and only blocks J <= I are transformed; for J < I the real-space v_ij is
+ * kept and a streaming pass adds the transposed contribution
+ * -f_i psi_i conj(v_ij) to W_j.  Roughly halves the pair solves. */
+px_status px_set_symmetry(px_context* ctx, int32_t enable);
+
 /* Measurement mode.  When enabled, px_exchange_apply and px_ace_build record
  * HIP events on their stream around pass 1 (pair product + forward xy
  * transforms), pass 2 (z transforms + kernel multiply) and pass 3 (inverse xy
@@ -180,10 +187,12 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
  * px_sync).  Off by default. */
 px_status px_set_profiling(px_context* ctx, int32_t enable);
 
-/* Totals since the last reset, per pass k = 0, 1, 2: ms[k] summed event time,
- * bytes[k] algorithmic HBM bytes (2 * N_g * element size per pair: pass 1 reads
- * psi_j and writes the pair slab, pass 2 reads and rewrites it, pass 3 reads it
- * and psi_j), launches[k] kernel launches.  reset != 0 zeroes the totals. */
+/* Totals since the last reset, per pass k = 0..3 (arrays of 4): ms[k] summed
+ * event time, bytes[k] algorithmic HBM bytes (2 * N_g * element size per pair:
+ * pass 1 reads psi_j and writes the pair slab, pass 2 reads and rewrites it,
+ * pass 3 reads it and psi_j, plus one more slab write per pair in symmetric
+ * mode; pass 4, symmetric mode only, reads v_ij and psi_i), launches[k] kernel
+ * launches.  reset != 0 zeroes the totals. */
 px_status px_profile_read(px_context* ctx, double* ms, double* bytes, int64_t* launches,
                           int32_t reset);
 

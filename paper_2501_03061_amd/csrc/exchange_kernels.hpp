@@ -480,6 +480,12 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
           acc[k][r].x += wj * t.x;
           acc[k][r].y += wj * t.y;
         }
+        if (a.store_v) {
+          // symmetric mode: keep N_g * v_ij (real space) for the transposed pass
+          cpx<T>* tv = reinterpret_cast<cpx<T>*>(a.t) + size_t(ii * a.jc + jj) * ng + z * slab;
+#pragma unroll
+          for (int r = 0; r < YL::R; ++r) stg(tv + line + (j + r * (N1 / YL::R)) * N0, v[r]);
+        }
       }
     }
     if constexpr (!PP) __syncthreads();

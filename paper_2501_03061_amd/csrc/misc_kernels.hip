@@ -80,20 +80,21 @@ hipError_t launch_convert_c128_c64(size_t n, const void* src, void* dst, hipStre
 }
 
 __global__ void expart_reduce_k(const double* expart, int n1, int i0, int ic, int j0, int jc,
-                                double* S, int lds) {
+                                double* S, int lds, int mirror) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ic * jc) return;
   const int ii = p / jc, jj = p % jc;
   double s = 0.0;
   for (int y = 0; y < n1; ++y) s += expart[size_t(p) * n1 + y];
   S[size_t(i0 + ii) * lds + (j0 + jj)] = s;
+  if (mirror) S[size_t(j0 + jj) * lds + (i0 + ii)] = s;  // S_ji = S_ij for a real even kernel
 }
 
 hipError_t launch_expart_reduce(const double* expart, int n1, int i0, int ic, int j0, int jc,
-                                double* S, int lds, hipStream_t s) {
+                                double* S, int lds, bool mirror, hipStream_t s) {
   const int np = ic * jc;
   hipLaunchKernelGGL(expart_reduce_k, dim3((np + 255) / 256), dim3(256), 0, s, expart, n1, i0, ic,
-                     j0, jc, S, lds);
+                     j0, jc, S, lds, int(mirror));
   return hipGetLastError();
 }
 

@@ -26,9 +26,10 @@ struct px_context {
   // measurement mode: HIP events around each pass of each chunk
   bool profiling = false;
   std::vector<hipEvent_t> events;
-  double prof_ms[3] = {0, 0, 0};
-  double prof_bytes[3] = {0, 0, 0};
-  int64_t prof_launches[3] = {0, 0, 0};
+  double prof_ms[4] = {0, 0, 0, 0};
+  double prof_bytes[4] = {0, 0, 0, 0};
+  int64_t prof_launches[4] = {0, 0, 0, 0};
+  bool symmetric_ace = true;  // ACE build solves only pairs j <= i (block level)
   ~px_context() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
   }
@@ -117,8 +118,10 @@ struct AceLayout {
   size_t W, M, L, U, part, end;
 };
 
-AceLayout ace_layout(const px_cell* cell, px_precision prec, int n, int ic, int jc) {
+AceLayout ace_layout(const px_cell* cell, px_precision prec, int n, int ic, int jc,
+                     bool symmetric) {
   AceLayout a{};
+  if (symmetric) ic = jc = (ic > jc ? ic : jc);
   a.ex = ex_layout(cell, prec, n, n, ic, jc, true);
   size_t off = a.ex.end;
   a.W = off;
@@ -197,11 +200,17 @@ px_status need_ws(px_context* c, size_t bytes) {
 
 // Enqueue the pair pipeline for all (i, j); `out` gets Vx phi.  S, when
 // non-null, receives sum_G K |rho_ij(G)|^2 per pair for the energy.
+// Enqueue the pair pipeline; `out` gets Vx phi.  With energy, S[i][j]
+// receives sum_G K |rho_ij(G)|^2 per pair.  Symmetric mode (phi is psi): the
+// orbitals are cut into square blocks of B = max(ic, jc); only blocks J <= I
+// are solved, and for J < I pass 3 keeps v_ij so that pass 4 adds the
+// transposed contributions to the J block (v_ji = conj(v_ij)).
 px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, int n_psi,
                        const void* psi, const double* occ, int n_phi, const void* phi,
                        const double* kern, void* out, const ExLayout& l, bool energy, int ic,
-                       int jc, hipStream_t s) {
+                       int jc, bool symmetric, hipStream_t s) {
   const bool fp32 = prec == PX_PREC_FP32;
+  const size_t ng = ngrid(cell);
   px::ChunkArgs a{};
   a.psi = psi;
   a.phi = phi;
@@ -212,56 +221,80 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
   a.g0 = reinterpret_cast<double2*>(c->ws + l.g0);
   a.expart = reinterpret_cast<double*>(c->ws + l.expart);
   a.n2 = cell->n[2];
-  a.inv_ng = 1.0 / double(ngrid(cell));
+  a.inv_ng = 1.0 / double(ng);
   double* S = reinterpret_cast<double*>(c->ws + l.S);
-  size_t nchunks = 0;
+  if (symmetric) ic = jc = (ic > jc ? ic : jc);
+  const size_t nch = size_t((n_phi + ic - 1) / ic) * ((n_psi + jc - 1) / jc);
   if (c->profiling) {
-    const size_t need = size_t((n_phi + ic - 1) / ic) * ((n_psi + jc - 1) / jc) * 4;
-    while (c->events.size() < need) {
+    while (c->events.size() < nch * 5) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return fail(c, PX_ERR_DEVICE, "hipEventCreate failed");
       c->events.push_back(e);
     }
   }
-  const size_t pair_bytes = ngrid(cell) * elem_bytes(prec);
+  const double pair_bytes = double(ng * elem_bytes(prec));
+  size_t nchunks = 0;
+  std::vector<int> has4;
   for (int i0 = 0; i0 < n_phi; i0 += ic) {
     a.i0 = i0;
     a.ic = (n_phi - i0) < ic ? (n_phi - i0) : ic;
     for (int j0 = 0; j0 < n_psi; j0 += jc) {
+      if (symmetric && j0 > i0) break;
       a.j0 = j0;
       a.jc = (n_psi - j0) < jc ? (n_psi - j0) : jc;
       a.first = j0 == 0;
-      hipEvent_t* ev = c->profiling ? &c->events[4 * nchunks] : nullptr;
+      a.store_v = symmetric && j0 < i0;
+      hipEvent_t* ev = c->profiling ? &c->events[5 * nchunks] : nullptr;
       px_status st = hip_check(
           c, px::launch_chunk(fp32, cell->n[0], a, a.ic * a.jc, energy, s, ev), "pair pipeline");
       if (st != PX_OK) return st;
+      if (a.store_v) {
+        st = hip_check(c, px::launch_pass4(fp32, a, ng, s), "transposed accumulation");
+        if (st != PX_OK) return st;
+      }
       if (c->profiling) {
-        // algorithmic bytes of each pass: 2 N_g b per pair (pass 1: read psi_j,
-        // write the pair slab; pass 2: read and write it; pass 3: read it and psi_j)
+        (void)hipEventRecord(c->events[5 * nchunks + 4], s);
+        // algorithmic bytes, 2 N_g b per pair in each pass (pass 1: read psi_j,
+        // write the pair slab; pass 2: read and rewrite it; pass 3: read it and
+        // psi_j); in symmetric mode pass 3 also writes v_ij (1 N_g b) and
+        // pass 4 reads v_ij and psi_i (2 N_g b)
+        const double np = double(a.ic) * a.jc;
         for (int k = 0; k < 3; ++k) {
-          c->prof_bytes[k] += 2.0 * double(pair_bytes) * a.ic * a.jc;
+          c->prof_bytes[k] += 2.0 * pair_bytes * np + (k == 2 && a.store_v ? pair_bytes * np : 0.0);
           c->prof_launches[k] += 1;
         }
+        if (a.store_v) {
+          c->prof_bytes[3] += 2.0 * pair_bytes * np;
+          c->prof_launches[3] += 1;
+        }
+        has4.push_back(a.store_v);
       }
       ++nchunks;
       if (energy) {
-        st = hip_check(c, px::launch_expart_reduce(a.expart, cell->n[1], i0, a.ic, j0, a.jc, S,
-                                                   n_psi, s),
+        st = hip_check(c, px::launch_expart_reduce(a.expart, cell->n[1], i0,
+                                                   a.ic, j0, a.jc, S, n_psi, a.store_v != 0, s),
                        "energy partials");
         if (st != PX_OK) return st;
       }
     }
   }
   if (c->profiling && nchunks > 0) {
-    hipError_t e = hipEventSynchronize(c->events[4 * nchunks - 1]);
+    hipError_t e = hipEventSynchronize(c->events[5 * nchunks - 1]);
     if (e != hipSuccess) return hip_check(c, e, "profiling sync");
-    for (size_t k = 0; k < nchunks; ++k)
+    for (size_t k = 0; k < nchunks; ++k) {
       for (int p = 0; p < 3; ++p) {
         float ms = 0.f;
-        e = hipEventElapsedTime(&ms, c->events[4 * k + p], c->events[4 * k + p + 1]);
+        e = hipEventElapsedTime(&ms, c->events[5 * k + p], c->events[5 * k + p + 1]);
         if (e != hipSuccess) return hip_check(c, e, "hipEventElapsedTime");
         c->prof_ms[p] += ms;
       }
+      if (has4[k]) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, c->events[5 * k + 3], c->events[5 * k + 4]);
+        if (e != hipSuccess) return hip_check(c, e, "hipEventElapsedTime");
+        c->prof_ms[3] += ms;
+      }
+    }
   }
   return PX_OK;
 }
@@ -307,7 +340,7 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
       if (n_phi <= 0) return 0;
       return ex_layout(cell, prec, n_psi, n_phi, ic, jc, true).end;
     case PX_OP_ACE_BUILD:
-      return ace_layout(cell, prec, n_psi, ic, jc).end;
+      return ace_layout(cell, prec, n_psi, ic, jc, ctx->symmetric_ace).end;
     case PX_OP_ACE_APPLY:
       if (n_phi <= 0) return 0;
       return apply_layout(cell, n_psi, n_phi).end;
@@ -393,7 +426,7 @@ px_status px_exchange_apply(px_context* ctx, const px_cell* cell, px_precision p
   hipError_t he = hipSetDevice(ctx->device);
   if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
   st = run_exchange(ctx, cell, prec, n_psi, psi, occ, n_phi, phi, kernel_G, vx_phi, l,
-                    e_x != nullptr, ic, jc, stream);
+                    e_x != nullptr, ic, jc, false, stream);
   if (st != PX_OK) return st;
   if (e_x) {
     const double ng = double(ngrid(cell));
@@ -420,7 +453,7 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   if (xi == psi) return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: xi must not alias psi");
   int ic, jc;
   tuning_for(ctx, cell, prec, &ic, &jc);
-  const AceLayout l = ace_layout(cell, prec, n, ic, jc);
+  const AceLayout l = ace_layout(cell, prec, n, ic, jc, ctx->symmetric_ace);
   st = need_ws(ctx, l.end);
   if (st != PX_OK) return st;
   hipError_t he = hipSetDevice(ctx->device);
@@ -435,7 +468,8 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   double* U = reinterpret_cast<double*>(ctx->ws + l.U);
   double* part = reinterpret_cast<double*>(ctx->ws + l.part);
   // W = Vx Psi (pair pipeline) and the energy sums
-  st = run_exchange(ctx, cell, prec, n, psi, occ, n, psi, kernel_G, W, l.ex, true, ic, jc, stream);
+  st = run_exchange(ctx, cell, prec, n, psi, occ, n, psi, kernel_G, W, l.ex, true, ic, jc,
+                    ctx->symmetric_ace, stream);
   if (st != PX_OK) return st;
   if (e_x) {
     st = hip_check(ctx,
@@ -547,6 +581,12 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
   return PX_OK;
 }
 
+px_status px_set_symmetry(px_context* ctx, int32_t enable) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  ctx->symmetric_ace = enable != 0;
+  return PX_OK;
+}
+
 px_status px_set_profiling(px_context* ctx, int32_t enable) {
   if (!ctx) return PX_ERR_INVALID_ARG;
   ctx->profiling = enable != 0;
@@ -556,7 +596,7 @@ px_status px_set_profiling(px_context* ctx, int32_t enable) {
 px_status px_profile_read(px_context* ctx, double* ms, double* bytes, int64_t* launches,
                           int32_t reset) {
   if (!ctx || !ms || !bytes || !launches) return PX_ERR_INVALID_ARG;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     ms[k] = ctx->prof_ms[k];
     bytes[k] = ctx->prof_bytes[k];
     launches[k] = ctx->prof_launches[k];

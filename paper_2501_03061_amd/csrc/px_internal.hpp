@@ -22,6 +22,7 @@ struct ChunkArgs {
   int n2;
   int i0, ic, j0, jc;
   int first;            // pass 3 overwrites the output instead of accumulating
+  int store_v;          // pass 3 also writes N_g * v_ij back into the pair slab (symmetric mode)
   double inv_ng;
 };
 
@@ -31,6 +32,10 @@ bool grid_supported(int n0, int n1, int n2);
 hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
                         hipEvent_t* ev);
 
+// Pass 4 (symmetric mode): out[j] -= sum_i f_i/N_g psi_i conj(v_ij) from the
+// pair slabs that pass 3 left in the pair buffer.
+hipError_t launch_pass4(bool fp32, const ChunkArgs& a, size_t ng, hipStream_t s);
+
 // misc_kernels.hip
 hipError_t launch_kernel_hse(int n0, int n1, int n2, double L0, double L1, double L2, double mu,
                              double* kern, hipStream_t s);
@@ -38,7 +43,7 @@ hipError_t launch_convert_c128_c64(size_t n, const void* src, void* dst, hipStre
 hipError_t launch_stream_copy(size_t bytes, const void* src, void* dst, hipStream_t s);
 // S[i][j] (row stride lds) = sum_y expart[(ii*jc+jj)*n1 + y] for the chunk
 hipError_t launch_expart_reduce(const double* expart, int n1, int i0, int ic, int j0, int jc,
-                                double* S, int lds, hipStream_t s);
+                                double* S, int lds, bool mirror, hipStream_t s);
 // e_x = scale * sum_i sum_j f_i f_j S[i][j]
 hipError_t launch_energy(const double* S, const double* occ, int n, double scale, double* e_x,
                          hipStream_t s);

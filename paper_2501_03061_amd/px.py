@@ -48,6 +48,7 @@ SIGNATURES = {
     "px_ace_build": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "px_ace_apply": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
     "px_ptim_exchange_loop": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _i32, _dbl, _vp, _vp, _vp]),
+    "px_set_symmetry": (_i32, [_vp, _i32]),
     "px_set_profiling": (_i32, [_vp, _i32]),
     "px_profile_read": (_i32, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl),
                                ctypes.POINTER(ctypes.c_int64), _i32]),
@@ -273,13 +274,16 @@ class Context:
     def px_set_profiling(self, enable: bool):
         self._check(self.lib.px_set_profiling(self.h, 1 if enable else 0))
 
+    def px_set_symmetry(self, enable: bool):
+        self._check(self.lib.px_set_symmetry(self.h, 1 if enable else 0))
+
     def px_profile_read(self, reset: bool = False):
-        """Per pass (1, 2, 3): dict(ms=total event ms, bytes=algorithmic bytes, launches=n)."""
-        ms = (ctypes.c_double * 3)()
-        by = (ctypes.c_double * 3)()
-        la = (ctypes.c_int64 * 3)()
+        """Per pass (1, 2, 3, 4): dict(ms=total event ms, bytes=algorithmic bytes, launches=n)."""
+        ms = (ctypes.c_double * 4)()
+        by = (ctypes.c_double * 4)()
+        la = (ctypes.c_int64 * 4)()
         self._check(self.lib.px_profile_read(self.h, ms, by, la, 1 if reset else 0))
-        return [dict(ms=ms[k], bytes=by[k], launches=la[k]) for k in range(3)]
+        return [dict(ms=ms[k], bytes=by[k], launches=la[k]) for k in range(4)]
 
     def px_sync(self, stream=None):
         """Raises PxError(PX_ERR_NOT_POSITIVE_DEFINITE) after a failed ACE build."""

@@ -120,3 +120,34 @@ def test_ptim_loop_fp64_matches_oracle(px_ctx, toy):
                                             oracle.DT_50AS * oracle.ALPHA)
     assert relerr(to_host(out), ref_phi) < FP64_TOL
     assert np.allclose(to_host(res), ref_res, rtol=1e-9, atol=1e-15)
+
+
+@pytest.mark.parametrize("sym", [False, True])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_ace_build_symmetry_modes_ragged_blocks(px_ctx, fp32, sym):
+    """n = 70 on a 24^3 grid with 16x16 blocks: blocks of 16, 16, 16, 16, 6 give
+    off-diagonal, diagonal and ragged blocks in the Hermitian-pair mode."""
+    banner(f"ace symmetry={sym} fp32={fp32}")
+    inst = inputs.make_instance(24, 10.0, 70, kT=0.04, seed=7)
+    K = oracle.kernel_hse(inst.n, inst.L, 0.106)
+    dV = inst.omega / inst.ng
+    r = oracle.ace_build(inst.psi, inst.occ, K, dV)
+    ex = oracle.exchange_energy_gspace(inst.psi, inst.occ, K, inst.omega)
+    cell = px.Cell(inst.L, inst.n)
+    prec = px.PX_PREC_FP32 if fp32 else px.PX_PREC_FP64
+    px_ctx.set_tuning(cell, prec, 16, 16)
+    px_ctx.px_set_symmetry(sym)
+    try:
+        cell, psi, xi, M, e, st = _build(px_ctx, inst, to_dev(K), fp32)
+        y = to_host(px_ctx.px_ace_apply(cell, xi, psi))
+    finally:
+        px_ctx.px_set_symmetry(True)
+        px_ctx.set_tuning(cell, prec, 0, 0)
+    tol = FP32_TOL if fp32 else FP64_TOL
+    assert st == 0
+    print(f"sym={sym} fp32={fp32}: M {relerr(M, r['M']):.2e} W {relerr(y, r['W']):.2e} "
+          f"E_x {abs(e - ex) / abs(ex):.2e}")
+    assert relerr(M, r["M"]) < tol
+    assert relerr(y, r["W"]) < tol
+    assert relerr(to_host(xi), r["xi"]) < tol
+    assert abs(e - ex) < (FP32_EX_TOL if fp32 else FP64_TOL) * abs(ex)
