@@ -3,8 +3,8 @@
 //
 //   hermitize : M <- (M + M^H)/2
 //   cholesky  : -M = L L^H, L lower triangular with real positive diagonal
-//               (the unique factor); on breakdown the 1-based column goes to
-//               the status word and the factor is left incomplete
+//               (the unique factor), blocked in 32-column panels; on
+//               breakdown the 1-based column goes to the status word
 //   inverse   : U = L^{-H} (upper triangular), the right factor of xi = W U
 //
 // These steps stay in FP64 in both precision forms.
@@ -36,62 +36,170 @@ hipError_t launch_hermitize(double* M, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Left-looking (Crout) Cholesky of A = -M in one workgroup.  Column k:
-//   L[k][k] = sqrt(A[k][k] - sum_{p<k} |L[k][p]|^2)
-//   L[i][k] = (A[i][k] - sum_{p<k} L[i][p] conj(L[k][p])) / L[k][k],  i > k
-// Rows of L are contiguous, so each dot product streams two rows.
-__global__ __launch_bounds__(1024) void cholesky_k(const double* M, int n, double* L,
+// Blocked right-looking Cholesky of A = -M, block width KB = 32:
+//   for each diagonal block k: factor A_kk = L_kk L_kk^H in LDS (one
+//   workgroup) and keep inv(L_kk); panel L_ik = A_ik L_kk^{-H} (one thread per
+//   row); trailing update A_ij -= L_ik L_jk^H for i >= j (32 x 32 tiles).
+// The working matrix L starts as -M and ends as the lower factor with a
+// zeroed strict upper triangle.  A non-positive pivot stops the factorisation:
+// status = 1-based global column, and every later kernel returns at once.
+constexpr int KB = 32;
+
+__global__ void chol_init_k(const double* M, int n, double* L, int32_t* status) {
+  const size_t total = size_t(n) * n;
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += size_t(gridDim.x) * blockDim.x) {
+    L[2 * e] = -M[2 * e];
+    L[2 * e + 1] = -M[2 * e + 1];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) status[0] = 0;
+}
+
+// Factor the diagonal block at k0 (size kb <= KB) in LDS; write L_kk back and
+// inv(L_kk) into Dinv (KB x KB, row-major complex).
+__global__ __launch_bounds__(256) void chol_diag_k(double* L, int n, int k0, double* Dinv,
                                                    int32_t* status) {
-  __shared__ double diag;
-  __shared__ int failed;
-  if (threadIdx.x == 0) failed = 0;
-  // zero the strict upper triangle, copy -M's lower triangle
-  for (size_t e = threadIdx.x; e < size_t(n) * n; e += blockDim.x) {
-    const int i = int(e / n), j = int(e % n);
-    if (j > i) {
-      L[e * 2] = 0.0;
-      L[e * 2 + 1] = 0.0;
-    } else {
-      L[e * 2] = -M[e * 2];
-      L[e * 2 + 1] = -M[e * 2 + 1];
+  __shared__ double a[KB][KB][2];
+  __shared__ double x[KB][KB][2];
+  __shared__ int bad;
+  if (status[0] != 0) return;
+  const int kb = (n - k0) < KB ? (n - k0) : KB;
+  const int t = threadIdx.x;
+  for (int e = t; e < KB * KB; e += 256) {
+    const int r = e / KB, c = e % KB;
+    const bool in = r < kb && c < kb;
+    a[r][c][0] = in ? L[(size_t(k0 + r) * n + k0 + c) * 2] : 0.0;
+    a[r][c][1] = in ? L[(size_t(k0 + r) * n + k0 + c) * 2 + 1] : 0.0;
+  }
+  if (t == 0) bad = 0;
+  __syncthreads();
+  // unblocked right-looking factorisation of the lower triangle
+  for (int k = 0; k < kb; ++k) {
+    if (t == 0) {
+      const double d = a[k][k][0];
+      if (!(d > 0.0)) bad = k0 + k + 1;
+      a[k][k][0] = d > 0.0 ? sqrt(d) : 1.0;
+      a[k][k][1] = 0.0;
+    }
+    __syncthreads();
+    if (bad) break;
+    const double dk = a[k][k][0];
+    for (int r = k + 1 + t; r < kb; r += 256) {
+      a[r][k][0] /= dk;
+      a[r][k][1] /= dk;
+    }
+    __syncthreads();
+    for (int e = t; e < KB * KB; e += 256) {
+      const int r = e / KB, c = e % KB;
+      if (r > k && c > k && c <= r && r < kb) {
+        // a[r][c] -= a[r][k] * conj(a[c][k])
+        const double ar = a[r][k][0], ai = a[r][k][1], br = a[c][k][0], bi = a[c][k][1];
+        a[r][c][0] -= ar * br + ai * bi;
+        a[r][c][1] -= ai * br - ar * bi;
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (t == 0) status[0] = bad;
+    return;
+  }
+  // inverse of the lower factor: column c by forward substitution (thread c)
+  if (t < KB) {
+    const int c = t;
+    for (int r = 0; r < KB; ++r) x[r][c][0] = x[r][c][1] = 0.0;
+    if (c < kb) {
+      x[c][c][0] = 1.0 / a[c][c][0];
+      for (int r = c + 1; r < kb; ++r) {
+        double sr = 0.0, si = 0.0;
+        for (int p = c; p < r; ++p) {
+          sr += a[r][p][0] * x[p][c][0] - a[r][p][1] * x[p][c][1];
+          si += a[r][p][0] * x[p][c][1] + a[r][p][1] * x[p][c][0];
+        }
+        x[r][c][0] = -sr / a[r][r][0];
+        x[r][c][1] = -si / a[r][r][0];
+      }
     }
   }
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      const double* lk = L + size_t(k) * n * 2;
-      double d = lk[2 * k];
-      for (int p = 0; p < k; ++p) d -= lk[2 * p] * lk[2 * p] + lk[2 * p + 1] * lk[2 * p + 1];
-      if (!(d > 0.0)) {
-        failed = k + 1;
-        d = 1.0;
-      }
-      diag = sqrt(d);
+  for (int e = t; e < KB * KB; e += 256) {
+    const int r = e / KB, c = e % KB;
+    Dinv[2 * e] = x[r][c][0];
+    Dinv[2 * e + 1] = x[r][c][1];
+    if (r < kb && c < kb) {
+      const bool low = c <= r;
+      L[(size_t(k0 + r) * n + k0 + c) * 2] = low ? a[r][c][0] : 0.0;
+      L[(size_t(k0 + r) * n + k0 + c) * 2 + 1] = low ? a[r][c][1] : 0.0;
     }
-    __syncthreads();
-    if (failed) break;
-    const double lkk = diag;
-    const double* lk = L + size_t(k) * n * 2;
-    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) {
-      double* li = L + size_t(i) * n * 2;
-      double re = li[2 * k], im = li[2 * k + 1];
-      for (int p = 0; p < k; ++p) {
-        // L[i][p] * conj(L[k][p])
-        const double ar = li[2 * p], ai = li[2 * p + 1], br = lk[2 * p], bi = lk[2 * p + 1];
-        re -= ar * br + ai * bi;
-        im -= ai * br - ar * bi;
-      }
-      li[2 * k] = re / lkk;
-      li[2 * k + 1] = im / lkk;
-    }
-    if (threadIdx.x == 0) {
-      double* lkw = L + size_t(k) * n * 2;
-      lkw[2 * k] = lkk;
-      lkw[2 * k + 1] = 0.0;
-    }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) status[0] = failed;
+}
+
+// Panel: for rows i >= k0 + kb, L[i][k0:k0+kb] = A[i][k0:k0+kb] * inv(L_kk)^H,
+// and zero the block above the diagonal (L[k0..][i] for the same columns).
+__global__ __launch_bounds__(64) void chol_panel_k(double* L, int n, int k0, const double* Dinv,
+                                                   const int32_t* status) {
+  if (status[0] != 0) return;
+  const int kb = (n - k0) < KB ? (n - k0) : KB;
+  const int i = k0 + kb + blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  double ar[KB], ai[KB];
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    ar[c] = c < kb ? L[(size_t(i) * n + k0 + c) * 2] : 0.0;
+    ai[c] = c < kb ? L[(size_t(i) * n + k0 + c) * 2 + 1] : 0.0;
+  }
+  // out[c] = sum_p a[p] * conj(Dinv[c][p])
+  for (int c = 0; c < kb; ++c) {
+    double sr = 0.0, si = 0.0;
+    for (int p = 0; p <= c; ++p) {
+      const double dr = Dinv[(c * KB + p) * 2], di = Dinv[(c * KB + p) * 2 + 1];
+      sr += ar[p] * dr + ai[p] * di;
+      si += ai[p] * dr - ar[p] * di;
+    }
+    L[(size_t(i) * n + k0 + c) * 2] = sr;
+    L[(size_t(i) * n + k0 + c) * 2 + 1] = si;
+    // strict upper triangle of the final factor: zero L[k0 + c][i]
+    L[(size_t(k0 + c) * n + i) * 2] = 0.0;
+    L[(size_t(k0 + c) * n + i) * 2 + 1] = 0.0;
+  }
+}
+
+// Trailing update of the lower triangle: tile (bi, bj) of 32 x 32 with
+// bi >= bj over rows/columns >= k0 + kb.
+__global__ __launch_bounds__(256) void chol_update_k(double* L, int n, int k0,
+                                                     const int32_t* status) {
+  __shared__ double pi_[KB][KB + 1][2];
+  __shared__ double pj_[KB][KB + 1][2];
+  if (status[0] != 0) return;
+  const int kb = (n - k0) < KB ? (n - k0) : KB;
+  const int base = k0 + kb;
+  const int bi = blockIdx.x, bj = blockIdx.y;
+  if (bj > bi) return;
+  const int r0 = base + bi * KB, c0 = base + bj * KB;
+  const int t = threadIdx.x;
+  for (int e = t; e < KB * KB; e += 256) {
+    const int r = e / KB, p = e % KB;
+    const bool vi = r0 + r < n && p < kb, vj = c0 + r < n && p < kb;
+    pi_[r][p][0] = vi ? L[(size_t(r0 + r) * n + k0 + p) * 2] : 0.0;
+    pi_[r][p][1] = vi ? L[(size_t(r0 + r) * n + k0 + p) * 2 + 1] : 0.0;
+    pj_[r][p][0] = vj ? L[(size_t(c0 + r) * n + k0 + p) * 2] : 0.0;
+    pj_[r][p][1] = vj ? L[(size_t(c0 + r) * n + k0 + p) * 2 + 1] : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < KB * KB; e += 256) {
+    const int r = e / KB, c = e % KB;
+    const int gi = r0 + r, gj = c0 + c;
+    if (gi >= n || gj >= n || gj > gi) continue;
+    double sr = 0.0, si = 0.0;
+#pragma unroll 8
+    for (int p = 0; p < KB; ++p) {
+      const double ar = pi_[r][p][0], ai = pi_[r][p][1], br = pj_[c][p][0], bi2 = pj_[c][p][1];
+      sr += ar * br + ai * bi2;
+      si += ai * br - ar * bi2;
+    }
+    L[(size_t(gi) * n + gj) * 2] -= sr;
+    L[(size_t(gi) * n + gj) * 2 + 1] -= si;
+  }
 }
 
 // U = L^{-H}: thread c solves L x = e_c by forward substitution and writes
@@ -125,8 +233,21 @@ __global__ __launch_bounds__(64) void tri_inv_k(const double* L, int n, double* 
 }
 
 hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t* status,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(cholesky_k, dim3(1), dim3(1024), 0, s, M, n, L, status);
+                           double* dinv, hipStream_t s) {
+  const size_t total = size_t(n) * n;
+  const int blocks = int((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+  hipLaunchKernelGGL(chol_init_k, dim3(blocks), dim3(256), 0, s, M, n, L, status);
+  for (int k0 = 0; k0 < n; k0 += KB) {
+    hipLaunchKernelGGL(chol_diag_k, dim3(1), dim3(256), 0, s, L, n, k0, dinv, status);
+    const int kb = (n - k0) < KB ? (n - k0) : KB;
+    const int rest = n - k0 - kb;
+    if (rest > 0) {
+      hipLaunchKernelGGL(chol_panel_k, dim3((rest + 63) / 64), dim3(64), 0, s, L, n, k0, dinv,
+                         status);
+      const int nt = (rest + KB - 1) / KB;
+      hipLaunchKernelGGL(chol_update_k, dim3(nt, nt), dim3(256), 0, s, L, n, k0, status);
+    }
+  }
   hipLaunchKernelGGL(tri_inv_k, dim3((n + 63) / 64), dim3(64), 0, s, L, n, U, status);
   return hipGetLastError();
 }

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
   __shared__ cpx<T> lds[PP ? 2 * SL : SL];
   __shared__ cpx<T> tw0[N0];
   __shared__ cpx<T> tw1[N1];
-  __shared__ double red[2][NT / 64];
+  __shared__ double red[3][NT / 64];
   using GX = Lines<N0, N1, P0, 1, false>;  // rows: contiguous lines
   using GY = Lines<N1, N0, 1, P0, true>;   // columns: strided lines
   constexpr int NSX = Plan<N0>::nst, NSY = Plan<N1>::nst;
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
       gather<T, GX, X0::R, NT>(ph, [&](int line, int e) { return ldc(phi + line * N0 + e); });
     }
     const int p = ii * a.jc + jj;
-    double sre = 0.0, sim = 0.0;
+    double sre = 0.0, sim = 0.0, sen = 0.0;
     // first x stage from registers: product, radix butterfly, LDS
 #pragma unroll
     for (int k = 0; k < BPT0; ++k) {
@@ -179,6 +179,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
           sim += double(ps.x) * double(ph_.y) - double(ps.y) * double(ph_.x);
         }
         v[r] = cmulc(ps, ph_);
+        if (G0 && valid) sen += double(v[r].x) * double(v[r].x) + double(v[r].y) * double(v[r].y);
       }
       dft<T, X0::R, false>(v);
       if (valid) {
@@ -189,21 +190,24 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
     if constexpr (G0) {
       sre = wave_sum(sre);
       sim = wave_sum(sim);
+      sen = wave_sum(sen);
       if ((tid & 63) == 0) {
         red[0][tid >> 6] = sre;
         red[1][tid >> 6] = sim;
+        red[2][tid >> 6] = sen;
       }
     }
     __syncthreads();
     if constexpr (G0) {
       if (tid == 0) {
-        double s0 = 0.0, s1 = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int w = 0; w < NT / 64; ++w) {
           s0 += red[0][w];
           s1 += red[1][w];
+          s2 += red[2][w];
         }
-        a.g0[size_t(p) * a.n2 + z] = make_double2(s0, s1);
+        a.g0[size_t(p) * a.n2 + z] = G0Part{s0, s1, s2, 0.0};
       }
     }
     if constexpr (PP) {
@@ -242,7 +246,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
   constexpr int P0 = N0 + 1;
   __shared__ cpx<T> lds[N2 * P0];
   __shared__ cpx<T> tw2[N2];
-  __shared__ double red[NT / 64];
+  __shared__ double red[3][NT / 64];
   using GZ = Lines<N2, N0, 1, P0, true>;  // plane [z][x], lines along z
   constexpr int NS = Plan<N2>::nst;
   using F0 = StageOf<N2, 0, false>;
@@ -290,7 +294,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
   stages_lds<T, GZ, false, NT, 1, NS - 1>(lds, tw2);
   // last forward stage into registers, kernel multiply, first inverse stage
   cpx<T> v[BPTL][FL::R];
-  double ex = 0.0;
+  double ex = 0.0, en = 0.0, ex0 = 0.0;  // FP32 form: sum_{G!=0} K|rho|^2, sum_{G!=0} |rho|^2, G = 0 term
 #pragma unroll
   for (int k = 0; k < BPTL; ++k) {
     const int b = tid + k * NT;
@@ -309,16 +313,17 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
         if (G0 && y == 0 && line == 0 && kz == 0) {
           // G = 0 from the FP64 slab sums of pass 1
           double s0 = 0.0, s1 = 0.0;
-          const double2* g = a.g0 + size_t(p) * N2;
+          const G0Part* g = a.g0 + size_t(p) * N2;
           for (int zz = 0; zz < N2; ++zz) {
-            double2 t = g[zz];
-            s0 += t.x;
-            s1 += t.y;
+            s0 += g[zz].re;
+            s1 += g[zz].im;
           }
-          if (EX) ex += kg * (s0 * s0 + s1 * s1);
+          if (EX) ex0 = kg * (s0 * s0 + s1 * s1);
           v[k][r] = {T(kg * s0), T(kg * s1)};
         } else {
-          if (EX) ex += kg * (double(c.x) * double(c.x) + double(c.y) * double(c.y));
+          const double c2 = double(c.x) * double(c.x) + double(c.y) * double(c.y);
+          if (EX) ex += kg * c2;
+          if (EX && G0) en += c2;
           v[k][r] = {T(kg * double(c.x)), T(kg * double(c.y))};
         }
       }
@@ -326,7 +331,15 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
   }
   if constexpr (EX) {
     ex = wave_sum(ex);
-    if ((tid & 63) == 0) red[tid >> 6] = ex;
+    if ((tid & 63) == 0) red[0][tid >> 6] = ex;
+    if constexpr (G0) {
+      en = wave_sum(en);
+      ex0 = wave_sum(ex0);
+      if ((tid & 63) == 0) {
+        red[1][tid >> 6] = en;
+        red[2][tid >> 6] = ex0;
+      }
+    }
   }
   __syncthreads();  // every thread is done reading LDS before it is overwritten
 #pragma unroll
@@ -343,10 +356,23 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
   __syncthreads();
   if constexpr (EX) {
     if (tid == 0) {
-      double s2 = 0.0;
+      double s2 = 0.0, s3 = 0.0, s4 = 0.0;
 #pragma unroll
-      for (int w = 0; w < NT / 64; ++w) s2 += red[w];
-      a.expart[size_t(p) * N1 + y] = s2;
+      for (int w = 0; w < NT / 64; ++w) {
+        s2 += red[0][w];
+        if (G0) {
+          s3 += red[1][w];
+          s4 += red[2][w];
+        }
+      }
+      if constexpr (G0) {
+        double* e = a.expart + (size_t(p) * N1 + y) * 3;
+        e[0] = s2;
+        e[1] = s3;
+        e[2] = s4;
+      } else {
+        a.expart[size_t(p) * N1 + y] = s2;
+      }
     }
   }
   stages_lds<T, GZ, true, NT, 1, NS - 1>(lds, tw2);

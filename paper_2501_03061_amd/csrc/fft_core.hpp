@@ -276,17 +276,30 @@ template <int N, int R> constexpr int butterflies_per_thread(int nl, int nt) {
 
 // Twiddle w^(r*k) for r = 1..R-1 applied in place; k = j mod NS, base root
 // index k*(N/(NS*R)) in the N-entry table (forward table; inverse conjugates).
+// FP32: every power is read from the table (each correctly rounded from FP64),
+// so the transform carries no error growth from repeated products.  FP64:
+// powers by repeated multiplication (error r * 1e-16, far below tolerance).
 template <typename T, int N, int R, int NS, bool INV>
 __device__ __forceinline__ void twiddle(cpx<T>* v, int j, const cpx<T>* tw) {
   if constexpr (NS == 1) return;
   const int k = j % NS;
-  cpx<T> w = tw[k * (N / (NS * R))];
-  if (INV) w.y = -w.y;
-  cpx<T> wr = w;
+  constexpr int STEP = N / (NS * R);
+  if constexpr (sizeof(T) == 4) {
 #pragma unroll
-  for (int r = 1; r < R; ++r) {
-    v[r] = cmul(v[r], wr);
-    if (r + 1 < R) wr = cmul(wr, w);
+    for (int r = 1; r < R; ++r) {
+      cpx<T> w = tw[r * k * STEP];
+      if (INV) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+  } else {
+    cpx<T> w = tw[k * STEP];
+    if (INV) w.y = -w.y;
+    cpx<T> wr = w;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      v[r] = cmul(v[r], wr);
+      if (r + 1 < R) wr = cmul(wr, w);
+    }
   }
 }
 

@@ -79,22 +79,46 @@ hipError_t launch_convert_c128_c64(size_t n, const void* src, void* dst, hipStre
   return hipGetLastError();
 }
 
-__global__ void expart_reduce_k(const double* expart, int n1, int i0, int ic, int j0, int jc,
-                                double* S, int lds, int mirror) {
+// Pair energy S_ij = sum_G K |rho_ij(G)|^2 from the per-plane partials.
+// FP32 form: S = K(0)|rho(0)|^2 + A * (N_g E_r - |rho(0)|^2) / B, where A and B
+// are the FP32-transform sums of K|rho|^2 and |rho|^2 over G != 0, E_r the
+// FP64 energy of the transform input and rho(0) its FP64 sum: the transform's
+// systematic norm drift (about 1e-7 relative in FP32) cancels in A / B.
+__global__ void expart_reduce_k(const double* expart, const G0Part* g0, int n1, int n2, double ng,
+                                int i0, int ic, int j0, int jc, double* S, int lds, int mirror) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ic * jc) return;
   const int ii = p / jc, jj = p % jc;
   double s = 0.0;
-  for (int y = 0; y < n1; ++y) s += expart[size_t(p) * n1 + y];
+  if (g0 == nullptr) {
+    for (int y = 0; y < n1; ++y) s += expart[size_t(p) * n1 + y];
+  } else {
+    double a = 0.0, b = 0.0, e0 = 0.0;
+    for (int y = 0; y < n1; ++y) {
+      const double* e = expart + (size_t(p) * n1 + y) * 3;
+      a += e[0];
+      b += e[1];
+      e0 += e[2];
+    }
+    double sr = 0.0, si = 0.0, er = 0.0;
+    for (int z = 0; z < n2; ++z) {
+      sr += g0[size_t(p) * n2 + z].re;
+      si += g0[size_t(p) * n2 + z].im;
+      er += g0[size_t(p) * n2 + z].en;
+    }
+    const double target = ng * er - (sr * sr + si * si);
+    s = e0 + (b > 0.0 && target > 0.0 ? a * (target / b) : a);
+  }
   S[size_t(i0 + ii) * lds + (j0 + jj)] = s;
   if (mirror) S[size_t(j0 + jj) * lds + (i0 + ii)] = s;  // S_ji = S_ij for a real even kernel
 }
 
-hipError_t launch_expart_reduce(const double* expart, int n1, int i0, int ic, int j0, int jc,
-                                double* S, int lds, bool mirror, hipStream_t s) {
+hipError_t launch_expart_reduce(const double* expart, const G0Part* g0, int n1, int n2, double ng,
+                                int i0, int ic, int j0, int jc, double* S, int lds, bool mirror,
+                                hipStream_t s) {
   const int np = ic * jc;
-  hipLaunchKernelGGL(expart_reduce_k, dim3((np + 255) / 256), dim3(256), 0, s, expart, n1, i0, ic,
-                     j0, jc, S, lds, int(mirror));
+  hipLaunchKernelGGL(expart_reduce_k, dim3((np + 255) / 256), dim3(256), 0, s, expart, g0, n1, n2,
+                     ng, i0, ic, j0, jc, S, lds, int(mirror));
   return hipGetLastError();
 }
 

@@ -101,11 +101,11 @@ ExLayout ex_layout(const px_cell* cell, px_precision prec, int n_psi, int n_phi,
   l.t = off;
   off = align_up(off + pairs * ngrid(cell) * elem_bytes(prec));
   l.g0 = off;
-  if (prec == PX_PREC_FP32) off = align_up(off + pairs * cell->n[2] * 16);
+  if (prec == PX_PREC_FP32) off = align_up(off + pairs * cell->n[2] * sizeof(px::G0Part));
   l.expart = off;
   l.S = off;
   if (energy) {
-    off = align_up(off + pairs * cell->n[1] * 8);
+    off = align_up(off + pairs * cell->n[1] * 8 * (prec == PX_PREC_FP32 ? 3 : 1));
     l.S = off;
     off = align_up(off + size_t(n_phi) * n_psi * 8);
   }
@@ -115,7 +115,7 @@ ExLayout ex_layout(const px_cell* cell, px_precision prec, int n_psi, int n_phi,
 
 struct AceLayout {
   ExLayout ex;
-  size_t W, M, L, U, part, end;
+  size_t W, M, L, U, dinv, part, end;
 };
 
 AceLayout ace_layout(const px_cell* cell, px_precision prec, int n, int ic, int jc,
@@ -132,6 +132,8 @@ AceLayout ace_layout(const px_cell* cell, px_precision prec, int n, int ic, int 
   off = align_up(off + size_t(n) * n * 16);
   a.U = off;
   off = align_up(off + size_t(n) * n * 16);
+  a.dinv = off;
+  off = align_up(off + 32 * 32 * 16);
   int nsplit = 0;
   const size_t pe = px::gemm_xhy_part_elems(n, n, ngrid(cell), &nsplit);
   a.part = off;
@@ -159,7 +161,7 @@ ApplyLayout apply_layout(const px_cell* cell, int n, int n_phi) {
 
 struct LoopLayout {
   ApplyLayout ap;
-  size_t mid, y, buf0, buf1, partial, end;
+  size_t mid, buf0, buf1, partial, end;
 };
 
 LoopLayout loop_layout(const px_cell* cell, px_precision prec, int n, int n_phi) {
@@ -167,9 +169,7 @@ LoopLayout loop_layout(const px_cell* cell, px_precision prec, int n, int n_phi)
   l.ap = apply_layout(cell, n, n_phi);
   size_t off = l.ap.end;
   const size_t blk = size_t(n_phi) * ngrid(cell) * elem_bytes(prec);
-  l.mid = off;
-  off = align_up(off + blk);
-  l.y = off;
+  l.mid = off;  // the midpoint, then V_ACE of it (xi^H mid is taken before it is overwritten)
   off = align_up(off + blk);
   l.buf0 = off;
   off = align_up(off + blk);
@@ -218,7 +218,7 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
   a.out = out;
   a.occ = occ;
   a.kern = kern;
-  a.g0 = reinterpret_cast<double2*>(c->ws + l.g0);
+  a.g0 = reinterpret_cast<px::G0Part*>(c->ws + l.g0);
   a.expart = reinterpret_cast<double*>(c->ws + l.expart);
   a.n2 = cell->n[2];
   a.inv_ng = 1.0 / double(ng);
@@ -271,8 +271,9 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       }
       ++nchunks;
       if (energy) {
-        st = hip_check(c, px::launch_expart_reduce(a.expart, cell->n[1], i0,
-                                                   a.ic, j0, a.jc, S, n_psi, a.store_v != 0, s),
+        st = hip_check(c, px::launch_expart_reduce(a.expart, fp32 ? a.g0 : nullptr, cell->n[1],
+                                                   cell->n[2], double(ng), i0, a.ic, j0, a.jc, S,
+                                                   n_psi, a.store_v != 0, s),
                        "energy partials");
         if (st != PX_OK) return st;
       }
@@ -486,7 +487,10 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   if (st != PX_OK) return st;
   st = hip_check(ctx, px::launch_hermitize(Mw, n, stream), "hermitize");
   if (st != PX_OK) return st;
-  st = hip_check(ctx, px::launch_chol_inv(Mw, n, L, U, status, stream), "cholesky");
+  st = hip_check(ctx,
+                 px::launch_chol_inv(Mw, n, L, U, status,
+                                     reinterpret_cast<double*>(ctx->ws + l.dinv), stream),
+                 "cholesky");
   if (st != PX_OK) return st;
   st = hip_check(ctx, px::launch_gemm_xc(fp32, n, n, ng, W, U, n, 1.0, xi, true, stream),
                  "xi = W L^-H");
@@ -555,7 +559,7 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
   double* C = reinterpret_cast<double*>(ctx->ws + l.ap.C);
   double* part = reinterpret_cast<double*>(ctx->ws + l.ap.part);
   void* mid = ctx->ws + l.mid;
-  void* y = ctx->ws + l.y;
+  void* y = mid;
   void* bufs[2] = {ctx->ws + l.buf0, ctx->ws + l.buf1};
   double* partial = reinterpret_cast<double*>(ctx->ws + l.partial);
   int nsplit = 0;

@@ -7,6 +7,12 @@
 
 namespace px {
 
+// FP64 per-slab sums of one pair product (FP32 form): sum of rho, and sum
+// of |rho|^2 of the values handed to the transform.
+struct G0Part {
+  double re, im, en, pad;
+};
+
 // One chunk of orbital pairs: i in [i0, i0+ic) (output orbitals phi_i) times
 // j in [j0, j0+jc) (density orbitals psi_j).  Pair p = (i-i0)*jc + (j-j0)
 // owns slab p of the pair buffer t ([pairs][n2][n1][n0]).
@@ -17,8 +23,9 @@ struct ChunkArgs {
   void* out;            // [n_phi][N_g]
   const double* occ;    // [n_psi]
   const double* kern;   // [N_g] FP64, FFT order
-  double2* g0;          // [ic*jc][n2] FP64 slab sums (FP32 form)
-  double* expart;       // [ic*jc][n1] FP64 partial sums of K |rho(G)|^2
+  G0Part* g0;           // [ic*jc][n2] FP64 slab sums (FP32 form)
+  double* expart;       // FP64 energy partials per (pair, y-plane): sum K|rho(G)|^2 (FP64
+                        // form), or {sum_{G!=0} K|rho|^2, sum_{G!=0} |rho|^2, G=0 term} (FP32 form)
   int n2;
   int i0, ic, j0, jc;
   int first;            // pass 3 overwrites the output instead of accumulating
@@ -41,9 +48,12 @@ hipError_t launch_kernel_hse(int n0, int n1, int n2, double L0, double L1, doubl
                              double* kern, hipStream_t s);
 hipError_t launch_convert_c128_c64(size_t n, const void* src, void* dst, hipStream_t s);
 hipError_t launch_stream_copy(size_t bytes, const void* src, void* dst, hipStream_t s);
-// S[i][j] (row stride lds) = sum_y expart[(ii*jc+jj)*n1 + y] for the chunk
-hipError_t launch_expart_reduce(const double* expart, int n1, int i0, int ic, int j0, int jc,
-                                double* S, int lds, bool mirror, hipStream_t s);
+// S[i][j] (row stride lds) from the chunk's energy partials (see ChunkArgs);
+// FP32 form (g0 non-null): the G != 0 part is rescaled so that its energy
+// matches Parseval's identity with the FP64 energy of the transform input.
+hipError_t launch_expart_reduce(const double* expart, const G0Part* g0, int n1, int n2, double ng,
+                                int i0, int ic, int j0, int jc, double* S, int lds, bool mirror,
+                                hipStream_t s);
 // e_x = scale * sum_i sum_j f_i f_j S[i][j]
 hipError_t launch_energy(const double* S, const double* occ, int n, double scale, double* e_x,
                          hipStream_t s);
@@ -72,7 +82,8 @@ hipError_t launch_gemm_xc(bool fp32, int na, int nb, size_t ng, const void* X, c
 // chol_kernels.hip: FP64 Hermitian tools on an n x n complex128 matrix (row-major)
 hipError_t launch_hermitize(double* M, int n, hipStream_t s);
 // U = L^{-H} where -M = L L^H; status[0] = 0 on success or the 1-based failing column
+// dinv: workspace of 32 x 32 complex128 (inverse of the current diagonal block)
 hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t* status,
-                           hipStream_t s);
+                           double* dinv, hipStream_t s);
 
 }  // namespace px

@@ -178,7 +178,10 @@ class Context:
         if nbytes <= 0:
             raise PxError(PX_ERR_INVALID_ARG, "invalid problem for workspace sizing")
         if self.ws is None or self.ws.numel() < nbytes:
-            self.ws = None
+            if self.ws is not None:
+                self.ws = None
+                torch.cuda.synchronize(self.device)
+                torch.cuda.empty_cache()
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
         self._check(self.lib.px_set_workspace(self.h, _ptr(self.ws), self.ws.numel()))
 

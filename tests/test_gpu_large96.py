@@ -1,0 +1,112 @@
+"""Full-size single-GPU share: 96^3 grid, 1536 orbitals, kT = 0.03 Ha.
+
+The oracle cannot do all 2.4 M pair solves on a few host cores, so parity is
+checked on sampled output orbitals (the oracle computes them one by one) and
+the FP32 form is compared with the FP64 GPU path over the whole block:
+ACE matrix M, exchange energy, ACE action on Psi and the 4-iteration
+PT-IM-style loop on Phi = Psi + 1e-3 Z.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_03061_amd import inputs, px
+from _gpu import banner, relerr, to_dev, to_host
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1200)]
+
+FP64_TOL, FP32_TOL, FP32_EX_TOL = 1e-11, 2e-5, 1e-7
+COLS = [3, 1100]   # a fully occupied orbital and one near the Fermi level
+
+
+@pytest.fixture(scope="module")
+def large():
+    import torch
+    c = inputs.CONFIGS["large96"]
+    banner("large96: generating inputs")
+    inst = inputs.make_instance(c["n"], c["L"], c["n_orb"], c["kT"], seed=c["seed"])
+    frac = float(np.mean((inst.occ > 0.1) & (inst.occ < 0.9)))
+    print(f"large96: fraction of 0.1<f<0.9 occupations {frac:.3f}", flush=True)
+    psi64 = to_dev(inst.psi)
+    yield inst, psi64
+    del psi64
+    torch.cuda.empty_cache()
+
+
+def test_large96_sampled_columns_vs_oracle(px_ctx, large):
+    inst, psi64 = large
+    banner("large96: sampled columns, FP64 path vs oracle")
+    import torch
+    cell = px.Cell(inst.L, inst.n)
+    kd = px_ctx.px_kernel_hse(cell, 0.106)
+    occ = to_dev(inst.occ)
+    phi = psi64[COLS].contiguous()
+    w = to_host(px_ctx.px_exchange_apply(cell, psi64, occ, phi, kd))
+    K = oracle.kernel_hse(inst.n, inst.L, 0.106)
+    ref = oracle.exchange_apply(inst.psi, inst.occ, inst.psi[COLS], K)
+    err = relerr(w, ref)
+    print(f"large96 sampled FP64 err {err:.2e}", flush=True)
+    assert err < FP64_TOL
+    # the same columns in the FP32 form
+    psi32 = px_ctx.px_convert_c128_to_c64(psi64)
+    w32 = to_host(px_ctx.px_exchange_apply(cell, psi32, occ, psi32[COLS].contiguous(), kd))
+    err32 = relerr(w32, ref)
+    print(f"large96 sampled FP32 err {err32:.2e}", flush=True)
+    assert err32 < FP32_TOL
+    del psi32
+    torch.cuda.synchronize()
+
+
+def test_large96_ace_fp32_vs_fp64_and_loop(px_ctx, large):
+    inst, psi64 = large
+    import torch
+    cell = px.Cell(inst.L, inst.n)
+    n = inst.n_orb
+    kd = px_ctx.px_kernel_hse(cell, 0.106)
+    occ = to_dev(inst.occ)
+    dev = psi64.device
+
+    def build(psi):
+        M = torch.empty((n, n), dtype=torch.complex128, device=dev)
+        e = torch.zeros(1, dtype=torch.float64, device=dev)
+        xi, st = px_ctx.px_ace_build(cell, psi, occ, kd, M=M, e_x=e)
+        px_ctx.px_sync()
+        assert int(st.item()) == 0
+        return xi, M, float(e.item())
+
+    banner("large96: FP64 ACE build")
+    xi64, M64, e64 = build(psi64)
+    # ACE exactness on sampled columns: V_ACE psi_c = W_c = Vx psi_c
+    y = to_host(px_ctx.px_ace_apply(cell, xi64, psi64[COLS].contiguous()))
+    w = to_host(px_ctx.px_exchange_apply(cell, psi64, occ, psi64[COLS].contiguous(), kd))
+    assert relerr(y, w) < FP64_TOL
+
+    banner("large96: FP32 ACE build")
+    psi32 = px_ctx.px_convert_c128_to_c64(psi64)
+    xi32, M32, e32 = build(psi32)
+    em = float(torch.linalg.matrix_norm(M32 - M64) / torch.linalg.matrix_norm(M64))
+    ee = abs(e32 - e64) / abs(e64)
+    print(f"large96 FP32 vs FP64: M {em:.2e} E_x {ee:.2e} (E_x = {e64:.10f})", flush=True)
+    assert em < FP32_TOL
+    assert ee < FP32_EX_TOL
+
+    banner("large96: PT-IM-style loops")
+    z = inputs.noise_block(inst.n, inst.L, n, seed=1001)
+    phi_n64 = to_dev(inst.psi + 1e-3 * z)
+    del z
+    dta = oracle.DT_50AS * oracle.ALPHA
+    out64, res64 = px_ctx.px_ptim_exchange_loop(cell, xi64, phi_n64, 4, dta)
+    del xi64
+    phi_n32 = px_ctx.px_convert_c128_to_c64(phi_n64)
+    del phi_n64
+    out32, res32 = px_ctx.px_ptim_exchange_loop(cell, xi32, phi_n32, 4, dta)
+    torch.cuda.synchronize()
+    eo = float(torch.linalg.vector_norm((out32.to(torch.complex128) - out64).flatten()) /
+               torch.linalg.vector_norm(out64.flatten()))
+    r64, r32 = to_host(res64), to_host(res32)
+    print(f"large96 loop: out err {eo:.2e}; residuals fp64 {r64} fp32 {r32}", flush=True)
+    assert eo < FP32_TOL
+    assert np.all(np.diff(r64) < 0)                       # contracting fixed point
+    assert abs(r32[0] - r64[0]) < 1e-4 * r64[0]
+    del out32, out64, phi_n32, xi32, psi32
+    torch.cuda.synchronize()
