@@ -27,6 +27,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_pipeline_mid72_traffic.json")
+KERNEL_SOURCES = ("exchange_kernels.hpp", "fft_core.hpp", "px_internal.hpp", "exchange_inst.hip",
+                  "pair_transpose.hip")
+
+
+def source_digest():
+    """Digest of the pair-pipeline kernel sources with comments and blank lines
+    removed: counter figures measured on other code are not reported."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        text = open(os.path.join(ROOT, "paper_2501_03061_amd", "csrc", name)).read()
+        text = re.sub(r"//[^\n]*", "", text)
+        lines = [l.strip() for l in text.splitlines() if l.strip()]
+        h.update(("\n".join(lines) + "\n").encode())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when that summary was taken on different kernel code."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
 def log(msg):
@@ -278,7 +308,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": measured_traffic(names[dom]),
             "kernel": names[dom],
             "per_unit_bytes": pd["bytes"] / max(1, pd["launches"]),
             "unit_desc": "algorithmic bytes per launch: 2*N_g*8 B per pair of the launch's chunk "

@@ -24,51 +24,51 @@ template <typename T> __device__ __forceinline__ cpx<T> ld2nt(const cpx<T>* p) {
   return {v.x, v.y};
 }
 
-// grid (ceil(N_g / 256), jc): thread = one grid point of one output orbital j.
+// grid (ceil(N_g / 256), ceil(jc / JB)): a thread owns one grid point and JB
+// output orbitals j, so each psi_i value is loaded once for the JB of them.
+constexpr int JB = 16;
+
 template <typename T>
 __global__ __launch_bounds__(256) void pass4_transpose_acc(ChunkArgs a, size_t ng) {
   const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
-  const int jj = blockIdx.y;
+  const int j0 = blockIdx.y * JB;
   if (e >= ng) return;
+  const int nj = (a.jc - j0) < JB ? (a.jc - j0) : JB;
   const cpx<T>* psi = reinterpret_cast<const cpx<T>*>(a.psi);
   const cpx<T>* t = reinterpret_cast<const cpx<T>*>(a.t);
-  T accx = T(0), accy = T(0);
-  int ii = 0;
-  for (; ii + 4 <= a.ic; ii += 4) {
-    cpx<T> ps[4], v[4];
-    T w[4];
+  T ax[JB], ay[JB];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      ps[u] = ld2(psi + size_t(a.i0 + ii + u) * ng + e);
-      v[u] = ld2nt(t + size_t((ii + u) * a.jc + jj) * ng + e);
-      w[u] = T(a.occ[a.i0 + ii + u] * a.inv_ng);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      // psi_i * conj(v)
-      const T rx = ps[u].x * v[u].x + ps[u].y * v[u].y;
-      const T ry = ps[u].y * v[u].x - ps[u].x * v[u].y;
-      accx += w[u] * rx;
-      accy += w[u] * ry;
-    }
-  }
-  for (; ii < a.ic; ++ii) {
+  for (int u = 0; u < JB; ++u) ax[u] = ay[u] = T(0);
+  for (int ii = 0; ii < a.ic; ++ii) {
     const cpx<T> ps = ld2(psi + size_t(a.i0 + ii) * ng + e);
-    const cpx<T> v = ld2nt(t + size_t(ii * a.jc + jj) * ng + e);
     const T w = T(a.occ[a.i0 + ii] * a.inv_ng);
-    accx += w * (ps.x * v.x + ps.y * v.y);
-    accy += w * (ps.y * v.x - ps.x * v.y);
+    const T px_ = w * ps.x, py_ = w * ps.y;
+    const cpx<T>* row = t + size_t(ii * a.jc + j0) * ng + e;
+    cpx<T> v[JB];
+#pragma unroll
+    for (int u = 0; u < JB; ++u) v[u] = u < nj ? ld2nt(row + size_t(u) * ng) : cpx<T>{T(0), T(0)};
+#pragma unroll
+    for (int u = 0; u < JB; ++u) {
+      // f_i/N_g psi_i * conj(v)
+      ax[u] += px_ * v[u].x + py_ * v[u].y;
+      ay[u] += py_ * v[u].x - px_ * v[u].y;
+    }
   }
-  cpx<T>* o = reinterpret_cast<cpx<T>*>(a.out) + size_t(a.j0 + jj) * ng + e;
-  const cpx<T> prev = ld2(o);
-  typename V2t<T>::t r;
-  r.x = prev.x - accx;
-  r.y = prev.y - accy;
-  *reinterpret_cast<typename V2t<T>::t*>(o) = r;
+#pragma unroll
+  for (int u = 0; u < JB; ++u) {
+    if (u < nj) {
+      cpx<T>* o = reinterpret_cast<cpx<T>*>(a.out) + size_t(a.j0 + j0 + u) * ng + e;
+      const cpx<T> prev = ld2(o);
+      typename V2t<T>::t r;
+      r.x = prev.x - ax[u];
+      r.y = prev.y - ay[u];
+      *reinterpret_cast<typename V2t<T>::t*>(o) = r;
+    }
+  }
 }
 
 hipError_t launch_pass4(bool fp32, const ChunkArgs& a, size_t ng, hipStream_t s) {
-  dim3 grid(unsigned((ng + 255) / 256), a.jc);
+  dim3 grid(unsigned((ng + 255) / 256), (a.jc + JB - 1) / JB);
   if (fp32) hipLaunchKernelGGL(pass4_transpose_acc<float>, grid, dim3(256), 0, s, a, ng);
   else hipLaunchKernelGGL(pass4_transpose_acc<double>, grid, dim3(256), 0, s, a, ng);
   return hipGetLastError();

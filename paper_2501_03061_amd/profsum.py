@@ -1,0 +1,128 @@
+"""Summaries of rocprofv3 CSV output for the pair pipeline.
+
+    python -m paper_2501_03061_amd.profsum --trace DIR --fetch DIR --write DIR \
+        --copy-fetch DIR --copy-write DIR --bench-json FILE --out profiles
+
+DIR are rocprofv3 output directories (``--output-format csv``): a
+``--kernel-trace --stats`` run of ``bench.py``, two ``--pmc`` runs of
+``bench.py`` (FETCH_SIZE, then WRITE_SIZE) and the same two counters on
+``bench.py --calibrate-copy`` (the plain copy kernel, 2 GiB).  Writes
+``pair_pipeline_mid72_kernel_trace.md``, ``pair_pipeline_mid72_hbm_counters.md``
+and ``pair_pipeline_mid72_traffic.json`` (calibrated HBM bytes per launch,
+tagged with the digest of the kernel sources they were measured on).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import json
+import os
+
+COPY_BYTES = 2 << 30
+
+
+def _csv(d, suffix):
+    hits = glob.glob(os.path.join(d, f"*{suffix}"))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} in {d}")
+    return list(csv.DictReader(open(hits[0])))
+
+
+def _per_kernel(d):
+    agg = collections.defaultdict(list)
+    for r in _csv(d, "counter_collection.csv"):
+        agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return agg
+
+
+def _short(name):
+    # "void px::pass3_inv_xy_acc<float, 72, ...>(...)" -> "pass3_inv_xy_acc"
+    base = name.split("(")[0].split("<")[0]
+    return base.split("::")[-1].replace("void ", "").strip()
+
+
+def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, commands):
+    import bench  # noqa: E402  (repository root on sys.path)
+    os.makedirs(out, exist_ok=True)
+    rec = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    stats = _csv(trace, "kernel_stats.csv")
+    lines = ["# Kernel trace: exchange/ACE hot path, mid72 workload (72^3 grid, 512 orbitals)", "",
+             "Command (repository root, one MI355X):", "", "```", commands["trace"], "```", "",
+             f"The bench run inside the profiler printed: value {rec['value']:.4g} pair-solves/s, "
+             f"{rec['ms_per_step']:.1f} ms/step (FP32 form, Hermitian-pair mode); FP64 form "
+             f"{rec['extra'].get('fp64_pair_solves_per_s', float('nan')):.4g} pair-solves/s.", "",
+             "Per-pass averages measured by bench.py with HIP events over the timed region (FP32 form):", "",
+             "| pass | avg per launch (us) | launches per step | model GB/s |", "|---|---|---|---|"]
+    for k, v in rec["extra"]["passes"].items():
+        lines.append(f"| {k} | {v['avg_us']:.1f} | {v['launches_per_step']} | {v['GBps']:.0f} |")
+    lines += ["", "Top kernels (`kernel_stats.csv`, whole run: warmup, timed FP32 steps, FP64 comparison):", "",
+              "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in stats[:18]:
+        name = r["Name"] if len(r["Name"]) < 90 else r["Name"][:90] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    open(os.path.join(out, "pair_pipeline_mid72_kernel_trace.md"), "w").write("\n".join(lines) + "\n")
+
+    fc, wc = _per_kernel(copy_fetch), _per_kernel(copy_write)
+    ck = [k for k in fc if "stream_copy" in k][0]
+    f_copy = sum(fc[ck]) / len(fc[ck])
+    w_copy = sum(wc[ck]) / len(wc[ck])
+    ff = COPY_BYTES / 1024 / f_copy
+    wf = COPY_BYTES / 1024 / w_copy
+    fb, wb = _per_kernel(fetch), _per_kernel(write)
+    lines = ["# HBM traffic counters: pair pipeline, mid72 workload", "",
+             "Commands (each counter in a run of its own):", "", "```"] + commands["pmc"] + ["```", "",
+             f"Calibration with the plain copy kernel (`px_stream_copy`, 2 GiB read and 2 GiB written per "
+             f"launch): FETCH_SIZE reads {f_copy:,.0f} KiB per launch (factor {ff:.3f} to bytes read), "
+             f"WRITE_SIZE {w_copy:,.0f} KiB (factor {wf:.3f}).", "",
+             "Per dispatch, averaged over the launches of one FP32 step:", "",
+             "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read GB | write GB | read+write GB |",
+             "|---|---|---|---|---|---|---|"]
+    kernels = {}
+    for k in sorted(fb, key=lambda k: -sum(fb[k])):
+        if k not in wb:
+            continue
+        f = sum(fb[k]) / len(fb[k])
+        w = sum(wb[k]) / len(wb[k])
+        if f + w < 1000:
+            continue
+        rb, wbts = f * ff * 1024, w * wf * 1024
+        name = k if len(k) < 80 else k[:80] + "..."
+        lines.append(f"| `{name}` | {len(fb[k])} | {f:,.0f} | {w:,.0f} | {rb / 1e9:.3f} | "
+                     f"{wbts / 1e9:.3f} | {(rb + wbts) / 1e9:.3f} |")
+        if "float" in k and _short(k).startswith("pass"):
+            kernels[_short(k)] = dict(read_bytes=rb, write_bytes=wbts, dispatches=len(fb[k]), name=k)
+    open(os.path.join(out, "pair_pipeline_mid72_hbm_counters.md"), "w").write("\n".join(lines) + "\n")
+    json.dump(dict(source_digest=bench.source_digest(), fetch_factor=ff, write_factor=wf,
+                   kernels=kernels, note="FP32 form, bytes per dispatch averaged over one step"),
+              open(os.path.join(out, "pair_pipeline_mid72_traffic.json"), "w"), indent=1)
+
+
+def main():
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    ap = argparse.ArgumentParser()
+    for a in ("trace", "fetch", "write", "copy-fetch", "copy-write", "bench-json"):
+        ap.add_argument("--" + a, required=True)
+    ap.add_argument("--out", default="profiles")
+    args = ap.parse_args()
+    pre = "cd /tmp && export TMPDIR=/tmp"
+    commands = {
+        "trace": pre + "\nrocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/trace_bench "
+                       "-o run -- python3 $REPO/bench.py",
+        "pmc": [pre] + [
+            f"timeout -s KILL {t} rocprofv3 --pmc {c} --output-format csv -d $REPO/gpurun_out/{d} -o run -- "
+            f"python3 $REPO/bench.py {a}"
+            for t, c, d, a in ((120, "FETCH_SIZE", "pmc_fetch_copy", "--calibrate-copy"),
+                               (120, "WRITE_SIZE", "pmc_write_copy", "--calibrate-copy"),
+                               (300, "FETCH_SIZE", "pmc_fetch_bench", "--steps 1 --warmup 0 --no-fp64 --no-cpu"),
+                               (300, "WRITE_SIZE", "pmc_write_bench", "--steps 1 --warmup 0 --no-fp64 --no-cpu"))],
+    }
+    summarize(args.trace, args.fetch, args.write, args.copy_fetch, args.copy_write, args.bench_json,
+              args.out, commands)
+
+
+if __name__ == "__main__":
+    main()
