@@ -196,6 +196,57 @@ px_status px_set_profiling(px_context* ctx, int32_t enable);
 px_status px_profile_read(px_context* ctx, double* ms, double* bytes, int64_t* launches,
                           int32_t reset);
 
+/* One instance of the batched form: the exchange operator of an orbital block
+ * applied to the same block (Phi = Psi), optionally followed by its ACE
+ * construction.  Arrays as in px_exchange_apply / px_ace_build, element type
+ * of the call's precision. */
+typedef struct {
+  px_cell cell;
+  int32_t n;               /* orbitals */
+  const void* psi;         /* [n][N_g] */
+  const double* occ;       /* [n] */
+  const double* kernel_G;  /* [N_g] FP64 */
+  void* out;               /* Vx psi (ace == 0) or xi (ace != 0), [n][N_g] */
+  double* e_x;             /* nullable: exchange energy */
+  double* M;               /* nullable, ace only: Hermitised M, complex128 [n][n] */
+  int32_t* status;         /* ace only, required: Cholesky status word */
+} px_instance;
+
+/* Workspace for px_exchange_apply_batched with these instances (0 if invalid). */
+size_t px_workspace_bytes_batched(const px_context* ctx, int32_t n_inst, const px_instance* inst,
+                                  px_precision prec, int32_t ace);
+
+/* Batched form (Sec. III-B(b) batches pairs to fill the GPU): all block pairs
+ * of all instances (Hermitian-pair mode, square blocks from the tuning) are
+ * grouped by grid size and scheduled by block diagonal, so each pass runs as
+ * one launch over a task table for many chunks of many instances; then the
+ * per-instance energies and, with ace != 0, the ACE construction.  The whole
+ * call is captured once into a HIP graph and replayed while the instance
+ * descriptors, the workspace and the tuning stay the same (rebuilding it
+ * synchronises `stream` once).  Results equal those of per-instance
+ * px_exchange_apply / px_ace_build calls up to summation order. */
+px_status px_exchange_apply_batched(px_context* ctx, int32_t n_inst, const px_instance* inst,
+                                    px_precision prec, int32_t ace, hipStream_t stream);
+
+/* Pair-buffer bytes of one wave of the batched form (0 = default 4 GiB). */
+px_status px_set_batch_capacity(px_context* ctx, size_t pair_buffer_bytes);
+
+/* Graph capture of the batched form on (default) or off (direct enqueue). */
+px_status px_set_graph(px_context* ctx, int32_t enable);
+
+/* Autotuner: times the Hermitian-pair pipeline on this instance (Phi = Psi)
+ * for square pair blocks B in {8, 16, 24, 32, 48, 64} that fit the attached
+ * workspace, keeps the fastest as the context's tuning for this grid and
+ * precision, writes it to *best_block (nullable) and appends a JSON line to
+ * cache_path (nullable).  Synchronises `stream`; `out` receives Vx psi. */
+px_status px_autotune(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                      const void* psi, const double* occ, const double* kernel_G, void* out,
+                      const char* cache_path, int32_t* best_block, hipStream_t stream);
+
+/* Applies the tuning lines of a px_autotune cache file (last entry per grid
+ * and precision wins); *applied (nullable) receives the number of lines used. */
+px_status px_load_tuning(px_context* ctx, const char* cache_path, int32_t* applied);
+
 /* Synchronises `stream`, then reads the status word of the last px_ace_build
  * on this context: PX_ERR_NOT_POSITIVE_DEFINITE if it reported a breakdown
  * (the error stays latched until px_clear_error), PX_ERR_DEVICE on a HIP error. */

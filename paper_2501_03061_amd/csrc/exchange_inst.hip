@@ -8,5 +8,5 @@
 
 namespace px {
 template hipError_t launch_chunk_n<PX_N>(bool, const ChunkArgs&, int, bool, hipStream_t,
-                                         hipEvent_t*);
+                                         hipEvent_t*, const ChunkArgs*, int, int);
 }

@@ -108,7 +108,9 @@ __device__ __forceinline__ void gather(cpx<T> (&v)[BPT][R], F&& load) {
 // out of place and the buffers swap roles each pair, so a slab costs three
 // barriers; otherwise the middle stages run in place (two barriers each).
 template <typename T, int N0, int N1, int NT, bool G0, bool PF>
-__global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
+__global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs* tasks) {
+  const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
+  if (int(blockIdx.y) >= a.ic) return;
   constexpr bool PP = pingpong_fits<T, N0, N1>();
   constexpr int P0 = N0 + 1;  // odd row pitch: no bank conflicts on stride-R writes
   constexpr int SL = N1 * P0;
@@ -242,7 +244,9 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a) {
 
 // ============================================================== pass 2
 template <typename T, int N0, int N1, int N2, int NT, bool G0, bool EX>
-__global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
+__global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
+  const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
+  if (int(blockIdx.y) >= a.ic * a.jc) return;
   constexpr int P0 = N0 + 1;
   __shared__ cpx<T> lds[N2 * P0];
   __shared__ cpx<T> tw2[N2];
@@ -398,7 +402,9 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a) {
 // PF: prefetch the next pair slab and the next psi_j slab during the transform.
 // PP as in pass 1.
 template <typename T, int N0, int N1, int NT, bool PF>
-__global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a) {
+__global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const ChunkArgs* tasks) {
+  const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
+  if (int(blockIdx.y) >= a.ic) return;
   constexpr bool PP = pingpong_fits<T, N0, N1>();
   constexpr int P0 = N0 + 1;
   constexpr int SL = N1 * P0;
@@ -549,32 +555,38 @@ template <typename T, int N> constexpr bool prefetch3_for() {
   return sizeof(T) == 4 ? N <= 80 : N <= 48;
 }
 
-// Pass 1, 2, 3 of one chunk for the cubic grid N^3.  The FP32 form always
-// takes the G = 0 coefficient from FP64 slab sums.
+// Pass 1, 2, 3 for the cubic grid N^3: one chunk (tasks == nullptr, the
+// chunk in `a`), or ntasks chunks of a task table in device memory, one per
+// blockIdx.z (max_ic / max_pairs: the largest chunk of the table).  The FP32
+// form always takes the G = 0 coefficient from FP64 slab sums.
 // ev (optional, 4 events) brackets the passes: ev[0] | pass 1 | ev[1] | pass 2 | ev[2] | pass 3 | ev[3].
 template <int N>
 hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
-                          hipEvent_t* ev) {
+                          hipEvent_t* ev, const ChunkArgs* tasks, int ntasks, int max_ic) {
   constexpr int NT = threads_for<N>();
-  dim3 g1(N, a.ic), g2(N, npairs), g3(N, a.ic);
+  if (!tasks) {
+    ntasks = 1;
+    max_ic = a.ic;
+  }
+  dim3 g1(N, max_ic, ntasks), g2(N, npairs, ntasks), g3(N, max_ic, ntasks);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (fp32)
-    hipLaunchKernelGGL((pass1_fwd_xy<float, N, N, NT, true, prefetch1_for<float, N>()>), g1, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((pass1_fwd_xy<float, N, N, NT, true, prefetch1_for<float, N>()>), g1, dim3(NT), 0, s, a, tasks);
   else
-    hipLaunchKernelGGL((pass1_fwd_xy<double, N, N, NT, false, prefetch1_for<double, N>()>), g1, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((pass1_fwd_xy<double, N, N, NT, false, prefetch1_for<double, N>()>), g1, dim3(NT), 0, s, a, tasks);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (fp32) {
-    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, true>), g2, dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, false>), g2, dim3(NT), 0, s, a);
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, true>), g2, dim3(NT), 0, s, a, tasks);
+    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, false>), g2, dim3(NT), 0, s, a, tasks);
   } else {
-    if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, true>), g2, dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, false>), g2, dim3(NT), 0, s, a);
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, true>), g2, dim3(NT), 0, s, a, tasks);
+    else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, false>), g2, dim3(NT), 0, s, a, tasks);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
   if (fp32)
-    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT, prefetch3_for<float, N>()>), g3, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT, prefetch3_for<float, N>()>), g3, dim3(NT), 0, s, a, tasks);
   else
-    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT, prefetch3_for<double, N>()>), g3, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT, prefetch3_for<double, N>()>), g3, dim3(NT), 0, s, a, tasks);
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError();
 }

@@ -122,6 +122,44 @@ hipError_t launch_expart_reduce(const double* expart, const G0Part* g0, int n1, 
   return hipGetLastError();
 }
 
+// The same reduction for every chunk of a task table (S, its stride and the
+// mirror flag taken from each task).
+__global__ void expart_reduce_tasks_k(const ChunkArgs* tasks, int fp32, int n1, int n2, double ng) {
+  const ChunkArgs& a = tasks[blockIdx.y];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.ic * a.jc) return;
+  const int ii = p / a.jc, jj = p % a.jc;
+  double s = 0.0;
+  if (!fp32) {
+    for (int y = 0; y < n1; ++y) s += a.expart[size_t(p) * n1 + y];
+  } else {
+    double x = 0.0, b = 0.0, e0 = 0.0;
+    for (int y = 0; y < n1; ++y) {
+      const double* e = a.expart + (size_t(p) * n1 + y) * 3;
+      x += e[0];
+      b += e[1];
+      e0 += e[2];
+    }
+    double sr = 0.0, si = 0.0, er = 0.0;
+    for (int z = 0; z < n2; ++z) {
+      sr += a.g0[size_t(p) * n2 + z].re;
+      si += a.g0[size_t(p) * n2 + z].im;
+      er += a.g0[size_t(p) * n2 + z].en;
+    }
+    const double target = ng * er - (sr * sr + si * si);
+    s = e0 + (b > 0.0 && target > 0.0 ? x * (target / b) : x);
+  }
+  a.S[size_t(a.i0 + ii) * a.s_ld + (a.j0 + jj)] = s;
+  if (a.store_v) a.S[size_t(a.j0 + jj) * a.s_ld + (a.i0 + ii)] = s;
+}
+
+hipError_t launch_expart_reduce_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_pairs,
+                                      int n1, int n2, double ng, hipStream_t s) {
+  hipLaunchKernelGGL(expart_reduce_tasks_k, dim3((max_pairs + 255) / 256, ntasks), dim3(256), 0, s,
+                     tasks, int(fp32), n1, n2, ng);
+  return hipGetLastError();
+}
+
 // e_x = scale * sum_i f_i sum_j f_j S[i][j]; one block, fixed summation order.
 __global__ __launch_bounds__(256) void energy_k(const double* S, const double* occ, int n,
                                                 double scale, double* e_x) {

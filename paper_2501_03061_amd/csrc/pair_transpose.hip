@@ -29,10 +29,12 @@ template <typename T> __device__ __forceinline__ cpx<T> ld2nt(const cpx<T>* p) {
 constexpr int JB = 16;
 
 template <typename T>
-__global__ __launch_bounds__(256) void pass4_transpose_acc(ChunkArgs a, size_t ng) {
+__global__ __launch_bounds__(256) void pass4_transpose_acc(ChunkArgs a0, const ChunkArgs* tasks,
+                                                           size_t ng) {
+  const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
   const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
   const int j0 = blockIdx.y * JB;
-  if (e >= ng) return;
+  if (!a.store_v || j0 >= a.jc || e >= ng) return;
   const int nj = (a.jc - j0) < JB ? (a.jc - j0) : JB;
   const cpx<T>* psi = reinterpret_cast<const cpx<T>*>(a.psi);
   const cpx<T>* t = reinterpret_cast<const cpx<T>*>(a.t);
@@ -69,8 +71,18 @@ __global__ __launch_bounds__(256) void pass4_transpose_acc(ChunkArgs a, size_t n
 
 hipError_t launch_pass4(bool fp32, const ChunkArgs& a, size_t ng, hipStream_t s) {
   dim3 grid(unsigned((ng + 255) / 256), (a.jc + JB - 1) / JB);
-  if (fp32) hipLaunchKernelGGL(pass4_transpose_acc<float>, grid, dim3(256), 0, s, a, ng);
-  else hipLaunchKernelGGL(pass4_transpose_acc<double>, grid, dim3(256), 0, s, a, ng);
+  const ChunkArgs* none = nullptr;
+  if (fp32) hipLaunchKernelGGL(pass4_transpose_acc<float>, grid, dim3(256), 0, s, a, none, ng);
+  else hipLaunchKernelGGL(pass4_transpose_acc<double>, grid, dim3(256), 0, s, a, none, ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass4_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_jc, size_t ng,
+                              hipStream_t s) {
+  dim3 grid(unsigned((ng + 255) / 256), (max_jc + JB - 1) / JB, ntasks);
+  ChunkArgs dummy{};
+  if (fp32) hipLaunchKernelGGL(pass4_transpose_acc<float>, grid, dim3(256), 0, s, dummy, tasks, ng);
+  else hipLaunchKernelGGL(pass4_transpose_acc<double>, grid, dim3(256), 0, s, dummy, tasks, ng);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -20,7 +21,7 @@ struct px_context {
   std::string err = "";
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  int32_t* last_status = nullptr;  // device status word of the last ACE build
+  std::vector<int32_t*> last_status;  // device status words of the last ACE build(s)
   int latched = PX_OK;
   std::map<std::tuple<int, int, int, int>, std::pair<int, int>> tuning;  // (n0,n1,n2,prec) -> (ic, jc)
   // measurement mode: HIP events around each pass of each chunk
@@ -30,8 +31,20 @@ struct px_context {
   double prof_bytes[4] = {0, 0, 0, 0};
   int64_t prof_launches[4] = {0, 0, 0, 0};
   bool symmetric_ace = true;  // ACE build solves only pairs j <= i (block level)
+  // batched form: the graph of the last batched call, replayed while the call
+  // signature (instances, pointers, workspace) stays the same
+  bool use_graph = true;
+  size_t batch_cap_bytes = size_t(4) << 30;  // pair buffer of one wave
+  std::vector<unsigned char> graph_key;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  void* pinned_tasks = nullptr;  // host copy of the task table (page-locked)
+  size_t pinned_bytes = 0;
   ~px_context() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (pinned_tasks) (void)hipHostFree(pinned_tasks);
   }
 };
 
@@ -495,7 +508,7 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   st = hip_check(ctx, px::launch_gemm_xc(fp32, n, n, ng, W, U, n, 1.0, xi, true, stream),
                  "xi = W L^-H");
   if (st != PX_OK) return st;
-  ctx->last_status = status;
+  ctx->last_status.assign(1, status);
   return PX_OK;
 }
 
@@ -609,21 +622,486 @@ px_status px_profile_read(px_context* ctx, double* ms, double* bytes, int64_t* l
   return PX_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched form
+namespace {
+
+struct BatchWave {
+  int n;            // cubic grid size of the wave's instances
+  int first, count; // tasks [first, first + count)
+  int max_ic, max_jc, max_pairs;
+  bool any_v;       // some task keeps v_ij (needs pass 4)
+};
+
+struct BatchPlan {
+  size_t tasks_off = 0, t_off = 0, g0_off = 0, ex_off = 0;
+  std::vector<size_t> S_off, W_off;
+  size_t M_off = 0, L_off = 0, U_off = 0, dinv_off = 0, part_off = 0, end = 0;
+  std::vector<px::ChunkArgs> tasks;
+  std::vector<BatchWave> waves;
+};
+
+int block_for(const px_context* c, const px_cell* cell, px_precision prec) {
+  int ic, jc;
+  tuning_for(c, cell, prec, &ic, &jc);
+  return ic > jc ? ic : jc;
+}
+
+// Plan of one batched call.  Instances are grouped by grid size; within a
+// size the block pairs (I, J <= I) of every instance are scheduled by block
+// diagonal d = I - J, so that one launch never has two chunks writing the
+// same output block (pass 3 writes block I, pass 4 block J): d = 0 first
+// (those chunks initialise the output), then d = 1, 2, ...  A diagonal's
+// chunks are packed into waves that fit the pair buffer.  ws == nullptr:
+// sizes only.
+BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_precision prec,
+                     bool ace, char* ws) {
+  BatchPlan P;
+  const bool fp32 = prec == PX_PREC_FP32;
+  const size_t b = elem_bytes(prec);
+  int max_n = 0;
+  for (int k = 0; k < n_inst; ++k) max_n = std::max(max_n, int(in[k].n));
+  // pair-buffer capacity per grid size: batch_cap_bytes, at least one block
+  int max_block = 1;
+  for (int k = 0; k < n_inst; ++k) max_block = std::max(max_block, block_for(c, &in[k].cell, prec));
+  const size_t min_pairs = size_t(max_block) * max_block;
+  size_t t_bytes = 0, side_pairs = 0;  // sizes of the pair buffer and of the per-plane partials
+  // schedule
+  std::vector<int> sizes;
+  for (int k = 0; k < n_inst; ++k)
+    if (std::find(sizes.begin(), sizes.end(), in[k].cell.n[0]) == sizes.end())
+      sizes.push_back(in[k].cell.n[0]);
+  std::sort(sizes.begin(), sizes.end());
+  struct Chunk { int inst, I, J, B; };
+  for (int nsz : sizes) {
+    int max_nb = 0;
+    for (int k = 0; k < n_inst; ++k)
+      if (in[k].cell.n[0] == nsz) {
+        const int B = block_for(c, &in[k].cell, prec);
+        max_nb = std::max(max_nb, (int(in[k].n) + B - 1) / B);
+      }
+    const size_t ng = size_t(nsz) * nsz * nsz;
+    const size_t cap = std::max(min_pairs, c->batch_cap_bytes / (ng * b));
+    t_bytes = std::max(t_bytes, cap * ng * b);
+    side_pairs = std::max(side_pairs, cap * size_t(nsz));
+    for (int d = 0; d < max_nb; ++d) {
+      std::vector<Chunk> diag;
+      for (int k = 0; k < n_inst; ++k) {
+        if (in[k].cell.n[0] != nsz) continue;
+        const int B = block_for(c, &in[k].cell, prec);
+        const int nb = (int(in[k].n) + B - 1) / B;
+        for (int J = 0; J + d < nb; ++J) diag.push_back({k, J + d, J, B});
+      }
+      size_t used = cap;  // forces a new wave at the first chunk
+      for (const Chunk& ch : diag) {
+        const int n = in[ch.inst].n;
+        const int icc = std::min(ch.B, n - ch.I * ch.B), jcc = std::min(ch.B, n - ch.J * ch.B);
+        const size_t pairs = size_t(icc) * jcc;
+        if (used + pairs > cap) {
+          P.waves.push_back({nsz, int(P.tasks.size()), 0, 0, 0, 0, false});
+          used = 0;
+        }
+        BatchWave& w = P.waves.back();
+        px::ChunkArgs a{};
+        a.i0 = ch.I * ch.B;
+        a.ic = icc;
+        a.j0 = ch.J * ch.B;
+        a.jc = jcc;
+        a.first = d == 0;
+        a.store_v = d > 0;
+        a.n2 = nsz;
+        a.inv_ng = 1.0 / double(ng);
+        a.s_ld = n;
+        // pointers are filled below once the layout is known; keep the
+        // within-wave pair offset in t (as an integer) until then
+        a.t = reinterpret_cast<void*>(used);
+        a.psi = a.phi = in[ch.inst].psi;
+        a.occ = in[ch.inst].occ;
+        a.kern = in[ch.inst].kernel_G;
+        a.S = reinterpret_cast<double*>(size_t(ch.inst));  // instance index until layout
+        P.tasks.push_back(a);
+        w.count++;
+        w.max_ic = std::max(w.max_ic, icc);
+        w.max_jc = std::max(w.max_jc, jcc);
+        w.max_pairs = std::max(w.max_pairs, int(pairs));
+        w.any_v = w.any_v || d > 0;
+        used += pairs;
+      }
+    }
+  }
+  // layout
+  size_t off = 0;
+  P.tasks_off = off;
+  off = align_up(off + P.tasks.size() * sizeof(px::ChunkArgs));
+  P.t_off = off;
+  off = align_up(off + t_bytes);
+  P.g0_off = off;
+  if (fp32) off = align_up(off + side_pairs * sizeof(px::G0Part));
+  P.ex_off = off;
+  off = align_up(off + side_pairs * 8 * (fp32 ? 3 : 1));
+  P.S_off.resize(n_inst);
+  P.W_off.resize(n_inst);
+  for (int k = 0; k < n_inst; ++k) {
+    P.S_off[k] = off;
+    off = align_up(off + size_t(in[k].n) * in[k].n * 8);
+  }
+  if (ace) {
+    for (int k = 0; k < n_inst; ++k) {
+      P.W_off[k] = off;
+      off = align_up(off + size_t(in[k].n) * ngrid(&in[k].cell) * b);
+    }
+    P.M_off = off;
+    off = align_up(off + size_t(max_n) * max_n * 16);
+    P.L_off = off;
+    off = align_up(off + size_t(max_n) * max_n * 16);
+    P.U_off = off;
+    off = align_up(off + size_t(max_n) * max_n * 16);
+    P.dinv_off = off;
+    off = align_up(off + 32 * 32 * 16);
+    size_t part = 0;
+    for (int k = 0; k < n_inst; ++k) {
+      int ns = 0;
+      part = std::max(part, px::gemm_xhy_part_elems(in[k].n, in[k].n, ngrid(&in[k].cell), &ns));
+    }
+    P.part_off = off;
+    off = align_up(off + part * 16);
+  }
+  P.end = off;
+  if (ws) {
+    for (const BatchWave& w : P.waves) {
+      const size_t ng = size_t(w.n) * w.n * w.n;
+      for (int t = w.first; t < w.first + w.count; ++t) {
+        px::ChunkArgs& a = P.tasks[t];
+        const size_t pofs = reinterpret_cast<size_t>(a.t);
+        const int k = int(reinterpret_cast<size_t>(a.S));
+        a.t = ws + P.t_off + pofs * ng * b;
+        a.g0 = reinterpret_cast<px::G0Part*>(ws + P.g0_off + pofs * w.n * sizeof(px::G0Part));
+        a.expart = reinterpret_cast<double*>(ws + P.ex_off + pofs * w.n * 8 * (fp32 ? 3 : 1));
+        a.S = reinterpret_cast<double*>(ws + P.S_off[k]);
+        a.out = ace ? static_cast<void*>(ws + P.W_off[k]) : in[k].out;
+      }
+    }
+  }
+  return P;
+}
+
+px_status check_instances(px_context* c, int n_inst, const px_instance* in, px_precision prec,
+                          bool ace) {
+  if (n_inst <= 0 || !in) return fail(c, PX_ERR_INVALID_ARG, "batched: need n_inst > 0 instances");
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(c, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  for (int k = 0; k < n_inst; ++k) {
+    const px_instance& x = in[k];
+    px_status st = check_grid(c, &x.cell);
+    if (st != PX_OK) return fail(c, st, "instance %d: %s", k, c->err.c_str());
+    if (x.n <= 0) return fail(c, PX_ERR_INVALID_ARG, "instance %d: n must be > 0", k);
+    if (!x.psi || !x.occ || !x.kernel_G || !x.out)
+      return fail(c, PX_ERR_INVALID_ARG, "instance %d: null array argument", k);
+    if (x.out == x.psi) return fail(c, PX_ERR_INVALID_ARG, "instance %d: out aliases psi", k);
+    if (ace && !x.status)
+      return fail(c, PX_ERR_INVALID_ARG, "instance %d: ACE mode needs a status word", k);
+  }
+  return PX_OK;
+}
+
+// Everything of one batched call, stream ordered on s.
+px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_instance* in,
+                        px_precision prec, bool ace, const void* host_tasks, hipStream_t s) {
+  const bool fp32 = prec == PX_PREC_FP32;
+  char* ws = c->ws;
+  const px::ChunkArgs* dt = reinterpret_cast<const px::ChunkArgs*>(ws + P.tasks_off);
+  px_status st = hip_check(c, hipMemcpyAsync(ws + P.tasks_off, host_tasks,
+                                             P.tasks.size() * sizeof(px::ChunkArgs),
+                                             hipMemcpyHostToDevice, s),
+                           "task table upload");
+  if (st != PX_OK) return st;
+  for (const BatchWave& w : P.waves) {
+    const size_t ng = size_t(w.n) * w.n * w.n;
+    st = hip_check(c, px::launch_chunk_tasks(fp32, w.n, dt + w.first, w.count, w.max_ic,
+                                             w.max_pairs, true, s),
+                   "batched pair pipeline");
+    if (st != PX_OK) return st;
+    if (w.any_v) {
+      st = hip_check(c, px::launch_pass4_tasks(fp32, dt + w.first, w.count, w.max_jc, ng, s),
+                     "batched transposed accumulation");
+      if (st != PX_OK) return st;
+    }
+    st = hip_check(c, px::launch_expart_reduce_tasks(fp32, dt + w.first, w.count, w.max_pairs, w.n,
+                                                     w.n, double(ng), s),
+                   "batched energy partials");
+    if (st != PX_OK) return st;
+  }
+  for (int k = 0; k < n_inst; ++k) {
+    const px_instance& x = in[k];
+    const size_t ng = ngrid(&x.cell);
+    const double omega = x.cell.L[0] * x.cell.L[1] * x.cell.L[2];
+    const double* S = reinterpret_cast<const double*>(ws + P.S_off[k]);
+    if (x.e_x) {
+      st = hip_check(c, px::launch_energy(S, x.occ, x.n, -0.5 * omega / (double(ng) * double(ng)),
+                                          x.e_x, s),
+                     "batched energy");
+      if (st != PX_OK) return st;
+    }
+    if (!ace) continue;
+    const double dV = omega / double(ng);
+    void* W = ws + P.W_off[k];
+    double* Mw = x.M ? x.M : reinterpret_cast<double*>(ws + P.M_off);
+    int nsplit = 0;
+    px::gemm_xhy_part_elems(x.n, x.n, ng, &nsplit);
+    st = hip_check(c, px::launch_gemm_xhy(fp32, x.n, x.n, ng, x.psi, W, dV, Mw, x.n,
+                                          reinterpret_cast<double*>(ws + P.part_off), nsplit, s),
+                   "batched M");
+    if (st != PX_OK) return st;
+    st = hip_check(c, px::launch_hermitize(Mw, x.n, s), "batched hermitize");
+    if (st != PX_OK) return st;
+    st = hip_check(c, px::launch_chol_inv(Mw, x.n, reinterpret_cast<double*>(ws + P.L_off),
+                                          reinterpret_cast<double*>(ws + P.U_off), x.status,
+                                          reinterpret_cast<double*>(ws + P.dinv_off), s),
+                   "batched cholesky");
+    if (st != PX_OK) return st;
+    st = hip_check(c, px::launch_gemm_xc(fp32, x.n, x.n, ng, W,
+                                         reinterpret_cast<double*>(ws + P.U_off), x.n, 1.0, x.out,
+                                         true, s),
+                   "batched xi");
+    if (st != PX_OK) return st;
+  }
+  return PX_OK;
+}
+
+std::vector<unsigned char> batch_key(const px_context* c, int n_inst, const px_instance* in,
+                                     px_precision prec, bool ace) {
+  std::vector<unsigned char> key;
+  auto put = [&key](const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    key.insert(key.end(), b, b + n);
+  };
+  put(&n_inst, sizeof n_inst);
+  put(&prec, sizeof prec);
+  put(&ace, sizeof ace);
+  put(&c->ws, sizeof c->ws);
+  put(&c->ws_bytes, sizeof c->ws_bytes);
+  put(&c->batch_cap_bytes, sizeof c->batch_cap_bytes);
+  for (int k = 0; k < n_inst; ++k) {
+    put(&in[k], sizeof(px_instance));
+    const int B = block_for(c, &in[k].cell, prec);
+    put(&B, sizeof B);
+  }
+  return key;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t px_workspace_bytes_batched(const px_context* ctx, int32_t n_inst, const px_instance* inst,
+                                  px_precision prec, int32_t ace) {
+  if (!ctx || n_inst <= 0 || !inst) return 0;
+  for (int k = 0; k < n_inst; ++k)
+    if (!cell_ok(&inst[k].cell) || inst[k].n <= 0 ||
+        !px::grid_supported(inst[k].cell.n[0], inst[k].cell.n[1], inst[k].cell.n[2]))
+      return 0;
+  return plan_batch(ctx, n_inst, inst, prec, ace != 0, nullptr).end;
+}
+
+px_status px_set_batch_capacity(px_context* ctx, size_t pair_buffer_bytes) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  ctx->batch_cap_bytes = pair_buffer_bytes ? pair_buffer_bytes : (size_t(4) << 30);
+  return PX_OK;
+}
+
+px_status px_set_graph(px_context* ctx, int32_t enable) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  ctx->use_graph = enable != 0;
+  return PX_OK;
+}
+
+px_status px_exchange_apply_batched(px_context* ctx, int32_t n_inst, const px_instance* inst,
+                                    px_precision prec, int32_t ace, hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  px_status st = check_instances(ctx, n_inst, inst, prec, ace != 0);
+  if (st != PX_OK) return st;
+  BatchPlan P = plan_batch(ctx, n_inst, inst, prec, ace != 0, nullptr);
+  st = need_ws(ctx, P.end);
+  if (st != PX_OK) return st;
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  P = plan_batch(ctx, n_inst, inst, prec, ace != 0, ctx->ws);
+  const size_t tbytes = P.tasks.size() * sizeof(px::ChunkArgs);
+  if (ace) {
+    ctx->last_status.clear();
+    for (int k = 0; k < n_inst; ++k) ctx->last_status.push_back(inst[k].status);
+  }
+  std::vector<unsigned char> key = batch_key(ctx, n_inst, inst, prec, ace != 0);
+  if (ctx->use_graph && ctx->graph_exec && key == ctx->graph_key)
+    return hip_check(ctx, hipGraphLaunch(ctx->graph_exec, stream), "hipGraphLaunch");
+  // new signature: (re)build the page-locked task table; wait for work that
+  // may still read the old one
+  if (ctx->pinned_tasks) {
+    he = hipStreamSynchronize(stream);
+    if (he != hipSuccess) return hip_check(ctx, he, "hipStreamSynchronize");
+  }
+  if (ctx->pinned_bytes < tbytes) {
+    if (ctx->pinned_tasks) (void)hipHostFree(ctx->pinned_tasks);
+    ctx->pinned_tasks = nullptr;
+    ctx->pinned_bytes = 0;
+    he = hipHostMalloc(&ctx->pinned_tasks, tbytes, hipHostMallocDefault);
+    if (he != hipSuccess) return hip_check(ctx, he, "hipHostMalloc (task table)");
+    ctx->pinned_bytes = tbytes;
+  }
+  std::memcpy(ctx->pinned_tasks, P.tasks.data(), tbytes);
+  if (!ctx->use_graph) return enqueue_batch(ctx, P, n_inst, inst, prec, ace != 0, ctx->pinned_tasks, stream);
+  if (!ctx->cap_stream) {
+    he = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+    if (he != hipSuccess) return hip_check(ctx, he, "hipStreamCreate (capture)");
+  }
+  if (ctx->graph_exec) {
+    (void)hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+    ctx->graph_key.clear();
+  }
+  he = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipStreamBeginCapture");
+  st = enqueue_batch(ctx, P, n_inst, inst, prec, ace != 0, ctx->pinned_tasks, ctx->cap_stream);
+  hipGraph_t g = nullptr;
+  he = hipStreamEndCapture(ctx->cap_stream, &g);
+  if (st != PX_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (he != hipSuccess) return hip_check(ctx, he, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  he = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipGraphInstantiate");
+  ctx->graph_exec = ex;
+  ctx->graph_key = key;
+  return hip_check(ctx, hipGraphLaunch(ex, stream), "hipGraphLaunch");
+}
+
+// Times the symmetric pair pipeline for square blocks B in the candidate list
+// on the caller's instance, keeps the fastest as the context's tuning for this
+// grid and precision, and appends it to cache_path (JSON lines) when given.
+px_status px_autotune(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                      const void* psi, const double* occ, const double* kernel_G, void* out,
+                      const char* cache_path, int32_t* best_block, hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  px_status st = check_grid(ctx, cell);
+  if (st != PX_OK) return st;
+  if (n <= 0 || !psi || !occ || !kernel_G || !out || out == psi)
+    return fail(ctx, PX_ERR_INVALID_ARG, "autotune: need n > 0 and valid, non-aliased arrays");
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  const int cand[] = {8, 16, 24, 32, 48, 64};
+  const auto key = std::make_tuple(cell->n[0], cell->n[1], cell->n[2], int(prec));
+  const auto saved = ctx->tuning.count(key) ? ctx->tuning[key] : std::make_pair(0, 0);
+  const bool had = ctx->tuning.count(key) != 0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(ctx, PX_ERR_DEVICE, "hipEventCreate failed");
+  double best = 1e300;
+  int bestB = 0;
+  std::string trials;
+  for (int B : cand) {
+    if (B > n && B != cand[0]) break;
+    const ExLayout l = ex_layout(cell, prec, n, n, B, B, false);
+    if (ctx->ws == nullptr || ctx->ws_bytes < l.end) continue;
+    float ms = 0.f, best_ms = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      (void)hipEventRecord(e0, stream);
+      st = run_exchange(ctx, cell, prec, n, psi, occ, n, psi, kernel_G, out, l, false, B, B, true,
+                        stream);
+      (void)hipEventRecord(e1, stream);
+      if (st != PX_OK) break;
+      he = hipEventSynchronize(e1);
+      if (he != hipSuccess) {
+        st = hip_check(ctx, he, "autotune sync");
+        break;
+      }
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) best_ms = std::min(best_ms, ms);  // first run warms up
+    }
+    if (st != PX_OK) break;
+    const double us_pair = 1e3 * best_ms / (double(n) * n);
+    char buf[64];
+    snprintf(buf, sizeof buf, "%s\"%d\": %.4f", trials.empty() ? "" : ", ", B, us_pair);
+    trials += buf;
+    if (us_pair < best) {
+      best = us_pair;
+      bestB = B;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != PX_OK) return st;
+  if (bestB == 0) {
+    if (had) ctx->tuning[key] = saved;
+    return fail(ctx, PX_ERR_WORKSPACE, "autotune: workspace too small for every candidate block");
+  }
+  ctx->tuning[key] = {bestB, bestB};
+  if (best_block) *best_block = bestB;
+  if (cache_path && cache_path[0]) {
+    FILE* f = fopen(cache_path, "a");
+    if (!f) return fail(ctx, PX_ERR_INVALID_ARG, "autotune: cannot open %s", cache_path);
+    fprintf(f,
+            "{\"arch\": \"gfx950\", \"n\": [%d, %d, %d], \"prec\": \"%s\", \"n_orb\": %d, "
+            "\"block\": %d, \"us_per_pair\": %.4f, \"trials_us_per_pair\": {%s}}\n",
+            cell->n[0], cell->n[1], cell->n[2], prec == PX_PREC_FP32 ? "fp32" : "fp64", n, bestB,
+            best, trials.c_str());
+    fclose(f);
+  }
+  return PX_OK;
+}
+
+// Reads the JSON lines written by px_autotune; the last entry per (grid,
+// precision) wins.  Returns the number of entries applied in *applied.
+px_status px_load_tuning(px_context* ctx, const char* cache_path, int32_t* applied) {
+  if (!ctx || !cache_path) return PX_ERR_INVALID_ARG;
+  FILE* f = fopen(cache_path, "r");
+  if (!f) return fail(ctx, PX_ERR_INVALID_ARG, "load_tuning: cannot open %s", cache_path);
+  char line[4096];
+  int count = 0;
+  while (fgets(line, sizeof line, f)) {
+    int n0, n1, n2, blk;
+    char prec[8] = {0};
+    const char* pn = strstr(line, "\"n\": [");
+    const char* pp = strstr(line, "\"prec\": \"");
+    const char* pb = strstr(line, "\"block\": ");
+    if (!pn || !pp || !pb) continue;
+    if (sscanf(pn, "\"n\": [%d, %d, %d]", &n0, &n1, &n2) != 3) continue;
+    if (sscanf(pp, "\"prec\": \"%4[a-z0-9]\"", prec) != 1) continue;
+    if (sscanf(pb, "\"block\": %d", &blk) != 1 || blk <= 0 || blk > 4096) continue;
+    const int pr = strcmp(prec, "fp32") == 0 ? int(PX_PREC_FP32) : int(PX_PREC_FP64);
+    ctx->tuning[std::make_tuple(n0, n1, n2, pr)] = {blk, blk};
+    ++count;
+  }
+  fclose(f);
+  if (applied) *applied = count;
+  return PX_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
 px_status px_sync(px_context* ctx, hipStream_t stream) {
   if (!ctx) return PX_ERR_INVALID_ARG;
   hipError_t e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_check(ctx, e, "hipStreamSynchronize");
-  if (ctx->last_status) {
+  for (size_t k = 0; k < ctx->last_status.size(); ++k) {
     int32_t s = 0;
-    e = hipMemcpy(&s, ctx->last_status, sizeof s, hipMemcpyDeviceToHost);
+    e = hipMemcpy(&s, ctx->last_status[k], sizeof s, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_check(ctx, e, "status readback");
-    ctx->last_status = nullptr;
-    if (s != 0) {
+    if (s != 0 && ctx->latched == PX_OK) {
       ctx->latched = PX_ERR_NOT_POSITIVE_DEFINITE;
       fail(ctx, PX_ERR_NOT_POSITIVE_DEFINITE,
-           "ace_build: -M is not positive definite (Cholesky breakdown at column %d)", s);
+           "ace_build (instance %zu): -M is not positive definite (Cholesky breakdown at column %d)",
+           k, s);
     }
   }
+  ctx->last_status.clear();
   return px_status(ctx->latched);
 }
 

@@ -29,6 +29,8 @@ struct ChunkArgs {
   int n2;
   int i0, ic, j0, jc;
   int first;            // pass 3 overwrites the output instead of accumulating
+  double* S;            // pair-energy matrix of the instance (task-table mode)
+  int s_ld;             // its row stride
   int store_v;          // pass 3 also writes N_g * v_ij back into the pair slab (symmetric mode)
   double inv_ng;
 };
@@ -38,6 +40,17 @@ bool grid_supported(int n0, int n1, int n2);
 // before pass 1, between the passes and after pass 3.
 hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
                         hipEvent_t* ev);
+
+// The same passes over a task table in device memory (ntasks chunks of one
+// grid size, all with ic <= max_ic and ic*jc <= max_pairs), one launch each.
+hipError_t launch_chunk_tasks(bool fp32, int n, const ChunkArgs* tasks, int ntasks, int max_ic,
+                              int max_pairs, bool ex, hipStream_t s);
+// Pass 4 over a task table (tasks without kept v_ij are skipped).
+hipError_t launch_pass4_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_jc, size_t ng,
+                              hipStream_t s);
+// Energy partials -> S for every task of a table (see launch_expart_reduce).
+hipError_t launch_expart_reduce_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_pairs,
+                                      int n1, int n2, double ng, hipStream_t s);
 
 // Pass 4 (symmetric mode): out[j] -= sum_i f_i/N_g psi_i conj(v_ij) from the
 // pair slabs that pass 3 left in the pair buffer.

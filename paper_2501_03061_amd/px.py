@@ -32,6 +32,15 @@ class PxCell(ctypes.Structure):
 
 
 _cellp = ctypes.POINTER(PxCell)
+
+
+class PxInstance(ctypes.Structure):
+    _fields_ = [("cell", PxCell), ("n", ctypes.c_int32), ("psi", ctypes.c_void_p),
+                ("occ", ctypes.c_void_p), ("kernel_G", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("e_x", ctypes.c_void_p), ("M", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+_instp = ctypes.POINTER(PxInstance)
 SIGNATURES = {
     "px_abi_version": (_i32, []),
     "px_create": (_i32, [_i32, ctypes.POINTER(_vp)]),
@@ -52,6 +61,13 @@ SIGNATURES = {
     "px_set_profiling": (_i32, [_vp, _i32]),
     "px_profile_read": (_i32, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl),
                                ctypes.POINTER(ctypes.c_int64), _i32]),
+    "px_workspace_bytes_batched": (_sz, [_vp, _i32, _instp, _i32, _i32]),
+    "px_exchange_apply_batched": (_i32, [_vp, _i32, _instp, _i32, _i32, _vp]),
+    "px_set_batch_capacity": (_i32, [_vp, _sz]),
+    "px_set_graph": (_i32, [_vp, _i32]),
+    "px_autotune": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.c_char_p,
+                           ctypes.POINTER(_i32), _vp]),
+    "px_load_tuning": (_i32, [_vp, ctypes.c_char_p, ctypes.POINTER(_i32)]),
     "px_sync": (_i32, [_vp, _vp]),
     "px_clear_error": (None, [_vp]),
 }
@@ -287,6 +303,69 @@ class Context:
         la = (ctypes.c_int64 * 4)()
         self._check(self.lib.px_profile_read(self.h, ms, by, la, 1 if reset else 0))
         return [dict(ms=ms[k], bytes=by[k], launches=la[k]) for k in range(4)]
+
+    def px_exchange_apply_batched(self, instances, ace=False, stream=None):
+        """instances: list of dicts with cell (Cell), psi, occ, kern and optional
+        out, e_x, M, status (torch device tensors).  Returns the list of outputs
+        (Vx psi, or xi with ace=True) and the status tensors (ace)."""
+        import torch
+        if not instances:
+            raise ValueError("need at least one instance")
+        prec = _prec(instances[0]["psi"].dtype)
+        arr = (PxInstance * len(instances))()
+        outs, stats = [], []
+        for k, d in enumerate(instances):
+            cell, psi = d["cell"], d["psi"]
+            _check_block(f"instances[{k}].psi", psi, cell, instances[0]["psi"].dtype)
+            out = d.get("out")
+            if out is None:
+                out = torch.empty_like(psi)
+            st = d.get("status")
+            if ace and st is None:
+                st = torch.zeros(1, dtype=torch.int32, device=psi.device)
+            outs.append(out)
+            stats.append(st)
+            arr[k] = PxInstance(cell.c(), psi.shape[0], psi.data_ptr(), d["occ"].data_ptr(),
+                                d["kern"].data_ptr(), out.data_ptr(),
+                                d["e_x"].data_ptr() if d.get("e_x") is not None else None,
+                                d["M"].data_ptr() if d.get("M") is not None else None,
+                                st.data_ptr() if st is not None else None)
+        need = int(self.lib.px_workspace_bytes_batched(self.h, len(instances), arr, prec, int(ace)))
+        self.ensure_workspace(need)
+        self._check(self.lib.px_exchange_apply_batched(self.h, len(instances), arr, prec, int(ace),
+                                                       _stream(stream)))
+        return outs, stats
+
+    def px_set_graph(self, enable: bool):
+        self._check(self.lib.px_set_graph(self.h, 1 if enable else 0))
+
+    def px_set_batch_capacity(self, nbytes: int):
+        self._check(self.lib.px_set_batch_capacity(self.h, int(nbytes)))
+
+    def px_autotune(self, cell: Cell, psi, occ, kern, out=None, cache_path=None, stream=None):
+        """Returns the fastest square pair block for this grid and precision
+        (also applied to the context)."""
+        import torch
+        prec = _prec(psi.dtype)
+        _check_block("psi", psi, cell)
+        if out is None:
+            out = torch.empty_like(psi)
+        need = max(self.workspace_bytes(PX_OP_EXCHANGE, cell, prec, psi.shape[0], psi.shape[0]), 1)
+        # room for the largest candidate block (64 x 64 pair slabs)
+        b = psi.element_size()
+        need = max(need, 64 * 64 * cell.ng * b + (64 << 20))
+        self.ensure_workspace(need)
+        best = ctypes.c_int32(0)
+        self._check(self.lib.px_autotune(self.h, ctypes.byref(cell.c()), prec, psi.shape[0],
+                                         _ptr(psi), _ptr(occ), _ptr(kern), _ptr(out),
+                                         cache_path.encode() if cache_path else None,
+                                         ctypes.byref(best), _stream(stream)))
+        return best.value
+
+    def px_load_tuning(self, path: str) -> int:
+        n = ctypes.c_int32(0)
+        self._check(self.lib.px_load_tuning(self.h, path.encode(), ctypes.byref(n)))
+        return n.value
 
     def px_sync(self, stream=None):
         """Raises PxError(PX_ERR_NOT_POSITIVE_DEFINITE) after a failed ACE build."""

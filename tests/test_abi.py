@@ -101,7 +101,7 @@ def test_workspace_sizes(lib, ctx):
     ng = 72 ** 3
     b64 = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 0, 512, 512)
     b32 = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 1, 512, 512)
-    # default chunk: 32 x 8 pair slabs dominate
+    # default chunk: 32 x 16 pair slabs dominate
     assert b64 >= 256 * ng * 16 and b32 >= 256 * ng * 8 and b32 < b64
     ace = lib.px_workspace_bytes(ctx, px.PX_OP_ACE_BUILD, ctypes.byref(c), 0, 512, 0)
     assert ace >= b64 + 512 * ng * 16             # plus W
@@ -141,3 +141,44 @@ def test_kernel_and_convert_validation(lib, ctx):
     assert lib.px_kernel_hse(ctx, ctypes.byref(c), 0.106, None, None) == px.PX_ERR_INVALID_ARG
     assert lib.px_convert_c128_to_c64(ctx, 10, None, FAKE, None) == px.PX_ERR_INVALID_ARG
     assert lib.px_convert_c128_to_c64(ctx, 10, ctypes.c_void_p(0x1010), ctypes.c_void_p(0x2000), None) == px.PX_ERR_INVALID_ARG
+
+
+def _inst(n=24, n_orb=4, psi=FAKE, out=ctypes.c_void_p(0x9000), status=None):
+    return px.PxInstance(px.Cell.cubic(n, 10.0).c(), n_orb, psi, FAKE, FAKE, out, None, None, status)
+
+
+def test_batched_validation(lib, ctx):
+    arr = (px.PxInstance * 2)(_inst(), _inst(32))
+    f = lib.px_exchange_apply_batched
+    assert f(ctx, 0, arr, 0, 0, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, 2, None, 0, 0, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, 2, arr, 5, 0, None) == px.PX_ERR_INVALID_ARG
+    bad = (px.PxInstance * 2)(_inst(), _inst(7))
+    assert f(ctx, 2, bad, 0, 0, None) == px.PX_ERR_UNSUPPORTED_GRID
+    alias = (px.PxInstance * 1)(_inst(out=FAKE))
+    assert f(ctx, 1, alias, 0, 0, None) == px.PX_ERR_INVALID_ARG
+    # ACE mode needs a status word per instance
+    assert f(ctx, 2, arr, 0, 1, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, 2, arr, 0, 0, None) == px.PX_ERR_WORKSPACE
+    need = lib.px_workspace_bytes_batched(ctx, 2, arr, 0, 0)
+    assert need > 0
+    assert lib.px_workspace_bytes_batched(ctx, 2, bad, 0, 0) == 0
+    with_ace = (px.PxInstance * 2)(_inst(status=FAKE), _inst(32, status=FAKE))
+    assert lib.px_workspace_bytes_batched(ctx, 2, with_ace, 0, 1) > need
+
+
+def test_load_tuning_cache(lib, ctx, tmp_path):
+    """The cache lines written by the autotuner set the context's pair block."""
+    c = _cell(72, 20.0)
+    base = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 1, 512, 512)
+    path = tmp_path / "tune.jsonl"
+    path.write_text(
+        '{"arch": "gfx950", "n": [72, 72, 72], "prec": "fp32", "n_orb": 512, "block": 8, "us_per_pair": 1.0}\n'
+        'not json at all\n'
+        '{"arch": "gfx950", "n": [48, 48, 48], "prec": "fp64", "n_orb": 100, "block": 16, "us_per_pair": 2.0}\n')
+    n = ctypes.c_int32(0)
+    assert lib.px_load_tuning(ctx, str(path).encode(), ctypes.byref(n)) == px.PX_OK
+    assert n.value == 2
+    tuned = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 1, 512, 512)
+    assert tuned < base                       # 8 x 8 pair block instead of the default
+    assert lib.px_load_tuning(ctx, b"/nonexistent/file", None) == px.PX_ERR_INVALID_ARG
