@@ -169,6 +169,74 @@ def cpu_baseline(inst, kern_np, seconds):
                        f"scipy.fft workers={os.cpu_count()}")
 
 
+def bench_batch48(args):
+    """48 uneven instances (grids {32,40,48,64}^3, 32..256 orbitals): FP32 ACE
+    builds of all of them in one batched, graph-replayed call, against the
+    same builds one instance at a time (FP32 and plain FP64)."""
+    import torch
+    from paper_2501_03061_amd import inputs, px
+    ctx = px.Context(0)
+    t0 = time.perf_counter()
+    recipe = inputs.batch_recipe()
+    insts, args64 = [], []
+    for r in recipe:
+        inst = inputs.make_instance(r["n"], r["L"], r["n_orb"], r["kT"], seed=r["seed"])
+        cell = px.Cell(inst.L, inst.n)
+        args64.append(dict(cell=cell, psi=torch.from_numpy(inst.psi).cuda(),
+                           occ=torch.from_numpy(inst.occ).cuda(), kern=ctx.px_kernel_hse(cell, 0.106)))
+        insts.append((inst.n[0], inst.n_orb))
+        del inst
+    log(f"batch48 inputs in {time.perf_counter() - t0:.1f}s")
+    args32 = [dict(a, psi=ctx.px_convert_c128_to_c64(a["psi"])) for a in args64]
+    for a in args32:
+        a["out"] = torch.empty_like(a["psi"])
+        a["status"] = torch.zeros(1, dtype=torch.int32, device="cuda")
+    blocks = {}
+    for n in sorted(set(i[0] for i in insts)):
+        k = max((i for i, x in enumerate(insts) if x[0] == n), key=lambda i: insts[i][1])
+        blocks[n] = ctx.px_autotune(args32[k]["cell"], args32[k]["psi"], args32[k]["occ"], args32[k]["kern"])
+    log(f"autotuned blocks {blocks}")
+    pairs = sum(n_orb * n_orb for _, n_orb in insts)
+
+    def batched():
+        ctx.px_exchange_apply_batched(args32, ace=True)
+    for _ in range(max(1, args.warmup)):
+        batched()                                  # first call captures the graph
+    torch.cuda.synchronize()
+    ms_b = 1e3 * run_steps(batched, args.steps)
+    ctx.px_sync()
+
+    def single(a_list):
+        def f():
+            for a in a_list:
+                ctx.px_ace_build(a["cell"], a["psi"], a["occ"], a["kern"], xi=a.get("out"),
+                                 status=a.get("status"))
+        return f
+    ms_1 = 1e3 * run_steps(single(args32), 1)
+    for a in args64:
+        a["out"] = torch.empty_like(a["psi"])
+        a["status"] = torch.zeros(1, dtype=torch.int32, device="cuda")
+    single(args64)()
+    torch.cuda.synchronize()
+    ms_64 = 1e3 * run_steps(single(args64), 1)
+    ctx.px_sync()
+    rec = {
+        "metric": "exchange pair-solves/s + ACE build s, FP32-batched vs FP64 at <=2e-5 err",
+        "value": pairs / (ms_b * 1e-3), "unit": "pair-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch48: 48 instances, grids {32,40,48,64}^3, 32..256 orbitals, "
+                               "kT 0.005..0.05 Ha, L = 0.28 n bohr; FP32 ACE builds, batched + graph",
+                   "pairs_per_step": pairs},
+        "extra": {"autotuned_blocks": blocks, "single_fp32_ms": ms_1, "single_fp64_ms": ms_64,
+                  "single_fp32_pair_solves_per_s": pairs / (ms_1 * 1e-3),
+                  "single_fp64_pair_solves_per_s": pairs / (ms_64 * 1e-3),
+                  "speedup_batched_fp32_vs_single_fp64": ms_64 / ms_b},
+    }
+    ctx.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +246,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default="mid72", choices=["mid72", "batch48"],
+                    help="mid72 (default, the headline): one 72^3 x 512 instance; batch48: the "
+                         "48-instance uneven batch in the batched form")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy kernel (2 GiB, 5 launches) and print its bandwidth")
     args = ap.parse_args()
@@ -194,6 +265,9 @@ def main():
     if args.calibrate_copy:
         ctx = px.Context(0)
         print(json.dumps(copy_bandwidth(ctx, reps=5)), flush=True)
+        return
+    if args.workload == "batch48":
+        print(json.dumps(bench_batch48(args)), flush=True)
         return
 
     cfg = inputs.CONFIGS["mid72"]

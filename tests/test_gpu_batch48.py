@@ -1,0 +1,70 @@
+"""The 48-instance uneven batch: grids from {32, 40, 48, 64}^3, 32..256 orbitals,
+kT in [0.005, 0.05] Ha, L = 0.28 n; FP32 bulk, blocks autotuned per grid,
+ACE construction of all instances in one batched call (graph-captured)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_03061_amd import inputs, px
+from _gpu import banner, relerr, to_dev, to_host
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+FP32_TOL, FP32_EX_TOL = 2e-5, 1e-7
+
+
+def test_batch48_ace_fp32(px_ctx, tmp_path):
+    import torch
+    recipe = inputs.batch_recipe()
+    banner(f"batch48: {len(recipe)} instances, sizes {sorted(set(r['n'] for r in recipe))}")
+    insts, args = [], []
+    for r in recipe:
+        inst = inputs.make_instance(r["n"], r["L"], r["n_orb"], r["kT"], seed=r["seed"])
+        cell = px.Cell(inst.L, inst.n)
+        psi = px_ctx.px_convert_c128_to_c64(to_dev(inst.psi))
+        n = inst.n_orb
+        d = dict(cell=cell, psi=psi, occ=to_dev(inst.occ), kern=px_ctx.px_kernel_hse(cell, 0.106),
+                 e_x=torch.zeros(1, dtype=torch.float64, device="cuda"),
+                 M=torch.zeros((n, n), dtype=torch.complex128, device="cuda"))
+        insts.append(inst)
+        args.append(d)
+    # autotune one representative instance per grid size
+    cache = str(tmp_path / "tune.jsonl")
+    for n in sorted(set(r["n"] for r in recipe)):
+        k = max((i for i, r in enumerate(recipe) if r["n"] == n), key=lambda i: recipe[i]["n_orb"])
+        best = px_ctx.px_autotune(args[k]["cell"], args[k]["psi"], args[k]["occ"], args[k]["kern"],
+                                  cache_path=cache)
+        print(f"autotune n={n}: block {best}", flush=True)
+    xis, stats = px_ctx.px_exchange_apply_batched(args, ace=True)
+    px_ctx.px_sync()
+    assert all(int(s.item()) == 0 for s in stats)
+    # every instance against its own single FP32 ACE build (same precision,
+    # different chunking and summation order)
+    worst = 0.0
+    for k, d in enumerate(args):
+        n = insts[k].n_orb
+        M1 = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+        e1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        xi1, st1 = px_ctx.px_ace_build(d["cell"], d["psi"], d["occ"], d["kern"], M=M1, e_x=e1)
+        px_ctx.px_sync()
+        em = float(torch.linalg.matrix_norm(d["M"] - M1) / torch.linalg.matrix_norm(M1))
+        ee = abs(float(d["e_x"].item()) - float(e1.item())) / abs(float(e1.item()))
+        worst = max(worst, em)
+        assert em < 1e-6 and ee < 1e-8, (k, em, ee)
+    print(f"batch48: worst M difference batched vs single {worst:.2e}", flush=True)
+    # the three smallest instances against the oracle
+    small = sorted(range(len(insts)), key=lambda k: insts[k].n_orb * insts[k].ng)[:3]
+    for k in small:
+        inst = insts[k]
+        K = oracle.kernel_hse(inst.n, inst.L, 0.106)
+        dV = inst.omega / inst.ng
+        r = oracle.ace_build(inst.psi, inst.occ, K, dV)
+        ex = oracle.exchange_energy_gspace(inst.psi, inst.occ, K, inst.omega)
+        em = relerr(to_host(args[k]["M"]), r["M"])
+        exi = relerr(to_host(xis[k]), r["xi"])
+        ee = abs(float(args[k]["e_x"].item()) - ex) / abs(ex)
+        print(f"batch48 instance {k} (n={inst.n[0]}, N={inst.n_orb}) vs oracle: M {em:.2e} xi {exi:.2e} E_x {ee:.2e}",
+              flush=True)
+        assert em < FP32_TOL and exi < FP32_TOL and ee < FP32_EX_TOL
+    for d in args:
+        px_ctx.set_tuning(d["cell"], px.PX_PREC_FP32, 0, 0)
