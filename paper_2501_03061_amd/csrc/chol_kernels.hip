@@ -202,35 +202,108 @@ __global__ __launch_bounds__(256) void chol_update_k(double* L, int n, int k0,
   }
 }
 
-// U = L^{-H}: thread c solves L x = e_c by forward substitution and writes
-// row c of U as conj(x) (U[c][i] = conj(Linv[i][c]), zero for i < c).
-__global__ __launch_bounds__(64) void tri_inv_k(const double* L, int n, double* U,
-                                                const int32_t* status) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  double* urow = U + size_t(c) * n * 2;
-  if (status[0] != 0) {
-    for (int i = 0; i < n; ++i) urow[2 * i] = urow[2 * i + 1] = 0.0;
-    return;
-  }
-  for (int i = 0; i < c; ++i) urow[2 * i] = urow[2 * i + 1] = 0.0;
-  // x_c = 1/L[c][c]; x_i = -(sum_{p=c}^{i-1} L[i][p] x_p)/L[i][i]; x kept in urow (conjugated at the end)
-  urow[2 * c] = 1.0 / L[(size_t(c) * n + c) * 2];
-  urow[2 * c + 1] = 0.0;
-  for (int i = c + 1; i < n; ++i) {
-    const double* li = L + size_t(i) * n * 2;
-    double re = 0.0, im = 0.0;
-    for (int p = c; p < i; ++p) {
-      const double ar = li[2 * p], ai = li[2 * p + 1], xr = urow[2 * p], xi = urow[2 * p + 1];
-      re += ar * xr - ai * xi;
-      im += ar * xi + ai * xr;
-    }
-    const double inv = 1.0 / li[2 * i];
-    urow[2 * i] = -re * inv;
-    urow[2 * i + 1] = -im * inv;
-  }
-  for (int i = c; i < n; ++i) urow[2 * i + 1] = -urow[2 * i + 1];
+// U = L^{-H} from the blocked inverse X = L^{-1}, by block wavefronts.  The
+// factorisation leaves inv(L_kk) of every diagonal block in Dinv
+// (nb x KB x KB).  Wavefront d = 0 sets X_cc = inv(L_cc); wavefront d >= 1
+// computes, for every block column c with r = c + d < nb,
+//   X_rc = -inv(L_rr) * sum_{p=c}^{r-1} L_rp X_pc,
+// one workgroup per block.  X is never stored itself: block (r, c) of X goes
+// to U as U[c0 + j][r0 + i] = conj(X_rc[i][j]), and later wavefronts read X_pc
+// back from there (a launch boundary orders the store before the load).
+// The strict lower triangle of U is zeroed first; after a breakdown U stays 0.
+__global__ void tri_zero_k(double* U, int n) {
+  const size_t total = size_t(n) * n * 2;
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += size_t(gridDim.x) * blockDim.x)
+    U[e] = 0.0;
 }
+
+__global__ __launch_bounds__(256) void tri_wave_k(const double* L, int n, const double* Dinv,
+                                                  double* U, int d, const int32_t* status) {
+  __shared__ double ls[KB][KB + 1][2];
+  __shared__ double xs[KB][KB + 1][2];
+  if (status[0] != 0) return;
+  const int nb = (n + KB - 1) / KB;
+  const int c = blockIdx.x, r = c + d;
+  if (r >= nb) return;
+  const int c0 = c * KB, r0 = r * KB;
+  const int rb = (n - r0) < KB ? (n - r0) : KB;   // only the last block row can be short
+  const int t = threadIdx.x;
+  const int row = t / 8, col = t % 8;              // outputs (row, col + 8k), k < 4
+  double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+  const double* dr = Dinv + size_t(r) * KB * KB * 2;
+  if (d == 0) {
+    for (int k = 0; k < 4; ++k) {
+      ar[k] = dr[(row * KB + col + 8 * k) * 2];
+      ai[k] = dr[(row * KB + col + 8 * k) * 2 + 1];
+    }
+  } else {
+    // T = sum_p L_rp X_pc
+    for (int p = c; p < r; ++p) {
+      const int p0 = p * KB;
+      const double* dp = Dinv + size_t(p) * KB * KB * 2;
+      for (int e = t; e < KB * KB; e += 256) {
+        const int i = e / KB, q = e % KB;
+        const bool in = i < rb;
+        ls[i][q][0] = in ? L[(size_t(r0 + i) * n + p0 + q) * 2] : 0.0;
+        ls[i][q][1] = in ? L[(size_t(r0 + i) * n + p0 + q) * 2 + 1] : 0.0;
+        // X_pc[q][j] with j = e / KB, q = e % KB (contiguous reads of U row c0 + j)
+        const int j = e / KB, qq = e % KB;
+        if (p == c) {
+          xs[qq][j][0] = dp[(qq * KB + j) * 2];
+          xs[qq][j][1] = dp[(qq * KB + j) * 2 + 1];
+        } else {
+          xs[qq][j][0] = U[(size_t(c0 + j) * n + p0 + qq) * 2];
+          xs[qq][j][1] = -U[(size_t(c0 + j) * n + p0 + qq) * 2 + 1];
+        }
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int q = 0; q < KB; ++q) {
+        const double lr = ls[row][q][0], li = ls[row][q][1];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double xr = xs[q][col + 8 * k][0], xi = xs[q][col + 8 * k][1];
+          ar[k] += lr * xr - li * xi;
+          ai[k] += lr * xi + li * xr;
+        }
+      }
+      __syncthreads();
+    }
+    // X_rc = -inv(L_rr) T
+    for (int k = 0; k < 4; ++k) {
+      xs[row][col + 8 * k][0] = ar[k];
+      xs[row][col + 8 * k][1] = ai[k];
+    }
+    for (int e = t; e < KB * KB; e += 256) {
+      const int i = e / KB, q = e % KB;
+      ls[i][q][0] = dr[e * 2];
+      ls[i][q][1] = dr[e * 2 + 1];
+    }
+    __syncthreads();
+    for (int k = 0; k < 4; ++k) ar[k] = ai[k] = 0.0;
+#pragma unroll 4
+    for (int q = 0; q < KB; ++q) {
+      const double lr = ls[row][q][0], li = ls[row][q][1];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double xr = xs[q][col + 8 * k][0], xi = xs[q][col + 8 * k][1];
+        ar[k] -= lr * xr - li * xi;
+        ai[k] -= lr * xi + li * xr;
+      }
+    }
+  }
+  if (row < rb) {
+    for (int k = 0; k < 4; ++k) {
+      const int j = col + 8 * k;
+      if (c0 + j >= n) continue;
+      U[(size_t(c0 + j) * n + r0 + row) * 2] = ar[k];
+      U[(size_t(c0 + j) * n + r0 + row) * 2 + 1] = -ai[k];
+    }
+  }
+}
+
+size_t chol_dinv_bytes(int n) { return size_t((n + KB - 1) / KB) * KB * KB * 16; }
 
 hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t* status,
                            double* dinv, hipStream_t s) {
@@ -238,17 +311,21 @@ hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t
   const int blocks = int((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
   hipLaunchKernelGGL(chol_init_k, dim3(blocks), dim3(256), 0, s, M, n, L, status);
   for (int k0 = 0; k0 < n; k0 += KB) {
-    hipLaunchKernelGGL(chol_diag_k, dim3(1), dim3(256), 0, s, L, n, k0, dinv, status);
+    double* dk = dinv + size_t(k0 / KB) * KB * KB * 2;
+    hipLaunchKernelGGL(chol_diag_k, dim3(1), dim3(256), 0, s, L, n, k0, dk, status);
     const int kb = (n - k0) < KB ? (n - k0) : KB;
     const int rest = n - k0 - kb;
     if (rest > 0) {
-      hipLaunchKernelGGL(chol_panel_k, dim3((rest + 63) / 64), dim3(64), 0, s, L, n, k0, dinv,
+      hipLaunchKernelGGL(chol_panel_k, dim3((rest + 63) / 64), dim3(64), 0, s, L, n, k0, dk,
                          status);
       const int nt = (rest + KB - 1) / KB;
       hipLaunchKernelGGL(chol_update_k, dim3(nt, nt), dim3(256), 0, s, L, n, k0, status);
     }
   }
-  hipLaunchKernelGGL(tri_inv_k, dim3((n + 63) / 64), dim3(64), 0, s, L, n, U, status);
+  hipLaunchKernelGGL(tri_zero_k, dim3(blocks), dim3(256), 0, s, U, n);
+  const int nb = (n + KB - 1) / KB;
+  for (int d = 0; d < nb; ++d)
+    hipLaunchKernelGGL(tri_wave_k, dim3(nb - d), dim3(256), 0, s, L, n, dinv, U, d, status);
   return hipGetLastError();
 }
 

@@ -243,10 +243,16 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
 }
 
 // ============================================================== pass 2
-template <typename T, int N0, int N1, int N2, int NT, bool G0, bool EX>
+// One workgroup takes the same y-plane of PQ consecutive pairs: the kernel
+// values of the plane are loaded once and, with PF, the next pair's plane is
+// in flight while the current one is transformed.
+template <typename T, int N0, int N1, int N2, int NT, bool G0, bool EX, int PQ, bool PF>
 __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
   const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
-  if (int(blockIdx.y) >= a.ic * a.jc) return;
+  const int np = a.ic * a.jc;
+  const int pbeg = int(blockIdx.y) * PQ;
+  if (pbeg >= np) return;
+  const int pend = pbeg + PQ < np ? pbeg + PQ : np;
   constexpr int P0 = N0 + 1;
   __shared__ cpx<T> lds[N2 * P0];
   __shared__ cpx<T> tw2[N2];
@@ -262,16 +268,18 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
   constexpr int NBL = N0 * (N2 / FL::R), BPTL = (NBL + NT - 1) / NT;
   constexpr int NBI = N0 * (N2 / IL::R), BPTI = (NBI + NT - 1) / NT;
 
-  const int y = blockIdx.x, p = blockIdx.y;
+  const int y = blockIdx.x;
   const size_t slab = size_t(N0) * N1;
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(a.t) + size_t(p) * slab * N2 + size_t(y) * N0;
+  cpx<T>* const buf0 = reinterpret_cast<cpx<T>*>(a.t) + size_t(y) * N0;
   const double* kern = a.kern + size_t(y) * N0;
   const int tid = threadIdx.x;
 
-  // all global loads first: the plane (at stage-0 positions) and the kernel
+  // global loads first: the first plane (at stage-0 positions) and the kernel
   // values at the positions the last forward stage produces
-  cpx<T> v0[BPT0][F0::R];
-  gather<T, GZ, F0::R, NT>(v0, [&](int line, int e) { return ldc(buf + size_t(e) * slab + line); });
+  cpx<T> nx[BPT0][F0::R];
+  gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) {
+    return ldc(buf0 + size_t(pbeg) * slab * N2 + size_t(e) * slab + line);
+  });
   double kv[BPTL][FL::R];
 #pragma unroll
   for (int k = 0; k < BPTL; ++k) {
@@ -283,6 +291,20 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
     for (int r = 0; r < FL::R; ++r) kv[k][r] = kern[size_t(j + r * (N2 / FL::R)) * slab + line];
   }
   fill_twiddles<T, N2, NT>(tw2);
+  for (int p = pbeg; p < pend; ++p) {
+  cpx<T>* const buf = buf0 + size_t(p) * slab * N2;
+  cpx<T> v0[BPT0][F0::R];
+  if (PQ == 1 || PF || p == pbeg) {
+#pragma unroll
+    for (int k = 0; k < BPT0; ++k)
+#pragma unroll
+      for (int r = 0; r < F0::R; ++r) v0[k][r] = nx[k][r];
+  } else {
+    gather<T, GZ, F0::R, NT>(v0, [&](int line, int e) { return ldc(buf + size_t(e) * slab + line); });
+  }
+  if (PF && p + 1 < pend)
+    gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) { return ldc(buf + slab * N2 + size_t(e) * slab + line); });
+  if (p > pbeg) __syncthreads();  // the previous pair's last stage has read LDS
 #pragma unroll
   for (int k = 0; k < BPT0; ++k) {
     const int b = tid + k * NT;
@@ -396,6 +418,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
       for (int r = 0; r < IL::R; ++r) stg(buf + size_t(j + r * (N2 / IL::R)) * slab + line, w[r]);
     }
   }
+  }  // pairs
 }
 
 // ============================================================== pass 3
@@ -555,6 +578,14 @@ template <typename T, int N> constexpr bool prefetch3_for() {
   return sizeof(T) == 4 ? N <= 80 : N <= 48;
 }
 
+// Pairs per pass-2 workgroup, with prefetch of the next plane: FP64 at 72^3,
+// where the plane's LDS already limits a CU to one workgroup and the loop
+// fits the registers.  Elsewhere two workgroups per CU overlap better than one
+// with a loop (FP32 at 72^3), or the loop would spill (FP64 at 80^3, 96^3).
+template <typename T, int N> constexpr int pass2_pairs_per_wg() {
+  return sizeof(T) == 8 && N == 72 ? 8 : 1;
+}
+
 // Pass 1, 2, 3 for the cubic grid N^3: one chunk (tasks == nullptr, the
 // chunk in `a`), or ntasks chunks of a task table in device memory, one per
 // blockIdx.z (max_ic / max_pairs: the largest chunk of the table).  The FP32
@@ -568,7 +599,9 @@ hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hi
     ntasks = 1;
     max_ic = a.ic;
   }
-  dim3 g1(N, max_ic, ntasks), g2(N, npairs, ntasks), g3(N, max_ic, ntasks);
+  constexpr int Q32 = pass2_pairs_per_wg<float, N>(), Q64 = pass2_pairs_per_wg<double, N>();
+  const int pq = fp32 ? Q32 : Q64;
+  dim3 g1(N, max_ic, ntasks), g2(N, (npairs + pq - 1) / pq, ntasks), g3(N, max_ic, ntasks);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (fp32)
     hipLaunchKernelGGL((pass1_fwd_xy<float, N, N, NT, true, prefetch1_for<float, N>()>), g1, dim3(NT), 0, s, a, tasks);
@@ -576,11 +609,11 @@ hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hi
     hipLaunchKernelGGL((pass1_fwd_xy<double, N, N, NT, false, prefetch1_for<double, N>()>), g1, dim3(NT), 0, s, a, tasks);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (fp32) {
-    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, true>), g2, dim3(NT), 0, s, a, tasks);
-    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, false>), g2, dim3(NT), 0, s, a, tasks);
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, true, Q32, (Q32 > 1)>), g2, dim3(NT), 0, s, a, tasks);
+    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, false, Q32, (Q32 > 1)>), g2, dim3(NT), 0, s, a, tasks);
   } else {
-    if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, true>), g2, dim3(NT), 0, s, a, tasks);
-    else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, false>), g2, dim3(NT), 0, s, a, tasks);
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, true, Q64, (Q64 > 1)>), g2, dim3(NT), 0, s, a, tasks);
+    else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, false, Q64, (Q64 > 1)>), g2, dim3(NT), 0, s, a, tasks);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
   if (fp32)

@@ -146,7 +146,7 @@ AceLayout ace_layout(const px_cell* cell, px_precision prec, int n, int ic, int 
   a.U = off;
   off = align_up(off + size_t(n) * n * 16);
   a.dinv = off;
-  off = align_up(off + 32 * 32 * 16);
+  off = align_up(off + px::chol_dinv_bytes(n));
   int nsplit = 0;
   const size_t pe = px::gemm_xhy_part_elems(n, n, ngrid(cell), &nsplit);
   a.part = off;
@@ -758,7 +758,7 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
     P.U_off = off;
     off = align_up(off + size_t(max_n) * max_n * 16);
     P.dinv_off = off;
-    off = align_up(off + 32 * 32 * 16);
+    off = align_up(off + px::chol_dinv_bytes(max_n));
     size_t part = 0;
     for (int k = 0; k < n_inst; ++k) {
       int ns = 0;

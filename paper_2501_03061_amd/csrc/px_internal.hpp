@@ -95,7 +95,8 @@ hipError_t launch_gemm_xc(bool fp32, int na, int nb, size_t ng, const void* X, c
 // chol_kernels.hip: FP64 Hermitian tools on an n x n complex128 matrix (row-major)
 hipError_t launch_hermitize(double* M, int n, hipStream_t s);
 // U = L^{-H} where -M = L L^H; status[0] = 0 on success or the 1-based failing column
-// dinv: workspace of 32 x 32 complex128 (inverse of the current diagonal block)
+// dinv: workspace of chol_dinv_bytes(n) (inverses of the 32 x 32 diagonal blocks)
+size_t chol_dinv_bytes(int n);
 hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t* status,
                            double* dinv, hipStream_t s);
 
