@@ -18,6 +18,7 @@
 // Layout of every grid array: [n2][n1][n0] with x = n0 fastest; orbital blocks
 // are orbital-major.  T is float (complex64 data) or double (complex128).
 #pragma once
+#include <type_traits>
 #include "fft_core.hpp"
 #include "px_internal.hpp"
 
@@ -29,14 +30,27 @@ template <typename T> struct Vec;
 template <> struct Vec<double> { using t = vd2; };
 template <> struct Vec<float> { using t = vf2; };
 
-template <typename T> __device__ __forceinline__ cpx<T> ldg(const cpx<T>* p) {
+// Global-memory access through address-space-1 pointers.  The chunk
+// arguments arrive in a struct (or a task table), so the compiler cannot
+// prove that their pointers are global and would otherwise emit flat
+// instructions, which count against the LDS wait counter as well: every
+// wait for an LDS access would then also wait for the prefetched slabs.
+#define PX_GLOBAL __attribute__((address_space(1)))
+template <typename V> __device__ __forceinline__ V gld(const V* p) {
+  return *(const PX_GLOBAL V*)p;
+}
+template <typename V> __device__ __forceinline__ void gst(V* p, V v) {
+  *(PX_GLOBAL V*)p = v;
+}
+
+template <typename T> __device__ __forceinline__ cpx<T> ldg(const cpx<T>* p) {  // streaming load
   using V = typename Vec<T>::t;
-  V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  V v = __builtin_nontemporal_load((const PX_GLOBAL V*)p);
   return {v.x, v.y};
 }
 template <typename T> __device__ __forceinline__ cpx<T> ldc(const cpx<T>* p) {  // cached load
   using V = typename Vec<T>::t;
-  V v = *reinterpret_cast<const V*>(p);
+  V v = gld(reinterpret_cast<const V*>(p));
   return {v.x, v.y};
 }
 template <typename T> __device__ __forceinline__ void stg(cpx<T>* p, cpx<T> a) {
@@ -44,7 +58,17 @@ template <typename T> __device__ __forceinline__ void stg(cpx<T>* p, cpx<T> a) {
   V v;
   v.x = a.x;
   v.y = a.y;
-  *reinterpret_cast<V*>(p) = v;
+  gst(reinterpret_cast<V*>(p), v);
+}
+// Streaming store for the pair buffer: the slab is read back only by the
+// next pass, so it should not displace the orbital slabs that the current
+// pass re-reads from the caches.
+template <typename T> __device__ __forceinline__ void stn(cpx<T>* p, cpx<T> a) {
+  using V = typename Vec<T>::t;
+  V v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, (PX_GLOBAL V*)p);
 }
 
 // Twiddle table: tw[m] = exp(-2 pi i m / N), FP64 sincospi rounded to T.
@@ -56,27 +80,38 @@ template <typename T, int N, int NT> __device__ __forceinline__ void fill_twiddl
   }
 }
 
-// Block-wide FP64 sum; result valid in thread 0.  red must hold NT/64 doubles.
-template <int NT> __device__ __forceinline__ double block_sum(double v, double* red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NT / 64; ++k) s += red[k];
+// One DPP step on an FP64 value (both 32-bit halves moved with the same
+// control).  With ROW_MASK = 0xF every lane is written; otherwise lanes of the
+// rows outside the mask receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  int lo, hi;
+  if constexpr (ROW_MASK == 0xF) {
+    lo = __builtin_amdgcn_mov_dpp(int(unsigned(u)), CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(int(unsigned(u >> 32)), CTRL, 0xF, 0xF, false);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(0, int(unsigned(u)), CTRL, ROW_MASK, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, int(unsigned(u >> 32)), CTRL, ROW_MASK, 0xF, false);
   }
-  __syncthreads();
-  return s;
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo));
 }
 
-// FP64 sum over the 64 lanes of a wave (valid in every lane).
+// FP64 sum over the 64 lanes of a wave, returned wave-uniform.  Data-parallel
+// moves only: pair and quad swaps, half-row and row mirrors (every lane of a
+// 16-lane row then holds the row sum), then the GFX9 row broadcasts of lanes
+// 15 and 31, after which lane 63 holds the total.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane(int(unsigned(u)), 63);
+  const unsigned hi = __builtin_amdgcn_readlane(int(unsigned(u >> 32)), 63);
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
 // Whether two slab buffers (ping-pong) fit in LDS next to the small tables.
@@ -122,8 +157,11 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
   using GY = Lines<N1, N0, 1, P0, true>;   // columns: strided lines
   constexpr int NSX = Plan<N0>::nst, NSY = Plan<N1>::nst;
   static_assert(!PP || (NSX == 2 && NSY == 2), "ping-pong path assumes two-stage plans");
-  using X0 = StageOf<N0, 0, false>;
-  using X1 = StageOf<N0, 1, false>;
+  // x stages in the reversed radix order: the first stage writes LDS at a
+  // stride of its radix along a line, and the plans' later radices are the
+  // ones that spread such writes over the banks (9 before 8 at 72^3)
+  using X0 = StageOf<N0, 0, true>;
+  using X1 = StageOf<N0, 1, true>;
   using Y0 = StageOf<N1, 0, false>;
   using YL = StageOf<N1, NSY - 1, false>;
   constexpr int NB0 = N1 * (N0 / X0::R), BPT0 = (NB0 + NT - 1) / NT;
@@ -181,7 +219,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
           sim += double(ps.x) * double(ph_.y) - double(ps.y) * double(ph_.x);
         }
         v[r] = cmulc(ps, ph_);
-        if (G0 && valid) sen += double(v[r].x) * double(v[r].x) + double(v[r].y) * double(v[r].y);
+        if (G0 && valid) sen += double(v[r].x * v[r].x + v[r].y * v[r].y);
       }
       dft<T, X0::R, false>(v);
       if (valid) {
@@ -209,7 +247,10 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
           s1 += red[1][w];
           s2 += red[2][w];
         }
-        a.g0[size_t(p) * a.n2 + z] = G0Part{s0, s1, s2, 0.0};
+        double* g = reinterpret_cast<double*>(a.g0 + size_t(p) * a.n2 + z);
+        gst(g, s0);
+        gst(g + 1, s1);
+        gst(g + 2, s2);
       }
     }
     if constexpr (PP) {
@@ -218,7 +259,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
       stage_pp<T, GY, Y0::R, Y0::NS, false, NT>(B, A, tw1);
       __syncthreads();
     } else {
-      stages_lds<T, GX, false, NT, 1, NSX>(A, tw0);
+      stages_lds<T, GX, false, NT, 1, NSX, true>(A, tw0);
       stages_lds<T, GY, false, NT, 0, NSY - 1>(A, tw1);
     }
     // last y stage: LDS -> global pair buffer
@@ -235,7 +276,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
         twiddle<T, N1, YL::R, YL::NS, false>(v, j, tw1);
         dft<T, YL::R, false>(v);
 #pragma unroll
-        for (int r = 0; r < YL::R; ++r) stg(out + line + (j + r * (N1 / YL::R)) * N0, v[r]);
+        for (int r = 0; r < YL::R; ++r) stn(out + line + (j + r * (N1 / YL::R)) * N0, v[r]);
       }
     }
     if constexpr (!PP) __syncthreads();
@@ -271,7 +312,10 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
   const int y = blockIdx.x;
   const size_t slab = size_t(N0) * N1;
   cpx<T>* const buf0 = reinterpret_cast<cpx<T>*>(a.t) + size_t(y) * N0;
-  const double* kern = a.kern + size_t(y) * N0;
+  // kernel values: the FP32 copy in the FP32 form (G = 0 comes from kern)
+  using KT = typename std::conditional<G0, float, double>::type;
+  const KT* kern = (G0 ? reinterpret_cast<const KT*>(a.kern32) : reinterpret_cast<const KT*>(a.kern)) +
+                   size_t(y) * N0;
   const int tid = threadIdx.x;
 
   // global loads first: the first plane (at stage-0 positions) and the kernel
@@ -280,7 +324,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
   gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) {
     return ldc(buf0 + size_t(pbeg) * slab * N2 + size_t(e) * slab + line);
   });
-  double kv[BPTL][FL::R];
+  KT kv[BPTL][FL::R];
 #pragma unroll
   for (int k = 0; k < BPTL; ++k) {
     int b = tid + k * NT;
@@ -288,7 +332,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
     int line, j;
     decode<GZ, FL::R>(b, line, j);
 #pragma unroll
-    for (int r = 0; r < FL::R; ++r) kv[k][r] = kern[size_t(j + r * (N2 / FL::R)) * slab + line];
+    for (int r = 0; r < FL::R; ++r) kv[k][r] = gld(kern + size_t(j + r * (N2 / FL::R)) * slab + line);
   }
   fill_twiddles<T, N2, NT>(tw2);
   for (int p = pbeg; p < pend; ++p) {
@@ -337,19 +381,29 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
         const double kg = kv[k][r];
         cpx<T> c = v[k][r];
         if (G0 && y == 0 && line == 0 && kz == 0) {
+          const double k0 = gld(a.kern);
           // G = 0 from the FP64 slab sums of pass 1
           double s0 = 0.0, s1 = 0.0;
           const G0Part* g = a.g0 + size_t(p) * N2;
           for (int zz = 0; zz < N2; ++zz) {
-            s0 += g[zz].re;
-            s1 += g[zz].im;
+            s0 += gld(&g[zz].re);
+            s1 += gld(&g[zz].im);
           }
-          if (EX) ex0 = kg * (s0 * s0 + s1 * s1);
-          v[k][r] = {T(kg * s0), T(kg * s1)};
+          if (EX) ex0 = k0 * (s0 * s0 + s1 * s1);
+          v[k][r] = {T(k0 * s0), T(k0 * s1)};
+        } else if constexpr (G0) {
+          // FP32 form: K(G) rounded to FP32; the energy partials take
+          // |rho|^2 from FP32 squares and accumulate in FP64
+          const T kf = kv[k][r];
+          const double c2 = double(c.x * c.x + c.y * c.y);
+          if (EX) {
+            ex += kg * c2;
+            en += c2;
+          }
+          v[k][r] = {kf * c.x, kf * c.y};
         } else {
           const double c2 = double(c.x) * double(c.x) + double(c.y) * double(c.y);
           if (EX) ex += kg * c2;
-          if (EX && G0) en += c2;
           v[k][r] = {T(kg * double(c.x)), T(kg * double(c.y))};
         }
       }
@@ -393,11 +447,11 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
       }
       if constexpr (G0) {
         double* e = a.expart + (size_t(p) * N1 + y) * 3;
-        e[0] = s2;
-        e[1] = s3;
-        e[2] = s4;
+        gst(e, s2);
+        gst(e + 1, s3);
+        gst(e + 2, s4);
       } else {
-        a.expart[size_t(p) * N1 + y] = s2;
+        gst(a.expart + size_t(p) * N1 + y, s2);
       }
     }
   }
@@ -415,7 +469,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
       twiddle<T, N2, IL::R, IL::NS, true>(w, j, tw2);
       dft<T, IL::R, true>(w);
 #pragma unroll
-      for (int r = 0; r < IL::R; ++r) stg(buf + size_t(j + r * (N2 / IL::R)) * slab + line, w[r]);
+      for (int r = 0; r < IL::R; ++r) stn(buf + size_t(j + r * (N2 / IL::R)) * slab + line, w[r]);
     }
   }
   }  // pairs
@@ -491,7 +545,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
     } else {
       gather<T, GX, X0::R, NT>(tc, tload(t0 + size_t(jj) * ng));
     }
-    const T wj = T(a.occ[a.j0 + jj] * a.inv_ng);
+    const T wj = T(gld(a.occ + a.j0 + jj) * a.inv_ng);
 #pragma unroll
     for (int k = 0; k < BPT0; ++k) {
       const int b = tid + k * NT;
@@ -539,7 +593,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
           // symmetric mode: keep N_g * v_ij (real space) for the transposed pass
           cpx<T>* tv = reinterpret_cast<cpx<T>*>(a.t) + size_t(ii * a.jc + jj) * ng + z * slab;
 #pragma unroll
-          for (int r = 0; r < YL::R; ++r) stg(tv + line + (j + r * (N1 / YL::R)) * N0, v[r]);
+          for (int r = 0; r < YL::R; ++r) stn(tv + line + (j + r * (N1 / YL::R)) * N0, v[r]);
         }
       }
     }

@@ -237,7 +237,9 @@ PX_PLAN(80, 2, 8, 10, 1)
 PX_PLAN(96, 2, 8, 12, 1)
 #undef PX_PLAN
 
-// Radix and span of stage S of the forward (INV=false) or inverse sequence.
+// Radix and span of stage S of the plan's radix sequence (INV = false) or of
+// the reversed sequence (INV = true; the inverse transforms use it, and so
+// does the forward x transform of the pair product, see pass 1).
 template <int N, int S, bool INV> struct StageOf {
   static constexpr int nst = Plan<N>::nst;
   static constexpr int idx = INV ? (nst - 1 - S) : S;
@@ -367,13 +369,14 @@ __device__ __forceinline__ void stage_pp(const cpx<T>* src, cpx<T>* dst, const c
   }
 }
 
-// Run stages [S0, S1) of the length-N transform over geometry G, LDS -> LDS.
-template <typename T, class G, bool INV, int NT, int S, int S1>
+// Run stages [S0, S1) of the length-N transform over geometry G, LDS -> LDS,
+// in the forward (REV = false) or reversed radix order.
+template <typename T, class G, bool INV, int NT, int S, int S1, bool REV = INV>
 __device__ __forceinline__ void stages_lds(cpx<T>* lds, const cpx<T>* tw) {
   if constexpr (S < S1) {
-    using St = StageOf<G::n, S, INV>;
+    using St = StageOf<G::n, S, REV>;
     stage_lds<T, G, St::R, St::NS, INV, NT>(lds, tw);
-    stages_lds<T, G, INV, NT, S + 1, S1>(lds, tw);
+    stages_lds<T, G, INV, NT, S + 1, S1, REV>(lds, tw);
   }
 }
 

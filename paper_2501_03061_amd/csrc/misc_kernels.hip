@@ -79,6 +79,19 @@ hipError_t launch_convert_c128_c64(size_t n, const void* src, void* dst, hipStre
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void convert_real_k(size_t n, const double* src, float* dst) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = float(src[i]);
+}
+
+hipError_t launch_convert_f64_f32(size_t n, const double* src, float* dst, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(convert_real_k, dim3(unsigned(blocks)), dim3(256), 0, s, n, src, dst);
+  return hipGetLastError();
+}
+
 // Pair energy S_ij = sum_G K |rho_ij(G)|^2 from the per-plane partials.
 // FP32 form: S = K(0)|rho(0)|^2 + A * (N_g E_r - |rho(0)|^2) / B, where A and B
 // are the FP32-transform sums of K|rho|^2 and |rho|^2 over G != 0, E_r the

@@ -15,12 +15,15 @@ template <typename T> struct V2t;
 template <> struct V2t<double> { typedef double t __attribute__((ext_vector_type(2))); };
 template <> struct V2t<float> { typedef float t __attribute__((ext_vector_type(2))); };
 
+// Address-space-1 accesses: global instructions rather than flat ones (the
+// pointers come from a struct, so the compiler cannot infer it).
+#define PX_GLOBAL __attribute__((address_space(1)))
 template <typename T> __device__ __forceinline__ cpx<T> ld2(const cpx<T>* p) {
-  typename V2t<T>::t v = *reinterpret_cast<const typename V2t<T>::t*>(p);
+  typename V2t<T>::t v = *(const PX_GLOBAL typename V2t<T>::t*)p;
   return {v.x, v.y};
 }
 template <typename T> __device__ __forceinline__ cpx<T> ld2nt(const cpx<T>* p) {
-  typename V2t<T>::t v = __builtin_nontemporal_load(reinterpret_cast<const typename V2t<T>::t*>(p));
+  typename V2t<T>::t v = __builtin_nontemporal_load((const PX_GLOBAL typename V2t<T>::t*)p);
   return {v.x, v.y};
 }
 
@@ -43,7 +46,7 @@ __global__ __launch_bounds__(256) void pass4_transpose_acc(ChunkArgs a0, const C
   for (int u = 0; u < JB; ++u) ax[u] = ay[u] = T(0);
   for (int ii = 0; ii < a.ic; ++ii) {
     const cpx<T> ps = ld2(psi + size_t(a.i0 + ii) * ng + e);
-    const T w = T(a.occ[a.i0 + ii] * a.inv_ng);
+    const T w = T(*(const PX_GLOBAL double*)(a.occ + a.i0 + ii) * a.inv_ng);
     const T px_ = w * ps.x, py_ = w * ps.y;
     const cpx<T>* row = t + size_t(ii * a.jc + j0) * ng + e;
     cpx<T> v[JB];
@@ -64,7 +67,7 @@ __global__ __launch_bounds__(256) void pass4_transpose_acc(ChunkArgs a0, const C
       typename V2t<T>::t r;
       r.x = prev.x - ax[u];
       r.y = prev.y - ay[u];
-      *reinterpret_cast<typename V2t<T>::t*>(o) = r;
+      *(PX_GLOBAL typename V2t<T>::t*)o = r;
     }
   }
 }

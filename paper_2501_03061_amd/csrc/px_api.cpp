@@ -102,7 +102,7 @@ void tuning_for(const px_context* c, const px_cell* cell, px_precision prec, int
 
 // Workspace layout of one exchange application.
 struct ExLayout {
-  size_t t, g0, expart, S, end;
+  size_t t, g0, expart, S, k32, end;
 };
 
 ExLayout ex_layout(const px_cell* cell, px_precision prec, int n_psi, int n_phi, int ic, int jc,
@@ -122,6 +122,8 @@ ExLayout ex_layout(const px_cell* cell, px_precision prec, int n_psi, int n_phi,
     l.S = off;
     off = align_up(off + size_t(n_phi) * n_psi * 8);
   }
+  l.k32 = off;
+  if (prec == PX_PREC_FP32) off = align_up(off + ngrid(cell) * sizeof(float));
   l.end = off;
   return l;
 }
@@ -231,6 +233,13 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
   a.out = out;
   a.occ = occ;
   a.kern = kern;
+  if (fp32) {
+    // the FP32 form multiplies by K(G) rounded to FP32 (K(0) stays FP64)
+    float* k32 = reinterpret_cast<float*>(c->ws + l.k32);
+    px_status st = hip_check(c, px::launch_convert_f64_f32(ng, kern, k32, s), "kernel to FP32");
+    if (st != PX_OK) return st;
+    a.kern32 = k32;
+  }
   a.g0 = reinterpret_cast<px::G0Part*>(c->ws + l.g0);
   a.expart = reinterpret_cast<double*>(c->ws + l.expart);
   a.n2 = cell->n[2];
@@ -636,7 +645,7 @@ struct BatchWave {
 
 struct BatchPlan {
   size_t tasks_off = 0, t_off = 0, g0_off = 0, ex_off = 0;
-  std::vector<size_t> S_off, W_off;
+  std::vector<size_t> S_off, W_off, K32_off;
   size_t M_off = 0, L_off = 0, U_off = 0, dinv_off = 0, part_off = 0, end = 0;
   std::vector<px::ChunkArgs> tasks;
   std::vector<BatchWave> waves;
@@ -742,9 +751,16 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
   off = align_up(off + side_pairs * 8 * (fp32 ? 3 : 1));
   P.S_off.resize(n_inst);
   P.W_off.resize(n_inst);
+  P.K32_off.resize(n_inst);
   for (int k = 0; k < n_inst; ++k) {
     P.S_off[k] = off;
     off = align_up(off + size_t(in[k].n) * in[k].n * 8);
+  }
+  if (fp32) {
+    for (int k = 0; k < n_inst; ++k) {
+      P.K32_off[k] = off;
+      off = align_up(off + ngrid(&in[k].cell) * sizeof(float));
+    }
   }
   if (ace) {
     for (int k = 0; k < n_inst; ++k) {
@@ -780,6 +796,7 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         a.expart = reinterpret_cast<double*>(ws + P.ex_off + pofs * w.n * 8 * (fp32 ? 3 : 1));
         a.S = reinterpret_cast<double*>(ws + P.S_off[k]);
         a.out = ace ? static_cast<void*>(ws + P.W_off[k]) : in[k].out;
+        if (fp32) a.kern32 = reinterpret_cast<const float*>(ws + P.K32_off[k]);
       }
     }
   }
@@ -816,6 +833,14 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
                                              hipMemcpyHostToDevice, s),
                            "task table upload");
   if (st != PX_OK) return st;
+  if (fp32) {
+    for (int k = 0; k < n_inst; ++k) {
+      st = hip_check(c, px::launch_convert_f64_f32(ngrid(&in[k].cell), in[k].kernel_G,
+                                                   reinterpret_cast<float*>(ws + P.K32_off[k]), s),
+                     "batched kernel to FP32");
+      if (st != PX_OK) return st;
+    }
+  }
   for (const BatchWave& w : P.waves) {
     const size_t ng = size_t(w.n) * w.n * w.n;
     st = hip_check(c, px::launch_chunk_tasks(fp32, w.n, dt + w.first, w.count, w.max_ic,

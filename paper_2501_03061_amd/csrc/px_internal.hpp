@@ -23,6 +23,7 @@ struct ChunkArgs {
   void* out;            // [n_phi][N_g]
   const double* occ;    // [n_psi]
   const double* kern;   // [N_g] FP64, FFT order
+  const float* kern32;  // [N_g] the same rounded to FP32 (FP32 form; K(0) is read from kern)
   G0Part* g0;           // [ic*jc][n2] FP64 slab sums (FP32 form)
   double* expart;       // FP64 energy partials per (pair, y-plane): sum K|rho(G)|^2 (FP64
                         // form), or {sum_{G!=0} K|rho|^2, sum_{G!=0} |rho|^2, G=0 term} (FP32 form)
@@ -60,6 +61,8 @@ hipError_t launch_pass4(bool fp32, const ChunkArgs& a, size_t ng, hipStream_t s)
 hipError_t launch_kernel_hse(int n0, int n1, int n2, double L0, double L1, double L2, double mu,
                              double* kern, hipStream_t s);
 hipError_t launch_convert_c128_c64(size_t n, const void* src, void* dst, hipStream_t s);
+// n real FP64 values -> FP32 (round to nearest even)
+hipError_t launch_convert_f64_f32(size_t n, const double* src, float* dst, hipStream_t s);
 hipError_t launch_stream_copy(size_t bytes, const void* src, void* dst, hipStream_t s);
 // S[i][j] (row stride lds) from the chunk's energy partials (see ChunkArgs);
 // FP32 form (g0 non-null): the G != 0 part is rescaled so that its energy
