@@ -478,7 +478,9 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
 // ============================================================== pass 3
 // PF: prefetch the next pair slab and the next psi_j slab during the transform.
 // PP as in pass 1.
-template <typename T, int N0, int N1, int NT, bool PF>
+// SV: symmetric mode, keep N_g v_ij in the pair slab for pass 4 (a compile-time
+// switch, so that the loop has the same stores on every path).
+template <typename T, int N0, int N1, int NT, bool PF, bool SV>
 __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const ChunkArgs* tasks) {
   const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
   if (int(blockIdx.y) >= a.ic) return;
@@ -513,39 +515,30 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
   auto pload = [](const cpx<T>* base) {
     return [base](int line, int e) { return ldc(base + line + e * N0); };
   };
+  cpx<T>* const outz = reinterpret_cast<cpx<T>*>(a.out) + size_t(a.i0 + ii) * ng + z * slab;
   cpx<T> acc[BPTL][YL::R];
 #pragma unroll
   for (int k = 0; k < BPTL; ++k)
 #pragma unroll
     for (int r = 0; r < YL::R; ++r) acc[k][r] = {T(0), T(0)};
-  cpx<T> tn[BPT0][X0::R], pn[BPTL][YL::R];
-  if constexpr (PF) {
-    gather<T, GX, X0::R, NT>(tn, tload(t0));
-    gather<T, GY, YL::R, NT>(pn, pload(psi0));
-  }
-  __syncthreads();
+  auto weight = [&](int jj) { return T(gld(a.occ + a.j0 + jj) * a.inv_ng); };
 
-  for (int jj = 0; jj < a.jc; ++jj) {
+  // One pair: inverse x and y transforms of the pair slab held in tc, then
+  // the psi_j-weighted accumulation.  With PF the psi_j slab is requested
+  // first and then the next pair slab (into tn), so that waiting for psi_j
+  // at the end never waits for the prefetch; otherwise psi_j loads in the
+  // last stage.
+  auto step = [&](int jj, cpx<T>(&tc)[BPT0][X0::R], cpx<T>(&tn)[BPT0][X0::R]) {
     cpx<T>* A = lds + (PP ? (jj & 1) * SL : 0);
     cpx<T>* B = lds + (PP ? (1 - (jj & 1)) * SL : 0);
-    cpx<T> tc[BPT0][X0::R], pc[BPTL][YL::R];
+    cpx<T> pc[BPTL][YL::R];
+    const T wj = weight(jj);  // requested before the slabs: waiting for it waits for nothing else
     if constexpr (PF) {
-#pragma unroll
-      for (int k = 0; k < BPT0; ++k)
-#pragma unroll
-        for (int r = 0; r < X0::R; ++r) tc[k][r] = tn[k][r];
-#pragma unroll
-      for (int k = 0; k < BPTL; ++k)
-#pragma unroll
-        for (int r = 0; r < YL::R; ++r) pc[k][r] = pn[k][r];
-      if (jj + 1 < a.jc) {
-        gather<T, GX, X0::R, NT>(tn, tload(t0 + size_t(jj + 1) * ng));
-        gather<T, GY, YL::R, NT>(pn, pload(psi0 + size_t(jj + 1) * ng));
-      }
-    } else {
-      gather<T, GX, X0::R, NT>(tc, tload(t0 + size_t(jj) * ng));
+      gather<T, GY, YL::R, NT>(pc, pload(psi0 + size_t(jj) * ng));
+      // the last pair re-requests its own slab: the loop stays branch free
+      const int jn = jj + 1 < a.jc ? jj + 1 : jj;
+      gather<T, GX, X0::R, NT>(tn, tload(t0 + size_t(jn) * ng));
     }
-    const T wj = T(gld(a.occ + a.j0 + jj) * a.inv_ng);
 #pragma unroll
     for (int k = 0; k < BPT0; ++k) {
       const int b = tid + k * NT;
@@ -567,10 +560,13 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
       stages_lds<T, GX, true, NT, 1, NSX>(A, tw0);
       stages_lds<T, GY, true, NT, 0, NSY - 1>(A, tw1);
     }
+    // last stage: slots past the last butterfly repeat it (same values to the
+    // same addresses), so every thread issues the same loads and stores
 #pragma unroll
     for (int k = 0; k < BPTL; ++k) {
-      const int b = tid + k * NT;
-      if (NBL % NT == 0 || b < NBL) {
+      int b = tid + k * NT;
+      if (NBL % NT != 0) b = b < NBL ? b : NBL - 1;
+      {
         int line, j;
         decode<GY, YL::R>(b, line, j);
         if constexpr (!PF) {
@@ -589,7 +585,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
           acc[k][r].x += wj * t.x;
           acc[k][r].y += wj * t.y;
         }
-        if (a.store_v) {
+        if constexpr (SV) {
           // symmetric mode: keep N_g * v_ij (real space) for the transposed pass
           cpx<T>* tv = reinterpret_cast<cpx<T>*>(a.t) + size_t(ii * a.jc + jj) * ng + z * slab;
 #pragma unroll
@@ -598,8 +594,31 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
       }
     }
     if constexpr (!PP) __syncthreads();
+  };
+
+  if constexpr (PF) {
+    // two register sets for the pair slab, used alternately: the next slab
+    // loads into the idle set while the current one is transformed (no
+    // copies between iterations, so the loads stay in flight)
+    cpx<T> tA[BPT0][X0::R], tB[BPT0][X0::R];
+    gather<T, GX, X0::R, NT>(tA, tload(t0));
+    __syncthreads();
+    for (int jj = 0; jj < a.jc; jj += 2) {
+      step(jj, tA, tB);
+      if (jj + 1 < a.jc) step(jj + 1, tB, tA);
+    }
+  } else {
+    __syncthreads();
+    for (int jj = 0; jj < a.jc; ++jj) {
+      cpx<T> tc[BPT0][X0::R];
+      gather<T, GX, X0::R, NT>(tc, tload(t0 + size_t(jj) * ng));
+      step(jj, tc, tc);
+    }
   }
-  cpx<T>* out = reinterpret_cast<cpx<T>*>(a.out) + size_t(a.i0 + ii) * ng + z * slab;
+  // one read-modify-write of the output slab, all loads issued before the
+  // first store
+  cpx<T> pA[BPTL][YL::R];
+  if (!a.first) gather<T, GY, YL::R, NT>(pA, pload(outz));
 #pragma unroll
   for (int k = 0; k < BPTL; ++k) {
     const int b = tid + k * NT;
@@ -608,9 +627,8 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
       decode<GY, YL::R>(b, line, j);
 #pragma unroll
       for (int r = 0; r < YL::R; ++r) {
-        cpx<T>* o = out + line + (j + r * (N1 / YL::R)) * N0;
-        cpx<T> prev = a.first ? cpx<T>{T(0), T(0)} : ldc(o);
-        stg(o, csub(prev, acc[k][r]));
+        const cpx<T> prev = a.first ? cpx<T>{T(0), T(0)} : pA[k][r];
+        stg(outz + line + (j + r * (N1 / YL::R)) * N0, csub(prev, acc[k][r]));
       }
     }
   }
@@ -626,10 +644,10 @@ template <int N> constexpr int threads_for() {
 // Prefetch across pair iterations where the doubled register set fits
 // without spilling (checked with the compiler's resource report).
 template <typename T, int N> constexpr bool prefetch1_for() {
-  return sizeof(T) == 4 ? N <= 80 : N <= 72;
+  return N != 60 && (sizeof(T) == 4 ? N <= 80 : N <= 72);
 }
 template <typename T, int N> constexpr bool prefetch3_for() {
-  return sizeof(T) == 4 ? N <= 80 : N <= 48;
+  return sizeof(T) == 4 ? N <= 72 : N <= 48;
 }
 
 // Pairs per pass-2 workgroup, with prefetch of the next plane: FP64 at 72^3,
@@ -646,8 +664,9 @@ template <typename T, int N> constexpr int pass2_pairs_per_wg() {
 // form always takes the G = 0 coefficient from FP64 slab sums.
 // ev (optional, 4 events) brackets the passes: ev[0] | pass 1 | ev[1] | pass 2 | ev[2] | pass 3 | ev[3].
 template <int N>
-hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
-                          hipEvent_t* ev, const ChunkArgs* tasks, int ntasks, int max_ic) {
+hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, bool store_v,
+                          hipStream_t s, hipEvent_t* ev, const ChunkArgs* tasks, int ntasks,
+                          int max_ic) {
   constexpr int NT = threads_for<N>();
   if (!tasks) {
     ntasks = 1;
@@ -670,10 +689,15 @@ hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, hi
     else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, false, Q64, (Q64 > 1)>), g2, dim3(NT), 0, s, a, tasks);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
-  if (fp32)
-    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT, prefetch3_for<float, N>()>), g3, dim3(NT), 0, s, a, tasks);
+  constexpr bool P32 = prefetch3_for<float, N>(), P64 = prefetch3_for<double, N>();
+  if (fp32 && store_v)
+    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT, P32, true>), g3, dim3(NT), 0, s, a, tasks);
+  else if (fp32)
+    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT, P32, false>), g3, dim3(NT), 0, s, a, tasks);
+  else if (store_v)
+    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT, P64, true>), g3, dim3(NT), 0, s, a, tasks);
   else
-    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT, prefetch3_for<double, N>()>), g3, dim3(NT), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT, P64, false>), g3, dim3(NT), 0, s, a, tasks);
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError();
 }

@@ -59,15 +59,18 @@ __global__ __launch_bounds__(256) void pass4_transpose_acc(ChunkArgs a0, const C
       ay[u] += py_ * v[u].x - px_ * v[u].y;
     }
   }
+  // all output loads in flight before the first store
+  cpx<T>* const o = reinterpret_cast<cpx<T>*>(a.out) + size_t(a.j0 + j0) * ng + e;
+  cpx<T> prev[JB];
+#pragma unroll
+  for (int u = 0; u < JB; ++u) prev[u] = u < nj ? ld2(o + size_t(u) * ng) : cpx<T>{T(0), T(0)};
 #pragma unroll
   for (int u = 0; u < JB; ++u) {
     if (u < nj) {
-      cpx<T>* o = reinterpret_cast<cpx<T>*>(a.out) + size_t(a.j0 + j0 + u) * ng + e;
-      const cpx<T> prev = ld2(o);
       typename V2t<T>::t r;
-      r.x = prev.x - ax[u];
-      r.y = prev.y - ay[u];
-      *(PX_GLOBAL typename V2t<T>::t*)o = r;
+      r.x = prev[u].x - ax[u];
+      r.y = prev[u].y - ay[u];
+      *(PX_GLOBAL typename V2t<T>::t*)(o + size_t(u) * ng) = r;
     }
   }
 }

@@ -640,7 +640,8 @@ struct BatchWave {
   int n;            // cubic grid size of the wave's instances
   int first, count; // tasks [first, first + count)
   int max_ic, max_jc, max_pairs;
-  bool any_v;       // some task keeps v_ij (needs pass 4)
+  bool any_v;       // its tasks keep v_ij for pass 4 (a wave holds one block diagonal, so
+                    // all of its tasks or none)
 };
 
 struct BatchPlan {
@@ -844,7 +845,7 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
   for (const BatchWave& w : P.waves) {
     const size_t ng = size_t(w.n) * w.n * w.n;
     st = hip_check(c, px::launch_chunk_tasks(fp32, w.n, dt + w.first, w.count, w.max_ic,
-                                             w.max_pairs, true, s),
+                                             w.max_pairs, true, w.any_v, s),
                    "batched pair pipeline");
     if (st != PX_OK) return st;
     if (w.any_v) {

@@ -43,9 +43,10 @@ hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool e
                         hipEvent_t* ev);
 
 // The same passes over a task table in device memory (ntasks chunks of one
-// grid size, all with ic <= max_ic and ic*jc <= max_pairs), one launch each.
+// grid size, all with ic <= max_ic and ic*jc <= max_pairs, and all with the
+// given store_v), one launch each.
 hipError_t launch_chunk_tasks(bool fp32, int n, const ChunkArgs* tasks, int ntasks, int max_ic,
-                              int max_pairs, bool ex, hipStream_t s);
+                              int max_pairs, bool ex, bool store_v, hipStream_t s);
 // Pass 4 over a task table (tasks without kept v_ij are skipped).
 hipError_t launch_pass4_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_jc, size_t ng,
                               hipStream_t s);
