@@ -71,13 +71,11 @@ template <typename T> __device__ __forceinline__ void stn(cpx<T>* p, cpx<T> a) {
   __builtin_nontemporal_store(v, (PX_GLOBAL V*)p);
 }
 
-// Twiddle table: tw[m] = exp(-2 pi i m / N), FP64 sincospi rounded to T.
+// Twiddle table: tw[m] = exp(-2 pi i m / N) from the compile-time roots
+// (FP64, about one ulp) rounded to T; copied into LDS by each workgroup.
 template <typename T, int N, int NT> __device__ __forceinline__ void fill_twiddles(cpx<T>* tw) {
-  for (int m = threadIdx.x; m < N; m += NT) {
-    double s, c;
-    sincospi(2.0 * double(m) / double(N), &s, &c);
-    tw[m] = {T(c), T(-s)};
-  }
+  constexpr const RootTable<N>& tab = kRoots<N>;
+  for (int m = threadIdx.x; m < N; m += NT) tw[m] = {T(tab.c[m]), T(-tab.s[m])};
 }
 
 // One DPP step on an FP64 value (both 32-bit halves moved with the same
@@ -650,6 +648,12 @@ template <typename T, int N> constexpr bool prefetch3_for() {
   return sizeof(T) == 4 ? N <= 72 : N <= 48;
 }
 
+// Threads of a pass-2 workgroup.  FP32 at 72^3: 512 (two butterflies per
+// thread in each stage) lets three workgroups share a CU instead of two.
+template <typename T, int N> constexpr int pass2_threads_for() {
+  return sizeof(T) == 4 && N == 72 ? 512 : threads_for<N>();
+}
+
 // Pairs per pass-2 workgroup, with prefetch of the next plane: FP64 at 72^3,
 // where the plane's LDS already limits a CU to one workgroup and the loop
 // fits the registers.  Elsewhere two workgroups per CU overlap better than one
@@ -682,8 +686,9 @@ hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, bo
     hipLaunchKernelGGL((pass1_fwd_xy<double, N, N, NT, false, prefetch1_for<double, N>()>), g1, dim3(NT), 0, s, a, tasks);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (fp32) {
-    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, true, Q32, (Q32 > 1)>), g2, dim3(NT), 0, s, a, tasks);
-    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT, true, false, Q32, (Q32 > 1)>), g2, dim3(NT), 0, s, a, tasks);
+    constexpr int NT2 = pass2_threads_for<float, N>();
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT2, true, true, Q32, (Q32 > 1)>), g2, dim3(NT2), 0, s, a, tasks);
+    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT2, true, false, Q32, (Q32 > 1)>), g2, dim3(NT2), 0, s, a, tasks);
   } else {
     if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, true, Q64, (Q64 > 1)>), g2, dim3(NT), 0, s, a, tasks);
     else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, false, Q64, (Q64 > 1)>), g2, dim3(NT), 0, s, a, tasks);
