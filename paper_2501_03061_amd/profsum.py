@@ -93,7 +93,16 @@ def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, comm
         lines.append(f"| `{name}` | {len(fb[k])} | {f:,.0f} | {w:,.0f} | {rb / 1e9:.3f} | "
                      f"{wbts / 1e9:.3f} | {(rb + wbts) / 1e9:.3f} |")
         if "float" in k and _short(k).startswith("pass"):
-            kernels[_short(k)] = dict(read_bytes=rb, write_bytes=wbts, dispatches=len(fb[k]), name=k)
+            # instantiations of one pass (e.g. pass 3 with and without the kept
+            # v_ij) merge into a dispatch-weighted average per launch
+            d = len(fb[k])
+            prev = kernels.get(_short(k))
+            if prev:
+                n = prev["dispatches"] + d
+                rb = (prev["read_bytes"] * prev["dispatches"] + rb * d) / n
+                wbts = (prev["write_bytes"] * prev["dispatches"] + wbts * d) / n
+                d, k = n, prev["name"] + " + " + k
+            kernels[_short(k)] = dict(read_bytes=rb, write_bytes=wbts, dispatches=d, name=k)
     open(os.path.join(out, "pair_pipeline_mid72_hbm_counters.md"), "w").write("\n".join(lines) + "\n")
     json.dump(dict(source_digest=bench.source_digest(), fetch_factor=ff, write_factor=wf,
                    kernels=kernels, note="FP32 form, bytes per dispatch averaged over one step"),
