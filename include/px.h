@@ -24,6 +24,9 @@
  *     applied (the library returns Vx); there is no spin factor.
  *   FFT convention: forward exp(-iG.r) unnormalised, inverse exp(+iG.r) with
  *     1/N_g; for a real even kernel the result does not depend on the sign.
+ *   Alignment: orbital blocks (psi, phi, xi and the outputs) must be 16-byte
+ *     aligned; every orbital of a block then is too, since N_g is a multiple
+ *     of 64 on the supported grids.  Misaligned blocks: PX_ERR_INVALID_ARG.
  *   Memory: all array arguments are DEVICE pointers owned by the caller.  The
  *     library never allocates or frees device memory; scratch space comes from
  *     the workspace the caller attaches with px_set_workspace, sized by

@@ -51,6 +51,12 @@ template <typename T> __device__ __forceinline__ cpx<T> load_c(const cpx<T>* p) 
   }
 }
 
+typedef float vf4g __attribute__((ext_vector_type(4)));
+// Two consecutive complex64 values (16-byte aligned).
+__device__ __forceinline__ vf4g gload4(const cpx<float>* p) {
+  return *reinterpret_cast<const vf4g*>(p);
+}
+
 // Row of the 16x16 result held in item t of a lane with l/16 = q.
 template <typename T> __device__ __forceinline__ int drow(int q, int t) {
   return sizeof(T) == 8 ? q + 4 * t : 4 * q + t;
@@ -58,6 +64,7 @@ template <typename T> __device__ __forceinline__ int drow(int q, int t) {
 
 constexpr int XHY_SUB = 1024;  // FP32 form: r-span of one FP32 accumulation
 constexpr int XHY_KU = 4;      // k-steps of 4 per unrolled iteration (16 r)
+constexpr int XC_KU = 4;       // k-steps of 4 per group in xc (16 a)
 
 // ---------------------------------------------------------------- xhy
 // grid (ceil(na/64), ceil(nb/64), nsplit), 256 threads; wave w covers the
@@ -96,46 +103,85 @@ __global__ __launch_bounds__(256) void gemm_xhy_k(int na, int nb, size_t ng, con
       for (int t = 0; t < 4; ++t) dre[i][j][t] = dim[i][j][t] = 0.0;
     }
 
-  size_t r0 = r_begin;
-  while (r0 < r_end) {
-    const size_t sub_end = (sizeof(T) == 4) ? ((r0 + XHY_SUB < r_end) ? r0 + XHY_SUB : r_end) : r_end;
-    for (; r0 < sub_end; r0 += 4 * XHY_KU) {
-      // lane (m, q) reads r = r0 + 4q + s, s = 0..3 for each of its rows
-      cpx<T> xa[2][XHY_KU], yb[2][XHY_KU];
-      const size_t rl = r0 + 4 * q;
+  // Groups of 4*XHY_KU consecutive r.  Two register sets alternate: the next
+  // group loads into the idle set while the current one feeds the MFMAs.
+  // Loads past the chunk end read a valid address and are masked to zero, so
+  // every iteration issues the same loads (the group count is padded to even).
+  constexpr size_t GR = 4 * XHY_KU;
+  constexpr size_t GPS = XHY_SUB / GR;  // groups per FP32 accumulation span
+  const size_t ngroups = r_end > r_begin ? (r_end - r_begin + GR - 1) / GR : 0;
+  // (FP32: each lane's four consecutive complex values of a row come in two
+  // 16-byte loads, which halves the address work of the gather; the grids
+  // have N_g and the chunk bounds even, so a pair never straddles the end)
+  auto load = [&](size_t g, cpx<T>(&xa)[2][XHY_KU], cpx<T>(&yb)[2][XHY_KU]) {
+    const size_t rl = r_begin + g * GR + 4 * q;
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t) {
+      if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int s = 0; s < XHY_KU; s += 2) {
+          const size_t r = rl + s;
+          const bool in = r < r_end;
+          const size_t rc = in ? r : r_begin;
+          const vf4g x = gload4(xrow[t] + rc), y = gload4(yrow[t] + rc);
+          const bool ux = in && xv[t], uy = in && yv[t];
+          xa[t][s] = ux ? cpx<T>{x.x, x.y} : cpx<T>{T(0), T(0)};
+          xa[t][s + 1] = ux ? cpx<T>{x.z, x.w} : cpx<T>{T(0), T(0)};
+          yb[t][s] = uy ? cpx<T>{y.x, y.y} : cpx<T>{T(0), T(0)};
+          yb[t][s + 1] = uy ? cpx<T>{y.z, y.w} : cpx<T>{T(0), T(0)};
+        }
+      } else {
 #pragma unroll
         for (int s = 0; s < XHY_KU; ++s) {
-          const bool in = rl + s < sub_end;
-          xa[t][s] = (in && xv[t]) ? load_c(xrow[t] + rl + s) : cpx<T>{T(0), T(0)};
-          yb[t][s] = (in && yv[t]) ? load_c(yrow[t] + rl + s) : cpx<T>{T(0), T(0)};
+          const size_t r = rl + s;
+          const bool in = r < r_end;
+          const size_t rc = in ? r : r_begin;
+          const cpx<T> x = load_c(xrow[t] + rc), y = load_c(yrow[t] + rc);
+          xa[t][s] = (in && xv[t]) ? x : cpx<T>{T(0), T(0)};
+          yb[t][s] = (in && yv[t]) ? y : cpx<T>{T(0), T(0)};
         }
-#pragma unroll
-      for (int s = 0; s < XHY_KU; ++s)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            are[i][j] = mfma(xa[i][s].x, yb[j][s].x, are[i][j]);
-            are[i][j] = mfma(xa[i][s].y, yb[j][s].y, are[i][j]);
-            aim[i][j] = mfma(xa[i][s].x, yb[j][s].y, aim[i][j]);
-            aim[i][j] = mfma(-xa[i][s].y, yb[j][s].x, aim[i][j]);
-          }
+      }
     }
-    if constexpr (sizeof(T) == 4) {
+  };
+  auto compute = [&](size_t g, cpx<T>(&xa)[2][XHY_KU], cpx<T>(&yb)[2][XHY_KU]) {
+#pragma unroll
+    for (int s = 0; s < XHY_KU; ++s)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            dre[i][j][t] += double(are[i][j][t]);
-            dim[i][j][t] += double(aim[i][j][t]);
-          }
-          are[i][j] = A{0, 0, 0, 0};
-          aim[i][j] = A{0, 0, 0, 0};
+          are[i][j] = mfma(xa[i][s].x, yb[j][s].x, are[i][j]);
+          are[i][j] = mfma(xa[i][s].y, yb[j][s].y, are[i][j]);
+          aim[i][j] = mfma(xa[i][s].x, yb[j][s].y, aim[i][j]);
+          aim[i][j] = mfma(-xa[i][s].y, yb[j][s].x, aim[i][j]);
         }
+    if constexpr (sizeof(T) == 4) {
+      // FP32 accumulators span at most XHY_SUB values of r, then go to FP64
+      // (a padding group adds zeros, so a repeated flush is harmless)
+      if ((g + 1) % GPS == 0 || g + 1 >= ngroups) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              dre[i][j][t] += double(are[i][j][t]);
+              dim[i][j][t] += double(aim[i][j][t]);
+            }
+            are[i][j] = A{0, 0, 0, 0};
+            aim[i][j] = A{0, 0, 0, 0};
+          }
+      }
+    }
+  };
+  if (ngroups > 0) {
+    cpx<T> xa0[2][XHY_KU], yb0[2][XHY_KU], xa1[2][XHY_KU], yb1[2][XHY_KU];
+    load(0, xa0, yb0);
+    for (size_t g = 0; g < ngroups; g += 2) {
+      load(g + 1, xa1, yb1);
+      compute(g, xa0, yb0);
+      load(g + 2, xa0, yb0);
+      compute(g + 1, xa1, yb1);
     }
   }
   double* out = part + size_t(blockIdx.z) * na * nb * 2;
@@ -249,29 +295,50 @@ __global__ __launch_bounds__(256) void gemm_xc_k(int na, int nb, size_t ng, cons
       zre[i][j] = A{0, 0, 0, 0};
       zim[i][j] = A{0, 0, 0, 0};
     }
-  for (int a0 = 0; a0 < a_end; a0 += 4) {
-    const int a = a0 + q;
-    const bool av = a < a_end;
-    cpx<T> xa[2], cb[2];
+  // Groups of 4*XC_KU consecutive a (4 per MFMA k-step); two register sets
+  // alternate as in xhy, with masked loads from clamped addresses.
+  const size_t rc[2] = {rv[0] ? rr[0] : 0, rv[1] ? rr[1] : 0};
+  const int bc[2] = {bv[0] ? bb[0] : 0, bv[1] ? bb[1] : 0};
+  constexpr int GA = 4 * XC_KU;
+  const int ngroups = (a_end + GA - 1) / GA;
+  auto load = [&](int g, cpx<T>(&xa)[2][XC_KU], cpx<T>(&cb)[2][XC_KU]) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      xa[t] = (av && rv[t]) ? load_c(X + size_t(a) * ng + rr[t]) : cpx<T>{T(0), T(0)};
-      if (av && bv[t]) {
-        const double* c = C + (size_t(a) * ldc + bb[t]) * 2;
-        cb[t] = {T(c[0]), T(c[1])};
-      } else {
-        cb[t] = {T(0), T(0)};
+    for (int s = 0; s < XC_KU; ++s) {
+      const int a = g * GA + 4 * s + q;
+      const bool av = a < a_end;
+      const int ac = av ? a : 0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const cpx<T> x = load_c(X + size_t(ac) * ng + rc[t]);
+        const double* c = C + (size_t(ac) * ldc + bc[t]) * 2;
+        const double c0 = c[0], c1 = c[1];
+        xa[t][s] = (av && rv[t]) ? x : cpx<T>{T(0), T(0)};
+        cb[t][s] = (av && bv[t]) ? cpx<T>{T(c0), T(c1)} : cpx<T>{T(0), T(0)};
       }
     }
+  };
+  auto compute = [&](cpx<T>(&xa)[2][XC_KU], cpx<T>(&cb)[2][XC_KU]) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int s = 0; s < XC_KU; ++s)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        zre[i][j] = mfma(xa[i].x, cb[j].x, zre[i][j]);
-        zre[i][j] = mfma(-xa[i].y, cb[j].y, zre[i][j]);
-        zim[i][j] = mfma(xa[i].x, cb[j].y, zim[i][j]);
-        zim[i][j] = mfma(xa[i].y, cb[j].x, zim[i][j]);
-      }
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          zre[i][j] = mfma(xa[i][s].x, cb[j][s].x, zre[i][j]);
+          zre[i][j] = mfma(-xa[i][s].y, cb[j][s].y, zre[i][j]);
+          zim[i][j] = mfma(xa[i][s].x, cb[j][s].y, zim[i][j]);
+          zim[i][j] = mfma(xa[i][s].y, cb[j][s].x, zim[i][j]);
+        }
+  };
+  if (ngroups > 0) {
+    cpx<T> xa0[2][XC_KU], cb0[2][XC_KU], xa1[2][XC_KU], cb1[2][XC_KU];
+    load(0, xa0, cb0);
+    for (int g = 0; g < ngroups; g += 2) {
+      load(g + 1, xa1, cb1);
+      compute(xa0, cb0);
+      load(g + 2, xa0, cb0);
+      compute(xa1, cb1);
+    }
   }
   const T al = T(alpha);
 #pragma unroll

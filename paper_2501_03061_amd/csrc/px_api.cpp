@@ -14,6 +14,8 @@
 #include <vector>
 
 #include "../../include/px.h"
+#include <cstdint>
+
 #include "px_internal.hpp"
 
 struct px_context {
@@ -77,6 +79,8 @@ bool cell_ok(const px_cell* cell) {
 }
 
 size_t ngrid(const px_cell* c) { return size_t(c->n[0]) * c->n[1] * c->n[2]; }
+// Orbital blocks are read with 16-byte vector loads.
+bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) != 0; }
 size_t elem_bytes(px_precision p) { return p == PX_PREC_FP32 ? 8 : 16; }
 
 void default_tuning(const px_cell* cell, px_precision prec, int* ic, int* jc) {
@@ -439,6 +443,8 @@ px_status px_exchange_apply(px_context* ctx, const px_cell* cell, px_precision p
     return fail(ctx, PX_ERR_INVALID_ARG, "exchange_apply: null array argument");
   if (vx_phi == psi || vx_phi == phi)
     return fail(ctx, PX_ERR_INVALID_ARG, "exchange_apply: vx_phi must not alias psi or phi");
+  if (misaligned(psi) || misaligned(phi) || misaligned(vx_phi))
+    return fail(ctx, PX_ERR_INVALID_ARG, "exchange_apply: orbital blocks must be 16-byte aligned");
   if (e_x && (phi != psi || n_phi != n_psi))
     return fail(ctx, PX_ERR_INVALID_ARG, "exchange_apply: e_x requires phi == psi and n_phi == n_psi");
   int ic, jc;
@@ -474,6 +480,8 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   if (!psi || !occ || !kernel_G || !xi || !status)
     return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: null array argument");
   if (xi == psi) return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: xi must not alias psi");
+  if (misaligned(psi) || misaligned(xi))
+    return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: orbital blocks must be 16-byte aligned");
   int ic, jc;
   tuning_for(ctx, cell, prec, &ic, &jc);
   const AceLayout l = ace_layout(cell, prec, n, ic, jc, ctx->symmetric_ace);
@@ -534,6 +542,8 @@ px_status px_ace_apply(px_context* ctx, const px_cell* cell, px_precision prec, 
   if (!xi || !phi || !out) return fail(ctx, PX_ERR_INVALID_ARG, "ace_apply: null array argument");
   if (out == phi || out == xi)
     return fail(ctx, PX_ERR_INVALID_ARG, "ace_apply: out must not alias xi or phi");
+  if (misaligned(xi) || misaligned(phi) || misaligned(out))
+    return fail(ctx, PX_ERR_INVALID_ARG, "ace_apply: orbital blocks must be 16-byte aligned");
   const ApplyLayout l = apply_layout(cell, n, n_phi);
   px_status st = need_ws(ctx, l.end);
   if (st != PX_OK) return st;
@@ -569,6 +579,9 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
     return fail(ctx, PX_ERR_INVALID_ARG, "ptim_exchange_loop: null array argument");
   if (phi_out == phi_n || phi_out == xi)
     return fail(ctx, PX_ERR_INVALID_ARG, "ptim_exchange_loop: phi_out must not alias xi or phi_n");
+  if (misaligned(xi) || misaligned(phi_n) || misaligned(phi_out))
+    return fail(ctx, PX_ERR_INVALID_ARG,
+                "ptim_exchange_loop: orbital blocks must be 16-byte aligned");
   const LoopLayout l = loop_layout(cell, prec, n, n_phi);
   px_status st = need_ws(ctx, l.end);
   if (st != PX_OK) return st;
@@ -817,6 +830,8 @@ px_status check_instances(px_context* c, int n_inst, const px_instance* in, px_p
     if (!x.psi || !x.occ || !x.kernel_G || !x.out)
       return fail(c, PX_ERR_INVALID_ARG, "instance %d: null array argument", k);
     if (x.out == x.psi) return fail(c, PX_ERR_INVALID_ARG, "instance %d: out aliases psi", k);
+    if (misaligned(x.psi) || misaligned(x.out))
+      return fail(c, PX_ERR_INVALID_ARG, "instance %d: orbital blocks must be 16-byte aligned", k);
     if (ace && !x.status)
       return fail(c, PX_ERR_INVALID_ARG, "instance %d: ACE mode needs a status word", k);
   }
@@ -1016,8 +1031,10 @@ px_status px_autotune(px_context* ctx, const px_cell* cell, px_precision prec, i
     return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
   px_status st = check_grid(ctx, cell);
   if (st != PX_OK) return st;
-  if (n <= 0 || !psi || !occ || !kernel_G || !out || out == psi)
-    return fail(ctx, PX_ERR_INVALID_ARG, "autotune: need n > 0 and valid, non-aliased arrays");
+  if (n <= 0 || !psi || !occ || !kernel_G || !out || out == psi || misaligned(psi) ||
+      misaligned(out))
+    return fail(ctx, PX_ERR_INVALID_ARG,
+                "autotune: need n > 0 and valid, non-aliased, 16-byte aligned arrays");
   hipError_t he = hipSetDevice(ctx->device);
   if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
   const int cand[] = {8, 16, 24, 32, 48, 64};

@@ -91,6 +91,9 @@ def test_exchange_validation(lib, ctx):
     ex = ctypes.c_void_p(0x3000)
     assert _exchange(lib, ctx, c, phi=ctypes.c_void_p(0x4000), e_x=ex) == px.PX_ERR_INVALID_ARG
     assert _exchange(lib, ctx, c, n_phi=3, e_x=ex) == px.PX_ERR_INVALID_ARG
+    # orbital blocks are read with 16-byte vector loads
+    assert _exchange(lib, ctx, c, psi=ctypes.c_void_p(0x1008), phi=ctypes.c_void_p(0x1008)) == px.PX_ERR_INVALID_ARG
+    assert _exchange(lib, ctx, c, out=ctypes.c_void_p(0x2008)) == px.PX_ERR_INVALID_ARG
     # no workspace attached
     assert _exchange(lib, ctx, c) == px.PX_ERR_WORKSPACE
     assert b"workspace" in lib.px_last_error(ctx)
@@ -132,6 +135,8 @@ def test_ace_validation(lib, ctx):
     g = lib.px_ace_apply
     assert g(ctx, ctypes.byref(c), 0, 4, FAKE, 2, ctypes.c_void_p(0x7000), ctypes.c_void_p(0x7000), None) == px.PX_ERR_INVALID_ARG
     assert g(ctx, ctypes.byref(c), 0, 4, None, 2, ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000), None) == px.PX_ERR_INVALID_ARG
+    assert g(ctx, ctypes.byref(c), 0, 4, FAKE, 2, ctypes.c_void_p(0x7008), ctypes.c_void_p(0x8000), None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, ctypes.byref(c), 1, 4, ctypes.c_void_p(0x1008), FAKE, FAKE, ctypes.c_void_p(0x6000), None, None, st, None) == px.PX_ERR_INVALID_ARG
     assert g(ctx, ctypes.byref(c), 0, 4, FAKE, 2, ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000), None) == px.PX_ERR_WORKSPACE
 
 
