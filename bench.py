@@ -237,6 +237,69 @@ def bench_batch48(args):
     return rec
 
 
+def bench_large96(args):
+    """The large single-GPU share (96^3, 1536 orbitals, kT 0.03): one step of
+    each form (staging, ACE build, 4 PT-IM-style ACE iterations), timed after
+    one untimed step, and the ACE builds alone; FP32 against FP64 errors."""
+    import torch
+    from paper_2501_03061_amd import inputs, px
+    cfg = inputs.CONFIGS["large96"]
+    inst, psi64, phi64, occ = build_inputs(cfg)
+    n = inst.n_orb
+    cell = px.Cell(inst.L, inst.n)
+    ctx = px.Context(0)
+    kern = ctx.px_kernel_hse(cell, cfg["mu"])
+    pairs = n * n
+    res = {}
+    steps = {}
+    for name, fp32 in (("fp32", True), ("fp64", False)):
+        st = Step(ctx, cell, psi64, phi64, occ, kern, fp32=fp32)
+        st()
+        torch.cuda.synchronize()
+        ms = 1e3 * run_steps(st, 1)
+
+        def ace_only():
+            if fp32:
+                ctx.px_convert_c128_to_c64(psi64, st.psi)
+            ctx.px_ace_build(cell, st.psi, occ, kern, xi=st.xi, M=st.M, e_x=st.ex, status=st.status)
+        ace_s = run_steps(ace_only, 1)
+        st()
+        torch.cuda.synchronize()
+        ctx.px_sync()
+        res[name] = dict(ms_per_step=ms, pair_solves_per_s=pairs / (ms * 1e-3), ace_build_s=ace_s)
+        log(f"large96 {name}: step {ms:.0f} ms, ACE build {ace_s:.2f} s")
+        steps[name] = st
+        if not fp32:
+            continue
+        # keep only what the comparison needs before the FP64 buffers are allocated
+        st.psi = st.phi = None
+        torch.cuda.empty_cache()
+    s32, s64 = steps["fp32"], steps["fp64"]
+
+    def rel(a, b):
+        return float(torch.linalg.vector_norm((a.to(torch.complex128) - b).flatten()) /
+                     torch.linalg.vector_norm(b.flatten()))
+    ex32, ex64 = float(s32.ex.item()), float(s64.ex.item())
+    errs = dict(M=rel(s32.M, s64.M), e_x=abs(ex32 - ex64) / abs(ex64), ptim_out=rel(s32.out, s64.out),
+                residuals_fp32=[float(x) for x in s32.res.cpu()],
+                residuals_fp64=[float(x) for x in s64.res.cpu()])
+    rec = {
+        "metric": "exchange pair-solves/s + ACE build s, FP32-batched vs FP64 at <=2e-5 err",
+        "value": res["fp32"]["pair_solves_per_s"], "unit": "pair-solves/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": res["fp32"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "large96: cubic cell L=27 bohr, 96^3 grid, 1536 complex orbitals, "
+                               "Fermi-Dirac kT=0.03 Ha; step = staging + ACE build (2359296 pair "
+                               "solves) + 4 PT-IM-style ACE iterations",
+                   "grid": [96, 96, 96], "n_orbitals": n, "pairs_per_step": pairs},
+        "extra": {"fp32": res["fp32"], "fp64": res["fp64"],
+                  "speedup_fp32_vs_fp64": res["fp64"]["ms_per_step"] / res["fp32"]["ms_per_step"],
+                  "e_x_fp64": ex64, "err_fp32_vs_fp64": errs},
+    }
+    ctx.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,9 +309,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="mid72", choices=["mid72", "batch48"],
+    ap.add_argument("--workload", default="mid72", choices=["mid72", "batch48", "large96"],
                     help="mid72 (default, the headline): one 72^3 x 512 instance; batch48: the "
-                         "48-instance uneven batch in the batched form")
+                         "48-instance uneven batch in the batched form; large96: the 96^3 x 1536 "
+                         "single-GPU share, one step per form (several minutes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy kernel (2 GiB, 5 launches) and print its bandwidth")
     args = ap.parse_args()
@@ -268,6 +332,9 @@ def main():
         return
     if args.workload == "batch48":
         print(json.dumps(bench_batch48(args)), flush=True)
+        return
+    if args.workload == "large96":
+        print(json.dumps(bench_large96(args)), flush=True)
         return
 
     cfg = inputs.CONFIGS["mid72"]
