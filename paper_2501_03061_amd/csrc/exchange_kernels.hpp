@@ -494,8 +494,16 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
   static_assert(!PP || (NSX == 2 && NSY == 2), "ping-pong path assumes two-stage plans");
   using X0 = StageOf<N0, 0, true>;
   using X1 = StageOf<N0, 1, true>;
-  using Y0 = StageOf<N1, 0, true>;
-  using YL = StageOf<N1, NSY - 1, true>;
+  // FP32: y stages in the order whose last radix leaves fewer butterflies
+  // per thread, since the last stage's values stay in registers for the
+  // accumulation (96: 12 last, one butterfly per thread instead of two; 6 %
+  // faster).  Ties, and the FP64 form (slower that way at 96), keep the
+  // reversed order.
+  constexpr int RF = StageOf<N1, NSY - 1, false>::R, RR = StageOf<N1, NSY - 1, true>::R;
+  constexpr bool YREV = sizeof(T) == 8 ||
+                        (N0 * (N1 / RR) + NT - 1) / NT <= (N0 * (N1 / RF) + NT - 1) / NT;
+  using Y0 = StageOf<N1, 0, YREV>;
+  using YL = StageOf<N1, NSY - 1, YREV>;
   constexpr int NB0 = N1 * (N0 / X0::R), BPT0 = (NB0 + NT - 1) / NT;
   constexpr int NBL = N0 * (N1 / YL::R), BPTL = (NBL + NT - 1) / NT;
 
@@ -556,7 +564,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
       __syncthreads();
     } else {
       stages_lds<T, GX, true, NT, 1, NSX>(A, tw0);
-      stages_lds<T, GY, true, NT, 0, NSY - 1>(A, tw1);
+      stages_lds<T, GY, true, NT, 0, NSY - 1, YREV>(A, tw1);
     }
     // last stage: slots past the last butterfly repeat it (same values to the
     // same addresses), so every thread issues the same loads and stores
@@ -649,9 +657,11 @@ template <typename T, int N> constexpr bool prefetch3_for() {
 }
 
 // Threads of a pass-2 workgroup.  FP32 at 72^3: 512 (two butterflies per
-// thread in each stage) lets three workgroups share a CU instead of two.
+// thread in each stage) lets three workgroups share a CU instead of two; at
+// 96^3: 384 (two or three per thread), two workgroups of 6 waves instead of
+// one of 12 (measured on the same box).
 template <typename T, int N> constexpr int pass2_threads_for() {
-  return sizeof(T) == 4 && N == 72 ? 512 : threads_for<N>();
+  return sizeof(T) == 4 && N == 72 ? 512 : sizeof(T) == 4 && N == 96 ? 384 : threads_for<N>();
 }
 
 // Pairs per pass-2 workgroup, with prefetch of the next plane: FP64 at 72^3,
