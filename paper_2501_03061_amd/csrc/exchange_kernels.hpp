@@ -135,6 +135,25 @@ __device__ __forceinline__ void gather(cpx<T> (&v)[BPT][R], F&& load) {
   }
 }
 
+// The same for kernels without prefetch: a wave whose slots all lie past the
+// last butterfly issues no loads at all (the address unit is the bottleneck
+// of such kernels; their slots are never used).
+template <typename T, class G, int R, int NT, int BPT, class F>
+__device__ __forceinline__ void gather_live(cpx<T> (&v)[BPT][R], F&& load) {
+  constexpr int NB = G::nl * (G::n / R);
+  const int wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63);
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    if (NB % NT != 0 && wave0 + k * NT >= NB) continue;
+    int b = threadIdx.x + k * NT;
+    if (NB % NT != 0) b = b < NB ? b : NB - 1;
+    int line, j;
+    decode<G, R>(b, line, j);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[k][r] = load(line, j + r * (G::n / R));
+  }
+}
+
 // ============================================================== pass 1
 // PF: prefetch the next density orbital's slab while the current one is
 // transformed.  With two slab buffers in LDS (ping-pong, PP) every stage is
@@ -319,12 +338,14 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
   // global loads first: the first plane (at stage-0 positions) and the kernel
   // values at the positions the last forward stage produces
   cpx<T> nx[BPT0][F0::R];
-  gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) {
+  gather_live<T, GZ, F0::R, NT>(nx, [&](int line, int e) {
     return ldc(buf0 + size_t(pbeg) * slab * N2 + size_t(e) * slab + line);
   });
   KT kv[BPTL][FL::R];
+  const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
 #pragma unroll
   for (int k = 0; k < BPTL; ++k) {
+    if (NBL % NT != 0 && wave0 + k * NT >= NBL) continue;  // no live slot in this wave
     int b = tid + k * NT;
     if (NBL % NT != 0) b = b < NBL ? b : NBL - 1;
     int line, j;
@@ -342,7 +363,7 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
 #pragma unroll
       for (int r = 0; r < F0::R; ++r) v0[k][r] = nx[k][r];
   } else {
-    gather<T, GZ, F0::R, NT>(v0, [&](int line, int e) { return ldc(buf + size_t(e) * slab + line); });
+    gather_live<T, GZ, F0::R, NT>(v0, [&](int line, int e) { return ldc(buf + size_t(e) * slab + line); });
   }
   if (PF && p + 1 < pend)
     gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) { return ldc(buf + slab * N2 + size_t(e) * slab + line); });
@@ -411,12 +432,9 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
     ex = wave_sum(ex);
     if ((tid & 63) == 0) red[0][tid >> 6] = ex;
     if constexpr (G0) {
+      // the G = 0 term lives in thread 0 (slot 0 holds line 0, kz = 0)
       en = wave_sum(en);
-      ex0 = wave_sum(ex0);
-      if ((tid & 63) == 0) {
-        red[1][tid >> 6] = en;
-        red[2][tid >> 6] = ex0;
-      }
+      if ((tid & 63) == 0) red[1][tid >> 6] = en;
     }
   }
   __syncthreads();  // every thread is done reading LDS before it is overwritten
@@ -434,14 +452,12 @@ __global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkAr
   __syncthreads();
   if constexpr (EX) {
     if (tid == 0) {
-      double s2 = 0.0, s3 = 0.0, s4 = 0.0;
+      double s2 = 0.0, s3 = 0.0;
+      const double s4 = ex0;
 #pragma unroll
       for (int w = 0; w < NT / 64; ++w) {
         s2 += red[0][w];
-        if (G0) {
-          s3 += red[1][w];
-          s4 += red[2][w];
-        }
+        if (G0) s3 += red[1][w];
       }
       if constexpr (G0) {
         double* e = a.expart + (size_t(p) * N1 + y) * 3;
