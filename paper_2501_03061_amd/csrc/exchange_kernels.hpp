@@ -112,6 +112,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
+// Waves per SIMD that a CU could hold given the LDS of one workgroup (and at
+// most `cap`): used as the kernel's occupancy target, so that the register
+// allocation does not become the tighter limit.  Pass 2 in the FP32 form at
+// 40^3 and 64^3 gains from it (-22 %, -7 %; cap 6 keeps it free of spills);
+// elsewhere it did not help (32^3 got slower) and the cap is 1 (no target).
+template <typename T, int N> constexpr int pass2_wave_cap() {
+  return sizeof(T) == 4 && (N == 40 || N == 64) ? 6 : 1;
+}
+constexpr int lds_waves_per_simd(int lds_bytes, int nt, int cap) {
+  const int waves = (nt + 63) / 64;
+  int wgs = (160 * 1024) / lds_bytes;
+  if (wgs * waves > 32) wgs = 32 / waves;
+  const int w = (wgs * waves + 3) / 4;
+  return w < 1 ? 1 : (w > cap ? cap : w);
+}
+
 // Whether two slab buffers (ping-pong) fit in LDS next to the small tables.
 template <typename T, int N0, int N1> constexpr bool pingpong_fits() {
   return 2 * N1 * (N0 + 1) * int(sizeof(cpx<T>)) <= 150 * 1024;
@@ -305,7 +321,9 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
 // values of the plane are loaded once and, with PF, the next pair's plane is
 // in flight while the current one is transformed.
 template <typename T, int N0, int N1, int N2, int NT, bool G0, bool EX, int PQ, bool PF>
-__global__ __launch_bounds__(NT) void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    lds_waves_per_simd(N2 * (N0 + 1) * int(sizeof(cpx<T>)) + 1024, NT, pass2_wave_cap<T, N2>()))))
+void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
   const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
   const int np = a.ic * a.jc;
   const int pbeg = int(blockIdx.y) * PQ;
