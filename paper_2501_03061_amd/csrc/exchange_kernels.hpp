@@ -244,15 +244,24 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
       int line, j;
       decode<GX, X0::R>(valid ? b : 0, line, j);
       cpx<T> v[X0::R];
+      // G = 0 slab sums (FP32 form): the thread's few products are summed in
+      // FP32, the partials in FP64.  These are the transform's own inputs;
+      // with random rounding the partial sums add about 1e-10 relative to the
+      // coefficient of a diagonal pair, far below the FP32 transform's error.
+      T fre = T(0), fim = T(0), fen = T(0);
 #pragma unroll
       for (int r = 0; r < X0::R; ++r) {
-        const cpx<T> ps = cu[k][r], ph_ = ph[k][r];
-        if (G0 && valid) {
-          sre += double(ps.x) * double(ph_.x) + double(ps.y) * double(ph_.y);
-          sim += double(ps.x) * double(ph_.y) - double(ps.y) * double(ph_.x);
+        v[r] = cmulc(cu[k][r], ph[k][r]);
+        if (G0) {
+          fre += v[r].x;
+          fim += v[r].y;
+          fen += v[r].x * v[r].x + v[r].y * v[r].y;
         }
-        v[r] = cmulc(ps, ph_);
-        if (G0 && valid) sen += double(v[r].x * v[r].x + v[r].y * v[r].y);
+      }
+      if (G0 && valid) {
+        sre += double(fre);
+        sim += double(fim);
+        sen += double(fen);
       }
       dft<T, X0::R, false>(v);
       if (valid) {
