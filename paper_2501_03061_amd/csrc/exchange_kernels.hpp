@@ -177,7 +177,7 @@ __device__ __forceinline__ void gather_live(cpx<T> (&v)[BPT][R], F&& load) {
 // barriers; otherwise the middle stages run in place (two barriers each).
 template <typename T, int N0, int N1, int NT, bool G0, bool PF>
 __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs* tasks) {
-  const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
+  const ChunkArgs a = chunk_args(a0, tasks);
   if (int(blockIdx.y) >= a.ic) return;
   constexpr bool PP = pingpong_fits<T, N0, N1>();
   constexpr int P0 = N0 + 1;  // odd row pitch: no bank conflicts on stride-R writes
@@ -333,7 +333,7 @@ template <typename T, int N0, int N1, int N2, int NT, bool G0, bool EX, int PQ, 
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
     lds_waves_per_simd(N2 * (N0 + 1) * int(sizeof(cpx<T>)) + 1024, NT, pass2_wave_cap<T, N2>()))))
 void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
-  const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
+  const ChunkArgs a = chunk_args(a0, tasks);
   const int np = a.ic * a.jc;
   const int pbeg = int(blockIdx.y) * PQ;
   if (pbeg >= np) return;
@@ -523,7 +523,7 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
 // switch, so that the loop has the same stores on every path).
 template <typename T, int N0, int N1, int NT, bool PF, bool SV>
 __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const ChunkArgs* tasks) {
-  const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
+  const ChunkArgs a = chunk_args(a0, tasks);
   if (int(blockIdx.y) >= a.ic) return;
   constexpr bool PP = pingpong_fits<T, N0, N1>();
   constexpr int P0 = N0 + 1;

@@ -34,7 +34,7 @@ constexpr int JB = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void pass4_transpose_acc(ChunkArgs a0, const ChunkArgs* tasks,
                                                            size_t ng) {
-  const ChunkArgs a = tasks ? tasks[blockIdx.z] : a0;
+  const ChunkArgs a = chunk_args(a0, tasks);
   const size_t e = size_t(blockIdx.x) * 256 + threadIdx.x;
   const int j0 = blockIdx.y * JB;
   if (!a.store_v || j0 >= a.jc || e >= ng) return;

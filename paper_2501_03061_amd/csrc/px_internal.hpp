@@ -36,6 +36,46 @@ struct ChunkArgs {
   double inv_ng;
 };
 
+// The chunk of a kernel launch: the launch argument, or entry blockIdx.z of a
+// task table in device memory.  A table entry is read through the constant
+// address space (scalar loads), so that its fields are known to be uniform:
+// the compiler then keeps the base pointers in scalar registers and forms
+// addresses from 32-bit per-lane offsets.
+#if defined(__HIPCC__)
+__device__ __forceinline__ ChunkArgs chunk_args(const ChunkArgs& a0, const ChunkArgs* tasks) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (tasks) {
+    typedef const __attribute__((address_space(4))) ChunkArgs CChunk;
+    CChunk* c = (CChunk*)(tasks + blockIdx.z);
+    ChunkArgs a;
+    a.psi = c->psi;
+    a.phi = c->phi;
+    a.t = c->t;
+    a.out = c->out;
+    a.occ = c->occ;
+    a.kern = c->kern;
+    a.kern32 = c->kern32;
+    a.g0 = c->g0;
+    a.expart = c->expart;
+    a.n2 = c->n2;
+    a.i0 = c->i0;
+    a.ic = c->ic;
+    a.j0 = c->j0;
+    a.jc = c->jc;
+    a.first = c->first;
+    a.S = c->S;
+    a.s_ld = c->s_ld;
+    a.store_v = c->store_v;
+    a.inv_ng = c->inv_ng;
+    return a;
+  }
+  return a0;
+#else
+  return tasks ? tasks[blockIdx.z] : a0;
+#endif
+}
+#endif
+
 bool grid_supported(int n0, int n1, int n2);
 // Launches pass 1, 2, 3 of one chunk; ev (nullable) = 4 events recorded
 // before pass 1, between the passes and after pass 3.
