@@ -211,8 +211,8 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
 
   cpx<T> ph[BPT0][X0::R], nx[BPT0][X0::R];
   if constexpr (PF) {
-    gather<T, GX, X0::R, NT>(ph, [&](int line, int e) { return ldc(phi + line * N0 + e); });
-    gather<T, GX, X0::R, NT>(nx, [&](int line, int e) { return ldc(psi0 + line * N0 + e); });
+    gather<T, GX, X0::R, NT>(ph, [&](int line, int e) { return ldc(phi + unsigned(line * N0 + e)); });
+    gather<T, GX, X0::R, NT>(nx, [&](int line, int e) { return ldc(psi0 + unsigned(line * N0 + e)); });
   }
   __syncthreads();
 
@@ -227,12 +227,12 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
         for (int r = 0; r < X0::R; ++r) cu[k][r] = nx[k][r];
       if (jj + 1 < a.jc) {
         const cpx<T>* pn = psi0 + size_t(jj + 1) * ng;
-        gather<T, GX, X0::R, NT>(nx, [&](int line, int e) { return ldc(pn + line * N0 + e); });
+        gather<T, GX, X0::R, NT>(nx, [&](int line, int e) { return ldc(pn + unsigned(line * N0 + e)); });
       }
     } else {
       const cpx<T>* pc = psi0 + size_t(jj) * ng;
-      gather<T, GX, X0::R, NT>(cu, [&](int line, int e) { return ldc(pc + line * N0 + e); });
-      gather<T, GX, X0::R, NT>(ph, [&](int line, int e) { return ldc(phi + line * N0 + e); });
+      gather<T, GX, X0::R, NT>(cu, [&](int line, int e) { return ldc(pc + unsigned(line * N0 + e)); });
+      gather<T, GX, X0::R, NT>(ph, [&](int line, int e) { return ldc(phi + unsigned(line * N0 + e)); });
     }
     const int p = ii * a.jc + jj;
     double sre = 0.0, sim = 0.0, sen = 0.0;
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
         twiddle<T, N1, YL::R, YL::NS, false>(v, j, tw1);
         dft<T, YL::R, false>(v);
 #pragma unroll
-        for (int r = 0; r < YL::R; ++r) stn(out + line + (j + r * (N1 / YL::R)) * N0, v[r]);
+        for (int r = 0; r < YL::R; ++r) stn(out + unsigned(line + (j + r * (N1 / YL::R)) * N0), v[r]);
       }
     }
     if constexpr (!PP) __syncthreads();
@@ -366,7 +366,7 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
   // values at the positions the last forward stage produces
   cpx<T> nx[BPT0][F0::R];
   gather_live<T, GZ, F0::R, NT>(nx, [&](int line, int e) {
-    return ldc(buf0 + size_t(pbeg) * slab * N2 + size_t(e) * slab + line);
+    return ldc(buf0 + size_t(pbeg) * slab * N2 + unsigned(e * int(slab) + line));
   });
   KT kv[BPTL][FL::R];
   const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
@@ -378,7 +378,7 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
     int line, j;
     decode<GZ, FL::R>(b, line, j);
 #pragma unroll
-    for (int r = 0; r < FL::R; ++r) kv[k][r] = gld(kern + size_t(j + r * (N2 / FL::R)) * slab + line);
+    for (int r = 0; r < FL::R; ++r) kv[k][r] = gld(kern + unsigned((j + r * (N2 / FL::R)) * int(slab) + line));
   }
   fill_twiddles<T, N2, NT>(tw2);
   for (int p = pbeg; p < pend; ++p) {
@@ -390,10 +390,10 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
 #pragma unroll
       for (int r = 0; r < F0::R; ++r) v0[k][r] = nx[k][r];
   } else {
-    gather_live<T, GZ, F0::R, NT>(v0, [&](int line, int e) { return ldc(buf + size_t(e) * slab + line); });
+    gather_live<T, GZ, F0::R, NT>(v0, [&](int line, int e) { return ldc(buf + unsigned(e * int(slab) + line)); });
   }
   if (PF && p + 1 < pend)
-    gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) { return ldc(buf + slab * N2 + size_t(e) * slab + line); });
+    gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) { return ldc(buf + slab * N2 + unsigned(e * int(slab) + line)); });
   if (p > pbeg) __syncthreads();  // the previous pair's last stage has read LDS
 #pragma unroll
   for (int k = 0; k < BPT0; ++k) {
@@ -510,7 +510,7 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
       twiddle<T, N2, IL::R, IL::NS, true>(w, j, tw2);
       dft<T, IL::R, true>(w);
 #pragma unroll
-      for (int r = 0; r < IL::R; ++r) stn(buf + size_t(j + r * (N2 / IL::R)) * slab + line, w[r]);
+      for (int r = 0; r < IL::R; ++r) stn(buf + unsigned((j + r * (N2 / IL::R)) * int(slab) + line), w[r]);
     }
   }
   }  // pairs
@@ -559,10 +559,10 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
   const cpx<T>* t0 = reinterpret_cast<const cpx<T>*>(a.t) + size_t(ii * a.jc) * ng + z * slab;
   const cpx<T>* psi0 = reinterpret_cast<const cpx<T>*>(a.psi) + size_t(a.j0) * ng + z * slab;
   auto tload = [](const cpx<T>* base) {
-    return [base](int line, int e) { return ldg(base + line * N0 + e); };
+    return [base](int line, int e) { return ldg(base + unsigned(line * N0 + e)); };
   };
   auto pload = [](const cpx<T>* base) {
-    return [base](int line, int e) { return ldc(base + line + e * N0); };
+    return [base](int line, int e) { return ldc(base + unsigned(line + e * N0)); };
   };
   cpx<T>* const outz = reinterpret_cast<cpx<T>*>(a.out) + size_t(a.i0 + ii) * ng + z * slab;
   cpx<T> acc[BPTL][YL::R];
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
         if constexpr (!PF) {
           const cpx<T>* pj = psi0 + size_t(jj) * ng;
 #pragma unroll
-          for (int r = 0; r < YL::R; ++r) pc[k][r] = ldc(pj + line + (j + r * (N1 / YL::R)) * N0);
+          for (int r = 0; r < YL::R; ++r) pc[k][r] = ldc(pj + unsigned(line + (j + r * (N1 / YL::R)) * N0));
         }
         cpx<T> v[YL::R];
 #pragma unroll
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
           // symmetric mode: keep N_g * v_ij (real space) for the transposed pass
           cpx<T>* tv = reinterpret_cast<cpx<T>*>(a.t) + size_t(ii * a.jc + jj) * ng + z * slab;
 #pragma unroll
-          for (int r = 0; r < YL::R; ++r) stn(tv + line + (j + r * (N1 / YL::R)) * N0, v[r]);
+          for (int r = 0; r < YL::R; ++r) stn(tv + unsigned(line + (j + r * (N1 / YL::R)) * N0), v[r]);
         }
       }
     }
@@ -677,7 +677,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
 #pragma unroll
       for (int r = 0; r < YL::R; ++r) {
         const cpx<T> prev = a.first ? cpx<T>{T(0), T(0)} : pA[k][r];
-        stg(outz + line + (j + r * (N1 / YL::R)) * N0, csub(prev, acc[k][r]));
+        stg(outz + unsigned(line + (j + r * (N1 / YL::R)) * N0), csub(prev, acc[k][r]));
       }
     }
   }
