@@ -421,6 +421,7 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
       for (int r = 0; r < FL::R; ++r) v[k][r] = lds[(j + r * (N2 / FL::R)) * P0 + line];
       twiddle<T, N2, FL::R, FL::NS, false>(v[k], j, tw2);
       dft<T, FL::R, false>(v[k]);
+      T fex = T(0), fen = T(0);  // FP32 form: the thread's partial energy sums
 #pragma unroll
       for (int r = 0; r < FL::R; ++r) {
         const int kz = j + r * (N2 / FL::R);
@@ -438,13 +439,14 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
           if (EX) ex0 = k0 * (s0 * s0 + s1 * s1);
           v[k][r] = {T(k0 * s0), T(k0 * s1)};
         } else if constexpr (G0) {
-          // FP32 form: K(G) rounded to FP32; the energy partials take
-          // |rho|^2 from FP32 squares and accumulate in FP64
+          // FP32 form: K(G) rounded to FP32; the energy terms of the
+          // thread's few values are summed in FP32, the partials in FP64
+          // (random rounding: about 1e-10 relative on a pair's energy)
           const T kf = kv[k][r];
-          const double c2 = double(c.x * c.x + c.y * c.y);
+          const T c2 = c.x * c.x + c.y * c.y;
           if (EX) {
-            ex += kg * c2;
-            en += c2;
+            fex += kf * c2;
+            fen += c2;
           }
           v[k][r] = {kf * c.x, kf * c.y};
         } else {
@@ -452,6 +454,10 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
           if (EX) ex += kg * c2;
           v[k][r] = {T(kg * double(c.x)), T(kg * double(c.y))};
         }
+      }
+      if constexpr (G0 && EX) {
+        ex += double(fex);
+        en += double(fen);
       }
     }
   }
