@@ -120,6 +120,14 @@ class Step:
 DT_ALPHA = 50.0 / 24.188843265857 * 0.25
 
 
+def ace_stages(prof, ace):
+    """Per ACE build (ms): pair pipeline (passes 1-4), M contraction,
+    factorisation (Hermitise, Cholesky, inverse), xi contraction."""
+    calls = max(1, ace["calls"])
+    return dict(pair_pipeline=sum(p["ms"] for p in prof) / calls, M_contraction=ace["M"] / calls,
+                factorization=ace["factor"] / calls, xi_contraction=ace["xi"] / calls, builds=ace["calls"])
+
+
 def run_steps(step, k):
     import torch
     torch.cuda.synchronize()
@@ -352,10 +360,12 @@ def main():
     torch.cuda.synchronize()
     ctx.px_sync()
     ctx.px_profile_read(reset=True)
+    ctx.px_profile_read_ace(reset=True)
     ctx.px_set_profiling(True)
     ms_step = 1e3 * run_steps(step32, args.steps)
     ctx.px_set_profiling(False)
     prof = ctx.px_profile_read(reset=True)
+    ace_prof = ctx.px_profile_read_ace(reset=True)
     ctx.px_sync()
     pairs = n * n
     value = pairs / (ms_step * 1e-3)
@@ -385,6 +395,7 @@ def main():
                                launches_per_step=prof[k]["launches"] // args.steps,
                                GBps=prof[k]["bytes"] / (prof[k]["ms"] * 1e-3) / 1e9)
                 for k in range(4) if prof[k]["launches"] > 0},
+        ace_build_stages_fp32_ms=ace_stages(prof, ace_prof),
         e_x_fp32=float(step32.ex.item()),
         residuals_fp32=[float(x) for x in step32.res.cpu()],
     )
@@ -397,6 +408,14 @@ def main():
         ace_s64 = run_steps(lambda: ctx.px_ace_build(cell, psi64, occ, kern, xi=step64.xi, M=step64.M,
                                                      e_x=step64.ex, status=step64.status), 1)
         ctx.px_sync()
+        # stage breakdown of one more (profiled) FP64 build
+        ctx.px_profile_read(reset=True)
+        ctx.px_profile_read_ace(reset=True)
+        ctx.px_set_profiling(True)
+        ctx.px_ace_build(cell, psi64, occ, kern, xi=step64.xi, M=step64.M, e_x=step64.ex,
+                         status=step64.status)
+        ctx.px_set_profiling(False)
+        stages64 = ace_stages(ctx.px_profile_read(reset=True), ctx.px_profile_read_ace(reset=True))
         step32()
         torch.cuda.synchronize()
         ctx.px_sync()
@@ -409,6 +428,7 @@ def main():
             fp64_pair_solves_per_s=pairs / (ms64 * 1e-3),
             fp64_ms_per_step=ms64,
             ace_build_s_fp64=ace_s64,
+            ace_build_stages_fp64_ms=stages64,
             speedup_fp32_vs_fp64=(pairs / (ms_step * 1e-3)) / (pairs / (ms64 * 1e-3)),
             err_fp32_vs_fp64=dict(M=rel(step32.M, step64.M), e_x=abs(ex32 - ex64) / abs(ex64),
                                   xi=rel(step32.xi, step64.xi),

@@ -199,6 +199,14 @@ px_status px_set_profiling(px_context* ctx, int32_t enable);
 px_status px_profile_read(px_context* ctx, double* ms, double* bytes, int64_t* launches,
                           int32_t reset);
 
+/* Stage times of the ACE builds (px_ace_build) made while profiling was on,
+ * since the last reset (Sec. IV-A-2, Eq. (14): the steps after W = Vx Psi):
+ * ms[0] the contraction M = dV Psi^H W, ms[1] the factorisation (Hermitising,
+ * Cholesky of -M and U = L^{-H}), ms[2] the contraction xi = W U; *calls the
+ * number of builds.  The pair pipeline of the builds is in px_profile_read.
+ * Each profiled build synchronises on its last event.  reset != 0 zeroes. */
+px_status px_profile_read_ace(px_context* ctx, double* ms, int64_t* calls, int32_t reset);
+
 /* One instance of the batched form: the exchange operator of an orbital block
  * applied to the same block (Phi = Psi), optionally followed by its ACE
  * construction.  Arrays as in px_exchange_apply / px_ace_build, element type

@@ -32,6 +32,9 @@ struct px_context {
   double prof_ms[4] = {0, 0, 0, 0};
   double prof_bytes[4] = {0, 0, 0, 0};
   int64_t prof_launches[4] = {0, 0, 0, 0};
+  hipEvent_t ace_events[4] = {nullptr, nullptr, nullptr, nullptr};  // ACE build stages
+  double ace_ms[3] = {0, 0, 0};
+  int64_t ace_calls = 0;
   bool symmetric_ace = true;  // ACE build solves only pairs j <= i (block level)
   // batched form: the graph of the last batched call, replayed while the call
   // signature (instances, pointers, workspace) stays the same
@@ -44,6 +47,8 @@ struct px_context {
   size_t pinned_bytes = 0;
   ~px_context() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ace_events)
+      if (e) (void)hipEventDestroy(e);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (pinned_tasks) (void)hipHostFree(pinned_tasks);
@@ -511,10 +516,18 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   }
   int nsplit = 0;
   px::gemm_xhy_part_elems(n, n, ng, &nsplit);
+  hipEvent_t* ev = ctx->ace_events;
+  if (ctx->profiling) {
+    for (int k = 0; k < 4; ++k)
+      if (!ev[k] && hipEventCreate(&ev[k]) != hipSuccess)
+        return fail(ctx, PX_ERR_DEVICE, "hipEventCreate failed");
+    (void)hipEventRecord(ev[0], stream);
+  }
   // M = dV Psi^H W, Hermitised; -M = L L^H; U = L^{-H}; xi = W U
   st = hip_check(ctx, px::launch_gemm_xhy(fp32, n, n, ng, psi, W, dV, Mw, n, part, nsplit, stream),
                  "M = dV Psi^H W");
   if (st != PX_OK) return st;
+  if (ctx->profiling) (void)hipEventRecord(ev[1], stream);
   st = hip_check(ctx, px::launch_hermitize(Mw, n, stream), "hermitize");
   if (st != PX_OK) return st;
   st = hip_check(ctx,
@@ -522,10 +535,23 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
                                      reinterpret_cast<double*>(ctx->ws + l.dinv), stream),
                  "cholesky");
   if (st != PX_OK) return st;
+  if (ctx->profiling) (void)hipEventRecord(ev[2], stream);
   st = hip_check(ctx, px::launch_gemm_xc(fp32, n, n, ng, W, U, n, 1.0, xi, true, stream),
                  "xi = W L^-H");
   if (st != PX_OK) return st;
   ctx->last_status.assign(1, status);
+  if (ctx->profiling) {
+    (void)hipEventRecord(ev[3], stream);
+    he = hipEventSynchronize(ev[3]);
+    if (he != hipSuccess) return hip_check(ctx, he, "profiling sync");
+    for (int k = 0; k < 3; ++k) {
+      float ms = 0.f;
+      he = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      if (he != hipSuccess) return hip_check(ctx, he, "hipEventElapsedTime");
+      ctx->ace_ms[k] += ms;
+    }
+    ctx->ace_calls += 1;
+  }
   return PX_OK;
 }
 
@@ -641,6 +667,17 @@ px_status px_profile_read(px_context* ctx, double* ms, double* bytes, int64_t* l
     launches[k] = ctx->prof_launches[k];
     if (reset) ctx->prof_ms[k] = ctx->prof_bytes[k] = 0.0, ctx->prof_launches[k] = 0;
   }
+  return PX_OK;
+}
+
+px_status px_profile_read_ace(px_context* ctx, double* ms, int64_t* calls, int32_t reset) {
+  if (!ctx || !ms || !calls) return PX_ERR_INVALID_ARG;
+  for (int k = 0; k < 3; ++k) {
+    ms[k] = ctx->ace_ms[k];
+    if (reset) ctx->ace_ms[k] = 0.0;
+  }
+  *calls = ctx->ace_calls;
+  if (reset) ctx->ace_calls = 0;
   return PX_OK;
 }
 

@@ -59,6 +59,7 @@ SIGNATURES = {
     "px_ptim_exchange_loop": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _i32, _dbl, _vp, _vp, _vp]),
     "px_set_symmetry": (_i32, [_vp, _i32]),
     "px_set_profiling": (_i32, [_vp, _i32]),
+    "px_profile_read_ace": (_i32, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(ctypes.c_int64), _i32]),
     "px_profile_read": (_i32, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl),
                                ctypes.POINTER(ctypes.c_int64), _i32]),
     "px_workspace_bytes_batched": (_sz, [_vp, _i32, _instp, _i32, _i32]),
@@ -303,6 +304,13 @@ class Context:
         la = (ctypes.c_int64 * 4)()
         self._check(self.lib.px_profile_read(self.h, ms, by, la, 1 if reset else 0))
         return [dict(ms=ms[k], bytes=by[k], launches=la[k]) for k in range(4)]
+
+    def px_profile_read_ace(self, reset: bool = False):
+        """ACE build stages while profiling: dict(M=ms, factor=ms, xi=ms, calls=n)."""
+        ms = (ctypes.c_double * 3)()
+        calls = ctypes.c_int64()
+        self._check(self.lib.px_profile_read_ace(self.h, ms, ctypes.byref(calls), 1 if reset else 0))
+        return dict(M=ms[0], factor=ms[1], xi=ms[2], calls=calls.value)
 
     def px_exchange_apply_batched(self, instances, ace=False, stream=None):
         """instances: list of dicts with cell (Cell), psi, occ, kern and optional

@@ -151,3 +151,29 @@ def test_ace_build_symmetry_modes_ragged_blocks(px_ctx, fp32, sym):
     assert relerr(y, r["W"]) < tol
     assert relerr(to_host(xi), r["xi"]) < tol
     assert abs(e - ex) < (FP32_EX_TOL if fp32 else FP64_TOL) * abs(ex)
+
+
+def test_ace_build_profiling_stages(px_ctx, toy):
+    """Profiling mode: per-pass and per-stage times of one build are reported,
+    and the profiled build gives the same result as an unprofiled one."""
+    inst, K, dV, r = toy
+    banner("ace build profiling stages")
+    cell = px.Cell(inst.L, inst.n)
+    kd = px_ctx.px_kernel_hse(cell, 0.106)
+    _, _, xi0, M0, _, _ = _build(px_ctx, inst, kd, False)
+    px_ctx.px_profile_read(reset=True)
+    px_ctx.px_profile_read_ace(reset=True)
+    px_ctx.px_set_profiling(True)
+    try:
+        _, _, xi1, M1, _, st = _build(px_ctx, inst, kd, False)
+    finally:
+        px_ctx.px_set_profiling(False)
+    passes = px_ctx.px_profile_read(reset=True)
+    stages = px_ctx.px_profile_read_ace(reset=True)
+    assert st == 0
+    assert stages["calls"] == 1
+    assert stages["M"] > 0 and stages["factor"] > 0 and stages["xi"] > 0
+    assert all(p["launches"] > 0 and p["ms"] > 0 for p in passes[:3])
+    assert np.array_equal(M0, M1)
+    assert np.array_equal(to_host(xi0), to_host(xi1))
+    assert px_ctx.px_profile_read_ace()["calls"] == 0
