@@ -341,7 +341,7 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
   constexpr int P0 = N0 + 1;
   __shared__ cpx<T> lds[N2 * P0];
   __shared__ cpx<T> tw2[N2];
-  __shared__ double red[3][NT / 64];
+  __shared__ double red[2][NT / 64];
   using GZ = Lines<N2, N0, 1, P0, true>;  // plane [z][x], lines along z
   constexpr int NS = Plan<N2>::nst;
   using F0 = StageOf<N2, 0, false>;

@@ -222,8 +222,6 @@ px_status need_ws(px_context* c, size_t bytes) {
   return PX_OK;
 }
 
-// Enqueue the pair pipeline for all (i, j); `out` gets Vx phi.  S, when
-// non-null, receives sum_G K |rho_ij(G)|^2 per pair for the energy.
 // Enqueue the pair pipeline; `out` gets Vx phi.  With energy, S[i][j]
 // receives sum_G K |rho_ij(G)|^2 per pair.  Symmetric mode (phi is psi): the
 // orbitals are cut into square blocks of B = max(ic, jc); only blocks J <= I
