@@ -109,15 +109,66 @@ def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, comm
               open(os.path.join(out, "pair_pipeline_mid72_traffic.json"), "w"), indent=1)
 
 
+def summarize_mfma(mfma, out, command):
+    """MFMA counters of the contractions (one --pmc run of bench.py): flops
+    from SQ_INSTS_VALU_MFMA_MOPS_* (512 flops each), MFMA busy fraction from
+    SQ_VALU_MFMA_BUSY_CYCLES over 4 SIMDs x SQ_BUSY_CU_CYCLES, and the rate
+    over the dispatch duration recorded with the counters."""
+    rows = collections.defaultdict(lambda: collections.defaultdict(list))
+    durs = collections.defaultdict(dict)
+    for r in _csv(mfma, "counter_collection.csv"):
+        k = r["Kernel_Name"]
+        if "gemm_" not in k:
+            continue
+        rows[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        durs[k][r["Dispatch_Id"]] = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9
+    lines = ["# MFMA counters: complex contractions, mid72 workload (512 x 512 x 72^3)", "",
+             "Command (repository root, one MI355X):", "", "```", command, "```", "",
+             "Each row groups the dispatches of one kernel with the same flop count (the xi = W U "
+             "contraction of the ACE build uses only the upper-triangular U, about half the flops of "
+             "a dense one). GFLOP = SQ_INSTS_VALU_MFMA_MOPS x 512; MFMA busy = "
+             "SQ_VALU_MFMA_BUSY_CYCLES / (4 SIMDs x SQ_BUSY_CU_CYCLES); rate = GFLOP / dispatch "
+             "duration; peaks 157.3 TFLOP/s (FP32 MFMA) and 78.6 TFLOP/s (FP64 MFMA).", "",
+             "| kernel | dispatches | GFLOP per dispatch | avg duration (ms) | TFLOP/s | % of peak | MFMA busy |",
+             "|---|---|---|---|---|---|---|"]
+    for k, cs in rows.items():
+        mops = cs.get("SQ_INSTS_VALU_MFMA_MOPS_F32", []) if "float" in k else cs.get("SQ_INSTS_VALU_MFMA_MOPS_F64", [])
+        busy, cu = cs.get("SQ_VALU_MFMA_BUSY_CYCLES", []), cs.get("SQ_BUSY_CU_CYCLES", [])
+        d = list(durs[k].values())
+        if not (mops and busy and cu and len(d) == len(mops)):
+            continue
+        peak = 157.3 if "float" in k else 78.6
+        groups = collections.defaultdict(list)
+        for i, m in enumerate(mops):
+            groups[round(m / 1e6)].append(i)
+        name = _short(k) + ("<float>" if "float" in k else "<double>")
+        for g, idx in sorted(groups.items()):
+            gf = g * 1e6 * 512 / 1e9
+            dt = sum(d[i] for i in idx) / len(idx)
+            frac = sum(busy[i] / (4 * cu[i]) for i in idx) / len(idx)
+            tf = gf / dt / 1e3
+            lines.append(f"| `{name}` | {len(idx)} | {gf:.0f} | {dt * 1e3:.2f} | {tf:.1f} | "
+                         f"{100 * tf / peak:.0f} % | {100 * frac:.0f} % |")
+    open(os.path.join(out, "gemm_mid72_mfma_counters.md"), "w").write("\n".join(lines) + "\n")
+
+
 def main():
     import sys
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     ap = argparse.ArgumentParser()
     for a in ("trace", "fetch", "write", "copy-fetch", "copy-write", "bench-json"):
-        ap.add_argument("--" + a, required=True)
+        ap.add_argument("--" + a)
+    ap.add_argument("--mfma", help="rocprofv3 --pmc run with the MFMA counters (contractions)")
     ap.add_argument("--out", default="profiles")
     args = ap.parse_args()
     pre = "cd /tmp && export TMPDIR=/tmp"
+    if args.mfma:
+        summarize_mfma(args.mfma, args.out, pre + "\ntimeout -s KILL 300 rocprofv3 --pmc "
+                       "SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_VALU_MFMA_BUSY_CYCLES "
+                       "SQ_BUSY_CU_CYCLES --output-format csv -d $REPO/gpurun_out/pmc_mfma_bench -o run -- "
+                       "python3 $REPO/bench.py --steps 1 --warmup 0 --no-cpu")
+        if not args.trace:
+            return
     commands = {
         "trace": pre + "\nrocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/trace_bench "
                        "-o run -- python3 $REPO/bench.py",
