@@ -133,6 +133,31 @@ template <typename T, int N0, int N1> constexpr bool pingpong_fits() {
   return 2 * N1 * (N0 + 1) * int(sizeof(cpx<T>)) <= 150 * 1024;
 }
 
+// Workgroups of nt threads and lds bytes that a CU can hold (LDS and waves).
+constexpr int wgs_per_cu(int lds_bytes, int nt) {
+  const int cap = 32 / ((nt + 63) / 64);
+  const int w = (160 * 1024) / lds_bytes;
+  return w < cap ? w : cap;
+}
+// Whether a workgroup's LDS can grow from `base` to `with` bytes without
+// lowering the number of workgroups that a CU can hold.  Used for the
+// per-thread partial sums that a few waves add up after a barrier (one wave
+// per sum instead of a wave reduction in every wave).
+constexpr bool lds_growth_free(int base, int with, int nt) {
+  return with <= 160 * 1024 && wgs_per_cu(with, nt) >= wgs_per_cu(base, nt);
+}
+template <typename T, int N0, int N1, int NT> constexpr bool g0_lds_fits() {
+  constexpr int nw = (NT + 63) / 64;
+  constexpr int sl = N1 * (N0 + 1) * int(sizeof(cpx<T>));
+  constexpr int base = (pingpong_fits<T, N0, N1>() ? 2 : 1) * sl + (N0 + N1) * int(sizeof(cpx<T>)) + 3 * nw * 8;
+  return lds_growth_free(base, base - 3 * nw * 8 + 3 * NT * int(sizeof(T)), NT);
+}
+template <typename T, int N0, int N2, int NT, bool G0> constexpr bool ex_lds_fits() {
+  constexpr int nw = (NT + 63) / 64;
+  constexpr int base = (N2 * (N0 + 1) + N2) * int(sizeof(cpx<T>)) + 2 * nw * 8;
+  return lds_growth_free(base, base - 2 * nw * 8 + (G0 ? 2 : 1) * NT * 8, NT);
+}
+
 // Branch-free gather of the R inputs of every butterfly slot of a stage whose
 // reads are x[j + r*N/R] along the lines of geometry G: slot indices past the
 // last butterfly are clamped to it (loaded, never stored), so all loads of a
@@ -185,7 +210,6 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
   __shared__ cpx<T> lds[PP ? 2 * SL : SL];
   __shared__ cpx<T> tw0[N0];
   __shared__ cpx<T> tw1[N1];
-  __shared__ double red[3][NT / 64];
   using GX = Lines<N0, N1, P0, 1, false>;  // rows: contiguous lines
   using GY = Lines<N1, N0, 1, P0, true>;   // columns: strided lines
   constexpr int NSX = Plan<N0>::nst, NSY = Plan<N1>::nst;
@@ -199,6 +223,14 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
   using YL = StageOf<N1, NSY - 1, false>;
   constexpr int NB0 = N1 * (N0 / X0::R), BPT0 = (NB0 + NT - 1) / NT;
   constexpr int NBL = N0 * (N1 / YL::R), BPTL = (NBL + NT - 1) / NT;
+  // G = 0 sums: with GL every thread leaves its FP32 partials in LDS and a
+  // few waves add them in FP64 after the barrier that follows the first
+  // stage (one wave per sum instead of a wave reduction in every wave: -6 %
+  // pass time at 72^3); otherwise each wave reduces its own partials
+  constexpr int NW = NT / 64;
+  constexpr bool GL = G0 && BPT0 == 1 && NT % 64 == 0 && g0_lds_fits<T, N0, N1, NT>();
+  __shared__ T gpart[GL ? 3 * NT : 1];
+  __shared__ double red[GL || !G0 ? 1 : 3][NW];
 
   fill_twiddles<T, N0, NT>(tw0);
   fill_twiddles<T, N1, NT>(tw1);
@@ -236,6 +268,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
     }
     const int p = ii * a.jc + jj;
     double sre = 0.0, sim = 0.0, sen = 0.0;
+    T gre = T(0), gim = T(0), gen = T(0);
     // first x stage from registers: product, radix butterfly, LDS
 #pragma unroll
     for (int k = 0; k < BPT0; ++k) {
@@ -259,9 +292,15 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
         }
       }
       if (G0 && valid) {
-        sre += double(fre);
-        sim += double(fim);
-        sen += double(fen);
+        if constexpr (GL) {
+          gre = fre;
+          gim = fim;
+          gen = fen;
+        } else {
+          sre += double(fre);
+          sim += double(fim);
+          sen += double(fen);
+        }
       }
       dft<T, X0::R, false>(v);
       if (valid) {
@@ -269,7 +308,11 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
         for (int r = 0; r < X0::R; ++r) A[line * P0 + out_pos<X0::R, 1>(j, r)] = v[r];
       }
     }
-    if constexpr (G0) {
+    if constexpr (GL) {
+      gpart[tid] = gre;
+      gpart[NT + tid] = gim;
+      gpart[2 * NT + tid] = gen;
+    } else if constexpr (G0) {
       sre = wave_sum(sre);
       sim = wave_sum(sim);
       sen = wave_sum(sen);
@@ -280,11 +323,27 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
       }
     }
     __syncthreads();
-    if constexpr (G0) {
+    if constexpr (GL) {
+      // sum c (re, im, energy) is added by wave c mod NW; the partials are
+      // read before this wave reaches the next barrier, so the next pair
+      // cannot overwrite them earlier
+      const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+      double* g = reinterpret_cast<double*>(a.g0 + size_t(p) * a.n2 + z);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (w == c % NW) {
+          double sc = 0.0;
+#pragma unroll
+          for (int q = 0; q < NW; ++q) sc += double(gpart[c * NT + q * 64 + (tid & 63)]);
+          sc = wave_sum(sc);
+          if ((tid & 63) == 0) gst(g + c, sc);
+        }
+      }
+    } else if constexpr (G0) {
       if (tid == 0) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
-        for (int w = 0; w < NT / 64; ++w) {
+        for (int w = 0; w < NW; ++w) {
           s0 += red[0][w];
           s1 += red[1][w];
           s2 += red[2][w];
@@ -339,9 +398,14 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
   if (pbeg >= np) return;
   const int pend = pbeg + PQ < np ? pbeg + PQ : np;
   constexpr int P0 = N0 + 1;
+  // energy partials: as the G = 0 sums of pass 1 (EL: per thread in LDS, one
+  // wave per sum), else a wave reduction in every wave
+  constexpr int NW = NT / 64, NE = G0 ? 2 : 1;
+  constexpr bool EL = EX && NT % 64 == 0 && ex_lds_fits<T, N0, N2, NT, G0>();
   __shared__ cpx<T> lds[N2 * P0];
   __shared__ cpx<T> tw2[N2];
-  __shared__ double red[2][NT / 64];
+  __shared__ double red[EL ? 1 : 2][NW];
+  __shared__ double epart[EL ? NE * NT : 1];
   using GZ = Lines<N2, N0, 1, P0, true>;  // plane [z][x], lines along z
   constexpr int NS = Plan<N2>::nst;
   using F0 = StageOf<N2, 0, false>;
@@ -461,7 +525,10 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
       }
     }
   }
-  if constexpr (EX) {
+  if constexpr (EL) {
+    epart[tid] = ex;
+    if constexpr (G0) epart[NT + tid] = en;
+  } else if constexpr (EX) {
     ex = wave_sum(ex);
     if ((tid & 63) == 0) red[0][tid >> 6] = ex;
     if constexpr (G0) {
@@ -483,7 +550,23 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
     }
   }
   __syncthreads();
-  if constexpr (EX) {
+  if constexpr (EL) {
+    // sum c is added by wave c mod NW, which reads the partials before it
+    // reaches the next barrier; the G = 0 term lives in thread 0
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    double* e = G0 ? a.expart + (size_t(p) * N1 + y) * 3 : a.expart + size_t(p) * N1 + y;
+#pragma unroll
+    for (int c = 0; c < NE; ++c) {
+      if (w == c % NW) {
+        double sc = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) sc += epart[c * NT + q * 64 + (tid & 63)];
+        sc = wave_sum(sc);
+        if ((tid & 63) == 0) gst(e + c, sc);
+      }
+    }
+    if (G0 && tid == 0) gst(e + 2, ex0);
+  } else if constexpr (EX) {
     if (tid == 0) {
       double s2 = 0.0, s3 = 0.0;
       const double s4 = ex0;
