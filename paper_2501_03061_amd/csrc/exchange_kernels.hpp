@@ -281,16 +281,15 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
       // FP32, the partials in FP64.  These are the transform's own inputs;
       // with random rounding the partial sums add about 1e-10 relative to the
       // coefficient of a diagonal pair, far below the FP32 transform's error.
-      T fre = T(0), fim = T(0), fen = T(0);
+      T fen = T(0);
 #pragma unroll
       for (int r = 0; r < X0::R; ++r) {
         v[r] = cmulc(cu[k][r], ph[k][r]);
-        if (G0) {
-          fre += v[r].x;
-          fim += v[r].y;
-          fen += v[r].x * v[r].x + v[r].y * v[r].y;
-        }
+        if (G0) fen += v[r].x * v[r].x + v[r].y * v[r].y;
       }
+      dft<T, X0::R, false>(v);
+      // the butterfly's DC output is the FP32 sum of its R inputs
+      const T fre = v[0].x, fim = v[0].y;
       if (G0 && valid) {
         if constexpr (GL) {
           gre = fre;
@@ -302,7 +301,6 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
           sen += double(fen);
         }
       }
-      dft<T, X0::R, false>(v);
       if (valid) {
 #pragma unroll
         for (int r = 0; r < X0::R; ++r) A[line * P0 + out_pos<X0::R, 1>(j, r)] = v[r];
