@@ -622,6 +622,13 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
   }  // pairs
 }
 
+// Pass 3 with PF: also prefetch the next psi_j slab (a second register set),
+// FP32 only.  Measured on the same box: 72^3 -4 %, 32^3 and 40^3 -1 to -2 %;
+// 48^3 +11 % and 64^3 +7 % (the larger register set costs occupancy there).
+template <typename T, int N> constexpr bool psi_prefetch3_for() {
+  return sizeof(T) == 4 && (N == 72 || N <= 40);
+}
+
 // ============================================================== pass 3
 // PF: prefetch the next pair slab and the next psi_j slab during the transform.
 // PP as in pass 1.
@@ -655,6 +662,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
   using YL = StageOf<N1, NSY - 1, YREV>;
   constexpr int NB0 = N1 * (N0 / X0::R), BPT0 = (NB0 + NT - 1) / NT;
   constexpr int NBL = N0 * (N1 / YL::R), BPTL = (NBL + NT - 1) / NT;
+  constexpr bool PSI = PF && psi_prefetch3_for<T, N0>();
 
   fill_twiddles<T, N0, NT>(tw0);
   fill_twiddles<T, N1, NT>(tw1);
@@ -679,19 +687,21 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
   auto weight = [&](int jj) { return T(gld(a.occ + a.j0 + jj) * a.inv_ng); };
 
   // One pair: inverse x and y transforms of the pair slab held in tc, then
-  // the psi_j-weighted accumulation.  With PF the psi_j slab is requested
-  // first and then the next pair slab (into tn), so that waiting for psi_j
-  // at the end never waits for the prefetch; otherwise psi_j loads in the
-  // last stage.
-  auto step = [&](int jj, cpx<T>(&tc)[BPT0][X0::R], cpx<T>(&tn)[BPT0][X0::R]) {
+  // the psi_j-weighted accumulation with the psi_j slab in pc.  With PF the
+  // next pair slab is requested at the start (into tn).  With PSI the next
+  // psi_j slab is requested too (into pn), after the last stage and before
+  // this pair's stores: memory requests complete in order, so the wait for
+  // psi_j then never waits for stores.  Otherwise psi_j is requested at the
+  // start, before the next pair slab, or without PF in the last stage.
+  auto step = [&](int jj, cpx<T>(&tc)[BPT0][X0::R], cpx<T>(&tn)[BPT0][X0::R],
+                  cpx<T>(&pc)[BPTL][YL::R], cpx<T>(&pn)[BPTL][YL::R]) {
     cpx<T>* A = lds + (PP ? (jj & 1) * SL : 0);
     cpx<T>* B = lds + (PP ? (1 - (jj & 1)) * SL : 0);
-    cpx<T> pc[BPTL][YL::R];
     const T wj = weight(jj);  // requested before the slabs: waiting for it waits for nothing else
+    // the last pair re-requests its own slabs: the loop stays branch free
+    const int jn = jj + 1 < a.jc ? jj + 1 : jj;
     if constexpr (PF) {
-      gather<T, GY, YL::R, NT>(pc, pload(psi0 + size_t(jj) * ng));
-      // the last pair re-requests its own slab: the loop stays branch free
-      const int jn = jj + 1 < a.jc ? jj + 1 : jj;
+      if constexpr (!PSI) gather<T, GY, YL::R, NT>(pc, pload(psi0 + size_t(jj) * ng));
       gather<T, GX, X0::R, NT>(tn, tload(t0 + size_t(jn) * ng));
     }
 #pragma unroll
@@ -716,35 +726,47 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
       stages_lds<T, GY, true, NT, 0, NSY - 1, YREV>(A, tw1);
     }
     // last stage: slots past the last butterfly repeat it (same values to the
-    // same addresses), so every thread issues the same loads and stores
+    // same addresses), so every thread issues the same loads and stores.
+    // Symmetric mode (SV) keeps N_g * v_ij (real space) for the transposed pass.
+    cpx<T>* tv = reinterpret_cast<cpx<T>*>(a.t) + size_t(ii * a.jc + jj) * ng + z * slab;
+    cpx<T> v[BPTL][YL::R];
 #pragma unroll
     for (int k = 0; k < BPTL; ++k) {
       int b = tid + k * NT;
       if (NBL % NT != 0) b = b < NBL ? b : NBL - 1;
-      {
-        int line, j;
-        decode<GY, YL::R>(b, line, j);
-        if constexpr (!PF) {
-          const cpx<T>* pj = psi0 + size_t(jj) * ng;
+      int line, j;
+      decode<GY, YL::R>(b, line, j);
+      if constexpr (!PF) {
+        const cpx<T>* pj = psi0 + size_t(jj) * ng;
 #pragma unroll
-          for (int r = 0; r < YL::R; ++r) pc[k][r] = ldc(pj + unsigned(line + (j + r * (N1 / YL::R)) * N0));
-        }
-        cpx<T> v[YL::R];
+        for (int r = 0; r < YL::R; ++r) pc[k][r] = ldc(pj + unsigned(line + (j + r * (N1 / YL::R)) * N0));
+      }
 #pragma unroll
-        for (int r = 0; r < YL::R; ++r) v[r] = A[line + (j + r * (N1 / YL::R)) * P0];
-        twiddle<T, N1, YL::R, YL::NS, true>(v, j, tw1);
-        dft<T, YL::R, true>(v);
+      for (int r = 0; r < YL::R; ++r) v[k][r] = A[line + (j + r * (N1 / YL::R)) * P0];
+      twiddle<T, N1, YL::R, YL::NS, true>(v[k], j, tw1);
+      dft<T, YL::R, true>(v[k]);
 #pragma unroll
-        for (int r = 0; r < YL::R; ++r) {
-          cpx<T> t = cmul(pc[k][r], v[r]);
-          acc[k][r].x += wj * t.x;
-          acc[k][r].y += wj * t.y;
-        }
-        if constexpr (SV) {
-          // symmetric mode: keep N_g * v_ij (real space) for the transposed pass
-          cpx<T>* tv = reinterpret_cast<cpx<T>*>(a.t) + size_t(ii * a.jc + jj) * ng + z * slab;
+      for (int r = 0; r < YL::R; ++r) {
+        cpx<T> t = cmul(pc[k][r], v[k][r]);
+        acc[k][r].x += wj * t.x;
+        acc[k][r].y += wj * t.y;
+      }
+      if constexpr (SV && !PSI) {
 #pragma unroll
-          for (int r = 0; r < YL::R; ++r) stn(tv + unsigned(line + (j + r * (N1 / YL::R)) * N0), v[r]);
+        for (int r = 0; r < YL::R; ++r) stn(tv + unsigned(line + (j + r * (N1 / YL::R)) * N0), v[k][r]);
+      }
+    }
+    if constexpr (PSI) {
+      gather<T, GY, YL::R, NT>(pn, pload(psi0 + size_t(jn) * ng));
+      if constexpr (SV) {
+#pragma unroll
+        for (int k = 0; k < BPTL; ++k) {
+          int b = tid + k * NT;
+          if (NBL % NT != 0) b = b < NBL ? b : NBL - 1;
+          int line, j;
+          decode<GY, YL::R>(b, line, j);
+#pragma unroll
+          for (int r = 0; r < YL::R; ++r) stn(tv + unsigned(line + (j + r * (N1 / YL::R)) * N0), v[k][r]);
         }
       }
     }
@@ -756,24 +778,32 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
     // loads into the idle set while the current one is transformed (no
     // copies between iterations, so the loads stay in flight)
     cpx<T> tA[BPT0][X0::R], tB[BPT0][X0::R];
+    cpx<T> pA[BPTL][YL::R], pB[PSI ? BPTL : 1][YL::R];
     gather<T, GX, X0::R, NT>(tA, tload(t0));
+    if constexpr (PSI) gather<T, GY, YL::R, NT>(pA, pload(psi0));
     __syncthreads();
     for (int jj = 0; jj < a.jc; jj += 2) {
-      step(jj, tA, tB);
-      if (jj + 1 < a.jc) step(jj + 1, tB, tA);
+      if constexpr (PSI) {
+        step(jj, tA, tB, pA, pB);
+        if (jj + 1 < a.jc) step(jj + 1, tB, tA, pB, pA);
+      } else {
+        step(jj, tA, tB, pA, pA);
+        if (jj + 1 < a.jc) step(jj + 1, tB, tA, pA, pA);
+      }
     }
   } else {
     __syncthreads();
     for (int jj = 0; jj < a.jc; ++jj) {
       cpx<T> tc[BPT0][X0::R];
+      cpx<T> pc[BPTL][YL::R];
       gather<T, GX, X0::R, NT>(tc, tload(t0 + size_t(jj) * ng));
-      step(jj, tc, tc);
+      step(jj, tc, tc, pc, pc);
     }
   }
   // one read-modify-write of the output slab, all loads issued before the
   // first store
-  cpx<T> pA[BPTL][YL::R];
-  if (!a.first) gather<T, GY, YL::R, NT>(pA, pload(outz));
+  cpx<T> po[BPTL][YL::R];
+  if (!a.first) gather<T, GY, YL::R, NT>(po, pload(outz));
 #pragma unroll
   for (int k = 0; k < BPTL; ++k) {
     const int b = tid + k * NT;
@@ -782,7 +812,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
       decode<GY, YL::R>(b, line, j);
 #pragma unroll
       for (int r = 0; r < YL::R; ++r) {
-        const cpx<T> prev = a.first ? cpx<T>{T(0), T(0)} : pA[k][r];
+        const cpx<T> prev = a.first ? cpx<T>{T(0), T(0)} : po[k][r];
         stg(outz + unsigned(line + (j + r * (N1 / YL::R)) * N0), csub(prev, acc[k][r]));
       }
     }
