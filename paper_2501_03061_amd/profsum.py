@@ -57,6 +57,21 @@ def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, comm
              "| pass | avg per launch (us) | launches per step | model GB/s |", "|---|---|---|---|"]
     for k, v in rec["extra"]["passes"].items():
         lines.append(f"| {k} | {v['avg_us']:.1f} | {v['launches_per_step']} | {v['GBps']:.0f} |")
+    # the same passes in the trace: FP32 instantiations of each pass merged by
+    # dispatch count (pass 3 runs with and without the kept v_ij)
+    merged = collections.defaultdict(lambda: [0, 0.0])
+    for r in stats:
+        if "<float" in r["Name"] and _short(r["Name"]) in rec["extra"]["passes"]:
+            m = merged[_short(r["Name"])]
+            m[0] += int(r["Calls"])
+            m[1] += float(r["TotalDurationNs"])
+    lines += ["", "The same passes in the trace (FP32 instantiations, dispatch-weighted average over "
+              "every call of the run):", "",
+              "| pass | calls | trace avg (us) | bench HIP-event avg (us) | ratio |", "|---|---|---|---|---|"]
+    for k, v in rec["extra"]["passes"].items():
+        if k in merged and merged[k][0]:
+            t = merged[k][1] / merged[k][0] / 1e3
+            lines.append(f"| {k} | {merged[k][0]} | {t:.1f} | {v['avg_us']:.1f} | {t / v['avg_us']:.3f} |")
     lines += ["", "Top kernels (`kernel_stats.csv`, whole run: warmup, timed FP32 steps, FP64 comparison):", "",
               "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for r in stats[:18]:
