@@ -1,0 +1,104 @@
+"""The bench workload at full size: 72^3 grid, 512 orbitals, kT = 0.02 Ha.
+
+ACE builds in the launch configuration the bench times (default chunking,
+Hermitian-pair mode), checked against the oracle on sampled output orbitals:
+V_ACE psi_c = W_c = Vx psi_c (ACE is exact on the orbitals it is built from),
+with the oracle computing Vx psi_c one column at a time.  Over the whole block
+the FP32 form is compared with the FP64 GPU path (M, E_x, the ACE action on
+Phi = Psi + 1e-3 Z and the 4-iteration PT-IM-style loop).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_03061_amd import inputs, px
+from _gpu import banner, relerr, to_dev, to_host
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+FP64_TOL, FP32_TOL, FP32_EX_TOL = 1e-11, 2e-5, 1e-7
+COLS = [5, 256]   # a fully occupied orbital and one near the Fermi level (f = 0.90)
+
+
+@pytest.fixture(scope="module")
+def mid():
+    import torch
+    c = inputs.CONFIGS["mid72"]
+    banner("mid72: generating inputs")
+    inst = inputs.make_instance(c["n"], c["L"], c["n_orb"], c["kT"], seed=c["seed"])
+    print(f"mid72: occupations of the sampled columns {inst.occ[COLS]}", flush=True)
+    K = oracle.kernel_hse(inst.n, inst.L, c["mu"])
+    banner("mid72: oracle columns")
+    ref = oracle.exchange_apply(inst.psi, inst.occ, inst.psi[COLS], K)
+    yield inst, ref, c["mu"]
+    torch.cuda.empty_cache()
+
+
+def test_mid72_ace_builds_vs_oracle_and_fp32_vs_fp64(px_ctx, mid):
+    import torch
+    inst, ref, mu = mid
+    cell = px.Cell(inst.L, inst.n)
+    n = inst.n_orb
+    kd = px_ctx.px_kernel_hse(cell, mu)
+    occ = to_dev(inst.occ)
+    psi64 = to_dev(inst.psi)
+    dev = psi64.device
+
+    def build(psi):
+        M = torch.empty((n, n), dtype=torch.complex128, device=dev)
+        e = torch.zeros(1, dtype=torch.float64, device=dev)
+        xi, st = px_ctx.px_ace_build(cell, psi, occ, kd, M=M, e_x=e)
+        px_ctx.px_sync()
+        assert int(st.item()) == 0
+        return xi, M, float(e.item())
+
+    banner("mid72: FP64 ACE build")
+    xi64, M64, e64 = build(psi64)
+    y64 = to_host(px_ctx.px_ace_apply(cell, xi64, psi64[COLS].contiguous()))
+    err64 = relerr(y64, ref)
+    print(f"mid72 FP64 ACE columns vs oracle {err64:.2e}", flush=True)
+    assert err64 < FP64_TOL
+    # M columns against the oracle: M[a][c] = dV sum_r conj(psi_a) (Vx psi_c)
+    dv = float(np.prod(inst.L)) / float(np.prod(inst.n))
+    mref = dv * (inst.psi.reshape(n, -1).conj() @ ref.reshape(len(COLS), -1).T)
+    merr = relerr(to_host(M64)[:, COLS], mref)
+    print(f"mid72 FP64 M columns vs oracle {merr:.2e}", flush=True)
+    assert merr < FP64_TOL
+
+    banner("mid72: FP32 ACE build")
+    psi32 = px_ctx.px_convert_c128_to_c64(psi64)
+    xi32, M32, e32 = build(psi32)
+    y32 = to_host(px_ctx.px_ace_apply(cell, xi32, psi32[COLS].contiguous()))
+    err32 = relerr(y32, ref)
+    em = float(torch.linalg.matrix_norm(M32 - M64) / torch.linalg.matrix_norm(M64))
+    ee = abs(e32 - e64) / abs(e64)
+    print(f"mid72 FP32: ACE columns vs oracle {err32:.2e}, M vs FP64 {em:.2e}, "
+          f"E_x vs FP64 {ee:.2e} (E_x = {e64:.10f})", flush=True)
+    assert err32 < FP32_TOL
+    assert em < FP32_TOL
+    assert ee < FP32_EX_TOL
+
+    banner("mid72: ACE action and PT-IM-style loops on Phi = Psi + 1e-3 Z")
+    z = inputs.noise_block(inst.n, inst.L, n, seed=1001)
+    phi64 = to_dev(inst.psi + 1e-3 * z)
+    del z
+    phi32 = px_ctx.px_convert_c128_to_c64(phi64)
+    a64 = px_ctx.px_ace_apply(cell, xi64, phi64)
+    a32 = px_ctx.px_ace_apply(cell, xi32, phi32)
+    ea = float(torch.linalg.vector_norm((a32.to(torch.complex128) - a64).flatten()) /
+               torch.linalg.vector_norm(a64.flatten()))
+    dta = oracle.DT_50AS * oracle.ALPHA
+    out64, res64 = px_ctx.px_ptim_exchange_loop(cell, xi64, phi64, 4, dta)
+    out32, res32 = px_ctx.px_ptim_exchange_loop(cell, xi32, phi32, 4, dta)
+    torch.cuda.synchronize()
+    eo = float(torch.linalg.vector_norm((out32.to(torch.complex128) - out64).flatten()) /
+               torch.linalg.vector_norm(out64.flatten()))
+    r64, r32 = to_host(res64), to_host(res32)
+    print(f"mid72: ACE action FP32 vs FP64 {ea:.2e}; loop output {eo:.2e}; "
+          f"residuals fp64 {r64} fp32 {r32}", flush=True)
+    assert ea < FP32_TOL
+    assert eo < FP32_TOL
+    assert np.all(np.diff(r64) < 0)
+    assert abs(r32[0] - r64[0]) < 1e-4 * r64[0]
+    del xi64, xi32, M64, M32, psi64, psi32, phi64, phi32, a64, a32, out64, out32
+    torch.cuda.synchronize()
