@@ -71,9 +71,11 @@ constexpr int XC_KU = 4;       // k-steps of 4 per group in xc (16 a)
 
 // ---------------------------------------------------------------- xhy
 // grid (ceil(na/64), ceil(nb/64), nsplit), 256 threads; wave w covers the
-// 32x32 sub-block (w&1, w>>1) as 2x2 MFMA tiles.
+// 32x32 sub-block (w&1, w>>1) as 2x2 MFMA tiles.  Occupancy target of two
+// waves per SIMD: the three accumulator sets fit in 256 registers without
+// spills, where the default allocation (FP64) left one wave per SIMD.
 template <typename T>
-__global__ __launch_bounds__(256) void gemm_xhy_k(int na, int nb, size_t ng, const cpx<T>* X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_xhy_k(int na, int nb, size_t ng, const cpx<T>* X,
                                                   const cpx<T>* Y, double* part, size_t kchunk) {
   using A = typename Acc<T>::t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -272,9 +274,11 @@ hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, 
 
 // ---------------------------------------------------------------- xc
 // grid (ceil(ng/64), ceil(nb/64)), 256 threads; wave w covers r-block (w&1)
-// and b-block (w>>1) of 32 each, as 2x2 MFMA tiles (i: r, j: b).
+// and b-block (w>>1) of 32 each, as 2x2 MFMA tiles (i: r, j: b).  Occupancy
+// targets (no spills): three waves per SIMD in the FP32 form, two in FP64
+// (one by default; ACE application in FP64 -15 %).
 template <typename T>
-__global__ __launch_bounds__(256) void gemm_xc_k(int na, int nb, size_t ng, const cpx<T>* X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2))) void gemm_xc_k(int na, int nb, size_t ng, const cpx<T>* X,
                                                  const double* C, int ldc, double alpha,
                                                  cpx<T>* Z, int upper) {
   using A = typename Acc<T>::t;
