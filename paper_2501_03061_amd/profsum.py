@@ -49,7 +49,7 @@ def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, comm
     rec = json.loads(open(bench_json).read().strip().splitlines()[-1])
     stats = _csv(trace, "kernel_stats.csv")
     lines = ["# Kernel trace: exchange/ACE hot path, mid72 workload (72^3 grid, 512 orbitals)", "",
-             "Command (repository root, one MI355X):", "", "```", commands["trace"], "```", "",
+             "Command ($REPO: the repository root, $OUT: the raw output folder; one MI355X):", "", "```", commands["trace"], "```", "",
              f"The bench run inside the profiler printed: value {rec['value']:.4g} pair-solves/s, "
              f"{rec['ms_per_step']:.1f} ms/step (FP32 form, Hermitian-pair mode); FP64 form "
              f"{rec['extra'].get('fp64_pair_solves_per_s', float('nan')):.4g} pair-solves/s.", "",
@@ -88,7 +88,7 @@ def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, comm
     wf = COPY_BYTES / 1024 / w_copy
     fb, wb = _per_kernel(fetch), _per_kernel(write)
     lines = ["# HBM traffic counters: pair pipeline, mid72 workload", "",
-             "Commands (each counter in a run of its own):", "", "```"] + commands["pmc"] + ["```", "",
+             "Commands ($REPO: the repository root, $OUT: the raw output folder; each counter in a run of its own):", "", "```"] + commands["pmc"] + ["```", "",
              f"Calibration with the plain copy kernel (`px_stream_copy`, 2 GiB read and 2 GiB written per "
              f"launch): FETCH_SIZE reads {f_copy:,.0f} KiB per launch (factor {ff:.3f} to bytes read), "
              f"WRITE_SIZE {w_copy:,.0f} KiB (factor {wf:.3f}).", "",
@@ -138,7 +138,7 @@ def summarize_mfma(mfma, out, command):
         rows[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
         durs[k][r["Dispatch_Id"]] = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9
     lines = ["# MFMA counters: complex contractions, mid72 workload (512 x 512 x 72^3)", "",
-             "Command (repository root, one MI355X):", "", "```", command, "```", "",
+             "Command ($REPO: the repository root, $OUT: the raw output folder; one MI355X):", "", "```", command, "```", "",
              "Each row groups the dispatches of one kernel with the same flop count (the xi = W U "
              "contraction of the ACE build uses only the upper-triangular U, about half the flops of "
 "a dense one). GFLOP = SQ_INSTS_VALU_MFMA_MOPS x 512 (the flops the matrix cores execute); "
@@ -181,19 +181,20 @@ def main():
     ap.add_argument("--mfma", help="rocprofv3 --pmc run with the MFMA counters (contractions)")
     ap.add_argument("--out", default="profiles")
     args = ap.parse_args()
+    # $REPO: the repository root; $OUT: a folder for the raw rocprofv3 output
     pre = "cd /tmp && export TMPDIR=/tmp"
     if args.mfma:
         summarize_mfma(args.mfma, args.out, pre + "\ntimeout -s KILL 300 rocprofv3 --pmc "
                        "SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_VALU_MFMA_BUSY_CYCLES "
-                       "SQ_BUSY_CU_CYCLES --output-format csv -d $REPO/gpurun_out/pmc_mfma_bench -o run -- "
+                       "SQ_BUSY_CU_CYCLES --output-format csv -d $OUT/pmc_mfma_bench -o run -- "
                        "python3 $REPO/bench.py --steps 1 --warmup 0 --no-cpu")
         if not args.trace:
             return
     commands = {
-        "trace": pre + "\nrocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/trace_bench "
+        "trace": pre + "\nrocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace_bench "
                        "-o run -- python3 $REPO/bench.py",
         "pmc": [pre] + [
-            f"timeout -s KILL {t} rocprofv3 --pmc {c} --output-format csv -d $REPO/gpurun_out/{d} -o run -- "
+            f"timeout -s KILL {t} rocprofv3 --pmc {c} --output-format csv -d $OUT/{d} -o run -- "
             f"python3 $REPO/bench.py {a}"
             for t, c, d, a in ((120, "FETCH_SIZE", "pmc_fetch_copy", "--calibrate-copy"),
                                (120, "WRITE_SIZE", "pmc_write_copy", "--calibrate-copy"),
