@@ -235,6 +235,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
   fill_twiddles<T, N0, NT>(tw0);
   fill_twiddles<T, N1, NT>(tw1);
   const int z = blockIdx.x, ii = blockIdx.y;
+  const int jend = a.tri ? ii + 1 : a.jc;  // pairs jj < jend of row ii
   const size_t slab = size_t(N0) * N1;
   const size_t ng = slab * a.n2;
   const cpx<T>* phi = reinterpret_cast<const cpx<T>*>(a.phi) + size_t(a.i0 + ii) * ng + z * slab;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
   }
   __syncthreads();
 
-  for (int jj = 0; jj < a.jc; ++jj) {
+  for (int jj = 0; jj < jend; ++jj) {
     cpx<T>* A = lds + (PP ? (jj & 1) * SL : 0);
     cpx<T>* B = lds + (PP ? (1 - (jj & 1)) * SL : 0);
     cpx<T> cu[BPT0][X0::R];
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
       for (int k = 0; k < BPT0; ++k)
 #pragma unroll
         for (int r = 0; r < X0::R; ++r) cu[k][r] = nx[k][r];
-      if (jj + 1 < a.jc) {
+      if (jj + 1 < jend) {
         const cpx<T>* pn = psi0 + size_t(jj + 1) * ng;
         gather<T, GX, X0::R, NT>(nx, [&](int line, int e) { return ldc(pn + unsigned(line * N0 + e)); });
       }
@@ -409,12 +410,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
     lds_waves_per_simd(N2 * (N0 + 1) * int(sizeof(cpx<T>)) + 1024, NT, pass2_wave_cap<T, N2>()))))
 void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
   const ChunkArgs a = chunk_args(a0, tasks);
-  const int np = a.ic * a.jc;
+  // pairs q in [qbeg, qend) of the chunk; pair q owns slot pair_slot(a, q)
+  const int np = chunk_pairs(a);
   int y, grp;
   plane_tile(y, grp);
-  const int pbeg = grp * PQ;
-  if (pbeg >= np) return;
-  const int pend = pbeg + PQ < np ? pbeg + PQ : np;
+  const int qbeg = grp * PQ;
+  if (qbeg >= np) return;
+  const int qend = qbeg + PQ < np ? qbeg + PQ : np;
   constexpr int P0 = N0 + 1;
   // energy partials: as the G = 0 sums of pass 1 (EL: per thread in LDS, one
   // wave per sum), else a wave reduction in every wave
@@ -447,7 +449,7 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
   // values at the positions the last forward stage produces
   cpx<T> nx[BPT0][F0::R];
   gather_live<T, GZ, F0::R, NT>(nx, [&](int line, int e) {
-    return ldc(buf0 + size_t(pbeg) * slab * N2 + unsigned(e * int(slab) + line));
+    return ldc(buf0 + size_t(pair_slot(a, qbeg)) * slab * N2 + unsigned(e * int(slab) + line));
   });
   KT kv[BPTL][FL::R];
   const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
@@ -462,10 +464,11 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
     for (int r = 0; r < FL::R; ++r) kv[k][r] = gld(kern + unsigned((j + r * (N2 / FL::R)) * int(slab) + line));
   }
   fill_twiddles<T, N2, NT>(tw2);
-  for (int p = pbeg; p < pend; ++p) {
+  for (int q = qbeg; q < qend; ++q) {
+  const int p = pair_slot(a, q);
   cpx<T>* const buf = buf0 + size_t(p) * slab * N2;
   cpx<T> v0[BPT0][F0::R];
-  if (PQ == 1 || PF || p == pbeg) {
+  if (PQ == 1 || PF || q == qbeg) {
 #pragma unroll
     for (int k = 0; k < BPT0; ++k)
 #pragma unroll
@@ -473,9 +476,11 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
   } else {
     gather_live<T, GZ, F0::R, NT>(v0, [&](int line, int e) { return ldc(buf + unsigned(e * int(slab) + line)); });
   }
-  if (PF && p + 1 < pend)
-    gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) { return ldc(buf + slab * N2 + unsigned(e * int(slab) + line)); });
-  if (p > pbeg) __syncthreads();  // the previous pair's last stage has read LDS
+  if (PF && q + 1 < qend) {
+    cpx<T>* const bn = buf0 + size_t(pair_slot(a, q + 1)) * slab * N2;
+    gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) { return ldc(bn + unsigned(e * int(slab) + line)); });
+  }
+  if (q > qbeg) __syncthreads();  // the previous pair's last stage has read LDS
 #pragma unroll
   for (int k = 0; k < BPT0; ++k) {
     const int b = tid + k * NT;
@@ -667,6 +672,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
   fill_twiddles<T, N0, NT>(tw0);
   fill_twiddles<T, N1, NT>(tw1);
   const int z = blockIdx.x, ii = blockIdx.y;
+  const int jend = a.tri ? ii + 1 : a.jc;  // pairs jj < jend of row ii
   const size_t slab = size_t(N0) * N1;
   const size_t ng = slab * a.n2;
   const int tid = threadIdx.x;
@@ -699,7 +705,7 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
     cpx<T>* B = lds + (PP ? (1 - (jj & 1)) * SL : 0);
     const T wj = weight(jj);  // requested before the slabs: waiting for it waits for nothing else
     // the last pair re-requests its own slabs: the loop stays branch free
-    const int jn = jj + 1 < a.jc ? jj + 1 : jj;
+    const int jn = jj + 1 < jend ? jj + 1 : jj;
     if constexpr (PF) {
       if constexpr (!PSI) gather<T, GY, YL::R, NT>(pc, pload(psi0 + size_t(jj) * ng));
       gather<T, GX, X0::R, NT>(tn, tload(t0 + size_t(jn) * ng));
@@ -782,18 +788,18 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
     gather<T, GX, X0::R, NT>(tA, tload(t0));
     if constexpr (PSI) gather<T, GY, YL::R, NT>(pA, pload(psi0));
     __syncthreads();
-    for (int jj = 0; jj < a.jc; jj += 2) {
+    for (int jj = 0; jj < jend; jj += 2) {
       if constexpr (PSI) {
         step(jj, tA, tB, pA, pB);
-        if (jj + 1 < a.jc) step(jj + 1, tB, tA, pB, pA);
+        if (jj + 1 < jend) step(jj + 1, tB, tA, pB, pA);
       } else {
         step(jj, tA, tB, pA, pA);
-        if (jj + 1 < a.jc) step(jj + 1, tB, tA, pA, pA);
+        if (jj + 1 < jend) step(jj + 1, tB, tA, pA, pA);
       }
     }
   } else {
     __syncthreads();
-    for (int jj = 0; jj < a.jc; ++jj) {
+    for (int jj = 0; jj < jend; ++jj) {
       cpx<T> tc[BPT0][X0::R];
       cpx<T> pc[BPTL][YL::R];
       gather<T, GX, X0::R, NT>(tc, tload(t0 + size_t(jj) * ng));

@@ -98,10 +98,13 @@ hipError_t launch_convert_f64_f32(size_t n, const double* src, float* dst, hipSt
 // FP64 energy of the transform input and rho(0) its FP64 sum: the transform's
 // systematic norm drift (about 1e-7 relative in FP32) cancels in A / B.
 __global__ void expart_reduce_k(const double* expart, const G0Part* g0, int n1, int n2, double ng,
-                                int i0, int ic, int j0, int jc, double* S, int lds, int mirror) {
+                                int i0, int ic, int j0, int jc, double* S, int lds, int mirror,
+                                int tri) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ic * jc) return;
   const int ii = p / jc, jj = p % jc;
+  if (tri && jj > ii) return;  // a triangular block solves jj <= ii only
+  if (tri) mirror = jj < ii;
   double s = 0.0;
   if (g0 == nullptr) {
     for (int y = 0; y < n1; ++y) s += expart[size_t(p) * n1 + y];
@@ -128,10 +131,10 @@ __global__ void expart_reduce_k(const double* expart, const G0Part* g0, int n1, 
 
 hipError_t launch_expart_reduce(const double* expart, const G0Part* g0, int n1, int n2, double ng,
                                 int i0, int ic, int j0, int jc, double* S, int lds, bool mirror,
-                                hipStream_t s) {
+                                bool tri, hipStream_t s) {
   const int np = ic * jc;
   hipLaunchKernelGGL(expart_reduce_k, dim3((np + 255) / 256), dim3(256), 0, s, expart, g0, n1, n2,
-                     ng, i0, ic, j0, jc, S, lds, int(mirror));
+                     ng, i0, ic, j0, jc, S, lds, int(mirror), int(tri));
   return hipGetLastError();
 }
 
@@ -142,6 +145,7 @@ __global__ void expart_reduce_tasks_k(const ChunkArgs* tasks, int fp32, int n1, 
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.ic * a.jc) return;
   const int ii = p / a.jc, jj = p % a.jc;
+  if (a.tri && jj > ii) return;  // a triangular block solves jj <= ii only
   double s = 0.0;
   if (!fp32) {
     for (int y = 0; y < n1; ++y) s += a.expart[size_t(p) * n1 + y];
@@ -163,7 +167,7 @@ __global__ void expart_reduce_tasks_k(const ChunkArgs* tasks, int fp32, int n1, 
     s = e0 + (b > 0.0 && target > 0.0 ? x * (target / b) : x);
   }
   a.S[size_t(a.i0 + ii) * a.s_ld + (a.j0 + jj)] = s;
-  if (a.store_v) a.S[size_t(a.j0 + jj) * a.s_ld + (a.i0 + ii)] = s;
+  if (a.store_v && (!a.tri || jj < ii)) a.S[size_t(a.j0 + jj) * a.s_ld + (a.i0 + ii)] = s;
 }
 
 hipError_t launch_expart_reduce_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_pairs,

@@ -54,14 +54,22 @@ __global__ __launch_bounds__(256) void pass4_transpose_acc(ChunkArgs a0, const C
   V acc[JB];
 #pragma unroll
   for (int u = 0; u < JB; ++u) acc[u] = V{};
-  for (int ii = 0; ii < a.ic; ++ii) {
+  // a triangular diagonal block (tri) holds v_ij for jj <= ii; its transposed
+  // contributions are the pairs jj < ii, so rows start past the first j
+  const int ibeg = a.tri ? j0 + 1 : 0;
+  for (int ii = ibeg; ii < a.ic; ++ii) {
     const V ps = ldv(psi + 2 * (size_t(a.i0 + ii) * ng + e));
     const T w = T(*(const PX_GLOBAL double*)(a.occ + a.i0 + ii) * a.inv_ng);
     const T* row = t + 2 * (size_t(ii * a.jc + j0) * ng + e);
     V v[JB];
-    // slabs past the chunk's last j re-read its first (never stored)
+    // slabs past the chunk's last j re-read its first (never stored); in a
+    // triangular block the slots jj >= ii re-read the first too, and add zero
 #pragma unroll
-    for (int u = 0; u < JB; ++u) v[u] = ldvnt(row + 2 * size_t(u < nj ? u : 0) * ng);
+    for (int u = 0; u < JB; ++u) {
+      const bool live = u < nj && (!a.tri || j0 + u < ii);
+      const V x = ldvnt(row + 2 * size_t(live ? u : 0) * ng);
+      v[u] = live || !a.tri ? x : V{};
+    }
 #pragma unroll
     for (int u = 0; u < JB; ++u) {
 #pragma unroll

@@ -36,6 +36,7 @@ struct px_context {
   double ace_ms[3] = {0, 0, 0};
   int64_t ace_calls = 0;
   bool symmetric_ace = true;  // ACE build solves only pairs j <= i (block level)
+  bool tri_diag = true;       // ... and within the diagonal blocks (pair level)
   // batched form: the graph of the last batched call, replayed while the call
   // signature (instances, pointers, workspace) stays the same
   bool use_graph = true;
@@ -226,7 +227,9 @@ px_status need_ws(px_context* c, size_t bytes) {
 // receives sum_G K |rho_ij(G)|^2 per pair.  Symmetric mode (phi is psi): the
 // orbitals are cut into square blocks of B = max(ic, jc); only blocks J <= I
 // are solved, and for J < I pass 3 keeps v_ij so that pass 4 adds the
-// transposed contributions to the J block (v_ji = conj(v_ij)).
+// transposed contributions to the J block (v_ji = conj(v_ij)).  A diagonal
+// block J = I is solved as its lower triangle j <= i (pass 4 adds the pairs
+// j < i), so every unordered pair is solved once.
 px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, int n_psi,
                        const void* psi, const double* occ, int n_phi, const void* phi,
                        const double* kern, void* out, const ExLayout& l, bool energy, int ic,
@@ -272,10 +275,14 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       a.j0 = j0;
       a.jc = (n_psi - j0) < jc ? (n_psi - j0) : jc;
       a.first = j0 == 0;
-      a.store_v = symmetric && j0 < i0;
+      // a diagonal block is solved as its lower triangle and keeps v_ij for
+      // the transposed pass like the blocks below it
+      a.tri = symmetric && c->tri_diag && j0 == i0 && a.ic == a.jc;
+      a.store_v = symmetric && (j0 < i0 || a.tri);
+      const int npairs = px::chunk_pairs(a);
       hipEvent_t* ev = c->profiling ? &c->events[5 * nchunks] : nullptr;
       px_status st = hip_check(
-          c, px::launch_chunk(fp32, cell->n[0], a, a.ic * a.jc, energy, s, ev), "pair pipeline");
+          c, px::launch_chunk(fp32, cell->n[0], a, npairs, energy, s, ev), "pair pipeline");
       if (st != PX_OK) return st;
       if (a.store_v) {
         st = hip_check(c, px::launch_pass4(fp32, a, ng, s), "transposed accumulation");
@@ -287,13 +294,15 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
         // write the pair slab; pass 2: read and rewrite it; pass 3: read it and
         // psi_j); in symmetric mode pass 3 also writes v_ij (1 N_g b) and
         // pass 4 reads v_ij and psi_i (2 N_g b)
-        const double np = double(a.ic) * a.jc;
+        // (a triangular block keeps v_ij for its npairs pairs; pass 4 reads
+        // the npairs - ic of them below the diagonal)
+        const double np = double(npairs), np4 = a.tri ? double(npairs - a.ic) : np;
         for (int k = 0; k < 3; ++k) {
           c->prof_bytes[k] += 2.0 * pair_bytes * np + (k == 2 && a.store_v ? pair_bytes * np : 0.0);
           c->prof_launches[k] += 1;
         }
         if (a.store_v) {
-          c->prof_bytes[3] += 2.0 * pair_bytes * np;
+          c->prof_bytes[3] += 2.0 * pair_bytes * np4;
           c->prof_launches[3] += 1;
         }
         has4.push_back(a.store_v);
@@ -302,7 +311,7 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       if (energy) {
         st = hip_check(c, px::launch_expart_reduce(a.expart, fp32 ? a.g0 : nullptr, cell->n[1],
                                                    cell->n[2], double(ng), i0, a.ic, j0, a.jc, S,
-                                                   n_psi, a.store_v != 0, s),
+                                                   n_psi, a.store_v != 0, a.tri != 0, s),
                        "energy partials");
         if (st != PX_OK) return st;
       }
@@ -767,7 +776,8 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         a.j0 = ch.J * ch.B;
         a.jc = jcc;
         a.first = d == 0;
-        a.store_v = d > 0;
+        a.tri = d == 0 && c->tri_diag && icc == jcc;
+        a.store_v = d > 0 || a.tri;
         a.n2 = nsz;
         a.inv_ng = 1.0 / double(ng);
         a.s_ld = n;
@@ -783,7 +793,7 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         w.max_ic = std::max(w.max_ic, icc);
         w.max_jc = std::max(w.max_jc, jcc);
         w.max_pairs = std::max(w.max_pairs, int(pairs));
-        w.any_v = w.any_v || d > 0;
+        w.any_v = w.any_v || a.store_v;
         used += pairs;
       }
     }

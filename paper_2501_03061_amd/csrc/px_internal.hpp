@@ -34,7 +34,26 @@ struct ChunkArgs {
   int s_ld;             // its row stride
   int store_v;          // pass 3 also writes N_g * v_ij back into the pair slab (symmetric mode)
   double inv_ng;
+  int tri;              // diagonal block of the symmetric mode (i0 == j0, ic == jc) solved as
+                        // its lower triangle jj <= ii: passes 1 and 3 run jj = 0..ii, pass 2
+                        // takes the ic (ic + 1) / 2 pairs of the triangle (slots keep the
+                        // square layout p = ii jc + jj), pass 4 adds the pairs jj < ii
 };
+
+#if defined(__HIPCC__)
+// Pairs of a chunk, and the pair slot of the q-th of them (row-major over the
+// triangle jj <= ii when tri is set).
+__host__ __device__ inline int chunk_pairs(const ChunkArgs& a) {
+  return a.tri ? a.ic * (a.ic + 1) / 2 : a.ic * a.jc;
+}
+__device__ __forceinline__ int pair_slot(const ChunkArgs& a, int q) {
+  if (!a.tri) return q;
+  int ii = int((sqrt(8.0 * double(q) + 1.0) - 1.0) * 0.5);
+  if ((ii + 1) * (ii + 2) / 2 <= q) ++ii;  // rounding of the square root
+  if (ii * (ii + 1) / 2 > q) --ii;
+  return ii * a.jc + (q - ii * (ii + 1) / 2);
+}
+#endif
 
 // The chunk of a kernel launch: the launch argument, or entry blockIdx.z of a
 // task table in device memory.  A table entry is read through the constant
@@ -67,6 +86,7 @@ __device__ __forceinline__ ChunkArgs chunk_args(const ChunkArgs& a0, const Chunk
     a.s_ld = c->s_ld;
     a.store_v = c->store_v;
     a.inv_ng = c->inv_ng;
+    a.tri = c->tri;
     return a;
   }
   return a0;
@@ -110,7 +130,7 @@ hipError_t launch_stream_copy(size_t bytes, const void* src, void* dst, hipStrea
 // matches Parseval's identity with the FP64 energy of the transform input.
 hipError_t launch_expart_reduce(const double* expart, const G0Part* g0, int n1, int n2, double ng,
                                 int i0, int ic, int j0, int jc, double* S, int lds, bool mirror,
-                                hipStream_t s);
+                                bool tri, hipStream_t s);
 // e_x = scale * sum_i sum_j f_i f_j S[i][j]
 hipError_t launch_energy(const double* S, const double* occ, int n, double scale, double* e_x,
                          hipStream_t s);
