@@ -37,13 +37,6 @@ struct px_context {
   int64_t ace_calls = 0;
   bool symmetric_ace = true;  // ACE build solves only pairs j <= i (block level)
   bool tri_diag = true;       // ... and within the diagonal blocks (pair level)
-  // symmetric mode, FP32 form: pass 4 of a chunk runs on a second stream,
-  // beside the next chunk's passes 1-3 (two pair buffers; fork and join by
-  // events).  ACE build -1 % at 72^3; no gain in the FP64 form, which keeps
-  // one stream and one buffer.
-  bool overlap4 = true;
-  hipStream_t aux = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
   // batched form: the graph of the last batched call, replayed while the call
   // signature (instances, pointers, workspace) stays the same
   bool use_graph = true;
@@ -59,10 +52,6 @@ struct px_context {
       if (e) (void)hipEventDestroy(e);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    if (aux) (void)hipStreamDestroy(aux);
-    if (fork_ev) (void)hipEventDestroy(fork_ev);
-    for (hipEvent_t e : join_ev)
-      if (e) (void)hipEventDestroy(e);
     if (pinned_tasks) (void)hipHostFree(pinned_tasks);
   }
 };
@@ -123,24 +112,17 @@ void tuning_for(const px_context* c, const px_cell* cell, px_precision prec, int
 
 // Workspace layout of one exchange application.
 struct ExLayout {
-  size_t t, t2, g0, expart, S, k32, end;
+  size_t t, g0, expart, S, k32, end;
 };
 
-// two_t: a second pair buffer (symmetric mode, where pass 4 of a chunk reads
-// its buffer while the next chunk fills the other one)
 ExLayout ex_layout(const px_cell* cell, px_precision prec, int n_psi, int n_phi, int ic, int jc,
-                   bool energy, bool two_t) {
+                   bool energy) {
   ExLayout l{};
   const int icc = ic < n_phi ? ic : n_phi, jcc = jc < n_psi ? jc : n_psi;
   const size_t pairs = size_t(icc) * jcc;
   size_t off = 0;
   l.t = off;
   off = align_up(off + pairs * ngrid(cell) * elem_bytes(prec));
-  l.t2 = l.t;
-  if (two_t) {
-    l.t2 = off;
-    off = align_up(off + pairs * ngrid(cell) * elem_bytes(prec));
-  }
   l.g0 = off;
   if (prec == PX_PREC_FP32) off = align_up(off + pairs * cell->n[2] * sizeof(px::G0Part));
   l.expart = off;
@@ -165,7 +147,7 @@ AceLayout ace_layout(const px_cell* cell, px_precision prec, int n, int ic, int 
                      bool symmetric) {
   AceLayout a{};
   if (symmetric) ic = jc = (ic > jc ? ic : jc);
-  a.ex = ex_layout(cell, prec, n, n, ic, jc, true, symmetric && prec == PX_PREC_FP32);
+  a.ex = ex_layout(cell, prec, n, n, ic, jc, true);
   size_t off = a.ex.end;
   a.W = off;
   off = align_up(off + size_t(n) * ngrid(cell) * elem_bytes(prec));
@@ -275,37 +257,11 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
   double* S = reinterpret_cast<double*>(c->ws + l.S);
   if (symmetric) ic = jc = (ic > jc ? ic : jc);
   const size_t nch = size_t((n_phi + ic - 1) / ic) * ((n_psi + jc - 1) / jc);
-  // events per chunk: pass 1 | pass 2 | pass 3 boundaries on the stream, and
-  // the start and end of pass 4 on the stream that runs it
-  constexpr size_t EV = 6;
   if (c->profiling) {
-    while (c->events.size() < nch * EV) {
+    while (c->events.size() < nch * 5) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return fail(c, PX_ERR_DEVICE, "hipEventCreate failed");
       c->events.push_back(e);
-    }
-  }
-  // Symmetric mode with two pair buffers: pass 4 of chunk k (reads its pair
-  // buffer and psi_i, writes the output block J) runs on the second stream
-  // while chunk k + 1, in the other buffer, runs passes 1-3 on this one.  In
-  // the chunk order (blocks I in turn, J = 0..I) no later pass 3 writes a
-  // block J that a pending pass 4 writes, chunk k + 2 waits for the pass 4 of
-  // chunk k before it refills that buffer, and the call joins both at the end.
-  char* tbuf[2] = {c->ws + l.t, c->ws + l.t2};
-  bool overlap = symmetric && c->overlap4 && l.t2 != l.t;
-  bool pending[2] = {false, false};
-  if (overlap && !c->aux) {
-    // the second stream and its events are made by the first symmetric call;
-    // a first call under stream capture runs on its own stream only
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
-      overlap = false;
-    } else {
-      if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&c->join_ev[0], hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&c->join_ev[1], hipEventDisableTiming) != hipSuccess ||
-          hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess)
-        return fail(c, PX_ERR_DEVICE, "second stream or its events could not be created");
     }
   }
   const double pair_bytes = double(ng * elem_bytes(prec));
@@ -324,36 +280,16 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       a.tri = symmetric && c->tri_diag && j0 == i0 && a.ic == a.jc;
       a.store_v = symmetric && (j0 < i0 || a.tri);
       const int npairs = px::chunk_pairs(a);
-      const int b = overlap ? int(nchunks & 1) : 0;
-      a.t = tbuf[b];
-      if (pending[b]) {  // the pass 4 that reads this buffer is done before it is refilled
-        px_status st = hip_check(c, hipStreamWaitEvent(s, c->join_ev[b], 0), "stream wait");
-        if (st != PX_OK) return st;
-        pending[b] = false;
-      }
-      hipEvent_t* ev = c->profiling ? &c->events[EV * nchunks] : nullptr;
+      hipEvent_t* ev = c->profiling ? &c->events[5 * nchunks] : nullptr;
       px_status st = hip_check(
           c, px::launch_chunk(fp32, cell->n[0], a, npairs, energy, s, ev), "pair pipeline");
       if (st != PX_OK) return st;
       if (a.store_v) {
-        hipStream_t s4 = s;
-        if (overlap) {
-          s4 = c->aux;
-          st = hip_check(c, hipEventRecord(c->fork_ev, s), "event record");
-          if (st == PX_OK) st = hip_check(c, hipStreamWaitEvent(s4, c->fork_ev, 0), "stream wait");
-          if (st != PX_OK) return st;
-        }
-        if (c->profiling) (void)hipEventRecord(c->events[EV * nchunks + 4], s4);
-        st = hip_check(c, px::launch_pass4(fp32, a, ng, s4), "transposed accumulation");
+        st = hip_check(c, px::launch_pass4(fp32, a, ng, s), "transposed accumulation");
         if (st != PX_OK) return st;
-        if (c->profiling) (void)hipEventRecord(c->events[EV * nchunks + 5], s4);
-        if (overlap) {
-          st = hip_check(c, hipEventRecord(c->join_ev[b], s4), "event record");
-          if (st != PX_OK) return st;
-          pending[b] = true;
-        }
       }
       if (c->profiling) {
+        (void)hipEventRecord(c->events[5 * nchunks + 4], s);
         // algorithmic bytes, 2 N_g b per pair in each pass (pass 1: read psi_j,
         // write the pair slab; pass 2: read and rewrite it; pass 3: read it and
         // psi_j); in symmetric mode pass 3 also writes v_ij (1 N_g b) and
@@ -381,27 +317,19 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       }
     }
   }
-  for (int b = 0; b < 2; ++b) {  // join: the call's work is complete on its own stream
-    if (!pending[b]) continue;
-    px_status st = hip_check(c, hipStreamWaitEvent(s, c->join_ev[b], 0), "stream wait");
-    if (st != PX_OK) return st;
-  }
   if (c->profiling && nchunks > 0) {
-    hipError_t e = hipSuccess;
-    for (size_t k = 0; k < nchunks; ++k) {
-      e = hipEventSynchronize(c->events[EV * k + (has4[k] ? 5 : 3)]);
-      if (e != hipSuccess) return hip_check(c, e, "profiling sync");
-    }
+    hipError_t e = hipEventSynchronize(c->events[5 * nchunks - 1]);
+    if (e != hipSuccess) return hip_check(c, e, "profiling sync");
     for (size_t k = 0; k < nchunks; ++k) {
       for (int p = 0; p < 3; ++p) {
         float ms = 0.f;
-        e = hipEventElapsedTime(&ms, c->events[EV * k + p], c->events[EV * k + p + 1]);
+        e = hipEventElapsedTime(&ms, c->events[5 * k + p], c->events[5 * k + p + 1]);
         if (e != hipSuccess) return hip_check(c, e, "hipEventElapsedTime");
         c->prof_ms[p] += ms;
       }
       if (has4[k]) {
         float ms = 0.f;
-        e = hipEventElapsedTime(&ms, c->events[EV * k + 4], c->events[EV * k + 5]);
+        e = hipEventElapsedTime(&ms, c->events[5 * k + 3], c->events[5 * k + 4]);
         if (e != hipSuccess) return hip_check(c, e, "hipEventElapsedTime");
         c->prof_ms[3] += ms;
       }
@@ -449,7 +377,7 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
   switch (op) {
     case PX_OP_EXCHANGE:
       if (n_phi <= 0) return 0;
-      return ex_layout(cell, prec, n_psi, n_phi, ic, jc, true, false).end;
+      return ex_layout(cell, prec, n_psi, n_phi, ic, jc, true).end;
     case PX_OP_ACE_BUILD:
       return ace_layout(cell, prec, n_psi, ic, jc, ctx->symmetric_ace).end;
     case PX_OP_ACE_APPLY:
@@ -533,7 +461,7 @@ px_status px_exchange_apply(px_context* ctx, const px_cell* cell, px_precision p
     return fail(ctx, PX_ERR_INVALID_ARG, "exchange_apply: e_x requires phi == psi and n_phi == n_psi");
   int ic, jc;
   tuning_for(ctx, cell, prec, &ic, &jc);
-  const ExLayout l = ex_layout(cell, prec, n_psi, n_phi, ic, jc, e_x != nullptr, false);
+  const ExLayout l = ex_layout(cell, prec, n_psi, n_phi, ic, jc, e_x != nullptr);
   st = need_ws(ctx, l.end);
   if (st != PX_OK) return st;
   hipError_t he = hipSetDevice(ctx->device);
@@ -1166,7 +1094,7 @@ px_status px_autotune(px_context* ctx, const px_cell* cell, px_precision prec, i
   std::string trials;
   for (int B : cand) {
     if (B > n && B != cand[0]) break;
-    const ExLayout l = ex_layout(cell, prec, n, n, B, B, false, prec == PX_PREC_FP32);
+    const ExLayout l = ex_layout(cell, prec, n, n, B, B, false);
     if (ctx->ws == nullptr || ctx->ws_bytes < l.end) continue;
     float ms = 0.f, best_ms = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {
