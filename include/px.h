@@ -176,10 +176,11 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
                                 hipStream_t stream);
 
 /* Hermitian pair symmetry of the ACE build (default on).  With Phi = Psi and a
- * real even kernel, v_ji = conj(v_ij): the orbitals are cut into square blocks
- * and only blocks J <= I are transformed; for J < I the real-space v_ij is
- * kept and a streaming pass adds the transposed contribution
- * -f_i psi_i conj(v_ij) to W_j.  Roughly halves the pair solves. */
+ * real even kernel, v_ji = conj(v_ij): the orbitals are cut into square blocks,
+ * only blocks J <= I are transformed, and a diagonal block only for its pairs
+ * j <= i; the real-space v_ij is kept and a streaming pass adds the transposed
+ * contribution -f_i psi_i conj(v_ij) to W_j for j < i.  Every unordered pair
+ * is solved once (N (N + 1) / 2 pair solves instead of N^2). */
 px_status px_set_symmetry(px_context* ctx, int32_t enable);
 
 /* Measurement mode.  When enabled, px_exchange_apply and px_ace_build record
