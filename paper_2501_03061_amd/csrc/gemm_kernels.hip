@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 }
 
 __global__ void xhy_reduce_k(int na, int nb, const double* part, int nsplit, double scale,
-                             double* M, int ldm) {
+                             double* M, int ldm, float* M32) {
   const size_t n = size_t(na) * nb;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
        e += size_t(gridDim.x) * blockDim.x) {
@@ -232,6 +232,10 @@ __global__ void xhy_reduce_k(int na, int nb, const double* part, int nsplit, dou
     const size_t a = e / nb, b = e % nb;
     M[(a * ldm + b) * 2] = scale * re;
     M[(a * ldm + b) * 2 + 1] = scale * im;
+    if (M32) {  // the same, rounded to FP32 (operand of an FP32 contraction)
+      M32[(a * ldm + b) * 2] = float(scale * re);
+      M32[(a * ldm + b) * 2 + 1] = float(scale * im);
+    }
   }
 }
 
@@ -252,7 +256,7 @@ size_t gemm_xhy_part_elems(int na, int nb, size_t ng, int* nsplit) {
 
 hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, const void* Y,
                            double scale, double* M, int ldm, double* part, int nsplit_avail,
-                           hipStream_t s) {
+                           float* M32, hipStream_t s) {
   int nsplit;
   const size_t kchunk = xhy_kchunk(na, nb, ng, &nsplit);
   if (nsplit > nsplit_avail) return hipErrorInvalidValue;
@@ -268,7 +272,7 @@ hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, 
   const size_t n = size_t(na) * nb;
   const int blocks = int((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
   hipLaunchKernelGGL(xhy_reduce_k, dim3(blocks), dim3(256), 0, s, na, nb, part, nsplit, scale, M,
-                     ldm);
+                     ldm, M32);
   return hipGetLastError();
 }
 
@@ -279,7 +283,7 @@ hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, 
 // (one by default; ACE application in FP64 -15 %).
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2))) void gemm_xc_k(int na, int nb, size_t ng, const cpx<T>* X,
-                                                 const double* C, int ldc, double alpha,
+                                                 const T* C, int ldc, double alpha,
                                                  cpx<T>* Z, int upper) {
   using A = typename Acc<T>::t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -323,10 +327,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const cpx<T> x = load_c(X + size_t(ac) * ng + rc[t]);
-        const double* c = C + (size_t(ac) * ldc + bc[t]) * 2;
-        const double c0 = c[0], c1 = c[1];
+        const T* c = C + (size_t(ac) * ldc + bc[t]) * 2;
+        const T c0 = c[0], c1 = c[1];
         xa[t][s] = (av && rv[t]) ? x : cpx<T>{T(0), T(0)};
-        cb[t][s] = (av && bv[t]) ? cpx<T>{T(c0), T(c1)} : cpx<T>{T(0), T(0)};
+        cb[t][s] = (av && bv[t]) ? cpx<T>{c0, c1} : cpx<T>{T(0), T(0)};
       }
     }
   };
@@ -379,17 +383,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
 }
 
-hipError_t launch_gemm_xc(bool fp32, int na, int nb, size_t ng, const void* X, const double* C,
+hipError_t launch_gemm_xc(bool fp32, int na, int nb, size_t ng, const void* X, const void* C,
                           int ldc, double alpha, void* Z, bool upper, hipStream_t s) {
   dim3 grid(unsigned((ng + 63) / 64), (nb + 63) / 64);
   if (fp32)
     hipLaunchKernelGGL(gemm_xc_k<float>, grid, dim3(256), 0, s, na, nb, ng,
-                       static_cast<const cpx<float>*>(X), C, ldc, alpha,
-                       static_cast<cpx<float>*>(Z), int(upper));
+                       static_cast<const cpx<float>*>(X), static_cast<const float*>(C), ldc,
+                       alpha, static_cast<cpx<float>*>(Z), int(upper));
   else
     hipLaunchKernelGGL(gemm_xc_k<double>, grid, dim3(256), 0, s, na, nb, ng,
-                       static_cast<const cpx<double>*>(X), C, ldc, alpha,
-                       static_cast<cpx<double>*>(Z), int(upper));
+                       static_cast<const cpx<double>*>(X), static_cast<const double*>(C), ldc,
+                       alpha, static_cast<cpx<double>*>(Z), int(upper));
   return hipGetLastError();
 }
 

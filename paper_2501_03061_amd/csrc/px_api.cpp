@@ -168,7 +168,7 @@ AceLayout ace_layout(const px_cell* cell, px_precision prec, int n, int ic, int 
 }
 
 struct ApplyLayout {
-  size_t C, part, end;
+  size_t C, C32, part, end;
 };
 
 ApplyLayout apply_layout(const px_cell* cell, int n, int n_phi) {
@@ -176,6 +176,8 @@ ApplyLayout apply_layout(const px_cell* cell, int n, int n_phi) {
   size_t off = 0;
   a.C = off;
   off = align_up(off + size_t(n) * n_phi * 16);
+  a.C32 = off;  // C rounded to complex64, the operand of the FP32 form's xi C
+  off = align_up(off + size_t(n) * n_phi * 8);
   int nsplit = 0;
   const size_t pe = px::gemm_xhy_part_elems(n, n_phi, ngrid(cell), &nsplit);
   a.part = off;
@@ -531,7 +533,8 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
     (void)hipEventRecord(ev[0], stream);
   }
   // M = dV Psi^H W, Hermitised; -M = L L^H; U = L^{-H}; xi = W U
-  st = hip_check(ctx, px::launch_gemm_xhy(fp32, n, n, ng, psi, W, dV, Mw, n, part, nsplit, stream),
+  st = hip_check(ctx, px::launch_gemm_xhy(fp32, n, n, ng, psi, W, dV, Mw, n, part, nsplit, nullptr,
+                                          stream),
                  "M = dV Psi^H W");
   if (st != PX_OK) return st;
   if (ctx->profiling) (void)hipEventRecord(ev[1], stream);
@@ -543,7 +546,16 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
                  "cholesky");
   if (st != PX_OK) return st;
   if (ctx->profiling) (void)hipEventRecord(ev[2], stream);
-  st = hip_check(ctx, px::launch_gemm_xc(fp32, n, n, ng, W, U, n, 1.0, xi, true, stream),
+  // FP32 form: U rounded to complex64 into L's place (L is not read again)
+  const void* Uc = U;
+  if (fp32) {
+    st = hip_check(ctx, px::launch_convert_f64_f32(size_t(2) * n * n, U, reinterpret_cast<float*>(L),
+                                                   stream),
+                   "U to FP32");
+    if (st != PX_OK) return st;
+    Uc = L;
+  }
+  st = hip_check(ctx, px::launch_gemm_xc(fp32, n, n, ng, W, Uc, n, 1.0, xi, true, stream),
                  "xi = W L^-H");
   if (st != PX_OK) return st;
   ctx->last_status.assign(1, status);
@@ -586,14 +598,16 @@ px_status px_ace_apply(px_context* ctx, const px_cell* cell, px_precision prec, 
   const size_t ng = ngrid(cell);
   const double dV = cell->L[0] * cell->L[1] * cell->L[2] / double(ng);
   double* C = reinterpret_cast<double*>(ctx->ws + l.C);
+  float* C32 = fp32 ? reinterpret_cast<float*>(ctx->ws + l.C32) : nullptr;
   double* part = reinterpret_cast<double*>(ctx->ws + l.part);
   int nsplit = 0;
   px::gemm_xhy_part_elems(n, n_phi, ng, &nsplit);
   st = hip_check(ctx, px::launch_gemm_xhy(fp32, n, n_phi, ng, xi, phi, dV, C, n_phi, part, nsplit,
-                                          stream),
+                                          C32, stream),
                  "C = dV xi^H phi");
   if (st != PX_OK) return st;
-  return hip_check(ctx, px::launch_gemm_xc(fp32, n, n_phi, ng, xi, C, n_phi, -1.0, out, false, stream),
+  const void* Cc = fp32 ? static_cast<const void*>(C32) : C;
+  return hip_check(ctx, px::launch_gemm_xc(fp32, n, n_phi, ng, xi, Cc, n_phi, -1.0, out, false, stream),
                    "out = -xi C");
 }
 
@@ -625,6 +639,8 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
   const size_t nel = size_t(n_phi) * ng;
   const double dV = cell->L[0] * cell->L[1] * cell->L[2] / double(ng);
   double* C = reinterpret_cast<double*>(ctx->ws + l.ap.C);
+  float* C32 = fp32 ? reinterpret_cast<float*>(ctx->ws + l.ap.C32) : nullptr;
+  const void* Cc = fp32 ? static_cast<const void*>(C32) : C;
   double* part = reinterpret_cast<double*>(ctx->ws + l.ap.part);
   void* mid = ctx->ws + l.mid;
   void* y = mid;
@@ -638,10 +654,10 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
     st = hip_check(ctx, px::launch_midpoint(fp32, nel, phi_n, cur, mid, stream), "midpoint");
     if (st != PX_OK) return st;
     st = hip_check(ctx, px::launch_gemm_xhy(fp32, n, n_phi, ng, xi, mid, dV, C, n_phi, part,
-                                            nsplit, stream),
+                                            nsplit, C32, stream),
                    "C = dV xi^H mid");
     if (st != PX_OK) return st;
-    st = hip_check(ctx, px::launch_gemm_xc(fp32, n, n_phi, ng, xi, C, n_phi, -1.0, y, false, stream),
+    st = hip_check(ctx, px::launch_gemm_xc(fp32, n, n_phi, ng, xi, Cc, n_phi, -1.0, y, false, stream),
                    "y = -xi C");
     if (st != PX_OK) return st;
     st = hip_check(ctx, px::launch_ptim_update(fp32, nel, phi_n, y, cur, nxt, dt_alpha, partial,
@@ -936,7 +952,8 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
     int nsplit = 0;
     px::gemm_xhy_part_elems(x.n, x.n, ng, &nsplit);
     st = hip_check(c, px::launch_gemm_xhy(fp32, x.n, x.n, ng, x.psi, W, dV, Mw, x.n,
-                                          reinterpret_cast<double*>(ws + P.part_off), nsplit, s),
+                                          reinterpret_cast<double*>(ws + P.part_off), nsplit,
+                                          nullptr, s),
                    "batched M");
     if (st != PX_OK) return st;
     st = hip_check(c, px::launch_hermitize(Mw, x.n, s), "batched hermitize");
@@ -946,9 +963,17 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
                                           reinterpret_cast<double*>(ws + P.dinv_off), s),
                    "batched cholesky");
     if (st != PX_OK) return st;
-    st = hip_check(c, px::launch_gemm_xc(fp32, x.n, x.n, ng, W,
-                                         reinterpret_cast<double*>(ws + P.U_off), x.n, 1.0, x.out,
-                                         true, s),
+    // FP32 form: U rounded to complex64 into L's place (L is not read again)
+    const void* Uc = ws + P.U_off;
+    if (fp32) {
+      st = hip_check(c, px::launch_convert_f64_f32(size_t(2) * x.n * x.n,
+                                                   reinterpret_cast<double*>(ws + P.U_off),
+                                                   reinterpret_cast<float*>(ws + P.L_off), s),
+                     "batched U to FP32");
+      if (st != PX_OK) return st;
+      Uc = ws + P.L_off;
+    }
+    st = hip_check(c, px::launch_gemm_xc(fp32, x.n, x.n, ng, W, Uc, x.n, 1.0, x.out, true, s),
                    "batched xi");
     if (st != PX_OK) return st;
   }

@@ -147,13 +147,15 @@ int ptim_update_blocks();
 // gemm_kernels.hip: complex GEMMs on MFMA
 // M[a][b] (a < na, b < nb, row-major ldm) = scale * sum_r conj(X[a][r]) Y[b][r]
 //   X: [na][ng], Y: [nb][ng]; FP64 result.  part: workspace of nsplit*na*nb complex128.
+//   M32 (nullable): the result rounded to complex64 as well, same layout.
 hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, const void* Y,
                            double scale, double* M, int ldm, double* part, int nsplit,
-                           hipStream_t s);
+                           float* M32, hipStream_t s);
 size_t gemm_xhy_part_elems(int na, int nb, size_t ng, int* nsplit);
-// Z[b][r] = alpha * sum_a X[a][r] C[a][b]  (+ beta * Z[b][r] if accumulate)
-//   X: [na][ng], C: complex128 [na][ldc] row-major, Z: [nb][ng]; upper: C upper triangular
-hipError_t launch_gemm_xc(bool fp32, int na, int nb, size_t ng, const void* X, const double* C,
+// Z[b][r] = alpha * sum_a X[a][r] C[a][b]
+//   X: [na][ng], C: [na][ldc] row-major in the precision of the form (complex128, or
+//   complex64 rounded from the FP64 matrix), Z: [nb][ng]; upper: C upper triangular
+hipError_t launch_gemm_xc(bool fp32, int na, int nb, size_t ng, const void* X, const void* C,
                           int ldc, double alpha, void* Z, bool upper, hipStream_t s);
 
 // chol_kernels.hip: FP64 Hermitian tools on an n x n complex128 matrix (row-major)
