@@ -172,6 +172,56 @@ def summarize_mfma(mfma, out, command):
     open(os.path.join(out, "gemm_mid72_mfma_counters.md"), "w").write("\n".join(lines) + "\n")
 
 
+def summarize_sq(dirs, out, commands):
+    """SQ / TA / TCP counters of the pair-pipeline passes and the contractions
+    (FP32 form, one bench step), per dispatch, with ratios whose units cancel:
+    VALU issue share = SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES (a wave64 VALU
+    instruction holds its SIMD 4 cycles and a CU has 4 SIMDs; both counters are
+    summed over CUs), wait share = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES (both per
+    wave), LDS bank-conflict share = SQ_LDS_BANK_CONFLICT / SQ_BUSY_CU_CYCLES,
+    TA busy share = TA_TA_BUSY / SQ_BUSY_CU_CYCLES, and the mean L2 read
+    latency seen by the vector L1 = TCP_TCC_READ_REQ_LATENCY / TCP_TCC_READ_REQ."""
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in dirs:
+        for r in _csv(d, "counter_collection.csv"):
+            k = r["Kernel_Name"]
+            if "float" not in k or not (_short(k).startswith("pass") or "gemm_" in k):
+                continue
+            agg[_short(k)][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["# SQ / TA / TCP counters: pair pipeline and contractions, mid72 workload (FP32 form)", "",
+             "Commands ($REPO: the repository root, $OUT: the raw output folder; one counter group per "
+             "run):", "", "```"] + commands + ["```", "",
+             "Per dispatch, averaged over the dispatches of one FP32 bench step (instantiations of a "
+             "pass merged). VALU issue share = SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES (a wave64 VALU "
+             "instruction holds its SIMD 4 cycles, a CU has 4 SIMDs, both counters are summed over "
+             "CUs); wait share = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES (time waves spend at s_waitcnt); "
+             "LDS conflict share = SQ_LDS_BANK_CONFLICT / SQ_BUSY_CU_CYCLES; TA busy = TA_TA_BUSY / "
+             "SQ_BUSY_CU_CYCLES; L2 latency = TCP_TCC_READ_REQ_LATENCY / TCP_TCC_READ_REQ (cycles).", "",
+             "| kernel | dispatches | VALU instr. per wave | VALU issue share | wait share | LDS conflict "
+             "share | TA busy | L2 read latency (cycles) |", "|---|---|---|---|---|---|---|---|"]
+    order = ["pass1_fwd_xy", "pass2_z_kernel", "pass3_inv_xy_acc", "pass4_transpose_acc", "gemm_xhy_k",
+             "gemm_xc_k"]
+
+    def avg(cs, c):
+        v = cs.get(c, [])
+        return sum(v) / len(v) if v else float("nan")
+
+    for k in order:
+        if k not in agg:
+            continue
+        cs = agg[k]
+        busy = avg(cs, "SQ_BUSY_CU_CYCLES")
+        lines.append(
+            f"| `{k}<float>` | {len(cs.get('SQ_INSTS_VALU', []))} | "
+            f"{avg(cs, 'SQ_INSTS_VALU') / avg(cs, 'SQ_WAVES'):.0f} | "
+            f"{100 * avg(cs, 'SQ_INSTS_VALU') / busy:.0f} % | "
+            f"{100 * avg(cs, 'SQ_WAIT_INST_ANY') / avg(cs, 'SQ_WAVE_CYCLES'):.0f} % | "
+            f"{100 * avg(cs, 'SQ_LDS_BANK_CONFLICT') / busy:.1f} % | "
+            f"{100 * avg(cs, 'TA_TA_BUSY') / busy:.0f} % | "
+            f"{avg(cs, 'TCP_TCC_READ_REQ_LATENCY') / avg(cs, 'TCP_TCC_READ_REQ'):.0f} |")
+    open(os.path.join(out, "pair_pipeline_mid72_sq_counters.md"), "w").write("\n".join(lines) + "\n")
+
+
 def main():
     import sys
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -179,10 +229,22 @@ def main():
     for a in ("trace", "fetch", "write", "copy-fetch", "copy-write", "bench-json"):
         ap.add_argument("--" + a)
     ap.add_argument("--mfma", help="rocprofv3 --pmc run with the MFMA counters (contractions)")
+    ap.add_argument("--sq", nargs="+", help="rocprofv3 --pmc runs with the SQ / TA / TCP counter groups")
     ap.add_argument("--out", default="profiles")
     args = ap.parse_args()
     # $REPO: the repository root; $OUT: a folder for the raw rocprofv3 output
     pre = "cd /tmp && export TMPDIR=/tmp"
+    if args.sq:
+        groups = ["SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "
+                  "SQ_WAIT_INST_LDS SQ_WAIT_ANY SQ_INSTS_VALU",
+                  "SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VMEM SQ_INST_LEVEL_VMEM SQ_INSTS_LDS "
+                  "SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY SQ_INSTS_SALU SQ_BUSY_CU_CYCLES",
+                  "TA_TA_BUSY TA_ADDR_STALLED_BY_TC_CYCLES TCP_TCC_READ_REQ_LATENCY TCP_TCC_READ_REQ"]
+        summarize_sq(args.sq, args.out, [pre] + [
+            f"timeout -s KILL 240 rocprofv3 --pmc {g} --output-format csv -d $OUT/pmc_sq{i + 1} -o run -- "
+            "python3 $REPO/bench.py --steps 1 --warmup 0 --no-fp64 --no-cpu" for i, g in enumerate(groups)])
+        if not (args.trace or args.mfma):
+            return
     if args.mfma:
         summarize_mfma(args.mfma, args.out, pre + "\ntimeout -s KILL 300 rocprofv3 --pmc "
                        "SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_VALU_MFMA_BUSY_CYCLES "
