@@ -2,15 +2,18 @@
 """Throughput of the exchange / ACE hot path on one MI355X.
 
 One step is one pass of the whole path over the resident synthetic instance:
-  staging of Psi and Phi_n to complex64 (FP32 form),
-  ACE build: W = Vx Psi through the fused pair pipeline (N^2 pair solves),
+  staging of Psi to complex64 (FP32 form),
+  ACE build: W = Vx Psi through the fused pair pipeline (N^2 logical pair
+    solves, N(N+1)/2 physical ones in the Hermitian-pair mode),
     M = dV Psi^H W, Hermitisation, FP64 Cholesky of -M, U = L^-H, xi = W U,
+  staging of Phi_n = Psi + 1e-3 Z to complex64 (FP32 form),
   4 PT-IM-style fixed-point iterations with the ACE operator and FP64 residuals.
-The headline value is logical pair solves per second of whole steps.  The
-plain FP64 form of the same step is timed after the headline run for the
-precision/speed comparison, and the CPU oracle is timed on a bounded sample.
+The headline value is logical pair solves per second of whole steps on the
+large single-GPU share (96^3 grid, 1536 orbitals).  The plain FP64 form of the
+same step is timed after the headline run for the precision/speed comparison,
+and the CPU oracle is timed on a bounded sample of the same instance.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload large96|mid72|batch48]
 
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
@@ -18,8 +21,8 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import statistics
 import sys
 import time
 
@@ -27,40 +30,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_pipeline_mid72_traffic.json")
-KERNEL_SOURCES = ("exchange_kernels.hpp", "fft_core.hpp", "px_internal.hpp", "exchange_inst.hip",
-                  "pair_transpose.hip")
+METRIC = "exchange pair-solves/s + ACE build s, FP32-batched vs FP64 at <=2e-5 err"
+PASS_NAMES = ["pass1_fwd_xy", "pass2_z_kernel", "pass3_inv_xy_acc", "pass4_transpose_acc"]
+# Time step 50 as in atomic units of time times the hybrid mixing fraction 0.25.
+DT_ALPHA = 50.0 / 24.188843265857 * 0.25
 
-
-def source_digest():
-    """Digest of the pair-pipeline kernel sources with comments and blank lines
-    removed: counter figures measured on other code are not reported."""
-    import hashlib
-    import re
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        text = open(os.path.join(ROOT, "paper_2501_03061_amd", "csrc", name)).read()
-        text = re.sub(r"//[^\n]*", "", text)
-        lines = [l.strip() for l in text.splitlines() if l.strip()]
-        h.update(("\n".join(lines) + "\n").encode())
-    return h.hexdigest()
-
-
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when that summary was taken on different kernel code."""
-    try:
-        rec = json.load(open(TRAFFIC_FILE))
-    except (OSError, ValueError):
-        return None
-    if rec.get("source_digest") != source_digest():
-        return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k["read_bytes"] + k["write_bytes"]
+WORKLOAD_TEXT = {
+    "large96": "large96: cubic cell L=27 bohr, 96^3 grid, 1536 complex orbitals (10 Ha sphere, "
+               "QR-orthonormalised), Fermi-Dirac kT=0.03 Ha, HSE mu=0.106; FP32 bulk with FP64 "
+               "G=0/energy/reductions/Cholesky; step = staging + ACE build (2359296 logical pair "
+               "solves, Hermitian-pair mode) + 4 PT-IM-style ACE iterations on Phi = Psi + 1e-3 Z",
+    "mid72": "mid72: cubic cell L=20 bohr, 72^3 grid, 512 complex orbitals (10 Ha sphere, "
+             "QR-orthonormalised), Fermi-Dirac kT=0.02 Ha, HSE mu=0.106; FP32 bulk with FP64 "
+             "G=0/energy/reductions/Cholesky; step = staging + ACE build (262144 logical pair "
+             "solves, Hermitian-pair mode) + 4 PT-IM-style ACE iterations on Phi = Psi + 1e-3 Z",
+}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def build_inputs(cfg):
@@ -69,20 +67,24 @@ def build_inputs(cfg):
     from paper_2501_03061_amd import inputs
     t0 = time.perf_counter()
     inst = inputs.make_instance(cfg["n"], cfg["L"], cfg["n_orb"], cfg["kT"], seed=cfg["seed"])
-    z = inputs.noise_block(inst.n, inst.L, inst.n_orb, seed=1001)
-    phi_n = inst.psi + 1e-3 * z
-    del z
     psi_d = torch.from_numpy(inst.psi).cuda()
-    phi_d = torch.from_numpy(phi_n).cuda()
+    z = inputs.noise_block(inst.n, inst.L, inst.n_orb, seed=1001)
+    z *= 1e-3
+    z += inst.psi
+    phi_d = torch.from_numpy(z).cuda()
+    del z
     occ_d = torch.from_numpy(inst.occ).cuda()
-    del phi_n
     log(f"inputs generated in {time.perf_counter() - t0:.1f}s "
-        f"(frac. occupations 0.01<f<0.99: {float(np.mean((inst.occ > 0.01) & (inst.occ < 0.99))):.3f})")
+        f"(occupations 0.1<f<0.9: {float(np.mean((inst.occ > 0.1) & (inst.occ < 0.9))):.3f}, "
+        f"0.01<f<0.99: {float(np.mean((inst.occ > 0.01) & (inst.occ < 0.99))):.3f})")
     return inst, psi_d, phi_d, occ_d
 
 
 class Step:
-    """One pass of the hot path in one precision form, buffers preallocated."""
+    """One pass of the hot path in one precision form, buffers preallocated.
+    With events, a CUDA event pair brackets the staging of Psi plus the ACE
+    build (the "ACE build s" half of the metric) on the current stream, which
+    is the stream the library's calls are enqueued on."""
 
     def __init__(self, ctx, cell, psi64, phi64, occ, kern, fp32, n_iter=4):
         import torch
@@ -104,36 +106,41 @@ class Step:
         need = max(ctx.workspace_bytes(px.PX_OP_ACE_BUILD, cell, prec, n),
                    ctx.workspace_bytes(px.PX_OP_PTIM_LOOP, cell, prec, n, n))
         ctx.ensure_workspace(need)
+        self.events = []
 
-    def __call__(self):
+    def __call__(self, record=False):
+        import torch
         c = self.ctx
+        if record:
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
         if self.fp32:
             c.px_convert_c128_to_c64(self.psi64, self.psi)
-            c.px_convert_c128_to_c64(self.phi64, self.phi)
         c.px_ace_build(self.cell, self.psi, self.occ, self.kern, xi=self.xi, M=self.M,
                        e_x=self.ex, status=self.status)
+        if record:
+            e[1].record()
+        if self.fp32:
+            c.px_convert_c128_to_c64(self.phi64, self.phi)
         c.px_ptim_exchange_loop(self.cell, self.xi, self.phi, self.n_iter, DT_ALPHA,
                                 out=self.out, residuals=self.res)
+        if record:
+            e[2].record()
+            self.events.append(e)
+
+    def event_times(self):
+        """Per recorded step: (staging + ACE build ms, whole step ms)."""
+        out = [(e[0].elapsed_time(e[1]), e[0].elapsed_time(e[2])) for e in self.events]
+        self.events = []
+        return out
 
 
-# Time step 50 as in atomic units of time times the hybrid mixing fraction 0.25.
-DT_ALPHA = 50.0 / 24.188843265857 * 0.25
-
-
-def ace_stages(prof, ace):
-    """Per ACE build (ms): pair pipeline (passes 1-4), M contraction,
-    factorisation (Hermitise, Cholesky, inverse), xi contraction."""
-    calls = max(1, ace["calls"])
-    return dict(pair_pipeline=sum(p["ms"] for p in prof) / calls, M_contraction=ace["M"] / calls,
-                factorization=ace["factor"] / calls, xi_contraction=ace["xi"] / calls, builds=ace["calls"])
-
-
-def run_steps(step, k):
+def run_steps(step, k, record=False):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(k):
-        step()
+        step(record) if record else step()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / k
 
@@ -156,25 +163,186 @@ def copy_bandwidth(ctx, nbytes=2 << 30, reps=5):
 
 
 def cpu_baseline(inst, kern_np, seconds):
-    """The oracle as it stands on a bounded sample: a few output columns of
-    W = Vx Psi against all orbitals."""
-    import numpy as np
+    """The oracle as it stands on a bounded sample of the same instance: whole
+    output columns of W = Vx Psi (each column pairs one orbital with all N),
+    scipy.fft with all host threads; then the same oracle with one FFT thread
+    on a 64-pair piece of one column."""
     import oracle
-    cols = 1
+    import oracle.exchange as oex
+    threads = oex._WORKERS
     t0 = time.perf_counter()
-    oracle.exchange_apply(inst.psi, inst.occ, inst.psi[:cols], kern_np)
+    oracle.exchange_apply(inst.psi, inst.occ, inst.psi[:1], kern_np)
     t1 = time.perf_counter() - t0
     more = max(0, min(inst.n_orb - 1, int(seconds / max(t1, 1e-3)) - 1))
     t2 = 0.0
     if more:
         t0 = time.perf_counter()
-        oracle.exchange_apply(inst.psi, inst.occ, inst.psi[cols:cols + more], kern_np)
+        oracle.exchange_apply(inst.psi, inst.occ, inst.psi[1:1 + more], kern_np)
         t2 = time.perf_counter() - t0
-    pairs = (cols + more) * inst.n_orb
-    return dict(value=pairs / (t1 + t2), unit="pair-solves/s", cores=os.cpu_count(), kind="oracle",
-                sample=f"{cols + more} output orbitals x {inst.n_orb} density orbitals "
+    pairs = (1 + more) * inst.n_orb
+    # one thread: 64 density orbitals against one output orbital
+    oex._WORKERS = 1
+    try:
+        t0 = time.perf_counter()
+        oracle.exchange_apply(inst.psi[:64], inst.occ[:64], inst.psi[:1], kern_np)
+        t3 = time.perf_counter() - t0
+    finally:
+        oex._WORKERS = threads
+    return dict(value=pairs / (t1 + t2), unit="pair-solves/s", cores=threads, kind="oracle",
+                sample=f"{1 + more} output orbital(s) x {inst.n_orb} density orbitals "
                        f"({pairs} pair solves) of the same instance, {t1 + t2:.1f}s, "
-                       f"scipy.fft workers={os.cpu_count()}")
+                       f"scipy.fft workers={threads}, host CPU: {cpu_model()}",
+                one_thread_value=64 / t3, one_thread_sample="64 pair solves (one output orbital "
+                f"x 64 density orbitals), scipy.fft workers=1, {t3:.1f}s")
+
+
+def roofline_fields(prof, ace, steps, pairs_phys, ng, b, copy_gbps):
+    """Roofline of the dominant pass (HIP-event durations over the timed
+    region) and of the whole pair pipeline, both with the 6*N_g*b model."""
+    dom = max(range(4), key=lambda k: prof[k]["ms"])
+    pd = prof[dom]
+    per_launch = pd["bytes"] / max(1, pd["launches"])
+    avg_s = pd["ms"] * 1e-3 / max(1, pd["launches"])
+    achieved = per_launch / avg_s / 1e9
+    pipe_ms = sum(p["ms"] for p in prof)
+    model_bytes = pairs_phys * 6.0 * ng * b * steps
+    pipe_gbps = model_bytes / (pipe_ms * 1e-3) / 1e9
+    # bytes the Hermitian-pair mode moves beyond the model: the kept v_ij,
+    # written by pass 3 and read back by pass 4
+    extra_bytes = pairs_phys * ng * b * steps + prof[3]["bytes"]
+    passes = {}
+    for k in range(4):
+        if prof[k]["launches"] == 0:
+            continue
+        passes[PASS_NAMES[k]] = dict(
+            avg_us=1e3 * prof[k]["ms"] / prof[k]["launches"],
+            launches_per_step=prof[k]["launches"] // steps,
+            ms_per_step=prof[k]["ms"] / steps,
+            model_GBps=prof[k]["bytes"] / (prof[k]["ms"] * 1e-3) / 1e9)
+    roof = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": PASS_NAMES[dom],
+        "per_unit_bytes": per_launch,
+        "unit_desc": "algorithmic bytes per launch of the dominant pass: 2*N_g*b per pair "
+                     "solved in the launch (its share of the 6*N_g*b pair model), b = 8 B "
+                     "(complex64); the kept v_ij of the Hermitian-pair mode is not counted",
+    }
+    pipeline = dict(ms_per_step=pipe_ms / steps, model_GBps=pipe_gbps,
+                    model_frac=pipe_gbps / HBM_PEAK_GBPS,
+                    model_plus_kept_v_GBps=(model_bytes + extra_bytes) / (pipe_ms * 1e-3) / 1e9,
+                    copy_kernel_GBps=copy_gbps,
+                    desc="physical pair solves x 6*N_g*b over the summed pass times of the "
+                         "pair pipeline; model_plus_kept_v adds the v_ij that the Hermitian-pair "
+                         "mode writes in pass 3 and reads in pass 4")
+    stages = dict(pair_pipeline_ms=pipe_ms / max(1, ace["calls"]),
+                  M_contraction_ms=ace["M"] / max(1, ace["calls"]),
+                  factorization_ms=ace["factor"] / max(1, ace["calls"]),
+                  xi_contraction_ms=ace["xi"] / max(1, ace["calls"]),
+                  build_ms=ace["build"] / max(1, ace["calls"]), builds=ace["calls"])
+    return dom, roof, pipeline, passes, stages
+
+
+def bench_single(args, workload):
+    import torch
+    from paper_2501_03061_amd import inputs, px
+    import profsum
+    cfg = inputs.CONFIGS[workload]
+    inst, psi64, phi64, occ = build_inputs(cfg)
+    n = inst.n_orb
+    cell = px.Cell(inst.L, inst.n)
+    ng = cell.ng
+    ctx = px.Context(0)
+    kern = ctx.px_kernel_hse(cell, cfg["mu"])
+    pairs = n * n
+    pairs_phys = n * (n + 1) // 2
+
+    copy = copy_bandwidth(ctx)
+    log(f"copy kernel: {copy['copy_GBps']:.0f} GB/s")
+    step32 = Step(ctx, cell, psi64, phi64, occ, kern, fp32=True)
+    for k in range(args.warmup):
+        step32()
+        log(f"warmup step {k + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    ctx.px_sync()
+    ctx.px_profile_read(reset=True)
+    ctx.px_profile_read_ace(reset=True)
+    ctx.px_set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step32(True)
+        if args.steps > 3:
+            log(f"timed step {k + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    ctx.px_set_profiling(False)
+    prof = ctx.px_profile_read(reset=True)
+    ace = ctx.px_profile_read_ace(reset=True)
+    ctx.px_sync()
+    ev32 = step32.event_times()
+    value = pairs / (ms_step * 1e-3)
+    log(f"fp32 step {ms_step:.1f} ms -> {value:.4g} pair-solves/s")
+    dom, roof, pipeline, passes, stages = roofline_fields(prof, ace, args.steps, pairs_phys, ng, 8,
+                                                          copy["copy_GBps"])
+    roof["traffic"] = profsum.measured_traffic(workload, PASS_NAMES[dom])
+    ace_s = [a * 1e-3 for a, _ in ev32]
+    extra = dict(
+        logical_pair_solves_per_step=pairs, physical_pair_solves_per_step=pairs_phys,
+        physical_pair_solves_per_s=pairs_phys / (ms_step * 1e-3),
+        ace_build_s_fp32=statistics.median(ace_s), ace_build_s_fp32_all=ace_s,
+        step_ms_median=statistics.median(s for _, s in ev32),
+        pair_pipeline=pipeline, passes=passes, ace_build_stages_fp32=stages,
+        e_x_fp32=float(step32.ex.item()), residuals_fp32=[float(x) for x in step32.res.cpu()],
+        gpu=torch.cuda.get_device_name(0),
+    )
+
+    if not args.no_fp64:
+        step64 = Step(ctx, cell, psi64, phi64, occ, kern, fp32=False)
+        step64()
+        torch.cuda.synchronize()
+        log("fp64 warmup step done")
+        ms64 = 1e3 * run_steps(step64, args.fp64_steps, record=True)
+        ctx.px_sync()
+        ev64 = step64.event_times()
+        ace64 = [a * 1e-3 for a, _ in ev64]
+
+        def rel(a, b):
+            return float(torch.linalg.vector_norm((a.to(torch.complex128) - b).flatten()) /
+                         torch.linalg.vector_norm(b.flatten()))
+        ex64, ex32 = float(step64.ex.item()), float(step32.ex.item())
+        errs = dict(M=rel(step32.M, step64.M), e_x=abs(ex32 - ex64) / abs(ex64),
+                    xi=rel(step32.xi, step64.xi), ptim_out=rel(step32.out, step64.out),
+                    residuals_fp64=[float(a) for a in step64.res.cpu()])
+        extra.update(
+            fp64_pair_solves_per_s=pairs / (ms64 * 1e-3),
+            fp64_physical_pair_solves_per_s=pairs_phys / (ms64 * 1e-3),
+            fp64_ms_per_step=ms64, fp64_steps=args.fp64_steps,
+            ace_build_s_fp64=statistics.median(ace64),
+            speedup_fp32_vs_fp64=ms64 / ms_step,
+            speedup_fp32_vs_fp64_ace_build=statistics.median(ace64) / statistics.median(ace_s),
+            err_fp32_vs_fp64=errs, e_x_fp64=ex64,
+        )
+        log(f"fp64 step {ms64:.1f} ms; errors {errs}")
+        step64 = None
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(inst, kern.cpu().numpy(), args.cpu_seconds)
+        log(f"cpu oracle: {cpu['value']:.4g} pair-solves/s on {cpu['cores']} threads "
+            f"({cpu['one_thread_value']:.3g} on one)")
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "pair-solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[workload], "grid": list(inst.n), "n_orbitals": n,
+                   "pairs_per_step": pairs},
+        "roofline": roof, "cpu_baseline": cpu, "extra": extra,
+    }
+    ctx.close()
+    return rec
 
 
 def bench_batch48(args):
@@ -229,80 +397,17 @@ def bench_batch48(args):
     ms_64 = 1e3 * run_steps(single(args64), 1)
     ctx.px_sync()
     rec = {
-        "metric": "exchange pair-solves/s + ACE build s, FP32-batched vs FP64 at <=2e-5 err",
-        "value": pairs / (ms_b * 1e-3), "unit": "pair-solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "metric": METRIC, "value": pairs / (ms_b * 1e-3), "unit": "pair-solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batch48: 48 instances, grids {32,40,48,64}^3, 32..256 orbitals, "
                                "kT 0.005..0.05 Ha, L = 0.28 n bohr; FP32 ACE builds, batched + graph",
                    "pairs_per_step": pairs},
         "extra": {"autotuned_blocks": blocks, "single_fp32_ms": ms_1, "single_fp64_ms": ms_64,
                   "single_fp32_pair_solves_per_s": pairs / (ms_1 * 1e-3),
                   "single_fp64_pair_solves_per_s": pairs / (ms_64 * 1e-3),
+                  "speedup_batched_fp32_vs_single_fp32": ms_1 / ms_b,
                   "speedup_batched_fp32_vs_single_fp64": ms_64 / ms_b},
-    }
-    ctx.close()
-    return rec
-
-
-def bench_large96(args):
-    """The large single-GPU share (96^3, 1536 orbitals, kT 0.03): one step of
-    each form (staging, ACE build, 4 PT-IM-style ACE iterations), timed after
-    one untimed step, and the ACE builds alone; FP32 against FP64 errors."""
-    import torch
-    from paper_2501_03061_amd import inputs, px
-    cfg = inputs.CONFIGS["large96"]
-    inst, psi64, phi64, occ = build_inputs(cfg)
-    n = inst.n_orb
-    cell = px.Cell(inst.L, inst.n)
-    ctx = px.Context(0)
-    kern = ctx.px_kernel_hse(cell, cfg["mu"])
-    pairs = n * n
-    res = {}
-    steps = {}
-    for name, fp32 in (("fp32", True), ("fp64", False)):
-        st = Step(ctx, cell, psi64, phi64, occ, kern, fp32=fp32)
-        st()
-        torch.cuda.synchronize()
-        ms = 1e3 * run_steps(st, 1)
-
-        def ace_only():
-            if fp32:
-                ctx.px_convert_c128_to_c64(psi64, st.psi)
-            ctx.px_ace_build(cell, st.psi, occ, kern, xi=st.xi, M=st.M, e_x=st.ex, status=st.status)
-        ace_s = run_steps(ace_only, 1)
-        st()
-        torch.cuda.synchronize()
-        ctx.px_sync()
-        res[name] = dict(ms_per_step=ms, pair_solves_per_s=pairs / (ms * 1e-3), ace_build_s=ace_s)
-        log(f"large96 {name}: step {ms:.0f} ms, ACE build {ace_s:.2f} s")
-        steps[name] = st
-        if not fp32:
-            continue
-        # keep only what the comparison needs before the FP64 buffers are allocated
-        st.psi = st.phi = None
-        torch.cuda.empty_cache()
-    s32, s64 = steps["fp32"], steps["fp64"]
-
-    def rel(a, b):
-        return float(torch.linalg.vector_norm((a.to(torch.complex128) - b).flatten()) /
-                     torch.linalg.vector_norm(b.flatten()))
-    ex32, ex64 = float(s32.ex.item()), float(s64.ex.item())
-    errs = dict(M=rel(s32.M, s64.M), e_x=abs(ex32 - ex64) / abs(ex64), ptim_out=rel(s32.out, s64.out),
-                residuals_fp32=[float(x) for x in s32.res.cpu()],
-                residuals_fp64=[float(x) for x in s64.res.cpu()])
-    rec = {
-        "metric": "exchange pair-solves/s + ACE build s, FP32-batched vs FP64 at <=2e-5 err",
-        "value": res["fp32"]["pair_solves_per_s"], "unit": "pair-solves/s", "n_gpus": 1, "steps": 1,
-        "warmup": 1, "ms_per_step": res["fp32"]["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "large96: cubic cell L=27 bohr, 96^3 grid, 1536 complex orbitals, "
-                               "Fermi-Dirac kT=0.03 Ha; step = staging + ACE build (2359296 pair "
-                               "solves) + 4 PT-IM-style ACE iterations",
-                   "grid": [96, 96, 96], "n_orbitals": n, "pairs_per_step": pairs},
-        "extra": {"fp32": res["fp32"], "fp64": res["fp64"],
-                  "speedup_fp32_vs_fp64": res["fp64"]["ms_per_step"] / res["fp32"]["ms_per_step"],
-                  "e_x_fp64": ex64, "err_fp32_vs_fp64": errs},
     }
     ctx.close()
     return rec
@@ -314,13 +419,13 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="mid72", choices=["mid72", "batch48", "large96"],
-                    help="mid72 (default, the headline): one 72^3 x 512 instance; batch48: the "
-                         "48-instance uneven batch in the batched form; large96: the 96^3 x 1536 "
-                         "single-GPU share, one step per form (several minutes)")
+    ap.add_argument("--workload", default="large96", choices=["large96", "mid72", "batch48"],
+                    help="large96 (default, the headline): the 96^3 x 1536 single-GPU share; "
+                         "mid72: one 72^3 x 512 instance; batch48: the 48-instance uneven batch "
+                         "in the batched form")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy kernel (2 GiB, 5 launches) and print its bandwidth")
     args = ap.parse_args()
@@ -329,10 +434,7 @@ def main():
               "(the exchange shards by orbital columns; see the design notes). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-    from paper_2501_03061_amd import inputs, px
+    from paper_2501_03061_amd import px
 
     if args.calibrate_copy:
         ctx = px.Context(0)
@@ -341,146 +443,7 @@ def main():
     if args.workload == "batch48":
         print(json.dumps(bench_batch48(args)), flush=True)
         return
-    if args.workload == "large96":
-        print(json.dumps(bench_large96(args)), flush=True)
-        return
-
-    cfg = inputs.CONFIGS["mid72"]
-    inst, psi64, phi64, occ = build_inputs(cfg)
-    n = inst.n_orb
-    cell = px.Cell(inst.L, inst.n)
-    ctx = px.Context(0)
-    kern = ctx.px_kernel_hse(cell, cfg["mu"])
-
-    copy = copy_bandwidth(ctx)
-    log(f"copy kernel: {copy['copy_GBps']:.0f} GB/s")
-    step32 = Step(ctx, cell, psi64, phi64, occ, kern, fp32=True)
-    for _ in range(args.warmup):
-        step32()
-    torch.cuda.synchronize()
-    ctx.px_sync()
-    ctx.px_profile_read(reset=True)
-    ctx.px_profile_read_ace(reset=True)
-    ctx.px_set_profiling(True)
-    ms_step = 1e3 * run_steps(step32, args.steps)
-    ctx.px_set_profiling(False)
-    prof = ctx.px_profile_read(reset=True)
-    ace_prof = ctx.px_profile_read_ace(reset=True)
-    ctx.px_sync()
-    pairs = n * n
-    value = pairs / (ms_step * 1e-3)
-    log(f"fp32 step {ms_step:.1f} ms -> {value:.4g} pair-solves/s")
-
-    # ACE build alone (FP32 form including staging), for the second half of the metric
-    def ace_only():
-        ctx.px_convert_c128_to_c64(psi64, step32.psi)
-        ctx.px_ace_build(cell, step32.psi, occ, kern, xi=step32.xi, M=step32.M, e_x=step32.ex,
-                         status=step32.status)
-    ace_s32 = run_steps(ace_only, 1)
-
-    # pipeline roofline: dominant pass of the pair pipeline
-    names = ["pass1_fwd_xy", "pass2_z_kernel", "pass3_inv_xy_acc", "pass4_transpose_acc"]
-    dom = max(range(4), key=lambda k: prof[k]["ms"])
-    pd = prof[dom]
-    achieved = pd["bytes"] / (pd["ms"] * 1e-3) / 1e9
-    pipe_ms = sum(p["ms"] for p in prof)
-    pipe_gbps = sum(p["bytes"] for p in prof) / (pipe_ms * 1e-3) / 1e9
-
-    extra = dict(
-        copy_kernel_GBps=copy["copy_GBps"],
-        ace_build_s_fp32=ace_s32,
-        pair_pipeline_ms_per_step=pipe_ms / args.steps,
-        pair_pipeline_model_GBps=pipe_gbps,
-        passes={names[k]: dict(avg_us=1e3 * prof[k]["ms"] / max(1, prof[k]["launches"]),
-                               launches_per_step=prof[k]["launches"] // args.steps,
-                               GBps=prof[k]["bytes"] / (prof[k]["ms"] * 1e-3) / 1e9)
-                for k in range(4) if prof[k]["launches"] > 0},
-        ace_build_stages_fp32_ms=ace_stages(prof, ace_prof),
-        e_x_fp32=float(step32.ex.item()),
-        residuals_fp32=[float(x) for x in step32.res.cpu()],
-    )
-
-    if not args.no_fp64:
-        step64 = Step(ctx, cell, psi64, phi64, occ, kern, fp32=False)
-        step64()
-        torch.cuda.synchronize()
-        ms64 = 1e3 * run_steps(step64, args.fp64_steps)
-        ace_s64 = run_steps(lambda: ctx.px_ace_build(cell, psi64, occ, kern, xi=step64.xi, M=step64.M,
-                                                     e_x=step64.ex, status=step64.status), 1)
-        ctx.px_sync()
-        # stage breakdown of one more (profiled) FP64 build
-        ctx.px_profile_read(reset=True)
-        ctx.px_profile_read_ace(reset=True)
-        ctx.px_set_profiling(True)
-        ctx.px_ace_build(cell, psi64, occ, kern, xi=step64.xi, M=step64.M, e_x=step64.ex,
-                         status=step64.status)
-        ctx.px_set_profiling(False)
-        stages64 = ace_stages(ctx.px_profile_read(reset=True), ctx.px_profile_read_ace(reset=True))
-        step32()
-        torch.cuda.synchronize()
-        ctx.px_sync()
-
-        def rel(a, b):
-            return float(torch.linalg.vector_norm((a.to(torch.complex128) - b).flatten()) /
-                         torch.linalg.vector_norm(b.flatten()))
-        ex64, ex32 = float(step64.ex.item()), float(step32.ex.item())
-        extra.update(
-            fp64_pair_solves_per_s=pairs / (ms64 * 1e-3),
-            fp64_ms_per_step=ms64,
-            ace_build_s_fp64=ace_s64,
-            ace_build_stages_fp64_ms=stages64,
-            speedup_fp32_vs_fp64=(pairs / (ms_step * 1e-3)) / (pairs / (ms64 * 1e-3)),
-            err_fp32_vs_fp64=dict(M=rel(step32.M, step64.M), e_x=abs(ex32 - ex64) / abs(ex64),
-                                  xi=rel(step32.xi, step64.xi),
-                                  ptim_out=rel(step32.out, step64.out),
-                                  residuals=[float(a) for a in step64.res.cpu()]),
-        )
-        log(f"fp64 step {ms64:.1f} ms; errors {extra['err_fp32_vs_fp64']}")
-        del step64
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(inst, kern.cpu().numpy(), args.cpu_seconds)
-        log(f"cpu oracle: {cpu['value']:.4g} pair-solves/s on {cpu['cores']} threads")
-
-    rec = {
-        "metric": "exchange pair-solves/s + ACE build s, FP32-batched vs FP64 at <=2e-5 err",
-        "value": value,
-        "unit": "pair-solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": "mid72: cubic cell L=20 bohr, 72^3 grid, 512 complex orbitals (10 Ha sphere, "
-                        "QR-orthonormalised), Fermi-Dirac kT=0.02 Ha, HSE mu=0.106; FP32 bulk with FP64 "
-                        "G=0/energy/reductions/Cholesky; step = staging + ACE build (262144 pair solves) "
-                        "+ 4 PT-IM-style ACE iterations",
-            "grid": [72, 72, 72], "n_orbitals": n, "pairs_per_step": pairs,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": measured_traffic(names[dom]),
-            "kernel": names[dom],
-            "per_unit_bytes": pd["bytes"] / max(1, pd["launches"]),
-            "unit_desc": "algorithmic bytes per launch: 2*N_g*8 B per pair of the launch's chunk "
-                         "(its share of the 6*N_g*b pair model), plus N_g*8 B per pair for the kept "
-                         "v_ij when pass 3 runs an off-diagonal block of the Hermitian-pair mode",
-        },
-        "cpu_baseline": cpu,
-        "extra": extra,
-    }
-    print(json.dumps(rec), flush=True)
-    ctx.close()
+    print(json.dumps(bench_single(args, args.workload)), flush=True)
 
 
 if __name__ == "__main__":

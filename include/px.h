@@ -26,7 +26,8 @@
  *     1/N_g; for a real even kernel the result does not depend on the sign.
  *   Alignment: orbital blocks (psi, phi, xi and the outputs) must be 16-byte
  *     aligned; every orbital of a block then is too, since N_g is a multiple
- *     of 64 on the supported grids.  Misaligned blocks: PX_ERR_INVALID_ARG.
+ *     of 64 on the grids with FFT plans and must be even for FP32 blocks in
+ *     the contraction-only entry points.  Misaligned blocks: PX_ERR_INVALID_ARG.
  *   Memory: all array arguments are DEVICE pointers owned by the caller.  The
  *     library never allocates or frees device memory; scratch space comes from
  *     the workspace the caller attaches with px_set_workspace, sized by
@@ -151,13 +152,20 @@ px_status px_exchange_apply(px_context* ctx, const px_cell* cell, px_precision p
  * Outputs: xi [n][N_g] (element type of prec); M (nullable) complex128 [n][n]
  * after Hermitisation; e_x (nullable) as in px_exchange_apply; status (device
  * int32, required): 0 on success, else the 1-based column where the Cholesky
- * factorisation of -M broke down (xi is then undefined). */
+ * factorisation of -M broke down (xi is then undefined).
+ * In the Hermitian-pair mode (px_set_symmetry, on by default) each unordered
+ * pair is solved once and v_ji = conj(v_ij) is used for the other; that holds
+ * only for a real kernel with K(G) = K(-G) (true of px_kernel_hse and of any
+ * radial interaction).  For another kernel turn the mode off: with it on, the
+ * results are those of the kernel's even real part on the pairs j < i. */
 px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
                        const void* psi, const double* occ, const double* kernel_G, void* xi,
                        double* M, double* e_x, int32_t* status, hipStream_t stream);
 
 /* ACE application (Eq. 14): out = V_ACE phi = -xi (dV xi^H phi).
- * xi [n][N_g], phi and out [n_phi][N_g], element type of prec. */
+ * xi [n][N_g], phi and out [n_phi][N_g], element type of prec.  Only
+ * contractions: any grid in the FP64 form; the FP32 form needs an even N_g
+ * (PX_ERR_UNSUPPORTED_GRID otherwise). */
 px_status px_ace_apply(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
                        const void* xi, int32_t n_phi, const void* phi, void* out,
                        hipStream_t stream);
@@ -169,7 +177,7 @@ px_status px_ace_apply(px_context* ctx, const px_cell* cell, px_precision prec, 
  * for k = 0 .. n_iter-1, with residual R_k = ||Phi^(k+1) - Phi^(k)||_F / ||Phi^(k+1)||_F
  * accumulated in FP64.  dt_alpha = dt * alpha (e.g. 50 as * 0.25).
  * xi [n][N_g], phi_n and phi_out [n_phi][N_g] (element type of prec),
- * residuals: device float64 [n_iter]. */
+ * residuals: device float64 [n_iter].  Grids as in px_ace_apply. */
 px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
                                 const void* xi, int32_t n_phi, const void* phi_n, int32_t n_iter,
                                 double dt_alpha, void* phi_out, double* residuals,
@@ -192,19 +200,24 @@ px_status px_set_symmetry(px_context* ctx, int32_t enable);
 px_status px_set_profiling(px_context* ctx, int32_t enable);
 
 /* Totals since the last reset, per pass k = 0..3 (arrays of 4): ms[k] summed
- * event time, bytes[k] algorithmic HBM bytes (2 * N_g * element size per pair:
- * pass 1 reads psi_j and writes the pair slab, pass 2 reads and rewrites it,
- * pass 3 reads it and psi_j, plus one more slab write per pair in symmetric
- * mode; pass 4, symmetric mode only, reads v_ij and psi_i), launches[k] kernel
+ * event time (pass 4: the time from the end of pass 3 to the end of the
+ * chunk, which is the transposed accumulation), bytes[k] algorithmic HBM
+ * bytes of the 6 * N_g * b pair model (b = element size), 2 * N_g * b per
+ * solved pair in each of passes 1-3: pass 1 reads psi_j and writes the pair
+ * slab, pass 2 reads and rewrites it, pass 3 reads it and psi_j.  The
+ * Hermitian-pair mode keeps v_ij outside that model: pass 3 also writes it
+ * (N_g * b per solved pair, not counted in bytes[2]) and pass 4 reads it back,
+ * bytes[3] = N_g * b per pair below the diagonal.  launches[k] kernel
  * launches.  reset != 0 zeroes the totals. */
 px_status px_profile_read(px_context* ctx, double* ms, double* bytes, int64_t* launches,
                           int32_t reset);
 
 /* Stage times of the ACE builds (px_ace_build) made while profiling was on,
- * since the last reset (Sec. IV-A-2, Eq. (14): the steps after W = Vx Psi):
- * ms[0] the contraction M = dV Psi^H W, ms[1] the factorisation (Hermitising,
- * Cholesky of -M and U = L^{-H}), ms[2] the contraction xi = W U; *calls the
- * number of builds.  The pair pipeline of the builds is in px_profile_read.
+ * since the last reset (Sec. IV-A-2, Eq. (14)), ms an array of 4: ms[0] the
+ * contraction M = dV Psi^H W, ms[1] the factorisation (Hermitising, Cholesky
+ * of -M and U = L^{-H}), ms[2] the contraction xi = W U, ms[3] the whole
+ * build from its first enqueued work (W = Vx Psi) to its last; *calls the
+ * number of builds.  The passes of the pair pipeline are in px_profile_read.
  * Each profiled build synchronises on its last event.  reset != 0 zeroes. */
 px_status px_profile_read_ace(px_context* ctx, double* ms, int64_t* calls, int32_t reset);
 
@@ -229,7 +242,8 @@ size_t px_workspace_bytes_batched(const px_context* ctx, int32_t n_inst, const p
                                   px_precision prec, int32_t ace);
 
 /* Batched form (Sec. III-B(b) batches pairs to fill the GPU): all block pairs
- * of all instances (Hermitian-pair mode, square blocks from the tuning) are
+ * of all instances (Hermitian-pair mode, always on here, so every kernel_G
+ * must be real and even, K(G) = K(-G); square blocks from the tuning) are
  * grouped by grid size and scheduled by block diagonal, so each pass runs as
  * one launch over a task table for many chunks of many instances; then the
  * per-instance energies and, with ace != 0, the ACE construction.  The whole

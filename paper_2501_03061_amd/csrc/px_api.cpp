@@ -32,8 +32,10 @@ struct px_context {
   double prof_ms[4] = {0, 0, 0, 0};
   double prof_bytes[4] = {0, 0, 0, 0};
   int64_t prof_launches[4] = {0, 0, 0, 0};
-  hipEvent_t ace_events[4] = {nullptr, nullptr, nullptr, nullptr};  // ACE build stages
-  double ace_ms[3] = {0, 0, 0};
+  // ACE build stages: start of the build, start of M, after M, after the
+  // factorisation, after xi
+  hipEvent_t ace_events[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double ace_ms[4] = {0, 0, 0, 0};
   int64_t ace_calls = 0;
   bool symmetric_ace = true;  // ACE build solves only pairs j <= i (block level)
   bool tri_diag = true;       // ... and within the diagonal blocks (pair level)
@@ -218,6 +220,20 @@ px_status check_grid(px_context* c, const px_cell* cell) {
   return PX_OK;
 }
 
+// Grids of the contraction-only entry points (ACE application, PT-IM-style
+// loop): any positive grid in the FP64 form; the FP32 form reads two complex64
+// values per 16-byte load, so N_g must be even (every orbital of a block then
+// stays 16-byte aligned and a load never straddles two orbitals).
+px_status check_gemm_grid(px_context* c, const px_cell* cell, px_precision prec) {
+  if (!cell_ok(cell))
+    return fail(c, PX_ERR_INVALID_ARG, "cell: edge lengths must be > 0 and grid sizes > 0");
+  if (prec == PX_PREC_FP32 && ngrid(cell) % 2 != 0)
+    return fail(c, PX_ERR_UNSUPPORTED_GRID,
+                "grid %dx%dx%d: the FP32 form needs an even number of grid points", cell->n[0],
+                cell->n[1], cell->n[2]);
+  return PX_OK;
+}
+
 px_status need_ws(px_context* c, size_t bytes) {
   if (c->ws == nullptr || c->ws_bytes < bytes)
     return fail(c, PX_ERR_WORKSPACE, "workspace of %zu bytes attached, %zu needed", c->ws_bytes,
@@ -292,19 +308,20 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       }
       if (c->profiling) {
         (void)hipEventRecord(c->events[5 * nchunks + 4], s);
-        // algorithmic bytes, 2 N_g b per pair in each pass (pass 1: read psi_j,
-        // write the pair slab; pass 2: read and rewrite it; pass 3: read it and
-        // psi_j); in symmetric mode pass 3 also writes v_ij (1 N_g b) and
-        // pass 4 reads v_ij and psi_i (2 N_g b)
-        // (a triangular block keeps v_ij for its npairs pairs; pass 4 reads
-        // the npairs - ic of them below the diagonal)
+        // algorithmic bytes of the 6 N_g b pair model, 2 N_g b per solved pair
+        // in each pass (pass 1: read psi_j, write the pair slab; pass 2: read
+        // and rewrite it; pass 3: read it and psi_j).  The symmetric mode's
+        // kept v_ij is outside the model: pass 3 writes it (not counted here)
+        // and pass 4 reads it back, N_g b per pair below the diagonal (a
+        // triangular block keeps v_ij for its npairs pairs; pass 4 reads the
+        // npairs - ic of them below the diagonal)
         const double np = double(npairs), np4 = a.tri ? double(npairs - a.ic) : np;
         for (int k = 0; k < 3; ++k) {
-          c->prof_bytes[k] += 2.0 * pair_bytes * np + (k == 2 && a.store_v ? pair_bytes * np : 0.0);
+          c->prof_bytes[k] += 2.0 * pair_bytes * np;
           c->prof_launches[k] += 1;
         }
         if (a.store_v) {
-          c->prof_bytes[3] += 2.0 * pair_bytes * np4;
+          c->prof_bytes[3] += pair_bytes * np4;
           c->prof_launches[3] += 1;
         }
         has4.push_back(a.store_v);
@@ -374,6 +391,9 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
                           int32_t n_psi, int32_t n_phi) {
   if (!ctx || !cell_ok(cell) || n_psi <= 0) return 0;
   if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32) return 0;
+  const bool fft_grid = px::grid_supported(cell->n[0], cell->n[1], cell->n[2]);
+  const bool gemm_grid = prec == PX_PREC_FP64 || ngrid(cell) % 2 == 0;
+  if (op == PX_OP_EXCHANGE || op == PX_OP_ACE_BUILD ? !fft_grid : !gemm_grid) return 0;
   int ic, jc;
   tuning_for(ctx, cell, prec, &ic, &jc);
   switch (op) {
@@ -507,6 +527,13 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   const size_t ng = ngrid(cell);
   const double omega = cell->L[0] * cell->L[1] * cell->L[2];
   const double dV = omega / double(ng);
+  hipEvent_t* ev = ctx->ace_events;
+  if (ctx->profiling) {
+    for (int k = 0; k < 5; ++k)
+      if (!ev[k] && hipEventCreate(&ev[k]) != hipSuccess)
+        return fail(ctx, PX_ERR_DEVICE, "hipEventCreate failed");
+    (void)hipEventRecord(ev[0], stream);
+  }
   void* W = ctx->ws + l.W;
   double* Mw = M ? M : reinterpret_cast<double*>(ctx->ws + l.M);
   double* L = reinterpret_cast<double*>(ctx->ws + l.L);
@@ -525,19 +552,13 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   }
   int nsplit = 0;
   px::gemm_xhy_part_elems(n, n, ng, &nsplit);
-  hipEvent_t* ev = ctx->ace_events;
-  if (ctx->profiling) {
-    for (int k = 0; k < 4; ++k)
-      if (!ev[k] && hipEventCreate(&ev[k]) != hipSuccess)
-        return fail(ctx, PX_ERR_DEVICE, "hipEventCreate failed");
-    (void)hipEventRecord(ev[0], stream);
-  }
+  if (ctx->profiling) (void)hipEventRecord(ev[1], stream);
   // M = dV Psi^H W, Hermitised; -M = L L^H; U = L^{-H}; xi = W U
   st = hip_check(ctx, px::launch_gemm_xhy(fp32, n, n, ng, psi, W, dV, Mw, n, part, nsplit, nullptr,
                                           stream),
                  "M = dV Psi^H W");
   if (st != PX_OK) return st;
-  if (ctx->profiling) (void)hipEventRecord(ev[1], stream);
+  if (ctx->profiling) (void)hipEventRecord(ev[2], stream);
   st = hip_check(ctx, px::launch_hermitize(Mw, n, stream), "hermitize");
   if (st != PX_OK) return st;
   st = hip_check(ctx,
@@ -545,7 +566,7 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
                                      reinterpret_cast<double*>(ctx->ws + l.dinv), stream),
                  "cholesky");
   if (st != PX_OK) return st;
-  if (ctx->profiling) (void)hipEventRecord(ev[2], stream);
+  if (ctx->profiling) (void)hipEventRecord(ev[3], stream);
   // FP32 form: U rounded to complex64 into L's place (L is not read again)
   const void* Uc = U;
   if (fp32) {
@@ -560,12 +581,13 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   if (st != PX_OK) return st;
   ctx->last_status.assign(1, status);
   if (ctx->profiling) {
-    (void)hipEventRecord(ev[3], stream);
-    he = hipEventSynchronize(ev[3]);
+    (void)hipEventRecord(ev[4], stream);
+    he = hipEventSynchronize(ev[4]);
     if (he != hipSuccess) return hip_check(ctx, he, "profiling sync");
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       float ms = 0.f;
-      he = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      // stages M, factorisation, xi; then the whole build
+      he = k < 3 ? hipEventElapsedTime(&ms, ev[k + 1], ev[k + 2]) : hipEventElapsedTime(&ms, ev[0], ev[4]);
       if (he != hipSuccess) return hip_check(ctx, he, "hipEventElapsedTime");
       ctx->ace_ms[k] += ms;
     }
@@ -580,8 +602,8 @@ px_status px_ace_apply(px_context* ctx, const px_cell* cell, px_precision prec, 
   if (!ctx) return PX_ERR_INVALID_ARG;
   if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
     return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
-  if (!cell_ok(cell))
-    return fail(ctx, PX_ERR_INVALID_ARG, "cell: edge lengths must be > 0 and grid sizes > 0");
+  px_status st = check_gemm_grid(ctx, cell, prec);
+  if (st != PX_OK) return st;
   if (n <= 0 || n_phi <= 0)
     return fail(ctx, PX_ERR_INVALID_ARG, "n and n_phi must be > 0 (got %d, %d)", n, n_phi);
   if (!xi || !phi || !out) return fail(ctx, PX_ERR_INVALID_ARG, "ace_apply: null array argument");
@@ -590,7 +612,7 @@ px_status px_ace_apply(px_context* ctx, const px_cell* cell, px_precision prec, 
   if (misaligned(xi) || misaligned(phi) || misaligned(out))
     return fail(ctx, PX_ERR_INVALID_ARG, "ace_apply: orbital blocks must be 16-byte aligned");
   const ApplyLayout l = apply_layout(cell, n, n_phi);
-  px_status st = need_ws(ctx, l.end);
+  st = need_ws(ctx, l.end);
   if (st != PX_OK) return st;
   hipError_t he = hipSetDevice(ctx->device);
   if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
@@ -618,8 +640,8 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
   if (!ctx) return PX_ERR_INVALID_ARG;
   if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
     return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
-  if (!cell_ok(cell))
-    return fail(ctx, PX_ERR_INVALID_ARG, "cell: edge lengths must be > 0 and grid sizes > 0");
+  px_status st = check_gemm_grid(ctx, cell, prec);
+  if (st != PX_OK) return st;
   if (n <= 0 || n_phi <= 0 || n_iter <= 0)
     return fail(ctx, PX_ERR_INVALID_ARG, "n, n_phi and n_iter must be > 0");
   if (!xi || !phi_n || !phi_out || !residuals)
@@ -630,7 +652,7 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
     return fail(ctx, PX_ERR_INVALID_ARG,
                 "ptim_exchange_loop: orbital blocks must be 16-byte aligned");
   const LoopLayout l = loop_layout(cell, prec, n, n_phi);
-  px_status st = need_ws(ctx, l.end);
+  st = need_ws(ctx, l.end);
   if (st != PX_OK) return st;
   hipError_t he = hipSetDevice(ctx->device);
   if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
@@ -695,7 +717,7 @@ px_status px_profile_read(px_context* ctx, double* ms, double* bytes, int64_t* l
 
 px_status px_profile_read_ace(px_context* ctx, double* ms, int64_t* calls, int32_t reset) {
   if (!ctx || !ms || !calls) return PX_ERR_INVALID_ARG;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     ms[k] = ctx->ace_ms[k];
     if (reset) ctx->ace_ms[k] = 0.0;
   }

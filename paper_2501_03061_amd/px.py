@@ -306,11 +306,12 @@ class Context:
         return [dict(ms=ms[k], bytes=by[k], launches=la[k]) for k in range(4)]
 
     def px_profile_read_ace(self, reset: bool = False):
-        """ACE build stages while profiling: dict(M=ms, factor=ms, xi=ms, calls=n)."""
-        ms = (ctypes.c_double * 3)()
+        """ACE build stages while profiling: dict(M=ms, factor=ms, xi=ms, build=ms of the
+        whole builds, calls=n)."""
+        ms = (ctypes.c_double * 4)()
         calls = ctypes.c_int64()
         self._check(self.lib.px_profile_read_ace(self.h, ms, ctypes.byref(calls), 1 if reset else 0))
-        return dict(M=ms[0], factor=ms[1], xi=ms[2], calls=calls.value)
+        return dict(M=ms[0], factor=ms[1], xi=ms[2], build=ms[3], calls=calls.value)
 
     def px_exchange_apply_batched(self, instances, ace=False, stream=None):
         """instances: list of dicts with cell (Cell), psi, occ, kern and optional

@@ -1,15 +1,20 @@
-"""Summaries of rocprofv3 CSV output for the pair pipeline.
+"""Summaries of rocprofv3 CSV output for the pair pipeline and the contractions.
 
-    python -m paper_2501_03061_amd.profsum --trace DIR --fetch DIR --write DIR \
+Measurement harness beside bench.py (not part of the library):
+
+    python profsum.py --workload W --trace DIR --fetch DIR --write DIR \
         --copy-fetch DIR --copy-write DIR --bench-json FILE --out profiles
+    python profsum.py --workload W --mfma DIR --out profiles
+    python profsum.py --workload W --sq DIR DIR DIR --out profiles
 
 DIR are rocprofv3 output directories (``--output-format csv``): a
 ``--kernel-trace --stats`` run of ``bench.py``, two ``--pmc`` runs of
 ``bench.py`` (FETCH_SIZE, then WRITE_SIZE) and the same two counters on
 ``bench.py --calibrate-copy`` (the plain copy kernel, 2 GiB).  Writes
-``pair_pipeline_mid72_kernel_trace.md``, ``pair_pipeline_mid72_hbm_counters.md``
-and ``pair_pipeline_mid72_traffic.json`` (calibrated HBM bytes per launch,
-tagged with the digest of the kernel sources they were measured on).
+``pair_pipeline_W_kernel_trace.md``, ``pair_pipeline_W_hbm_counters.md`` and
+``pair_pipeline_W_traffic.json`` (calibrated HBM bytes per launch, tagged with
+the digest of the kernel sources they were measured on; bench.py reports them
+only while the sources still have that digest).
 """
 from __future__ import annotations
 
@@ -21,6 +26,43 @@ import json
 import os
 
 COPY_BYTES = 2 << 30
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("exchange_kernels.hpp", "fft_core.hpp", "px_internal.hpp", "exchange_inst.hip",
+                  "pair_transpose.hip")
+WORKLOAD_TEXT = {"large96": "large96 workload (96^3 grid, 1536 orbitals)",
+                 "mid72": "mid72 workload (72^3 grid, 512 orbitals)"}
+
+
+def source_digest():
+    """Digest of the pair-pipeline kernel sources with comments and blank lines
+    removed: counter figures measured on other code are not reported."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        text = open(os.path.join(ROOT, "paper_2501_03061_amd", "csrc", name)).read()
+        text = re.sub(r"//[^\n]*", "", text)
+        lines = [l.strip() for l in text.splitlines() if l.strip()]
+        h.update(("\n".join(lines) + "\n").encode())
+    return h.hexdigest()
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"pair_pipeline_{workload}_traffic.json")
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload, or None when that summary was taken on different kernel
+    code (or does not exist)."""
+    try:
+        rec = json.load(open(traffic_file(workload)))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
 def _csv(d, suffix):
@@ -43,20 +85,21 @@ def _short(name):
     return base.split("::")[-1].replace("void ", "").strip()
 
 
-def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, commands):
-    import bench  # noqa: E402  (repository root on sys.path)
+def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, commands, workload):
     os.makedirs(out, exist_ok=True)
     rec = json.loads(open(bench_json).read().strip().splitlines()[-1])
     stats = _csv(trace, "kernel_stats.csv")
-    lines = ["# Kernel trace: exchange/ACE hot path, mid72 workload (72^3 grid, 512 orbitals)", "",
+    lines = [f"# Kernel trace: exchange/ACE hot path, {WORKLOAD_TEXT[workload]}", "",
              "Command ($REPO: the repository root, $OUT: the raw output folder; one MI355X):", "", "```", commands["trace"], "```", "",
              f"The bench run inside the profiler printed: value {rec['value']:.4g} pair-solves/s, "
              f"{rec['ms_per_step']:.1f} ms/step (FP32 form, Hermitian-pair mode); FP64 form "
              f"{rec['extra'].get('fp64_pair_solves_per_s', float('nan')):.4g} pair-solves/s.", "",
              "Per-pass averages measured by bench.py with HIP events over the timed region (FP32 form):", "",
-             "| pass | avg per launch (us) | launches per step | model GB/s |", "|---|---|---|---|"]
+             "| pass | avg per launch (us) | launches per step | ms per step | model GB/s |",
+             "|---|---|---|---|---|"]
     for k, v in rec["extra"]["passes"].items():
-        lines.append(f"| {k} | {v['avg_us']:.1f} | {v['launches_per_step']} | {v['GBps']:.0f} |")
+        lines.append(f"| {k} | {v['avg_us']:.1f} | {v['launches_per_step']} | {v['ms_per_step']:.1f} | "
+                     f"{v['model_GBps']:.0f} |")
     # the same passes in the trace: FP32 instantiations of each pass merged by
     # dispatch count (pass 3 runs with and without the kept v_ij)
     merged = collections.defaultdict(lambda: [0, 0.0])
@@ -78,7 +121,7 @@ def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, comm
         name = r["Name"] if len(r["Name"]) < 90 else r["Name"][:90] + "..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
-    open(os.path.join(out, "pair_pipeline_mid72_kernel_trace.md"), "w").write("\n".join(lines) + "\n")
+    open(os.path.join(out, f"pair_pipeline_{workload}_kernel_trace.md"), "w").write("\n".join(lines) + "\n")
 
     fc, wc = _per_kernel(copy_fetch), _per_kernel(copy_write)
     ck = [k for k in fc if "stream_copy" in k][0]
@@ -87,7 +130,7 @@ def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, comm
     ff = COPY_BYTES / 1024 / f_copy
     wf = COPY_BYTES / 1024 / w_copy
     fb, wb = _per_kernel(fetch), _per_kernel(write)
-    lines = ["# HBM traffic counters: pair pipeline, mid72 workload", "",
+    lines = [f"# HBM traffic counters: pair pipeline, {WORKLOAD_TEXT[workload]}", "",
              "Commands ($REPO: the repository root, $OUT: the raw output folder; each counter in a run of its own):", "", "```"] + commands["pmc"] + ["```", "",
              f"Calibration with the plain copy kernel (`px_stream_copy`, 2 GiB read and 2 GiB written per "
              f"launch): FETCH_SIZE reads {f_copy:,.0f} KiB per launch (factor {ff:.3f} to bytes read), "
@@ -118,13 +161,13 @@ def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, comm
                 wbts = (prev["write_bytes"] * prev["dispatches"] + wbts * d) / n
                 d, k = n, prev["name"] + " + " + k
             kernels[_short(k)] = dict(read_bytes=rb, write_bytes=wbts, dispatches=d, name=k)
-    open(os.path.join(out, "pair_pipeline_mid72_hbm_counters.md"), "w").write("\n".join(lines) + "\n")
-    json.dump(dict(source_digest=bench.source_digest(), fetch_factor=ff, write_factor=wf,
+    open(os.path.join(out, f"pair_pipeline_{workload}_hbm_counters.md"), "w").write("\n".join(lines) + "\n")
+    json.dump(dict(source_digest=source_digest(), fetch_factor=ff, write_factor=wf,
                    kernels=kernels, note="FP32 form, bytes per dispatch averaged over one step"),
-              open(os.path.join(out, "pair_pipeline_mid72_traffic.json"), "w"), indent=1)
+              open(os.path.join(out, f"pair_pipeline_{workload}_traffic.json"), "w"), indent=1)
 
 
-def summarize_mfma(mfma, out, command):
+def summarize_mfma(mfma, out, command, workload):
     """MFMA counters of the contractions (one --pmc run of bench.py): flops
     from SQ_INSTS_VALU_MFMA_MOPS_* (512 flops each), MFMA busy fraction from
     SQ_VALU_MFMA_BUSY_CYCLES over 4 SIMDs x SQ_BUSY_CU_CYCLES, and the rate
@@ -137,7 +180,7 @@ def summarize_mfma(mfma, out, command):
             continue
         rows[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
         durs[k][r["Dispatch_Id"]] = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9
-    lines = ["# MFMA counters: complex contractions, mid72 workload (512 x 512 x 72^3)", "",
+    lines = [f"# MFMA counters: complex contractions, {WORKLOAD_TEXT[workload]}", "",
              "Command ($REPO: the repository root, $OUT: the raw output folder; one MI355X):", "", "```", command, "```", "",
              "Each row groups the dispatches of one kernel with the same flop count (the xi = W U "
              "contraction of the ACE build uses only the upper-triangular U, about half the flops of "
@@ -169,10 +212,10 @@ def summarize_mfma(mfma, out, command):
             lines.append(f"| `{name}` | {len(idx)} | {gf:.0f} | {dt * 1e3:.2f} | {tf:.1f} | "
                          f"{100 * tf / peak:.0f} % | {100 * frac:.0f} % | {tf * 4 / 3:.1f} | "
                          f"{100 * tf * 4 / 3 / peak:.0f} % |")
-    open(os.path.join(out, "gemm_mid72_mfma_counters.md"), "w").write("\n".join(lines) + "\n")
+    open(os.path.join(out, f"gemm_{workload}_mfma_counters.md"), "w").write("\n".join(lines) + "\n")
 
 
-def summarize_sq(dirs, out, commands):
+def summarize_sq(dirs, out, commands, workload):
     """SQ / TA / TCP counters of the pair-pipeline passes and the contractions
     (FP32 form, one bench step), per dispatch, with ratios whose units cancel:
     VALU issue share = SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES (a wave64 VALU
@@ -188,7 +231,7 @@ def summarize_sq(dirs, out, commands):
             if "float" not in k or not (_short(k).startswith("pass") or "gemm_" in k):
                 continue
             agg[_short(k)][r["Counter_Name"]].append(float(r["Counter_Value"]))
-    lines = ["# SQ / TA / TCP counters: pair pipeline and contractions, mid72 workload (FP32 form)", "",
+    lines = [f"# SQ / TA / TCP counters: pair pipeline and contractions, {WORKLOAD_TEXT[workload]} (FP32 form)", "",
              "Commands ($REPO: the repository root, $OUT: the raw output folder; one counter group per "
              "run):", "", "```"] + commands + ["```", "",
              "Per dispatch, averaged over the dispatches of one FP32 bench step (instantiations of a "
@@ -219,21 +262,22 @@ def summarize_sq(dirs, out, commands):
             f"{100 * avg(cs, 'SQ_LDS_BANK_CONFLICT') / busy:.1f} % | "
             f"{100 * avg(cs, 'TA_TA_BUSY') / busy:.0f} % | "
             f"{avg(cs, 'TCP_TCC_READ_REQ_LATENCY') / avg(cs, 'TCP_TCC_READ_REQ'):.0f} |")
-    open(os.path.join(out, "pair_pipeline_mid72_sq_counters.md"), "w").write("\n".join(lines) + "\n")
+    open(os.path.join(out, f"pair_pipeline_{workload}_sq_counters.md"), "w").write("\n".join(lines) + "\n")
 
 
 def main():
-    import sys
-    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     ap = argparse.ArgumentParser()
     for a in ("trace", "fetch", "write", "copy-fetch", "copy-write", "bench-json"):
         ap.add_argument("--" + a)
+    ap.add_argument("--workload", default="large96", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--mfma", help="rocprofv3 --pmc run with the MFMA counters (contractions)")
     ap.add_argument("--sq", nargs="+", help="rocprofv3 --pmc runs with the SQ / TA / TCP counter groups")
-    ap.add_argument("--out", default="profiles")
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     args = ap.parse_args()
+    w = args.workload
     # $REPO: the repository root; $OUT: a folder for the raw rocprofv3 output
     pre = "cd /tmp && export TMPDIR=/tmp"
+    one = f"--workload {w} --steps 1 --warmup 0"
     if args.sq:
         groups = ["SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "
                   "SQ_WAIT_INST_LDS SQ_WAIT_ANY SQ_INSTS_VALU",
@@ -241,30 +285,30 @@ def main():
                   "SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY SQ_INSTS_SALU SQ_BUSY_CU_CYCLES",
                   "TA_TA_BUSY TA_ADDR_STALLED_BY_TC_CYCLES TCP_TCC_READ_REQ_LATENCY TCP_TCC_READ_REQ"]
         summarize_sq(args.sq, args.out, [pre] + [
-            f"timeout -s KILL 240 rocprofv3 --pmc {g} --output-format csv -d $OUT/pmc_sq{i + 1} -o run -- "
-            "python3 $REPO/bench.py --steps 1 --warmup 0 --no-fp64 --no-cpu" for i, g in enumerate(groups)])
+            f"timeout -s KILL 300 rocprofv3 --pmc {g} --output-format csv -d $OUT/pmc_sq{i + 1} -o run -- "
+            f"python3 $REPO/bench.py {one} --no-fp64 --no-cpu" for i, g in enumerate(groups)], w)
         if not (args.trace or args.mfma):
             return
     if args.mfma:
-        summarize_mfma(args.mfma, args.out, pre + "\ntimeout -s KILL 300 rocprofv3 --pmc "
+        summarize_mfma(args.mfma, args.out, pre + "\ntimeout -s KILL 400 rocprofv3 --pmc "
                        "SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_VALU_MFMA_BUSY_CYCLES "
                        "SQ_BUSY_CU_CYCLES --output-format csv -d $OUT/pmc_mfma_bench -o run -- "
-                       "python3 $REPO/bench.py --steps 1 --warmup 0 --no-cpu")
+                       f"python3 $REPO/bench.py {one} --no-cpu", w)
         if not args.trace:
             return
     commands = {
         "trace": pre + "\nrocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace_bench "
-                       "-o run -- python3 $REPO/bench.py",
+                       f"-o run -- python3 $REPO/bench.py --workload {w}",
         "pmc": [pre] + [
             f"timeout -s KILL {t} rocprofv3 --pmc {c} --output-format csv -d $OUT/{d} -o run -- "
             f"python3 $REPO/bench.py {a}"
             for t, c, d, a in ((120, "FETCH_SIZE", "pmc_fetch_copy", "--calibrate-copy"),
                                (120, "WRITE_SIZE", "pmc_write_copy", "--calibrate-copy"),
-                               (300, "FETCH_SIZE", "pmc_fetch_bench", "--steps 1 --warmup 0 --no-fp64 --no-cpu"),
-                               (300, "WRITE_SIZE", "pmc_write_bench", "--steps 1 --warmup 0 --no-fp64 --no-cpu"))],
+                               (400, "FETCH_SIZE", "pmc_fetch_bench", f"{one} --no-fp64 --no-cpu"),
+                               (400, "WRITE_SIZE", "pmc_write_bench", f"{one} --no-fp64 --no-cpu"))],
     }
     summarize(args.trace, args.fetch, args.write, args.copy_fetch, args.copy_write, args.bench_json,
-              args.out, commands)
+              args.out, commands, w)
 
 
 if __name__ == "__main__":

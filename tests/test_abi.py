@@ -140,6 +140,31 @@ def test_ace_validation(lib, ctx):
     assert g(ctx, ctypes.byref(c), 0, 4, FAKE, 2, ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000), None) == px.PX_ERR_WORKSPACE
 
 
+def test_contraction_entry_points_reject_odd_grids_in_fp32(lib, ctx):
+    """ACE application and the PT-IM-style loop read FP32 blocks two complex64
+    values per 16-byte load: an odd N_g would misalign every second orbital and
+    let a load straddle two orbitals, so such grids are refused (FP64 is fine)."""
+    odd = px.Cell((5.0, 5.0, 5.0), (5, 5, 5)).c()      # N_g = 125
+    even = px.Cell((5.0, 5.0, 5.0), (6, 5, 5)).c()     # N_g = 150: no FFT plan, but contractions work
+    g = lib.px_ace_apply
+    a, b, o = FAKE, ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000)
+    assert g(ctx, ctypes.byref(odd), 1, 4, a, 2, b, o, None) == px.PX_ERR_UNSUPPORTED_GRID
+    assert g(ctx, ctypes.byref(odd), 0, 4, a, 2, b, o, None) == px.PX_ERR_WORKSPACE
+    assert g(ctx, ctypes.byref(even), 1, 4, a, 2, b, o, None) == px.PX_ERR_WORKSPACE
+    h = lib.px_ptim_exchange_loop
+    res = ctypes.c_void_p(0x9000)
+    assert h(ctx, ctypes.byref(odd), 1, 4, a, 2, b, 3, 0.5, o, res, None) == px.PX_ERR_UNSUPPORTED_GRID
+    assert h(ctx, ctypes.byref(odd), 0, 4, a, 2, b, 3, 0.5, o, res, None) == px.PX_ERR_WORKSPACE
+    wb = lib.px_workspace_bytes
+    assert wb(ctx, px.PX_OP_ACE_APPLY, ctypes.byref(odd), 1, 4, 2) == 0
+    assert wb(ctx, px.PX_OP_PTIM_LOOP, ctypes.byref(odd), 1, 4, 2) == 0
+    assert wb(ctx, px.PX_OP_ACE_APPLY, ctypes.byref(odd), 0, 4, 2) > 0
+    assert wb(ctx, px.PX_OP_ACE_APPLY, ctypes.byref(even), 1, 4, 2) > 0
+    # the FFT entry points need a compiled plan
+    assert wb(ctx, px.PX_OP_EXCHANGE, ctypes.byref(even), 0, 4, 2) == 0
+    assert wb(ctx, px.PX_OP_ACE_BUILD, ctypes.byref(even), 0, 4, 0) == 0
+
+
 def test_kernel_and_convert_validation(lib, ctx):
     c = _cell()
     assert lib.px_kernel_hse(ctx, ctypes.byref(c), 0.0, FAKE, None) == px.PX_ERR_INVALID_ARG

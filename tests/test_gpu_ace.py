@@ -107,19 +107,36 @@ def test_ace_cholesky_breakdown_reported(px_ctx, toy):
     torch.cuda.synchronize()
 
 
-def test_ptim_loop_fp64_matches_oracle(px_ctx, toy):
+@pytest.mark.parametrize("fp32", [False, True])
+def test_ptim_loop_matches_oracle(px_ctx, toy, fp32):
     """Exchange-only implicit-midpoint fixed point with V_ACE matches the
-    oracle loop, iterate and FP64 residuals."""
+    oracle loop, iterate and FP64 residuals.  The FP32 form runs the loop on
+    the complex64 copies of xi and Phi_n (its contractions in FP32, the
+    residual norms in FP64) and meets 2e-5 on the iterate.  A residual is a
+    norm of the difference of two iterates over the norm of one, so each
+    R_k can move by at most about twice the iterates' relative error: the
+    FP32 residuals are compared with an absolute bound of 4e-5, and R_0
+    (about 0.1 here) to 1e-4 relative."""
     inst, K, dV, r = toy
-    banner("ptim loop toy24")
+    banner(f"ptim loop toy24 fp32={fp32}")
     cell = px.Cell(inst.L, inst.n)
     z = inputs.noise_block(inst.n, inst.L, inst.n_orb, seed=1001)
     phi_n = inst.psi + 1e-3 * z
     ref_phi, ref_res = oracle.ptim_exchange_loop(r["xi"], phi_n, dV, n_iter=4)
-    out, res = px_ctx.px_ptim_exchange_loop(cell, to_dev(r["xi"]), to_dev(phi_n), 4,
-                                            oracle.DT_50AS * oracle.ALPHA)
-    assert relerr(to_host(out), ref_phi) < FP64_TOL
-    assert np.allclose(to_host(res), ref_res, rtol=1e-9, atol=1e-15)
+    xi_d, phi_d = to_dev(r["xi"]), to_dev(phi_n)
+    if fp32:
+        xi_d, phi_d = px_ctx.px_convert_c128_to_c64(xi_d), px_ctx.px_convert_c128_to_c64(phi_d)
+    out, res = px_ctx.px_ptim_exchange_loop(cell, xi_d, phi_d, 4, oracle.DT_50AS * oracle.ALPHA)
+    err, res_h = relerr(to_host(out), ref_phi), to_host(res)
+    print(f"ptim loop fp32={fp32}: iterate err {err:.2e}, residuals {res_h} oracle {ref_res}")
+    if not fp32:
+        assert err < FP64_TOL
+        assert np.allclose(res_h, ref_res, rtol=1e-9, atol=1e-15)
+    else:
+        assert err < FP32_TOL
+        assert np.all(np.abs(res_h - np.asarray(ref_res)) < 2 * FP32_TOL)
+        assert abs(res_h[0] - ref_res[0]) < 1e-4 * ref_res[0]
+        assert np.all(np.diff(res_h) < 0)
 
 
 @pytest.mark.parametrize("sym", [False, True])

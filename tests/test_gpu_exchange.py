@@ -140,9 +140,25 @@ def test_exchange_g0_kernel_is_projector(px_ctx):
     assert relerr(out, expect) < FP64_TOL
 
 
-def test_exchange_plane_wave_closed_form_72(px_ctx):
-    """Closed form at the full 72^3 grid: Vx e^{ik.r} = -sum_j f_j K(k-k_j)/Omega e^{ik.r}."""
-    banner("exchange plane waves 72")
+def _wrap(m, n):
+    m %= n
+    return m if m < n / 2 else m - n
+
+
+def _k_closed(q, n, L, mu):
+    g2 = sum((2 * math.pi * _wrap(q[a], n) / L) ** 2 for a in range(3))
+    return math.pi / mu ** 2 if g2 == 0 else 4 * math.pi * (-math.expm1(-g2 / (4 * mu * mu))) / g2
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_exchange_plane_wave_closed_form_72(px_ctx, fp32):
+    """Closed form at the full 72^3 grid: Vx e^{ik.r} = -sum_j f_j K(k-k_j)/Omega e^{ik.r}
+    (with a wrapped momentum difference), and with Phi = Psi the energy
+    E_x = -1/2 sum_ij f_i f_j K(k_i - k_j)/Omega.  Every pair product of plane
+    waves has a single Fourier component, so in the FP32 form the energy
+    rescaling of the G != 0 part meets its degenerate case: for i = j all
+    weight sits at G = 0 and the G != 0 sums are rounding noise."""
+    banner(f"exchange plane waves 72 fp32={fp32}")
     n, L, mu = 72, 20.0, 0.106
     ms = [(0, 0, 0), (3, -1, 2), (35, 0, 0), (-20, 7, 1), (1, 1, 1)]
     occ = np.array([1.0, 0.9, 0.3, 0.05, 1e-6])
@@ -151,20 +167,25 @@ def test_exchange_plane_wave_closed_form_72(px_ctx):
     phi = inputs.plane_wave_orbitals(n, L, [mk, (0, 0, 1)])
     cell = px.Cell.cubic(n, L)
     kd = px_ctx.px_kernel_hse(cell, mu)
-    out, _ = _run(px_ctx, cell, psi, occ, phi, kd)
-
-    def wrap(m):
-        m %= n
-        return m if m < n / 2 else m - n
-
+    tol = FP32_TOL if fp32 else FP64_TOL
+    out, _ = _run(px_ctx, cell, psi, occ, phi, kd, fp32=fp32)
     for c, kv in enumerate([mk, (0, 0, 1)]):
-        lam = 0.0
-        for j, mj in enumerate(ms):
-            q = [wrap(kv[a] - mj[a]) for a in range(3)]
-            g2 = sum((2 * math.pi * q[a] / L) ** 2 for a in range(3))
-            kq = math.pi / mu ** 2 if g2 == 0 else 4 * math.pi * (-math.expm1(-g2 / (4 * mu * mu))) / g2
-            lam -= occ[j] * kq / L ** 3
-        assert relerr(out[c], lam * phi[c]) < FP64_TOL
+        lam = -sum(occ[j] * _k_closed([kv[a] - mj[a] for a in range(3)], n, L, mu)
+                   for j, mj in enumerate(ms)) / L ** 3
+        err = relerr(out[c], lam * phi[c])
+        print(f"plane wave {kv} fp32={fp32}: Vx err {err:.2e}")
+        assert err < tol
+    # Phi = Psi: Vx psi_i and the energy
+    out, e = _run(px_ctx, cell, psi, occ, psi, kd, fp32=fp32, energy=True)
+    ex = 0.0
+    for i, mi in enumerate(ms):
+        lam = -sum(occ[j] * _k_closed([mi[a] - mj[a] for a in range(3)], n, L, mu)
+                   for j, mj in enumerate(ms)) / L ** 3
+        assert relerr(out[i], lam * psi[i]) < tol
+        ex += 0.5 * occ[i] * lam
+    eerr = abs(e - ex) / abs(ex)
+    print(f"plane waves fp32={fp32}: E_x {e:.15f} closed form {ex:.15f} err {eerr:.2e}")
+    assert eerr < (FP32_EX_TOL if fp32 else FP64_TOL)
 
 
 def test_exchange_tuning_invariance(px_ctx, toy24):

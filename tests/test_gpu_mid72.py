@@ -3,8 +3,13 @@
 ACE builds in the launch configuration the bench times (default chunking,
 Hermitian-pair mode), checked against the oracle on sampled output orbitals:
 V_ACE psi_c = W_c = Vx psi_c (ACE is exact on the orbitals it is built from),
-with the oracle computing Vx psi_c one column at a time.  Over the whole block
-the FP32 form is compared with the FP64 GPU path (M, E_x, the ACE action on
+with the oracle computing Vx psi_c one column at a time, and the matching
+columns of M = dV Psi^H W.  The 16 sampled columns cover every 32-orbital
+pair block of the Hermitian-pair schedule, both sides of a block edge (31,
+32), the first orbital (whose W comes almost entirely from the transposed
+accumulation of the pairs j < i), the orbital nearest the Fermi level and
+the last one (the smallest occupation).  Over the whole block the FP32 form
+is compared with the FP64 GPU path (M, E_x, the ACE action on
 Phi = Psi + 1e-3 Z and the 4-iteration PT-IM-style loop).
 """
 import numpy as np
@@ -17,7 +22,9 @@ from _gpu import banner, relerr, to_dev, to_host
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
 FP64_TOL, FP32_TOL, FP32_EX_TOL = 1e-11, 2e-5, 1e-7
-COLS = [5, 256]   # a fully occupied orbital and one near the Fermi level (f = 0.90)
+# one column in each 32-orbital block; 0 and 511 are the first and last orbitals,
+# 31/32 straddle a block edge, 256 is the orbital nearest the Fermi level
+COLS = [0, 31, 32, 70, 100, 140, 170, 200, 230, 256, 300, 340, 380, 420, 470, 511]
 
 
 @pytest.fixture(scope="module")
@@ -60,21 +67,30 @@ def test_mid72_ace_builds_vs_oracle_and_fp32_vs_fp64(px_ctx, mid):
     assert err64 < FP64_TOL
     # M columns against the oracle: M[a][c] = dV sum_r conj(psi_a) (Vx psi_c)
     dv = float(np.prod(inst.L)) / float(np.prod(inst.n))
-    mref = dv * (inst.psi.reshape(n, -1).conj() @ ref.reshape(len(COLS), -1).T)
+    # M[a][c] = dV sum_r conj(psi_a) W_c, formed without a conjugated copy of Psi
+    mref = dv * np.conj(inst.psi.reshape(n, -1) @ np.conj(ref.reshape(len(COLS), -1)).T)
     merr = relerr(to_host(M64)[:, COLS], mref)
     print(f"mid72 FP64 M columns vs oracle {merr:.2e}", flush=True)
     assert merr < FP64_TOL
+
+    for k, c in enumerate(COLS):   # column by column as well
+        assert relerr(y64[k], ref[k]) < FP64_TOL, c
 
     banner("mid72: FP32 ACE build")
     psi32 = px_ctx.px_convert_c128_to_c64(psi64)
     xi32, M32, e32 = build(psi32)
     y32 = to_host(px_ctx.px_ace_apply(cell, xi32, psi32[COLS].contiguous()))
     err32 = relerr(y32, ref)
+    merr32 = relerr(to_host(M32)[:, COLS], mref)
     em = float(torch.linalg.matrix_norm(M32 - M64) / torch.linalg.matrix_norm(M64))
     ee = abs(e32 - e64) / abs(e64)
-    print(f"mid72 FP32: ACE columns vs oracle {err32:.2e}, M vs FP64 {em:.2e}, "
+    worst = max(relerr(y32[k], ref[k]) for k in range(len(COLS)))
+    print(f"mid72 FP32: ACE columns vs oracle {err32:.2e} (worst column {worst:.2e}), "
+          f"M columns vs oracle {merr32:.2e}, M vs FP64 {em:.2e}, "
           f"E_x vs FP64 {ee:.2e} (E_x = {e64:.10f})", flush=True)
     assert err32 < FP32_TOL
+    assert worst < FP32_TOL
+    assert merr32 < FP32_TOL
     assert em < FP32_TOL
     assert ee < FP32_EX_TOL
 
