@@ -37,8 +37,9 @@
  *     except in px_sync.
  *   Errors: arguments are validated on the host before anything is enqueued;
  *     a non-PX_OK return means nothing was enqueued.  px_last_error gives a
- *     message.  Device-side failures (Cholesky breakdown) are reported through
- *     the caller's status word and surfaced by px_sync.
+ *     message.  Device-side failures (Cholesky breakdown, a diagonalisation
+ *     that did not converge) are reported through the caller's status word
+ *     and surfaced by px_sync.
  *   Precision forms: PX_PREC_FP64 runs everything in FP64.  PX_PREC_FP32 runs
  *     pair products, FFTs and contractions in FP32 (FP32 MFMA accumulation)
  *     while the G = 0 coefficient, the exchange energy sums, the reductions of
@@ -64,7 +65,8 @@ typedef enum {
   PX_ERR_UNSUPPORTED_GRID = 2,      /* grid shape without a compiled FFT plan    */
   PX_ERR_WORKSPACE = 3,             /* no workspace attached or too small        */
   PX_ERR_DEVICE = 4,                /* a HIP runtime call failed                 */
-  PX_ERR_NOT_POSITIVE_DEFINITE = 5  /* -M is not positive definite (px_sync)     */
+  PX_ERR_NOT_POSITIVE_DEFINITE = 5, /* -M is not positive definite (px_sync)     */
+  PX_ERR_NOT_CONVERGED = 6          /* sigma diagonalisation did not converge    */
 } px_status;
 
 typedef enum { PX_PREC_FP64 = 0, PX_PREC_FP32 = 1 } px_precision;
@@ -73,7 +75,10 @@ typedef enum {
   PX_OP_EXCHANGE = 0,
   PX_OP_ACE_BUILD = 1,
   PX_OP_ACE_APPLY = 2,
-  PX_OP_PTIM_LOOP = 3
+  PX_OP_PTIM_LOOP = 3,
+  PX_OP_EXCHANGE_SIGMA = 4,  /* n_psi = n (Phi and sigma), n_phi = n_tgt */
+  PX_OP_SIGMA_DIAG = 5,      /* n_psi = n; n_phi ignored                 */
+  PX_OP_DENSITY_SIGMA = 6    /* n_psi = n; n_phi ignored                 */
 } px_op;
 
 /* Orthorhombic cell: edge lengths in bohr and the real-space grid, n[0] = x. */
@@ -183,6 +188,51 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
                                 double dt_alpha, void* phi_out, double* residuals,
                                 hipStream_t stream);
 
+/* Occupation-matrix diagonalisation (Sec. IV-A-1, Eq. 11): sigma = Q D Q^H
+ * for a Hermitian sigma (the input is Hermitised as (sigma + sigma^H)/2 first),
+ * in FP64 by cyclic Jacobi rotations.  sigma and Q: complex128 [n][n]
+ * row-major (device; Q[a][k] is component a of eigenvector k); d: float64 [n],
+ * the eigenvalues in ascending order.  Eigenvectors are unique up to a phase
+ * (and a rotation within a degenerate eigenspace); Q D Q^H is unique.
+ * status (device int32, required): 0 when the off-diagonal Frobenius norm fell
+ * below 64 eps sqrt(n) ||sigma||_F within 16 sweeps, else the sweeps made
+ * (Q, d then approximate; px_sync returns PX_ERR_NOT_CONVERGED).  Workspace:
+ * px_workspace_bytes(PX_OP_SIGMA_DIAG, cell (any), FP64, n, 0). */
+px_status px_sigma_diagonalize(px_context* ctx, int32_t n, const double* sigma, double* Q, double* d,
+                               int32_t* status, hipStream_t stream);
+
+/* Mixed-state exchange operator with a full occupation matrix (Eq. 10),
+ *   vx_tgt[j] = -sum_{i,k} sigma_ik Phi_i IFFT[K FFT(conj(Phi_k) tgt_j)],
+ * evaluated as the paper does after Eq. 11: sigma = Q D Q^H, phi = Phi Q
+ * (a contraction over the orbitals, in the form's precision), then Eq. 13 on
+ * (phi, d): N^2 pair solves instead of N^3.  Phi [n][N_g], tgt and vx_tgt
+ * [n_tgt][N_g] (element type of prec; tgt may be Phi itself), sigma
+ * complex128 [n][n], kernel_G as in px_exchange_apply.  status as in
+ * px_sigma_diagonalize.  Workspace: PX_OP_EXCHANGE_SIGMA with (n, n_tgt). */
+px_status px_exchange_apply_sigma(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                                  const void* phi_basis, const double* sigma, int32_t n_tgt,
+                                  const void* tgt, const double* kernel_G, void* vx_tgt,
+                                  int32_t* status, hipStream_t stream);
+
+/* Electron density of orbitals with occupations (Eq. 12 with sigma
+ * diagonalised: rho(r) = sum_i occ_i |phi_i(r)|^2, the density the paper
+ * evaluates with N products after the diagonalisation instead of N^2).
+ * phi [n][N_g] (element type of prec), occ float64 [n] (any real weights, e.g.
+ * the d of px_sigma_diagonalize), rho float64 [N_g] on the wavefunction grid.
+ * Products and sums in FP64 in both forms.  No workspace.  Grids as in
+ * px_ace_apply. */
+px_status px_density(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                     const void* phi, const double* occ, double* rho, hipStream_t stream);
+
+/* Density with a full occupation matrix (Sec. III-C:
+ * rho(r) = sum_{i,j} Phi_i(r) sigma_ij conj(Phi_j(r))), evaluated as
+ * diagonalisation, phi = Phi Q and px_density on (phi, d).  Phi [n][N_g],
+ * sigma complex128 [n][n], rho float64 [N_g]; status as in
+ * px_sigma_diagonalize.  Workspace: PX_OP_DENSITY_SIGMA with n. */
+px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                           const void* phi_basis, const double* sigma, double* rho, int32_t* status,
+                           hipStream_t stream);
+
 /* Hermitian pair symmetry of the ACE build (default on).  With Phi = Psi and a
  * real even kernel, v_ji = conj(v_ij): the orbitals are cut into square blocks,
  * only blocks J <= I are transformed, and a diagonal block only for its pairs
@@ -273,9 +323,11 @@ px_status px_autotune(px_context* ctx, const px_cell* cell, px_precision prec, i
  * and precision wins); *applied (nullable) receives the number of lines used. */
 px_status px_load_tuning(px_context* ctx, const char* cache_path, int32_t* applied);
 
-/* Synchronises `stream`, then reads the status word of the last px_ace_build
- * on this context: PX_ERR_NOT_POSITIVE_DEFINITE if it reported a breakdown
- * (the error stays latched until px_clear_error), PX_ERR_DEVICE on a HIP error. */
+/* Synchronises `stream`, then reads the status word(s) of the last call on
+ * this context that reports through one: PX_ERR_NOT_POSITIVE_DEFINITE if an
+ * ACE build reported a breakdown, PX_ERR_NOT_CONVERGED if a diagonalisation of
+ * sigma did not converge (the error stays latched until px_clear_error),
+ * PX_ERR_DEVICE on a HIP error. */
 px_status px_sync(px_context* ctx, hipStream_t stream);
 
 /* Clears a latched error. */

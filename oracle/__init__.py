@@ -12,6 +12,9 @@ Modules
                (Eq. 13 and the mixed-state form Eq. 10), exchange energy.
   ace       -- ACE construction and application (Eq. 14), and the
                exchange-only implicit-midpoint loop (Eq. 4, 6, 7).
+  sigma     -- occupation-matrix diagonalisation (Eq. 11), the rotated
+               orbitals Phi Q, and the density with a full sigma (Sec. III-C)
+               or with occupations (Eq. 12).
 
 Every function states the passage it follows and, where the paper is silent
 or garbled, the reading taken.  Parity pins live in tests/test_oracle_pins.py.
@@ -21,3 +24,4 @@ from .exchange import (  # noqa: F401
     exchange_energy_gspace, exchange_apply_sigma, pair_potential,
 )
 from .ace import ace_build, ace_apply, ptim_exchange_loop, DT_50AS, ALPHA  # noqa: F401
+from .sigma import sigma_eig, rotate, density_sigma, density  # noqa: F401

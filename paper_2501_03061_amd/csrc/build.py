@@ -38,7 +38,7 @@ def _units():
     for n in SIZES:
         units.append(("exchange_inst.hip", f"exchange_n{n}.o", [f"-DPX_N={n}"]))
     for src in ("exchange_dispatch.cpp", "pair_transpose.hip", "misc_kernels.hip", "gemm_kernels.hip",
-                "chol_kernels.hip", "px_api.cpp"):
+                "chol_kernels.hip", "eig_kernels.hip", "px_api.cpp"):
         units.append((src, os.path.splitext(src)[0] + ".o", []))
     return units
 

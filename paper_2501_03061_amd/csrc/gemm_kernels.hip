@@ -239,26 +239,37 @@ __global__ void xhy_reduce_k(int na, int nb, const double* part, int nsplit, dou
   }
 }
 
-static size_t xhy_kchunk(int na, int nb, size_t ng, int* nsplit) {
+// r-span of one split: aim at ~2048 workgroups, at least 1024 values of r,
+// and at most max_split splits (the partials need max_split * na * nb
+// complex128 values of scratch).
+static size_t xhy_kchunk(int na, int nb, size_t ng, int max_split, int* nsplit) {
   const size_t tiles = size_t((na + 63) / 64) * ((nb + 63) / 64);
-  size_t want = (2048 + tiles - 1) / tiles;  // aim at ~2048 workgroups
+  size_t want = (2048 + tiles - 1) / tiles;
   size_t kchunk = (ng + want - 1) / want;
   if (kchunk < 1024) kchunk = 1024;
+  if (max_split > 0 && (ng + kchunk - 1) / kchunk > size_t(max_split))
+    kchunk = (ng + size_t(max_split) - 1) / size_t(max_split);
   kchunk = (kchunk + 15) / 16 * 16;
   *nsplit = int((ng + kchunk - 1) / kchunk);
   return kchunk;
 }
 
 size_t gemm_xhy_part_elems(int na, int nb, size_t ng, int* nsplit) {
-  xhy_kchunk(na, nb, ng, nsplit);
+  xhy_kchunk(na, nb, ng, 0, nsplit);
   return size_t(*nsplit) * na * nb;
+}
+
+int gemm_xhy_splits(int na, int nb, size_t ng, int max_split) {
+  int nsplit = 0;
+  xhy_kchunk(na, nb, ng, max_split, &nsplit);
+  return nsplit;
 }
 
 hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, const void* Y,
                            double scale, double* M, int ldm, double* part, int nsplit_avail,
                            float* M32, hipStream_t s) {
   int nsplit;
-  const size_t kchunk = xhy_kchunk(na, nb, ng, &nsplit);
+  const size_t kchunk = xhy_kchunk(na, nb, ng, nsplit_avail, &nsplit);
   if (nsplit > nsplit_avail) return hipErrorInvalidValue;
   dim3 grid((na + 63) / 64, (nb + 63) / 64, nsplit);
   if (fp32)

@@ -312,3 +312,47 @@ hipError_t launch_ptim_update(bool fp32, size_t n, const void* phi_n, const void
 }
 
 }  // namespace px
+
+// ---------------------------------------------------------------- density
+namespace px {
+
+// rho(r) = sum_i w_i |phi_i(r)|^2 with the occupation-matrix eigenvalues w_i
+// (Eq. 12 with sigma diagonalised: N products instead of N^2), accumulated in
+// FP64 from the orbital values.  Two consecutive grid points per thread: one
+// 16-byte load per orbital in the FP32 form (N_g even), two in FP64; the
+// orbital loop is unrolled so that several loads are in flight.
+template <typename T>
+__global__ __launch_bounds__(256) void density_k(size_t ng, int n, const T* phi, const double* w,
+                                                 double* rho) {
+  using V = typename V2<T>::t;
+  const size_t r = (size_t(blockIdx.x) * blockDim.x + threadIdx.x) * 2;
+  if (r >= ng) return;
+  const bool two = r + 1 < ng;
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll 8
+  for (int i = 0; i < n; ++i) {
+    const V* p = reinterpret_cast<const V*>(phi) + size_t(i) * ng + r;
+    const V x = p[0];
+    const V y = two ? p[1] : V{T(0), T(0)};
+    const double wi = w[i];
+    a0 += wi * (double(x.x) * double(x.x) + double(x.y) * double(x.y));
+    a1 += wi * (double(y.x) * double(y.x) + double(y.y) * double(y.y));
+  }
+  rho[r] = a0;
+  if (two) rho[r + 1] = a1;
+}
+
+hipError_t launch_density(bool fp32, size_t ng, int n, const void* phi, const double* w,
+                          double* rho, hipStream_t s) {
+  const size_t threads = (ng + 1) / 2;
+  const unsigned blocks = unsigned((threads + 255) / 256);
+  if (fp32)
+    hipLaunchKernelGGL(density_k<float>, dim3(blocks), dim3(256), 0, s, ng, n,
+                       static_cast<const float*>(phi), w, rho);
+  else
+    hipLaunchKernelGGL(density_k<double>, dim3(blocks), dim3(256), 0, s, ng, n,
+                       static_cast<const double*>(phi), w, rho);
+  return hipGetLastError();
+}
+
+}  // namespace px

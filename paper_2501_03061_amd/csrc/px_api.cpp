@@ -23,7 +23,10 @@ struct px_context {
   std::string err = "";
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  std::vector<int32_t*> last_status;  // device status words of the last ACE build(s)
+  // device status words of the last calls that report through one: the
+  // error each stands for when non-zero (Cholesky breakdown of an ACE build,
+  // or no convergence of the occupation-matrix diagonalisation)
+  std::vector<std::pair<int32_t*, px_status>> last_status;
   int latched = PX_OK;
   std::map<std::tuple<int, int, int, int>, std::pair<int, int>> tuning;  // (n0,n1,n2,prec) -> (ic, jc)
   // measurement mode: HIP events around each pass of each chunk
@@ -206,6 +209,35 @@ LoopLayout loop_layout(const px_cell* cell, px_precision prec, int n, int n_phi)
   off = align_up(off + blk);
   l.partial = off;
   off = align_up(off + size_t(px::ptim_update_blocks()) * 16);
+  l.end = off;
+  return l;
+}
+
+// Maximum Jacobi sweeps of the occupation-matrix diagonalisation (the method
+// converges quadratically; a few sweeps past ten are rare for n in the
+// thousands).
+constexpr int kEigSweeps = 16;
+
+// Workspace of the sigma front end from `base` on: the Jacobi work arrays,
+// Q (complex128) and its complex64 copy, d, and the rotated orbital block
+// phi = Phi Q (element type of the form; omitted with no_phi).
+struct SigmaLayout {
+  size_t eig, Q, Q32, d, phi, end;
+};
+
+SigmaLayout sigma_layout(size_t base, const px_cell* cell, px_precision prec, int n, bool no_phi) {
+  SigmaLayout l{};
+  size_t off = align_up(base);
+  l.eig = off;
+  off = align_up(off + px::eig_work_bytes(n));
+  l.Q = off;
+  off = align_up(off + size_t(n) * n * 16);
+  l.Q32 = off;
+  off = align_up(off + size_t(n) * n * 8);
+  l.d = off;
+  off = align_up(off + size_t(n) * 8);
+  l.phi = off;
+  if (!no_phi) off = align_up(off + size_t(n) * ngrid(cell) * elem_bytes(prec));
   l.end = off;
   return l;
 }
@@ -393,7 +425,8 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
   if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32) return 0;
   const bool fft_grid = px::grid_supported(cell->n[0], cell->n[1], cell->n[2]);
   const bool gemm_grid = prec == PX_PREC_FP64 || ngrid(cell) % 2 == 0;
-  if (op == PX_OP_EXCHANGE || op == PX_OP_ACE_BUILD ? !fft_grid : !gemm_grid) return 0;
+  const bool fft_op = op == PX_OP_EXCHANGE || op == PX_OP_ACE_BUILD || op == PX_OP_EXCHANGE_SIGMA;
+  if (fft_op ? !fft_grid : !gemm_grid) return 0;
   int ic, jc;
   tuning_for(ctx, cell, prec, &ic, &jc);
   switch (op) {
@@ -408,6 +441,15 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
     case PX_OP_PTIM_LOOP:
       if (n_phi <= 0) return 0;
       return loop_layout(cell, prec, n_psi, n_phi).end;
+    case PX_OP_EXCHANGE_SIGMA: {
+      if (n_phi <= 0) return 0;
+      const ExLayout ex = ex_layout(cell, prec, n_psi, n_phi, ic, jc, false);
+      return sigma_layout(ex.end, cell, prec, n_psi, false).end;
+    }
+    case PX_OP_SIGMA_DIAG:
+      return align_up(px::eig_work_bytes(n_psi));
+    case PX_OP_DENSITY_SIGMA:
+      return sigma_layout(0, cell, prec, n_psi, false).end;
   }
   return 0;
 }
@@ -579,7 +621,7 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   st = hip_check(ctx, px::launch_gemm_xc(fp32, n, n, ng, W, Uc, n, 1.0, xi, true, stream),
                  "xi = W L^-H");
   if (st != PX_OK) return st;
-  ctx->last_status.assign(1, status);
+  ctx->last_status.assign(1, {status, PX_ERR_NOT_POSITIVE_DEFINITE});
   if (ctx->profiling) {
     (void)hipEventRecord(ev[4], stream);
     he = hipEventSynchronize(ev[4]);
@@ -689,6 +731,137 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
     cur = nxt;
   }
   return PX_OK;
+}
+
+px_status px_sigma_diagonalize(px_context* ctx, int32_t n, const double* sigma, double* Q, double* d,
+                               int32_t* status, hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (n <= 0) return fail(ctx, PX_ERR_INVALID_ARG, "n must be > 0 (got %d)", n);
+  if (!sigma || !Q || !d || !status)
+    return fail(ctx, PX_ERR_INVALID_ARG, "sigma_diagonalize: null array argument");
+  if (Q == sigma) return fail(ctx, PX_ERR_INVALID_ARG, "sigma_diagonalize: Q must not alias sigma");
+  if (misaligned(sigma) || misaligned(Q))
+    return fail(ctx, PX_ERR_INVALID_ARG, "sigma_diagonalize: matrices must be 16-byte aligned");
+  px_status st = need_ws(ctx, align_up(px::eig_work_bytes(n)));
+  if (st != PX_OK) return st;
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  st = hip_check(ctx, px::launch_eig_hermitian(sigma, n, Q, d, status, ctx->ws, kEigSweeps, stream),
+                 "sigma = Q D Q^H");
+  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED});
+  return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+// sigma = Q D Q^H into the layout's Q and d, then phi = Phi Q (Eq. 11): the
+// orbitals of the diagonal form that Eq. 12 and Eq. 13 sum over.
+px_status rotate_orbitals(px_context* c, const SigmaLayout& l, const px_cell* cell, px_precision prec,
+                          int n, const void* phi_basis, const double* sigma, int32_t* status,
+                          hipStream_t s) {
+  const bool fp32 = prec == PX_PREC_FP32;
+  double* Q = reinterpret_cast<double*>(c->ws + l.Q);
+  double* d = reinterpret_cast<double*>(c->ws + l.d);
+  px_status st = hip_check(
+      c, px::launch_eig_hermitian(sigma, n, Q, d, status, c->ws + l.eig, kEigSweeps, s),
+      "sigma = Q D Q^H");
+  if (st != PX_OK) return st;
+  const void* Qc = Q;
+  if (fp32) {  // the FP32 contraction reads Q rounded to complex64
+    float* Q32 = reinterpret_cast<float*>(c->ws + l.Q32);
+    st = hip_check(c, px::launch_convert_f64_f32(size_t(2) * n * n, Q, Q32, s), "Q to FP32");
+    if (st != PX_OK) return st;
+    Qc = Q32;
+  }
+  return hip_check(c, px::launch_gemm_xc(fp32, n, n, ngrid(cell), phi_basis, Qc, n, 1.0,
+                                         c->ws + l.phi, false, s),
+                   "phi = Phi Q");
+}
+
+}  // namespace
+
+extern "C" {
+
+px_status px_exchange_apply_sigma(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                                  const void* phi_basis, const double* sigma, int32_t n_tgt,
+                                  const void* tgt, const double* kernel_G, void* vx_tgt,
+                                  int32_t* status, hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  px_status st = check_grid(ctx, cell);
+  if (st != PX_OK) return st;
+  if (n <= 0 || n_tgt <= 0)
+    return fail(ctx, PX_ERR_INVALID_ARG, "n and n_tgt must be > 0 (got %d, %d)", n, n_tgt);
+  if (!phi_basis || !sigma || !tgt || !kernel_G || !vx_tgt || !status)
+    return fail(ctx, PX_ERR_INVALID_ARG, "exchange_apply_sigma: null array argument");
+  if (vx_tgt == phi_basis || vx_tgt == tgt)
+    return fail(ctx, PX_ERR_INVALID_ARG, "exchange_apply_sigma: vx_tgt must not alias Phi or tgt");
+  if (misaligned(phi_basis) || misaligned(tgt) || misaligned(vx_tgt) || misaligned(sigma))
+    return fail(ctx, PX_ERR_INVALID_ARG,
+                "exchange_apply_sigma: orbital blocks and sigma must be 16-byte aligned");
+  int ic, jc;
+  tuning_for(ctx, cell, prec, &ic, &jc);
+  const ExLayout ex = ex_layout(cell, prec, n, n_tgt, ic, jc, false);
+  const SigmaLayout sl = sigma_layout(ex.end, cell, prec, n, false);
+  st = need_ws(ctx, sl.end);
+  if (st != PX_OK) return st;
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  st = rotate_orbitals(ctx, sl, cell, prec, n, phi_basis, sigma, status, stream);
+  if (st != PX_OK) return st;
+  // Eq. 13 on (phi, d): the double loop over the rotated orbitals
+  st = run_exchange(ctx, cell, prec, n, ctx->ws + sl.phi, reinterpret_cast<double*>(ctx->ws + sl.d),
+                    n_tgt, tgt, kernel_G, vx_tgt, ex, false, ic, jc, false, stream);
+  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED});
+  return st;
+}
+
+px_status px_density(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                     const void* phi, const double* occ, double* rho, hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  px_status st = check_gemm_grid(ctx, cell, prec);
+  if (st != PX_OK) return st;
+  if (n <= 0) return fail(ctx, PX_ERR_INVALID_ARG, "n must be > 0 (got %d)", n);
+  if (!phi || !occ || !rho) return fail(ctx, PX_ERR_INVALID_ARG, "density: null array argument");
+  if (misaligned(phi) || (reinterpret_cast<uintptr_t>(rho) & 7) != 0)
+    return fail(ctx, PX_ERR_INVALID_ARG, "density: phi must be 16-byte and rho 8-byte aligned");
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  return hip_check(ctx, px::launch_density(prec == PX_PREC_FP32, ngrid(cell), n, phi, occ, rho, stream),
+                   "density");
+}
+
+px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                           const void* phi_basis, const double* sigma, double* rho, int32_t* status,
+                           hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  px_status st = check_gemm_grid(ctx, cell, prec);
+  if (st != PX_OK) return st;
+  if (n <= 0) return fail(ctx, PX_ERR_INVALID_ARG, "n must be > 0 (got %d)", n);
+  if (!phi_basis || !sigma || !rho || !status)
+    return fail(ctx, PX_ERR_INVALID_ARG, "density_sigma: null array argument");
+  if (misaligned(phi_basis) || misaligned(sigma) || (reinterpret_cast<uintptr_t>(rho) & 7) != 0)
+    return fail(ctx, PX_ERR_INVALID_ARG,
+                "density_sigma: Phi and sigma must be 16-byte and rho 8-byte aligned");
+  const SigmaLayout sl = sigma_layout(0, cell, prec, n, false);
+  st = need_ws(ctx, sl.end);
+  if (st != PX_OK) return st;
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  st = rotate_orbitals(ctx, sl, cell, prec, n, phi_basis, sigma, status, stream);
+  if (st != PX_OK) return st;
+  st = hip_check(ctx, px::launch_density(prec == PX_PREC_FP32, ngrid(cell), n, ctx->ws + sl.phi,
+                                         reinterpret_cast<double*>(ctx->ws + sl.d), rho, stream),
+                 "density");
+  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED});
+  return st;
 }
 
 px_status px_set_symmetry(px_context* ctx, int32_t enable) {
@@ -1063,7 +1236,8 @@ px_status px_exchange_apply_batched(px_context* ctx, int32_t n_inst, const px_in
   const size_t tbytes = P.tasks.size() * sizeof(px::ChunkArgs);
   if (ace) {
     ctx->last_status.clear();
-    for (int k = 0; k < n_inst; ++k) ctx->last_status.push_back(inst[k].status);
+    for (int k = 0; k < n_inst; ++k)
+      ctx->last_status.push_back({inst[k].status, PX_ERR_NOT_POSITIVE_DEFINITE});
   }
   std::vector<unsigned char> key = batch_key(ctx, n_inst, inst, prec, ace != 0);
   if (ctx->use_graph && ctx->graph_exec && key == ctx->graph_key)
@@ -1227,13 +1401,17 @@ px_status px_sync(px_context* ctx, hipStream_t stream) {
   if (e != hipSuccess) return hip_check(ctx, e, "hipStreamSynchronize");
   for (size_t k = 0; k < ctx->last_status.size(); ++k) {
     int32_t s = 0;
-    e = hipMemcpy(&s, ctx->last_status[k], sizeof s, hipMemcpyDeviceToHost);
+    e = hipMemcpy(&s, ctx->last_status[k].first, sizeof s, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_check(ctx, e, "status readback");
     if (s != 0 && ctx->latched == PX_OK) {
-      ctx->latched = PX_ERR_NOT_POSITIVE_DEFINITE;
-      fail(ctx, PX_ERR_NOT_POSITIVE_DEFINITE,
-           "ace_build (instance %zu): -M is not positive definite (Cholesky breakdown at column %d)",
-           k, s);
+      const px_status kind = ctx->last_status[k].second;
+      ctx->latched = kind;
+      if (kind == PX_ERR_NOT_POSITIVE_DEFINITE)
+        fail(ctx, kind,
+             "ace_build (instance %zu): -M is not positive definite (Cholesky breakdown at column %d)",
+             k, s);
+      else
+        fail(ctx, kind, "sigma diagonalisation: Jacobi sweeps did not converge (%d sweeps)", s);
     }
   }
   ctx->last_status.clear();
@@ -1247,3 +1425,4 @@ void px_clear_error(px_context* ctx) {
 }
 
 }  // extern "C"
+

@@ -144,14 +144,30 @@ hipError_t launch_ptim_update(bool fp32, size_t n, const void* phi_n, const void
                               double* res, hipStream_t s);
 int ptim_update_blocks();
 
+// rho[r] = sum_i w[i] |phi_i(r)|^2 (FP64), phi [n][ng] complex in the form's precision
+hipError_t launch_density(bool fp32, size_t ng, int n, const void* phi, const double* w,
+                          double* rho, hipStream_t s);
+
+// eig_kernels.hip: sigma = Q diag(d) Q^H (FP64, complex128 n x n row-major), d ascending;
+// status[0] = 0 when converged within max_sweeps Jacobi sweeps, else the sweeps made.
+// work: eig_work_bytes(n).
+size_t eig_work_bytes(int n);
+hipError_t launch_eig_hermitian(const double* sigma, int n, double* Q, double* d, int32_t* status,
+                                void* work, int max_sweeps, hipStream_t s);
+
 // gemm_kernels.hip: complex GEMMs on MFMA
 // M[a][b] (a < na, b < nb, row-major ldm) = scale * sum_r conj(X[a][r]) Y[b][r]
-//   X: [na][ng], Y: [nb][ng]; FP64 result.  part: workspace of nsplit*na*nb complex128.
+//   X: [na][ng], Y: [nb][ng]; FP64 result.  part: workspace of nsplit*na*nb complex128,
+//   where nsplit (the splits available) may be below gemm_xhy_part_elems' count: the
+//   sum over r then runs in fewer, longer splits.
 //   M32 (nullable): the result rounded to complex64 as well, same layout.
 hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, const void* Y,
                            double scale, double* M, int ldm, double* part, int nsplit,
                            float* M32, hipStream_t s);
 size_t gemm_xhy_part_elems(int na, int nb, size_t ng, int* nsplit);
+// Splits launch_gemm_xhy uses when at most max_split are available (fewer,
+// longer splits than the default when max_split is below it).
+int gemm_xhy_splits(int na, int nb, size_t ng, int max_split);
 // Z[b][r] = alpha * sum_a X[a][r] C[a][b]
 //   X: [na][ng], C: [na][ldc] row-major in the precision of the form (complex128, or
 //   complex64 rounded from the FP64 matrix), Z: [nb][ng]; upper: C upper triangular

@@ -16,12 +16,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpx.so")
 
 PX_OK, PX_ERR_INVALID_ARG, PX_ERR_UNSUPPORTED_GRID, PX_ERR_WORKSPACE, PX_ERR_DEVICE, \
-    PX_ERR_NOT_POSITIVE_DEFINITE = range(6)
+    PX_ERR_NOT_POSITIVE_DEFINITE, PX_ERR_NOT_CONVERGED = range(7)
 PX_PREC_FP64, PX_PREC_FP32 = 0, 1
 PX_OP_EXCHANGE, PX_OP_ACE_BUILD, PX_OP_ACE_APPLY, PX_OP_PTIM_LOOP = 0, 1, 2, 3
+PX_OP_EXCHANGE_SIGMA, PX_OP_SIGMA_DIAG, PX_OP_DENSITY_SIGMA = 4, 5, 6
 
 STATUS_NAMES = {0: "PX_OK", 1: "PX_ERR_INVALID_ARG", 2: "PX_ERR_UNSUPPORTED_GRID",
-                3: "PX_ERR_WORKSPACE", 4: "PX_ERR_DEVICE", 5: "PX_ERR_NOT_POSITIVE_DEFINITE"}
+                3: "PX_ERR_WORKSPACE", 4: "PX_ERR_DEVICE", 5: "PX_ERR_NOT_POSITIVE_DEFINITE",
+                6: "PX_ERR_NOT_CONVERGED"}
 
 # Every function declared in include/px.h, with its ctypes signature.
 _vp, _i32, _sz, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t, ctypes.c_double
@@ -57,6 +59,10 @@ SIGNATURES = {
     "px_ace_build": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "px_ace_apply": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
     "px_ptim_exchange_loop": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _i32, _dbl, _vp, _vp, _vp]),
+    "px_sigma_diagonalize": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "px_exchange_apply_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "px_density": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "px_density_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "px_set_symmetry": (_i32, [_vp, _i32]),
     "px_set_profiling": (_i32, [_vp, _i32]),
     "px_profile_read_ace": (_i32, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(ctypes.c_int64), _i32]),
@@ -290,6 +296,79 @@ class Context:
             self.h, ctypes.byref(cell.c()), prec, xi.shape[0], _ptr(xi), phi_n.shape[0],
             _ptr(phi_n), int(n_iter), float(dt_alpha), _ptr(out), _ptr(residuals), _stream(stream)))
         return out, residuals
+
+    def _status(self, status, device):
+        import torch
+        if status is None:
+            status = torch.zeros(1, dtype=torch.int32, device=device)
+        return status
+
+    def _sigma(self, sigma, n):
+        import torch
+        if sigma.dtype != torch.complex128 or not sigma.is_cuda or not sigma.is_contiguous() \
+                or tuple(sigma.shape) != (n, n):
+            raise ValueError(f"sigma must be a contiguous complex128 device tensor of shape ({n}, {n})")
+
+    def px_sigma_diagonalize(self, sigma, Q=None, d=None, status=None, stream=None):
+        """sigma = Q diag(d) Q^H; returns (Q, d, status)."""
+        import torch
+        n = sigma.shape[0]
+        self._sigma(sigma, n)
+        if Q is None:
+            Q = torch.empty_like(sigma)
+        if d is None:
+            d = torch.empty(n, dtype=torch.float64, device=sigma.device)
+        status = self._status(status, sigma.device)
+        cell = Cell.cubic(16, 1.0)
+        self.ensure_workspace(self.workspace_bytes(PX_OP_SIGMA_DIAG, cell, PX_PREC_FP64, n))
+        self._check(self.lib.px_sigma_diagonalize(self.h, n, _ptr(sigma), _ptr(Q), _ptr(d),
+                                                  _ptr(status), _stream(stream)))
+        return Q, d, status
+
+    def px_exchange_apply_sigma(self, cell: Cell, phi_basis, sigma, tgt, kern, out=None, status=None,
+                                stream=None):
+        """Vx[Phi sigma Phi^H] applied to tgt (Eq. 10 via Eq. 11-13); returns (out, status)."""
+        import torch
+        prec = _prec(phi_basis.dtype)
+        _check_block("phi_basis", phi_basis, cell)
+        _check_block("tgt", tgt, cell, phi_basis.dtype)
+        n = phi_basis.shape[0]
+        self._sigma(sigma, n)
+        if out is None:
+            out = torch.empty_like(tgt)
+        status = self._status(status, tgt.device)
+        self.ensure_workspace(self.workspace_bytes(PX_OP_EXCHANGE_SIGMA, cell, prec, n, tgt.shape[0]))
+        self._check(self.lib.px_exchange_apply_sigma(
+            self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis), _ptr(sigma), tgt.shape[0],
+            _ptr(tgt), _ptr(kern), _ptr(out), _ptr(status), _stream(stream)))
+        return out, status
+
+    def px_density(self, cell: Cell, phi, occ, rho=None, stream=None):
+        """rho(r) = sum_i occ_i |phi_i(r)|^2 (FP64, shape [n2][n1][n0])."""
+        import torch
+        prec = _prec(phi.dtype)
+        _check_block("phi", phi, cell)
+        if rho is None:
+            rho = torch.empty((cell.n[2], cell.n[1], cell.n[0]), dtype=torch.float64, device=phi.device)
+        self._check(self.lib.px_density(self.h, ctypes.byref(cell.c()), prec, phi.shape[0], _ptr(phi),
+                                        _ptr(occ), _ptr(rho), _stream(stream)))
+        return rho
+
+    def px_density_sigma(self, cell: Cell, phi_basis, sigma, rho=None, status=None, stream=None):
+        """rho(r) = sum_ij Phi_i sigma_ij conj(Phi_j); returns (rho, status)."""
+        import torch
+        prec = _prec(phi_basis.dtype)
+        _check_block("phi_basis", phi_basis, cell)
+        n = phi_basis.shape[0]
+        self._sigma(sigma, n)
+        if rho is None:
+            rho = torch.empty((cell.n[2], cell.n[1], cell.n[0]), dtype=torch.float64,
+                              device=phi_basis.device)
+        status = self._status(status, phi_basis.device)
+        self.ensure_workspace(self.workspace_bytes(PX_OP_DENSITY_SIGMA, cell, prec, n))
+        self._check(self.lib.px_density_sigma(self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis),
+                                              _ptr(sigma), _ptr(rho), _ptr(status), _stream(stream)))
+        return rho, status
 
     def px_set_profiling(self, enable: bool):
         self._check(self.lib.px_set_profiling(self.h, 1 if enable else 0))

@@ -212,3 +212,38 @@ def test_load_tuning_cache(lib, ctx, tmp_path):
     tuned = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 1, 512, 512)
     assert tuned < base                       # 8 x 8 pair block instead of the default
     assert lib.px_load_tuning(ctx, b"/nonexistent/file", None) == px.PX_ERR_INVALID_ARG
+
+
+def test_sigma_and_density_validation(lib, ctx):
+    c = _cell()
+    st = ctypes.c_void_p(0x5000)
+    S, Q, d = ctypes.c_void_p(0x6000), ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000)
+    f = lib.px_sigma_diagonalize
+    assert f(ctx, 0, S, Q, d, st, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, 4, S, S, d, st, None) == px.PX_ERR_INVALID_ARG        # Q aliases sigma
+    assert f(ctx, 4, S, Q, d, None, None) == px.PX_ERR_INVALID_ARG      # status required
+    assert f(ctx, 4, ctypes.c_void_p(0x6008), Q, d, st, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, 4, S, Q, d, st, None) == px.PX_ERR_WORKSPACE
+    g = lib.px_exchange_apply_sigma
+    phi, tgt, kern, out = ctypes.c_void_p(0x9000), ctypes.c_void_p(0xa000), FAKE, ctypes.c_void_p(0xb000)
+    assert g(ctx, ctypes.byref(c), 0, 4, phi, S, 2, tgt, kern, out, st, None) == px.PX_ERR_WORKSPACE
+    assert g(ctx, ctypes.byref(c), 0, 4, phi, S, 2, tgt, kern, phi, st, None) == px.PX_ERR_INVALID_ARG
+    assert g(ctx, ctypes.byref(c), 0, 4, phi, S, 2, tgt, kern, out, None, None) == px.PX_ERR_INVALID_ARG
+    assert g(ctx, ctypes.byref(_cell(7)), 0, 4, phi, S, 2, tgt, kern, out, st, None) == px.PX_ERR_UNSUPPORTED_GRID
+    assert g(ctx, ctypes.byref(c), 0, 0, phi, S, 2, tgt, kern, out, st, None) == px.PX_ERR_INVALID_ARG
+    h = lib.px_density
+    rho = ctypes.c_void_p(0xc000)
+    assert h(ctx, ctypes.byref(c), 0, 0, phi, d, rho, None) == px.PX_ERR_INVALID_ARG
+    assert h(ctx, ctypes.byref(c), 0, 4, None, d, rho, None) == px.PX_ERR_INVALID_ARG
+    assert h(ctx, ctypes.byref(c), 0, 4, phi, d, ctypes.c_void_p(0xc004), None) == px.PX_ERR_INVALID_ARG
+    odd = px.Cell((5.0, 5.0, 5.0), (5, 5, 5)).c()
+    assert h(ctx, ctypes.byref(odd), 1, 4, phi, d, rho, None) == px.PX_ERR_UNSUPPORTED_GRID
+    k = lib.px_density_sigma
+    assert k(ctx, ctypes.byref(c), 0, 4, phi, S, rho, st, None) == px.PX_ERR_WORKSPACE
+    assert k(ctx, ctypes.byref(c), 0, 4, phi, S, rho, None, None) == px.PX_ERR_INVALID_ARG
+    wb = lib.px_workspace_bytes
+    assert wb(ctx, px.PX_OP_SIGMA_DIAG, ctypes.byref(c), 0, 64, 0) >= 2 * 64 * 64 * 16
+    ws = wb(ctx, px.PX_OP_EXCHANGE_SIGMA, ctypes.byref(c), 1, 16, 5)
+    assert ws >= 16 * 24 ** 3 * 8 + 2 * 16 * 16 * 16    # phi = Phi Q plus the Jacobi arrays
+    assert wb(ctx, px.PX_OP_EXCHANGE_SIGMA, ctypes.byref(_cell(7)), 0, 16, 5) == 0
+    assert wb(ctx, px.PX_OP_DENSITY_SIGMA, ctypes.byref(c), 0, 16, 0) >= 16 * 24 ** 3 * 16

@@ -1,0 +1,147 @@
+"""GPU parity of the occupation-matrix front end (Sec. IV-A-1, Eq. 11-13) and
+the density (Sec. III-C, Eq. 12) against the CPU oracle.
+
+* px_sigma_diagonalize: eigenvalues against LAPACK's, Q D Q^H against sigma,
+  Q unitary; spectra with degenerate and tiny eigenvalues, odd and even n.
+* px_exchange_apply_sigma: against the oracle's triple loop of Eq. 10 on tiny
+  inputs (every (k, i, j) pair solve done directly), and against the oracle's
+  diagonalised form on a 24^3 instance with Phi as the target.
+* px_density / px_density_sigma: against the oracle's density (diagonal form)
+  and its double sum over sigma.
+Tolerances: FP64 form 1e-11 relative (1e-12 for the density and the
+eigenvalues); FP32 form 2e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_03061_amd import inputs, px
+from _gpu import banner, relerr, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL, FP32_TOL = 1e-11, 2e-5
+
+
+def _unitary(rng, n):
+    q, r = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _sigma(rng, n, degenerate=False):
+    d = rng.uniform(0.0, 1.0, n)
+    if degenerate and n >= 4:
+        d[1] = d[0]
+        d[3] = 1e-13
+    U = _unitary(rng, n)
+    return U @ np.diag(d) @ U.conj().T
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 201])
+def test_sigma_diagonalize(px_ctx, n):
+    import torch
+    banner(f"sigma diagonalize n={n}")
+    rng = np.random.default_rng(40 + n)
+    sigma = _sigma(rng, n, degenerate=True)
+    Q, d, st = px_ctx.px_sigma_diagonalize(to_dev(sigma))
+    px_ctx.px_sync()
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    Qh, dh = to_host(Q), to_host(d)
+    dref, _ = oracle.sigma_eig(sigma)
+    scale = max(1.0, float(np.abs(dref).max()))
+    print(f"n={n}: eigenvalue err {np.abs(dh - dref).max():.2e}, rebuild "
+          f"{relerr(Qh @ np.diag(dh) @ Qh.conj().T, sigma):.2e}", flush=True)
+    assert np.abs(dh - dref).max() < 1e-12 * scale
+    assert np.all(np.diff(dh) >= 0)
+    assert np.abs(Qh.conj().T @ Qh - np.eye(n)).max() < 1e-12
+    assert relerr(Qh @ np.diag(dh) @ Qh.conj().T, sigma) < 1e-12
+
+
+def test_sigma_diagonalize_diagonal_and_zero(px_ctx):
+    """Already diagonal (no rotation at all) and all-zero sigma."""
+    import torch
+    banner("sigma diagonalize trivial")
+    for sigma in (np.diag([0.3, 0.1, 0.9, 0.5]).astype(np.complex128), np.zeros((5, 5), np.complex128)):
+        Q, d, st = px_ctx.px_sigma_diagonalize(to_dev(sigma))
+        px_ctx.px_sync()
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        assert np.array_equal(to_host(d), np.sort(np.diag(sigma).real))
+        Qh = to_host(Q)
+        assert np.abs(np.abs(Qh) - np.abs(Qh).round()).max() == 0.0   # a permutation
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_exchange_sigma_vs_triple_loop(px_ctx, fp32):
+    """Eq. 10 directly (N^3 pair solves in the oracle) on a 16^3 grid."""
+    banner(f"exchange sigma vs triple loop fp32={fp32}")
+    rng = np.random.default_rng(7)
+    inst = inputs.make_instance(16, 6.0, 4, kT=0.05, seed=31)
+    Phi = inst.psi
+    tgt = inputs.noise_block(inst.n, inst.L, 3, seed=32)
+    sigma = _sigma(rng, 4)
+    K = oracle.kernel_hse(inst.n, inst.L, 0.106)
+    ref = oracle.exchange_apply_sigma(Phi, sigma, tgt, K)
+    cell = px.Cell(inst.L, inst.n)
+    P, T = to_dev(Phi), to_dev(tgt)
+    if fp32:
+        P, T = px_ctx.px_convert_c128_to_c64(P), px_ctx.px_convert_c128_to_c64(T)
+    out, st = px_ctx.px_exchange_apply_sigma(cell, P, to_dev(sigma), T, to_dev(K))
+    px_ctx.px_sync()
+    assert int(st.item()) == 0
+    err = relerr(to_host(out), ref)
+    print(f"exchange sigma fp32={fp32}: err vs Eq. 10 triple loop {err:.2e}", flush=True)
+    assert err < (FP32_TOL if fp32 else FP64_TOL)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_exchange_sigma_toy24_on_phi(px_ctx, fp32):
+    """24^3, 16 orbitals, sigma with the Fermi-Dirac spectrum in a random
+    basis, target Phi itself; against the oracle's diagonalised form."""
+    banner(f"exchange sigma toy24 fp32={fp32}")
+    c = inputs.CONFIGS["toy24"]
+    inst = inputs.make_instance(c["n"], c["L"], c["n_orb"], 0.05, seed=c["seed"])
+    rng = np.random.default_rng(8)
+    U = _unitary(rng, inst.n_orb)
+    sigma = U @ np.diag(inst.occ) @ U.conj().T
+    K = oracle.kernel_hse(inst.n, inst.L, c["mu"])
+    d, Q = oracle.sigma_eig(sigma)
+    ref = oracle.exchange_apply(oracle.rotate(inst.psi, Q), d, inst.psi, K)
+    cell = px.Cell(inst.L, inst.n)
+    P = to_dev(inst.psi)
+    if fp32:
+        P = px_ctx.px_convert_c128_to_c64(P)
+    out, st = px_ctx.px_exchange_apply_sigma(cell, P, to_dev(sigma), P, px_ctx.px_kernel_hse(cell, c["mu"]))
+    px_ctx.px_sync()
+    assert int(st.item()) == 0
+    err = relerr(to_host(out), ref)
+    print(f"exchange sigma toy24 fp32={fp32}: err {err:.2e}", flush=True)
+    assert err < (FP32_TOL if fp32 else FP64_TOL)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("n,L,N", [(24, 10.0, 16), (40, 11.2, 37)])
+def test_density(px_ctx, fp32, n, L, N):
+    import torch
+    banner(f"density n={n} N={N} fp32={fp32}")
+    inst = inputs.make_instance(n, L, N, kT=0.03, seed=50 + n)
+    rng = np.random.default_rng(9)
+    sigma = _sigma(rng, N)
+    cell = px.Cell(inst.L, inst.n)
+    P = to_dev(inst.psi)
+    psi = inst.psi
+    if fp32:
+        P = px_ctx.px_convert_c128_to_c64(P)
+        psi = to_host(P).astype(np.complex128)        # the oracle on the rounded orbitals
+    rho = to_host(px_ctx.px_density(cell, P, to_dev(inst.occ)))
+    rho_s, st = px_ctx.px_density_sigma(cell, P, to_dev(sigma))
+    px_ctx.px_sync()
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    ref = oracle.density(psi, inst.occ)
+    ref_s = oracle.density_sigma(psi, sigma)
+    e1, e2 = relerr(rho, ref), relerr(to_host(rho_s), ref_s)
+    print(f"density fp32={fp32}: occupations {e1:.2e}, sigma {e2:.2e}", flush=True)
+    assert e1 < 1e-12
+    assert e2 < (FP32_TOL if fp32 else 1e-12)

@@ -337,3 +337,85 @@ def test_generator_orthonormal_and_band_limited():
 
 def test_generator_sphere_size_mid72():
     assert len(inputs.sphere_indices((72, 72, 72), (20.0, 20.0, 20.0), 10.0)) == 12053
+
+
+# ---------------------------------------------------------------- sigma: diagonalisation and density
+def _unitary(rng, n):
+    q, r = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def test_sigma_eig_recovers_a_known_spectrum(rng):
+    """sigma built from a chosen spectrum (with a degenerate pair and a tiny
+    eigenvalue) and a random unitary: the eigenvalues come back in ascending
+    order, Q is unitary and Q D Q^H rebuilds sigma."""
+    n = 9
+    dd = np.array([1.0, 1.0, 0.9, 0.5, 0.25, 1e-12, 0.0, 0.75, 0.3])
+    U = _unitary(rng, n)
+    sigma = U @ np.diag(dd) @ U.conj().T
+    d, Q = oracle.sigma_eig(sigma)
+    assert np.allclose(d, np.sort(dd), atol=1e-14)
+    assert np.allclose(Q.conj().T @ Q, np.eye(n), atol=1e-14)
+    assert _relerr(Q @ np.diag(d) @ Q.conj().T, sigma) < 1e-14
+    # each column is an eigenvector of its eigenvalue
+    assert np.allclose(sigma @ Q, Q * d[None, :], atol=1e-14)
+
+
+def test_rotate_is_the_basis_change_of_eq11(rng):
+    """phi = Phi Q: for Q a permutation the orbitals are permuted, for a
+    diagonal phase matrix each orbital is multiplied by its phase."""
+    n = (4, 3, 5)
+    Phi = _rand_block(rng, 4, n)
+    perm = np.eye(4)[:, [2, 0, 3, 1]]          # column b picks orbital [2, 0, 3, 1][b]
+    assert np.array_equal(oracle.rotate(Phi, perm), Phi[[2, 0, 3, 1]])
+    ph = np.exp(1j * np.array([0.3, -1.2, 2.0, 0.0]))
+    assert _relerr(oracle.rotate(Phi, np.diag(ph)), Phi * ph[:, None, None, None]) < 1e-15
+
+
+def test_density_integrates_to_the_trace_of_sigma():
+    """dV-orthonormal orbitals: the integral of rho is Tr(sigma) (the electron
+    count of the mixed state), for the sigma form and the diagonal form."""
+    inst = inputs.make_instance(12, 6.0, 6, kT=0.05, seed=21)
+    dv = inst.omega / inst.ng
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6))
+    sigma = X @ X.conj().T / 10.0
+    rho = oracle.density_sigma(inst.psi, sigma)
+    assert abs(dv * rho.sum() - np.trace(sigma).real) < 1e-12
+    rho_f = oracle.density(inst.psi, inst.occ)
+    assert abs(dv * rho_f.sum() - inst.occ.sum()) < 1e-12
+
+
+def test_density_of_plane_waves_is_uniform():
+    """sigma = I over plane waves e^{ik.r}/sqrt(Omega): rho = N/Omega everywhere."""
+    n, L = 8, 5.0
+    psi = inputs.plane_wave_orbitals(n, L, [(0, 0, 0), (1, 2, -3), (4, 0, 1)])
+    rho = oracle.density_sigma(psi, np.eye(3))
+    assert np.allclose(rho, 3.0 / L ** 3, rtol=1e-14)
+
+
+def test_density_rank_one_sigma(rng):
+    """sigma = v v^H: rho = |sum_i v_i Phi_i|^2, a closed form of the double sum."""
+    n = (5, 4, 6)
+    Phi = _rand_block(rng, 4, n)
+    v = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    rho = oracle.density_sigma(Phi, np.outer(v, v.conj()))
+    f = np.einsum("i,izyx->zyx", v, Phi)
+    assert _relerr(rho, np.abs(f) ** 2) < 1e-14
+
+
+def test_density_gauge_invariance_and_diagonal_form(rng):
+    """Gauge invariance (Sec. II-A): (Phi U, U^H sigma U) gives the same
+    density; and Eq. 12: the diagonal form on (Phi Q, d) equals the double sum."""
+    n = (6, 5, 4)
+    Phi = _rand_block(rng, 5, n)
+    X = rng.standard_normal((5, 5)) + 1j * rng.standard_normal((5, 5))
+    sigma = X @ X.conj().T / 5.0
+    U = _unitary(rng, 5)
+    a = oracle.density_sigma(Phi, sigma)
+    b = oracle.density_sigma(oracle.rotate(Phi, U), U.conj().T @ sigma @ U)
+    assert _relerr(b, a) < 1e-13
+    d, Q = oracle.sigma_eig(sigma)
+    c = oracle.density(oracle.rotate(Phi, Q), d)
+    assert _relerr(c, a) < 1e-13
+    assert np.all(a >= -1e-12 * np.abs(a).max())      # PSD sigma: non-negative density
