@@ -10,8 +10,10 @@ leg of the benchmark may import it; the library never routes through it.
 Modules
   exchange  -- grid frequencies, screened kernel, Vx applied to orbitals
                (Eq. 13 and the mixed-state form Eq. 10), exchange energy.
-  ace       -- ACE construction and application (Eq. 14), and the
-               exchange-only implicit-midpoint loop (Eq. 4, 6, 7).
+  ace       -- ACE construction and application (Eq. 14), the
+               exchange-only implicit-midpoint loop (Eq. 4, 6, 7), and the
+               exchange-only PT-IM step with the projector and the occupation
+               matrix (Eq. 4-7).
   sigma     -- occupation-matrix diagonalisation (Eq. 11), the rotated
                orbitals Phi Q, and the density with a full sigma (Sec. III-C)
                or with occupations (Eq. 12).
@@ -23,5 +25,5 @@ from .exchange import (  # noqa: F401
     signed_freq, g2_grid, kernel_hse, exchange_apply, exchange_energy_real,
     exchange_energy_gspace, exchange_apply_sigma, pair_potential,
 )
-from .ace import ace_build, ace_apply, ptim_exchange_loop, DT_50AS, ALPHA  # noqa: F401
+from .ace import ace_build, ace_apply, ptim_exchange_loop, ptim_step, DT_50AS, ALPHA  # noqa: F401
 from .sigma import sigma_eig, rotate, density_sigma, density  # noqa: F401

@@ -74,3 +74,48 @@ def ptim_exchange_loop(xi, phi_n, dV, n_iter=4, dt=DT_50AS, alpha=ALPHA):
         res.append(float(np.linalg.norm(nxt - cur) / np.linalg.norm(nxt)))
         cur = nxt
     return cur, res
+
+
+def ptim_step(xi, phi_n, sigma_n, dV, n_iter=4, dt=DT_50AS, alpha=ALPHA):
+    """Exchange-only PT-IM step with the projection and the occupation matrix.
+
+    The scheme of Eq. (6) at the midpoints of Eq. (4), with the projector of
+    Eq. (5) and H reduced to its exchange part alpha * V_ACE (Eq. 8, V_ACE of
+    Eq. 14), iterated as the fixed point x = T(x) of Eq. (7) on
+    x = (Phi_{n+1}, sigma_{n+1}) from the guess x^(0) = (Phi_n, sigma_n):
+
+        Phi_mid   = (Phi_n + Phi^(k)) / 2,   sigma_mid = (sigma_n + sigma^(k)) / 2
+        Y         = alpha V_ACE Phi_mid                       (H Phi_mid)
+        S         = dV Phi_mid^H Phi_mid,    Hm = dV Phi_mid^H Y   (Phi^* H Phi)
+        Phi^(k+1)   = Phi_n   - i dt (Y - Phi_mid S^{-1} Hm)     ((I - P~) H Phi_mid)
+        sigma^(k+1) = sigma_n - i dt (Hm sigma_mid - sigma_mid Hm)
+
+    P~ Y = Phi (Phi^* Phi)^{-1} Phi^* Y of Eq. (5); the dV weights of S and of
+    Phi^H Y cancel there, and make Hm the matrix of H in the continuous inner
+    product.  Residuals R_k = ||x^(k+1) - x^(k)|| / ||x^(k+1)|| (Frobenius),
+    separately for Phi and sigma.  xi [N][...], phi_n [Nphi][...] orbitals,
+    sigma_n [Nphi][Nphi].  Returns (Phi^(n_iter), sigma^(n_iter),
+    [R_Phi,0 ..], [R_sigma,0 ..]).  Anderson mixing, the other terms of H and
+    the final orthogonalisation of Algorithm 1 are not part of this step.
+    """
+    phi_n = np.asarray(phi_n, dtype=np.complex128)
+    sigma_n = np.asarray(sigma_n, dtype=np.complex128)
+    shape = phi_n.shape
+    Pn = _flat(phi_n)
+    cur_p, cur_s = Pn.copy(), sigma_n.copy()
+    res_p, res_s = [], []
+    for _ in range(n_iter):
+        mid = 0.5 * (Pn + cur_p)
+        smid = 0.5 * (sigma_n + cur_s)
+        Y = alpha * _flat(ace_apply(xi, mid.reshape(shape), dV))
+        S = dV * (np.conj(mid) @ mid.T)            # S[a][b] = dV <mid_a | mid_b>
+        Hm = dV * (np.conj(mid) @ Y.T)             # Hm[a][b] = dV <mid_a | Y_b>
+        # P~ Y: column b of Y projected on span(mid), mid (S^{-1} Hm)
+        X = np.linalg.solve(S, Hm)
+        PY = X.T @ mid                             # row b = sum_a X[a][b] mid_a
+        nxt_p = Pn - 1j * dt * (Y - PY)
+        nxt_s = sigma_n - 1j * dt * (Hm @ smid - smid @ Hm)
+        res_p.append(float(np.linalg.norm(nxt_p - cur_p) / np.linalg.norm(nxt_p)))
+        res_s.append(float(np.linalg.norm(nxt_s - cur_s) / np.linalg.norm(nxt_s)))
+        cur_p, cur_s = nxt_p, nxt_s
+    return cur_p.reshape(shape), cur_s, res_p, res_s

@@ -320,6 +320,92 @@ def test_loop_plane_wave_scalar_recursion():
     assert np.allclose(c, cay, atol=1e-12)
 
 
+# ---------------------------------------------------------------- PT-IM step pins
+def _plane_wave_ace():
+    n, L, mu = 12, 7.0, 0.15
+    ms = [(0, 0, 0), (1, 1, 0), (-2, 0, 3)]
+    occ = np.array([1.0, 0.6, 0.3])
+    psi = inputs.plane_wave_orbitals(n, L, ms)
+    K = oracle.kernel_hse((n, n, n), (L, L, L), mu)
+    dV = L ** 3 / n ** 3
+    r = oracle.ace_build(psi, occ, K, dV)
+    return psi, r, dV, np.real(np.diag(r["M"]))
+
+
+def test_ptim_step_plane_waves_stay_and_sigma_rotates(rng):
+    """Plane waves are eigenfunctions of V_ACE (built from them), so H Phi lies
+    in span(Phi) and the projected update vanishes: Phi stays Phi_n.  Phi^* H Phi
+    is then diag(alpha lam), and element (i, j) of sigma follows the scalar
+    implicit-midpoint recursion s <- s_n - i dt alpha (lam_i - lam_j)(s_n + s)/2,
+    which after many iterations reaches the Cayley factor times s_n."""
+    psi, r, dV, lam = _plane_wave_ace()
+    X = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    sig = X @ X.conj().T / 3.0
+    dt, a = oracle.DT_50AS, oracle.ALPHA
+    w = a * (lam[:, None] - lam[None, :])
+    for iters in (3, 60):
+        p, sg, rp, rs = oracle.ptim_step(r["xi"], psi, sig, dV, n_iter=iters)
+        assert _relerr(p, psi) < 1e-13
+        assert max(rp) < 1e-13
+        s = sig.copy()
+        for _ in range(iters):
+            s = sig - 1j * dt * w * (sig + s) / 2
+        assert _relerr(sg, s) < 1e-13
+    cay = (1 - 0.5j * dt * w) / (1 + 0.5j * dt * w)
+    assert _relerr(sg, cay * sig) < 1e-12
+
+
+@pytest.fixture(scope="module")
+def toy_ace(toy):
+    inst, K = toy
+    dV = inst.omega / inst.ng
+    return inst, K, dV, oracle.ace_build(inst.psi, inst.occ, K, dV)
+
+
+def test_ptim_step_update_orthogonal_to_midpoint_and_trace_kept(rng, toy_ace):
+    """(I - P~) projects onto the orthogonal complement of span(Phi_mid): the
+    last update Phi^(k+1) - Phi_n is orthogonal to the midpoint it came from
+    (the unprojected V_ACE Phi_mid is not).  The commutator keeps sigma
+    Hermitian and its trace (the electron count) unchanged."""
+    inst, K, dV, r = toy_ace
+    z = inputs.noise_block(inst.n, inst.L, 5, seed=77)
+    phi_n = inst.psi[:5] + 0.3 * z
+    X = rng.standard_normal((5, 5)) + 1j * rng.standard_normal((5, 5))
+    sig = X @ X.conj().T / 5.0
+    p2, s2, _, _ = oracle.ptim_step(r["xi"], phi_n, sig, dV, n_iter=2)
+    p3, s3, rp, rs = oracle.ptim_step(r["xi"], phi_n, sig, dV, n_iter=3)
+    mid = 0.5 * (phi_n + p2).reshape(5, -1)
+    upd = (p3 - phi_n).reshape(5, -1)
+    proj = np.abs(np.conj(mid) @ upd.T).max() / (np.linalg.norm(mid) * np.linalg.norm(upd))
+    assert proj < 1e-14
+    y = oracle.ace_apply(r["xi"], mid.reshape(phi_n.shape), dV).reshape(5, -1)
+    assert np.abs(np.conj(mid) @ y.T).max() / (np.linalg.norm(mid) * np.linalg.norm(y)) > 1e-3
+    for s in (s2, s3):
+        assert abs(np.trace(s) - np.trace(sig)) < 1e-14 * abs(np.trace(sig))
+        assert np.linalg.norm(s - s.conj().T) < 1e-14 * np.linalg.norm(s)
+    assert rp[-1] < rp[0] and rs[-1] < rs[0]
+
+
+def test_ptim_step_gauge_covariance(rng, toy_ace):
+    """A unitary change of gauge, (Phi_n U, U^H sigma_n U), carries through the
+    step: the result is (Phi U, U^H sigma U) with the same residuals.  A
+    transposed or mis-ordered product (S^{-1} Hm against Hm S^{-1}, Hm sigma
+    against sigma Hm) breaks this."""
+    inst, K, dV, r = toy_ace
+    z = inputs.noise_block(inst.n, inst.L, 4, seed=78)
+    phi_n = inst.psi[2:6] + 0.2 * z
+    X = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    sig = X @ X.conj().T / 4.0
+    q, rr = np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))
+    U = q * (np.diag(rr) / np.abs(np.diag(rr)))
+    p, s, rp, rs = oracle.ptim_step(r["xi"], phi_n, sig, dV, n_iter=3)
+    pu, su, rpu, rsu = oracle.ptim_step(r["xi"], oracle.rotate(phi_n, U), U.conj().T @ sig @ U, dV,
+                                        n_iter=3)
+    assert _relerr(pu, oracle.rotate(p, U)) < 1e-13
+    assert _relerr(su, U.conj().T @ s @ U) < 1e-13
+    assert np.allclose(rpu, rp, rtol=1e-10) and np.allclose(rsu, rs, rtol=1e-10)
+
+
 # ---------------------------------------------------------------- generator sanity
 def test_generator_orthonormal_and_band_limited():
     inst = inputs.make_instance(24, 10.0, 16, kT=0.01, seed=0)
