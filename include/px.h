@@ -78,7 +78,8 @@ typedef enum {
   PX_OP_PTIM_LOOP = 3,
   PX_OP_EXCHANGE_SIGMA = 4,  /* n_psi = n (Phi and sigma), n_phi = n_tgt */
   PX_OP_SIGMA_DIAG = 5,      /* n_psi = n; n_phi ignored                 */
-  PX_OP_DENSITY_SIGMA = 6    /* n_psi = n; n_phi ignored                 */
+  PX_OP_DENSITY_SIGMA = 6,   /* n_psi = n; n_phi ignored                 */
+  PX_OP_PTIM_STEP = 7        /* n_psi = n (rank of xi), n_phi            */
 } px_op;
 
 /* Orthorhombic cell: edge lengths in bohr and the real-space grid, n[0] = x. */
@@ -232,6 +233,31 @@ px_status px_density(px_context* ctx, const px_cell* cell, px_precision prec, in
 px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
                            const void* phi_basis, const double* sigma, double* rho, int32_t* status,
                            hipStream_t stream);
+
+/* Exchange-only PT-IM step with the projector and the occupation matrix
+ * (Sec. II-A: the scheme of Eq. 6 at the midpoints of Eq. 4 with the
+ * projector P~ of Eq. 5, H reduced to alpha * V_ACE (Eq. 8, Eq. 14), iterated
+ * as the fixed point x = T(x) of Eq. 7 from x^(0) = (Phi_n, sigma_n)):
+ *   Phi_mid = (Phi_n + Phi^(k))/2,  sigma_mid = (sigma_n + sigma^(k))/2,
+ *   Y = V_ACE Phi_mid,  S = dV Phi_mid^H Phi_mid,  Hm = dV Phi_mid^H Y,
+ *   Phi^(k+1)   = Phi_n   - i dt_alpha (Y - Phi_mid S^{-1} Hm),
+ *   sigma^(k+1) = sigma_n - i dt_alpha (Hm sigma_mid - sigma_mid Hm),
+ * for k = 0 .. n_iter-1 (n_iter <= 64), dt_alpha = dt * alpha.  Orbital
+ * contractions in the form's precision; S^{-1} Hm (Cholesky of S, U = L^{-H},
+ * X = U U^H Hm), the sigma algebra and the residuals in FP64.
+ * xi [n][N_g], phi_n and phi_out [n_phi][N_g] (element type of prec);
+ * sigma_n, sigma_out complex128 [n_phi][n_phi]; residuals float64
+ * [2][n_iter]: R_Phi,k = ||Phi^(k+1) - Phi^(k)||_F / ||Phi^(k+1)||_F in
+ * residuals[k], the same for sigma in residuals[n_iter + k].  status (device
+ * int32, required): 0, or the 1-based column where the Cholesky factorisation
+ * of an overlap S broke down (Phi_mid linearly dependent; results undefined;
+ * px_sync returns PX_ERR_NOT_POSITIVE_DEFINITE).  Anderson mixing and the
+ * other terms of H are not part of the step.  Workspace: PX_OP_PTIM_STEP
+ * with (n, n_phi).  Grids as in px_ace_apply. */
+px_status px_ptim_step(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                       const void* xi, int32_t n_phi, const void* phi_n, const double* sigma_n,
+                       int32_t n_iter, double dt_alpha, void* phi_out, double* sigma_out,
+                       double* residuals, int32_t* status, hipStream_t stream);
 
 /* Hermitian pair symmetry of the ACE build (default on).  With Phi = Psi and a
  * real even kernel, v_ji = conj(v_ij): the orbitals are cut into square blocks,

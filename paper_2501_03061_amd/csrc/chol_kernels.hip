@@ -330,3 +330,132 @@ hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t
 }
 
 }  // namespace px
+
+// ---------------------------------------------------------------- small FP64 products
+namespace px {
+
+// C = op(A) B for n x n complex128 row-major matrices, op(A) = A or A^H:
+// 16 x 16 tiles of C per workgroup, 16 x 16 tiles of op(A) and B staged in
+// LDS, one entry of C per thread.  Used for the occupation-matrix algebra of
+// the PT-IM step (N_phi x N_phi), where the FP64 vector rate is ample.
+template <bool AH>
+__global__ __launch_bounds__(256) void zgemm_k(int n, const double* A, const double* B, double* C) {
+  __shared__ double2 sa[16][17], sb[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
+  double cr = 0.0, ci = 0.0;
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    // op(A)[row][k0 + tx]: A[row][k] or conj(A[k][row])
+    {
+      const int k = k0 + tx;
+      double2 v = make_double2(0.0, 0.0);
+      if (row < n && k < n) {
+        if (AH) {
+          const double* p = A + (size_t(k) * n + row) * 2;
+          v = make_double2(p[0], -p[1]);
+        } else {
+          const double* p = A + (size_t(row) * n + k) * 2;
+          v = make_double2(p[0], p[1]);
+        }
+      }
+      sa[ty][tx] = v;
+    }
+    {
+      const int k = k0 + ty;
+      double2 v = make_double2(0.0, 0.0);
+      if (k < n && col < n) {
+        const double* p = B + (size_t(k) * n + col) * 2;
+        v = make_double2(p[0], p[1]);
+      }
+      sb[ty][tx] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double2 a = sa[ty][k], b = sb[k][tx];
+      cr += a.x * b.x - a.y * b.y;
+      ci += a.x * b.y + a.y * b.x;
+    }
+    __syncthreads();
+  }
+  if (row < n && col < n) {
+    C[(size_t(row) * n + col) * 2] = cr;
+    C[(size_t(row) * n + col) * 2 + 1] = ci;
+  }
+}
+
+hipError_t launch_zgemm(bool ah, int n, const double* A, const double* B, double* C, hipStream_t s) {
+  const dim3 g((n + 15) / 16, (n + 15) / 16);
+  if (ah)
+    hipLaunchKernelGGL(zgemm_k<true>, g, dim3(256), 0, s, n, A, B, C);
+  else
+    hipLaunchKernelGGL(zgemm_k<false>, g, dim3(256), 0, s, n, A, B, C);
+  return hipGetLastError();
+}
+
+// dst = alpha * src over n real values
+__global__ void scale_k(size_t n, const double* src, double alpha, double* dst) {
+  for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+       e += size_t(gridDim.x) * blockDim.x)
+    dst[e] = alpha * src[e];
+}
+
+hipError_t launch_scale(size_t n, const double* src, double alpha, double* dst, hipStream_t s) {
+  const int blocks = int((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(scale_k, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, src, alpha, dst);
+  return hipGetLastError();
+}
+
+// sigma_nxt = sigma_n - i c (A1 - A2) over n x n complex values, and
+// res = ||sigma_nxt - sigma_cur||_F / ||sigma_nxt||_F (one workgroup, fixed
+// summation order).
+__global__ __launch_bounds__(1024) void sigma_update_k(size_t nel, const double* sigma_n,
+                                                       const double* A1, const double* A2,
+                                                       const double* cur, double* nxt, double c,
+                                                       double* res) {
+  __shared__ double rd[1024], rn[1024];
+  double dd = 0.0, nn = 0.0;
+  for (size_t e = threadIdx.x; e < nel; e += blockDim.x) {
+    const double gr = A1[2 * e] - A2[2 * e], gi = A1[2 * e + 1] - A2[2 * e + 1];
+    // -i c (gr + i gi) = c gi - i c gr
+    const double xr = sigma_n[2 * e] + c * gi, xi = sigma_n[2 * e + 1] - c * gr;
+    nxt[2 * e] = xr;
+    nxt[2 * e + 1] = xi;
+    const double dr = xr - cur[2 * e], di = xi - cur[2 * e + 1];
+    dd += dr * dr + di * di;
+    nn += xr * xr + xi * xi;
+  }
+  rd[threadIdx.x] = dd;
+  rn[threadIdx.x] = nn;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+      rd[threadIdx.x] += rd[threadIdx.x + w];
+      rn[threadIdx.x] += rn[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *res = rn[0] > 0.0 ? sqrt(rd[0] / rn[0]) : 0.0;
+}
+
+hipError_t launch_sigma_update(int n, const double* sigma_n, const double* A1, const double* A2,
+                               const double* cur, double* nxt, double c, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(sigma_update_k, dim3(1), dim3(1024), 0, s, size_t(n) * n, sigma_n, A1, A2, cur,
+                     nxt, c, res);
+  return hipGetLastError();
+}
+
+// out[0] = the first non-zero of st[0 .. k), else 0
+__global__ void status_first_k(const int32_t* st, int k, int32_t* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t v = 0;
+  for (int i = 0; i < k && v == 0; ++i) v = st[i];
+  out[0] = v;
+}
+
+hipError_t launch_status_first(const int32_t* st, int k, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(status_first_k, dim3(1), dim3(64), 0, s, st, k, out);
+  return hipGetLastError();
+}
+
+}  // namespace px

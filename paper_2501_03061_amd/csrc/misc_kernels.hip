@@ -231,10 +231,11 @@ __global__ void midpoint_k(size_t n, const T* a, const T* b, T* mid) {
   }
 }
 
-// nxt = phi_n - i*c*y; per-block FP64 partials of |nxt - cur|^2 and |nxt|^2
+// nxt = phi_n - i*c*(y + y2) (y2 nullable); per-block FP64 partials of
+// |nxt - cur|^2 and |nxt|^2
 template <typename T>
 __global__ __launch_bounds__(256) void ptim_update_k(size_t n, const T* phi_n, const T* y,
-                                                     const T* cur, T* nxt, double c,
+                                                     const T* y2, const T* cur, T* nxt, double c,
                                                      double* partial) {
   using V = typename V2<T>::t;
   __shared__ double red[2][256];
@@ -242,9 +243,15 @@ __global__ __launch_bounds__(256) void ptim_update_k(size_t n, const T* phi_n, c
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += size_t(gridDim.x) * blockDim.x) {
     V p = reinterpret_cast<const V*>(phi_n)[i], v = reinterpret_cast<const V*>(y)[i];
+    double vr = double(v.x), vi = double(v.y);
+    if (y2) {  // the two terms are added in FP64
+      const V w = reinterpret_cast<const V*>(y2)[i];
+      vr += double(w.x);
+      vi += double(w.y);
+    }
     V q = reinterpret_cast<const V*>(cur)[i];
     // -i c (vr + i vi) = c vi - i c vr
-    const double nr = double(p.x) + c * double(v.y), ni = double(p.y) - c * double(v.x);
+    const double nr = double(p.x) + c * vi, ni = double(p.y) - c * vr;
     V o = {T(nr), T(ni)};
     reinterpret_cast<V*>(nxt)[i] = o;
     const double dr = double(o.x) - double(q.x), di = double(o.y) - double(q.y);
@@ -297,16 +304,18 @@ hipError_t launch_midpoint(bool fp32, size_t n, const void* a, const void* b, vo
 }
 
 hipError_t launch_ptim_update(bool fp32, size_t n, const void* phi_n, const void* y,
-                              const void* cur, void* nxt, double c, double* partial,
+                              const void* y2, const void* cur, void* nxt, double c, double* partial,
                               double* res, hipStream_t s) {
   if (fp32)
     hipLaunchKernelGGL(ptim_update_k<float>, dim3(kUpdateBlocks), dim3(256), 0, s, n,
                        static_cast<const float*>(phi_n), static_cast<const float*>(y),
-                       static_cast<const float*>(cur), static_cast<float*>(nxt), c, partial);
+                       static_cast<const float*>(y2), static_cast<const float*>(cur),
+                       static_cast<float*>(nxt), c, partial);
   else
     hipLaunchKernelGGL(ptim_update_k<double>, dim3(kUpdateBlocks), dim3(256), 0, s, n,
                        static_cast<const double*>(phi_n), static_cast<const double*>(y),
-                       static_cast<const double*>(cur), static_cast<double*>(nxt), c, partial);
+                       static_cast<const double*>(y2), static_cast<const double*>(cur),
+                       static_cast<double*>(nxt), c, partial);
   hipLaunchKernelGGL(residual_k, dim3(1), dim3(64), 0, s, partial, kUpdateBlocks, res);
   return hipGetLastError();
 }

@@ -217,6 +217,8 @@ LoopLayout loop_layout(const px_cell* cell, px_precision prec, int n, int n_phi)
 // converges quadratically; a few sweeps past ten are rare for n in the
 // thousands).
 constexpr int kEigSweeps = 16;
+// Most fixed-point iterations of one px_ptim_step call.
+constexpr int kStepMaxIter = 64;
 
 // Workspace of the sigma front end from `base` on: the Jacobi work arrays,
 // Q (complex128) and its complex64 copy, d, and the rotated orbital block
@@ -238,6 +240,50 @@ SigmaLayout sigma_layout(size_t base, const px_cell* cell, px_precision prec, in
   off = align_up(off + size_t(n) * 8);
   l.phi = off;
   if (!no_phi) off = align_up(off + size_t(n) * ngrid(cell) * elem_bytes(prec));
+  l.end = off;
+  return l;
+}
+
+// Workspace of the exchange-only PT-IM step: the ACE application's pieces
+// (C, C32, partials for n x n_phi), partials of the n_phi x n_phi overlaps,
+// five orbital blocks (midpoint, V_ACE of it, its projection, two iterates),
+// the residual partials, and the n_phi x n_phi FP64 matrices.
+struct StepLayout {
+  ApplyLayout ap;
+  size_t part2, mid, Y, Z, buf0, buf1, partial;
+  size_t S, Hm, Mneg, L, U, dinv, T, X, X32, smid, sbuf0, sbuf1, A1, A2, st;
+  size_t end;
+};
+
+StepLayout step_layout(const px_cell* cell, px_precision prec, int n, int n_phi, int n_iter) {
+  StepLayout l{};
+  l.ap = apply_layout(cell, n, n_phi);
+  size_t off = l.ap.end;
+  int nsplit = 0;
+  const size_t pe = px::gemm_xhy_part_elems(n_phi, n_phi, ngrid(cell), &nsplit);
+  l.part2 = off;
+  off = align_up(off + pe * 16);
+  const size_t blk = size_t(n_phi) * ngrid(cell) * elem_bytes(prec);
+  size_t* blocks[5] = {&l.mid, &l.Y, &l.Z, &l.buf0, &l.buf1};
+  for (size_t* b : blocks) {
+    *b = off;
+    off = align_up(off + blk);
+  }
+  l.partial = off;
+  off = align_up(off + size_t(px::ptim_update_blocks()) * 16);
+  const size_t mat = size_t(n_phi) * n_phi * 16;
+  size_t* mats[12] = {&l.S, &l.Hm, &l.Mneg, &l.L, &l.U, &l.T, &l.X, &l.smid, &l.sbuf0, &l.sbuf1,
+                      &l.A1, &l.A2};
+  for (size_t* m : mats) {
+    *m = off;
+    off = align_up(off + mat);
+  }
+  l.X32 = off;
+  off = align_up(off + mat / 2);
+  l.dinv = off;
+  off = align_up(off + px::chol_dinv_bytes(n_phi));
+  l.st = off;
+  off = align_up(off + size_t(n_iter > 0 ? n_iter : 1) * sizeof(int32_t));
   l.end = off;
   return l;
 }
@@ -450,6 +496,9 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
       return align_up(px::eig_work_bytes(n_psi));
     case PX_OP_DENSITY_SIGMA:
       return sigma_layout(0, cell, prec, n_psi, false).end;
+    case PX_OP_PTIM_STEP:
+      if (n_phi <= 0) return 0;
+      return step_layout(cell, prec, n_psi, n_phi, kStepMaxIter).end;
   }
   return 0;
 }
@@ -724,8 +773,8 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
     st = hip_check(ctx, px::launch_gemm_xc(fp32, n, n_phi, ng, xi, Cc, n_phi, -1.0, y, false, stream),
                    "y = -xi C");
     if (st != PX_OK) return st;
-    st = hip_check(ctx, px::launch_ptim_update(fp32, nel, phi_n, y, cur, nxt, dt_alpha, partial,
-                                               residuals + k, stream),
+    st = hip_check(ctx, px::launch_ptim_update(fp32, nel, phi_n, y, nullptr, cur, nxt, dt_alpha,
+                                               partial, residuals + k, stream),
                    "update");
     if (st != PX_OK) return st;
     cur = nxt;
@@ -861,6 +910,100 @@ px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision pr
                                          reinterpret_cast<double*>(ctx->ws + sl.d), rho, stream),
                  "density");
   if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED});
+  return st;
+}
+
+px_status px_ptim_step(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                       const void* xi, int32_t n_phi, const void* phi_n, const double* sigma_n,
+                       int32_t n_iter, double dt_alpha, void* phi_out, double* sigma_out,
+                       double* residuals, int32_t* status, hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  px_status st = check_gemm_grid(ctx, cell, prec);
+  if (st != PX_OK) return st;
+  if (n <= 0 || n_phi <= 0 || n_iter <= 0 || n_iter > kStepMaxIter)
+    return fail(ctx, PX_ERR_INVALID_ARG, "n, n_phi > 0 and 0 < n_iter <= %d needed", kStepMaxIter);
+  if (!xi || !phi_n || !sigma_n || !phi_out || !sigma_out || !residuals || !status)
+    return fail(ctx, PX_ERR_INVALID_ARG, "ptim_step: null array argument");
+  if (phi_out == phi_n || phi_out == xi || sigma_out == sigma_n)
+    return fail(ctx, PX_ERR_INVALID_ARG, "ptim_step: outputs must not alias the inputs");
+  if (misaligned(xi) || misaligned(phi_n) || misaligned(phi_out) || misaligned(sigma_n) ||
+      misaligned(sigma_out))
+    return fail(ctx, PX_ERR_INVALID_ARG, "ptim_step: arrays must be 16-byte aligned");
+  const StepLayout l = step_layout(cell, prec, n, n_phi, kStepMaxIter);
+  st = need_ws(ctx, l.end);
+  if (st != PX_OK) return st;
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  const bool fp32 = prec == PX_PREC_FP32;
+  const size_t ng = ngrid(cell);
+  const size_t nel = size_t(n_phi) * ng;
+  const double dV = cell->L[0] * cell->L[1] * cell->L[2] / double(ng);
+  char* w = ctx->ws;
+  auto D = [w](size_t off) { return reinterpret_cast<double*>(w + off); };
+  double* C = D(l.ap.C);
+  float* C32 = fp32 ? reinterpret_cast<float*>(w + l.ap.C32) : nullptr;
+  const void* Cc = fp32 ? static_cast<const void*>(C32) : C;
+  float* X32 = reinterpret_cast<float*>(w + l.X32);
+  const void* Xc = fp32 ? static_cast<const void*>(X32) : D(l.X);
+  int32_t* sts = reinterpret_cast<int32_t*>(w + l.st);
+  int ns1 = 0, ns2 = 0;
+  px::gemm_xhy_part_elems(n, n_phi, ng, &ns1);
+  px::gemm_xhy_part_elems(n_phi, n_phi, ng, &ns2);
+  void* pbufs[2] = {w + l.buf0, w + l.buf1};
+  double* sbufs[2] = {D(l.sbuf0), D(l.sbuf1)};
+  const void* cur_p = phi_n;
+  const double* cur_s = sigma_n;
+  auto ok = [&](hipError_t e, const char* what) { return hip_check(ctx, e, what); };
+  for (int k = 0; k < n_iter; ++k) {
+    const bool last = k == n_iter - 1;
+    void* nxt_p = last ? phi_out : pbufs[k & 1];
+    double* nxt_s = last ? sigma_out : sbufs[k & 1];
+    void* mid = w + l.mid;
+    // Eq. 4: midpoints
+    if ((st = ok(px::launch_midpoint(fp32, nel, phi_n, cur_p, mid, stream), "midpoint")) != PX_OK) return st;
+    // Y = V_ACE mid = -xi (dV xi^H mid) (Eq. 14; alpha is folded into dt_alpha)
+    if ((st = ok(px::launch_gemm_xhy(fp32, n, n_phi, ng, xi, mid, dV, C, n_phi, D(l.ap.part), ns1, C32,
+                                     stream), "C = dV xi^H mid")) != PX_OK) return st;
+    if ((st = ok(px::launch_gemm_xc(fp32, n, n_phi, ng, xi, Cc, n_phi, -1.0, w + l.Y, false, stream),
+                 "Y = -xi C")) != PX_OK) return st;
+    // S = dV mid^H mid, Hm = dV mid^H Y (Eq. 5 and Eq. 6's Phi^* H Phi)
+    if ((st = ok(px::launch_gemm_xhy(fp32, n_phi, n_phi, ng, mid, mid, dV, D(l.S), n_phi, D(l.part2), ns2,
+                                     nullptr, stream), "S = dV mid^H mid")) != PX_OK) return st;
+    if ((st = ok(px::launch_gemm_xhy(fp32, n_phi, n_phi, ng, mid, w + l.Y, dV, D(l.Hm), n_phi, D(l.part2),
+                                     ns2, nullptr, stream), "Hm = dV mid^H Y")) != PX_OK) return st;
+    // X = S^{-1} Hm in FP64: S = L L^H (the Cholesky of -(-S)), U = L^{-H}, X = U (U^H Hm)
+    if ((st = ok(px::launch_scale(size_t(2) * n_phi * n_phi, D(l.S), -1.0, D(l.Mneg), stream), "-S")) != PX_OK)
+      return st;
+    if ((st = ok(px::launch_chol_inv(D(l.Mneg), n_phi, D(l.L), D(l.U), sts + k, D(l.dinv), stream),
+                 "cholesky of S")) != PX_OK) return st;
+    if ((st = ok(px::launch_zgemm(true, n_phi, D(l.U), D(l.Hm), D(l.T), stream), "U^H Hm")) != PX_OK) return st;
+    if ((st = ok(px::launch_zgemm(false, n_phi, D(l.U), D(l.T), D(l.X), stream), "U (U^H Hm)")) != PX_OK)
+      return st;
+    if (fp32 && (st = ok(px::launch_convert_f64_f32(size_t(2) * n_phi * n_phi, D(l.X), X32, stream),
+                         "X to FP32")) != PX_OK) return st;
+    // Z = -mid X (the projection P~ Y with its sign), then Phi^(k+1) = Phi_n - i dt_alpha (Y + Z)
+    if ((st = ok(px::launch_gemm_xc(fp32, n_phi, n_phi, ng, mid, Xc, n_phi, -1.0, w + l.Z, false, stream),
+                 "Z = -mid X")) != PX_OK) return st;
+    if ((st = ok(px::launch_ptim_update(fp32, nel, phi_n, w + l.Y, w + l.Z, cur_p, nxt_p, dt_alpha,
+                                        D(l.partial), residuals + k, stream), "orbital update")) != PX_OK)
+      return st;
+    // sigma^(k+1) = sigma_n - i dt_alpha (Hm smid - smid Hm) (Eq. 6)
+    if ((st = ok(px::launch_midpoint(false, size_t(n_phi) * n_phi, sigma_n, cur_s, D(l.smid), stream),
+                 "sigma midpoint")) != PX_OK) return st;
+    if ((st = ok(px::launch_zgemm(false, n_phi, D(l.Hm), D(l.smid), D(l.A1), stream), "Hm smid")) != PX_OK)
+      return st;
+    if ((st = ok(px::launch_zgemm(false, n_phi, D(l.smid), D(l.Hm), D(l.A2), stream), "smid Hm")) != PX_OK)
+      return st;
+    if ((st = ok(px::launch_sigma_update(n_phi, sigma_n, D(l.A1), D(l.A2), cur_s, nxt_s, dt_alpha,
+                                         residuals + n_iter + k, stream), "sigma update")) != PX_OK)
+      return st;
+    cur_p = nxt_p;
+    cur_s = nxt_s;
+  }
+  st = ok(px::launch_status_first(sts, n_iter, status, stream), "status");
+  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_POSITIVE_DEFINITE});
   return st;
 }
 

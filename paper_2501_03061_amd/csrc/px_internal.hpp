@@ -138,9 +138,9 @@ hipError_t launch_energy(const double* S, const double* occ, int n, double scale
 // PT-IM-style loop pieces (n = complex element count)
 hipError_t launch_midpoint(bool fp32, size_t n, const void* a, const void* b, void* mid,
                            hipStream_t s);
-// nxt = phi_n - i*c*y; res = ||nxt - cur|| / ||nxt|| accumulated in FP64
+// nxt = phi_n - i*c*(y + y2) (y2 nullable); res = ||nxt - cur|| / ||nxt|| accumulated in FP64
 hipError_t launch_ptim_update(bool fp32, size_t n, const void* phi_n, const void* y,
-                              const void* cur, void* nxt, double c, double* partial,
+                              const void* y2, const void* cur, void* nxt, double c, double* partial,
                               double* res, hipStream_t s);
 int ptim_update_blocks();
 
@@ -181,5 +181,14 @@ hipError_t launch_hermitize(double* M, int n, hipStream_t s);
 size_t chol_dinv_bytes(int n);
 hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t* status,
                            double* dinv, hipStream_t s);
+// C = op(A) B, n x n complex128 row-major, op(A) = A^H when ah
+hipError_t launch_zgemm(bool ah, int n, const double* A, const double* B, double* C, hipStream_t s);
+// dst = alpha * src, n real FP64 values
+hipError_t launch_scale(size_t n, const double* src, double alpha, double* dst, hipStream_t s);
+// nxt = sigma_n - i c (A1 - A2) (n x n complex128); *res = ||nxt - cur|| / ||nxt|| (FP64)
+hipError_t launch_sigma_update(int n, const double* sigma_n, const double* A1, const double* A2,
+                               const double* cur, double* nxt, double c, double* res, hipStream_t s);
+// out[0] = first non-zero of st[0 .. k), else 0
+hipError_t launch_status_first(const int32_t* st, int k, int32_t* out, hipStream_t s);
 
 }  // namespace px

@@ -19,7 +19,7 @@ PX_OK, PX_ERR_INVALID_ARG, PX_ERR_UNSUPPORTED_GRID, PX_ERR_WORKSPACE, PX_ERR_DEV
     PX_ERR_NOT_POSITIVE_DEFINITE, PX_ERR_NOT_CONVERGED = range(7)
 PX_PREC_FP64, PX_PREC_FP32 = 0, 1
 PX_OP_EXCHANGE, PX_OP_ACE_BUILD, PX_OP_ACE_APPLY, PX_OP_PTIM_LOOP = 0, 1, 2, 3
-PX_OP_EXCHANGE_SIGMA, PX_OP_SIGMA_DIAG, PX_OP_DENSITY_SIGMA = 4, 5, 6
+PX_OP_EXCHANGE_SIGMA, PX_OP_SIGMA_DIAG, PX_OP_DENSITY_SIGMA, PX_OP_PTIM_STEP = 4, 5, 6, 7
 
 STATUS_NAMES = {0: "PX_OK", 1: "PX_ERR_INVALID_ARG", 2: "PX_ERR_UNSUPPORTED_GRID",
                 3: "PX_ERR_WORKSPACE", 4: "PX_ERR_DEVICE", 5: "PX_ERR_NOT_POSITIVE_DEFINITE",
@@ -63,6 +63,8 @@ SIGNATURES = {
     "px_exchange_apply_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "px_density": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp]),
     "px_density_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "px_ptim_step": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _dbl, _vp, _vp, _vp,
+                            _vp, _vp]),
     "px_set_symmetry": (_i32, [_vp, _i32]),
     "px_set_profiling": (_i32, [_vp, _i32]),
     "px_profile_read_ace": (_i32, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(ctypes.c_int64), _i32]),
@@ -369,6 +371,30 @@ class Context:
         self._check(self.lib.px_density_sigma(self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis),
                                               _ptr(sigma), _ptr(rho), _ptr(status), _stream(stream)))
         return rho, status
+
+    def px_ptim_step(self, cell: Cell, xi, phi_n, sigma_n, n_iter: int, dt_alpha: float,
+                     phi_out=None, sigma_out=None, residuals=None, status=None, stream=None):
+        """Exchange-only PT-IM step with projector and sigma; returns
+        (phi_out, sigma_out, residuals [2][n_iter], status)."""
+        import torch
+        prec = _prec(xi.dtype)
+        _check_block("xi", xi, cell)
+        _check_block("phi_n", phi_n, cell, xi.dtype)
+        m = phi_n.shape[0]
+        self._sigma(sigma_n, m)
+        if phi_out is None:
+            phi_out = torch.empty_like(phi_n)
+        if sigma_out is None:
+            sigma_out = torch.empty_like(sigma_n)
+        if residuals is None:
+            residuals = torch.zeros((2, n_iter), dtype=torch.float64, device=phi_n.device)
+        status = self._status(status, phi_n.device)
+        self.ensure_workspace(self.workspace_bytes(PX_OP_PTIM_STEP, cell, prec, xi.shape[0], m))
+        self._check(self.lib.px_ptim_step(
+            self.h, ctypes.byref(cell.c()), prec, xi.shape[0], _ptr(xi), m, _ptr(phi_n), _ptr(sigma_n),
+            int(n_iter), float(dt_alpha), _ptr(phi_out), _ptr(sigma_out), _ptr(residuals), _ptr(status),
+            _stream(stream)))
+        return phi_out, sigma_out, residuals, status
 
     def px_set_profiling(self, enable: bool):
         self._check(self.lib.px_set_profiling(self.h, 1 if enable else 0))

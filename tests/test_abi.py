@@ -247,3 +247,27 @@ def test_sigma_and_density_validation(lib, ctx):
     assert ws >= 16 * 24 ** 3 * 8 + 2 * 16 * 16 * 16    # phi = Phi Q plus the Jacobi arrays
     assert wb(ctx, px.PX_OP_EXCHANGE_SIGMA, ctypes.byref(_cell(7)), 0, 16, 5) == 0
     assert wb(ctx, px.PX_OP_DENSITY_SIGMA, ctypes.byref(c), 0, 16, 0) >= 16 * 24 ** 3 * 16
+
+
+def test_ptim_step_validation(lib, ctx):
+    c = _cell()
+    f = lib.px_ptim_step
+    xi, p, s, po, so = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000, 0x5000))
+    res, st = ctypes.c_void_p(0x6000), ctypes.c_void_p(0x7000)
+
+    def call(n=4, n_phi=3, n_iter=2, **kw):
+        a = dict(xi=xi, p=p, s=s, po=po, so=so, res=res, st=st)
+        a.update(kw)
+        return f(ctx, ctypes.byref(c), 0, n, a["xi"], n_phi, a["p"], a["s"], n_iter, 0.5, a["po"], a["so"],
+                 a["res"], a["st"], None)
+    assert call(n_iter=0) == px.PX_ERR_INVALID_ARG
+    assert call(n_iter=65) == px.PX_ERR_INVALID_ARG
+    assert call(n_phi=0) == px.PX_ERR_INVALID_ARG
+    assert call(st=None) == px.PX_ERR_INVALID_ARG
+    assert call(po=p) == px.PX_ERR_INVALID_ARG
+    assert call(so=s) == px.PX_ERR_INVALID_ARG
+    assert call(s=ctypes.c_void_p(0x3008)) == px.PX_ERR_INVALID_ARG
+    assert call() == px.PX_ERR_WORKSPACE
+    wb = lib.px_workspace_bytes
+    assert wb(ctx, px.PX_OP_PTIM_STEP, ctypes.byref(c), 1, 16, 8) >= 5 * 8 * 24 ** 3 * 8
+    assert wb(ctx, px.PX_OP_PTIM_STEP, ctypes.byref(c), 1, 16, 0) == 0
