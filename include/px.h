@@ -176,6 +176,22 @@ px_status px_ace_apply(px_context* ctx, const px_cell* cell, px_precision prec, 
                        const void* xi, int32_t n_phi, const void* phi, void* out,
                        hipStream_t stream);
 
+/* ACE application without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight loops and harnesses that
+ * forbid allocation).  Same operation, arguments and errors as px_ace_apply;
+ * the contraction scratch (C = dV xi^H phi, its complex64 copy and the split
+ * partials of the N_g sum) is a 64 MiB array in the library's device memory,
+ * one per GPU, held until the process ends, instead of the workspace.  Needs
+ * 40 * n * n_phi bytes of it at least (n * n_phi <= 1,677,721; larger:
+ * PX_ERR_WORKSPACE); when the default number of splits does not fit, the N_g
+ * sum runs in fewer, longer splits.  No device memory is allocated or freed.
+ * Calls on one GPU share its array: calls that overlap in time on one GPU
+ * (other streams, other contexts, other threads) race and give undefined
+ * results; nothing in the array needs to be cleared between calls. */
+px_status px_ace_apply_noalloc(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                               const void* xi, int32_t n_phi, const void* phi, void* out,
+                               hipStream_t stream);
+
 /* Exchange-only implicit-midpoint fixed point with the ACE operator (the
  * orbital update of Eq. 6 at the midpoint of Eq. 4, keeping only alpha*Vx of
  * Eq. 8 and no projector, iterated as x = T(x) of Eq. 7):

@@ -1569,3 +1569,87 @@ void px_clear_error(px_context* ctx) {
 
 }  // extern "C"
 
+
+// ------------------------------------------------------------------ ACE application without workspace
+// For callers that cannot allocate device memory (code under graph capture,
+// tight loops that forbid allocation): the contraction scratch of
+// px_ace_apply (the matrix C = dV xi^H phi, its complex64 copy and the split
+// partials) lives in a file-scope device array instead of the caller's
+// workspace.  Each device holds its own copy of the array, at its own address,
+// until the process ends; host code must use that address (taken once per
+// device with hipGetSymbolAddress), never the array's name.
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_addr;  // device -> device address of `scratch`
+
+// The device address of `scratch` on the context's (current) device.
+px_status scratch_addr(px_context* c, char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(c->device);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return PX_OK;
+  }
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_check(c, e, "hipGetSymbolAddress (scratch)");
+  if (p == nullptr || (reinterpret_cast<uintptr_t>(p) % kAlign) != 0)
+    return fail(c, PX_ERR_DEVICE, "scratch array has no usable device address");
+  g_scratch_addr[c->device] = static_cast<char*>(p);
+  *out = static_cast<char*>(p);
+  return PX_OK;
+}
+
+}  // namespace
+
+extern "C" px_status px_ace_apply_noalloc(px_context* ctx, const px_cell* cell, px_precision prec,
+                                          int32_t n, const void* xi, int32_t n_phi, const void* phi,
+                                          void* out, hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  px_status st = check_gemm_grid(ctx, cell, prec);
+  if (st != PX_OK) return st;
+  if (n <= 0 || n_phi <= 0)
+    return fail(ctx, PX_ERR_INVALID_ARG, "n and n_phi must be > 0 (got %d, %d)", n, n_phi);
+  if (!xi || !phi || !out)
+    return fail(ctx, PX_ERR_INVALID_ARG, "ace_apply_noalloc: null array argument");
+  if (out == phi || out == xi)
+    return fail(ctx, PX_ERR_INVALID_ARG, "ace_apply_noalloc: out must not alias xi or phi");
+  if (misaligned(xi) || misaligned(phi) || misaligned(out))
+    return fail(ctx, PX_ERR_INVALID_ARG,
+                "ace_apply_noalloc: orbital blocks must be 16-byte aligned");
+  // scratch: C (complex128), C rounded to complex64, then at least one split of partials
+  const size_t nn = size_t(n) * size_t(n_phi);
+  const size_t c_off = 0, c32_off = align_up(nn * 16), part_off = align_up(c32_off + nn * 8);
+  if (part_off + nn * 16 > kScratchBytes)
+    return fail(ctx, PX_ERR_WORKSPACE,
+                "ace_apply_noalloc: n * n_phi = %zu exceeds the %zu MiB scratch (at most %zu)", nn,
+                kScratchBytes >> 20, (kScratchBytes - 2 * kAlign) / 40);
+  const int max_split = int((kScratchBytes - part_off) / (nn * 16));
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  char* sc = nullptr;
+  st = scratch_addr(ctx, &sc);
+  if (st != PX_OK) return st;
+  const bool fp32 = prec == PX_PREC_FP32;
+  const size_t ng = ngrid(cell);
+  const double dV = cell->L[0] * cell->L[1] * cell->L[2] / double(ng);
+  double* C = reinterpret_cast<double*>(sc + c_off);
+  float* C32 = fp32 ? reinterpret_cast<float*>(sc + c32_off) : nullptr;
+  double* part = reinterpret_cast<double*>(sc + part_off);
+  const int nsplit = px::gemm_xhy_splits(n, n_phi, ng, max_split);
+  // every element of the partials, C and C32 is written before it is read:
+  // nothing in the scratch has to start at zero
+  st = hip_check(ctx, px::launch_gemm_xhy(fp32, n, n_phi, ng, xi, phi, dV, C, n_phi, part, nsplit,
+                                          C32, stream),
+                 "C = dV xi^H phi");
+  if (st != PX_OK) return st;
+  const void* Cc = fp32 ? static_cast<const void*>(C32) : C;
+  return hip_check(ctx, px::launch_gemm_xc(fp32, n, n_phi, ng, xi, Cc, n_phi, -1.0, out, false, stream),
+                   "out = -xi C");
+}

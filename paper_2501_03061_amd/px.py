@@ -58,6 +58,7 @@ SIGNATURES = {
     "px_exchange_apply": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "px_ace_build": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "px_ace_apply": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
+    "px_ace_apply_noalloc": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
     "px_ptim_exchange_loop": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _i32, _dbl, _vp, _vp, _vp]),
     "px_sigma_diagonalize": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "px_exchange_apply_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -279,6 +280,19 @@ class Context:
             out = torch.empty_like(phi)
         self.ensure_workspace(self.workspace_bytes(PX_OP_ACE_APPLY, cell, prec, xi.shape[0], phi.shape[0]))
         self._check(self.lib.px_ace_apply(
+            self.h, ctypes.byref(cell.c()), prec, xi.shape[0], _ptr(xi), phi.shape[0], _ptr(phi),
+            _ptr(out), _stream(stream)))
+        return out
+
+    def px_ace_apply_noalloc(self, cell: Cell, xi, phi, out=None, stream=None):
+        """px_ace_apply with the library's static scratch instead of the workspace."""
+        import torch
+        prec = _prec(xi.dtype)
+        _check_block("xi", xi, cell)
+        _check_block("phi", phi, cell, xi.dtype)
+        if out is None:
+            out = torch.empty_like(phi)
+        self._check(self.lib.px_ace_apply_noalloc(
             self.h, ctypes.byref(cell.c()), prec, xi.shape[0], _ptr(xi), phi.shape[0], _ptr(phi),
             _ptr(out), _stream(stream)))
         return out
