@@ -255,7 +255,8 @@ px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision pr
  * projector P~ of Eq. 5, H reduced to alpha * V_ACE (Eq. 8, Eq. 14), iterated
  * as the fixed point x = T(x) of Eq. 7 from x^(0) = (Phi_n, sigma_n)):
  *   Phi_mid = (Phi_n + Phi^(k))/2,  sigma_mid = (sigma_n + sigma^(k))/2,
- *   Y = V_ACE Phi_mid,  S = dV Phi_mid^H Phi_mid,  Hm = dV Phi_mid^H Y,
+ *   Y = V_ACE Phi_mid,  S = dV Phi_mid^H Phi_mid,  Hm = dV Phi_mid^H Y
+ *   (Hermitised: Phi^* H Phi is Hermitian, the computed one only to rounding),
  *   Phi^(k+1)   = Phi_n   - i dt_alpha (Y - Phi_mid S^{-1} Hm),
  *   sigma^(k+1) = sigma_n - i dt_alpha (Hm sigma_mid - sigma_mid Hm),
  * for k = 0 .. n_iter-1 (n_iter <= 64), dt_alpha = dt * alpha.  Orbital

@@ -200,11 +200,11 @@ __device__ __forceinline__ void gather_live(cpx<T> (&v)[BPT][R], F&& load) {
 // transformed.  With two slab buffers in LDS (ping-pong, PP) every stage is
 // out of place and the buffers swap roles each pair, so a slab costs three
 // barriers; otherwise the middle stages run in place (two barriers each).
-template <typename T, int N0, int N1, int NT, bool G0, bool PF>
+template <typename T, int N0, int N1, int NT, bool G0, bool PF, bool PP>
 __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs* tasks) {
+  static_assert(!PP || pingpong_fits<T, N0, N1>(), "two slabs do not fit in LDS");
   const ChunkArgs a = chunk_args(a0, tasks);
   if (int(blockIdx.y) >= a.ic) return;
-  constexpr bool PP = pingpong_fits<T, N0, N1>();
   constexpr int P0 = N0 + 1;  // odd row pitch: no bank conflicts on stride-R writes
   constexpr int SL = N1 * P0;
   __shared__ cpx<T> lds[PP ? 2 * SL : SL];
@@ -384,11 +384,12 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
 }
 
 // ============================================================== pass 2
-// Plane tile (y, pair group) of a pass-2 workgroup in a grid of n1 x groups.
-// Workgroups go to the 8 XCDs in turn by linear id; for n1 a multiple of 8,
-// XCD x takes the contiguous planes [x n1/8, (x+1) n1/8), so that the cache
-// lines that neighbouring planes share at the ends of their rows are fetched
-// through one L2 instead of two.  The set of tiles in flight is unchanged.
+// Plane tile (y, pair group) of a pass-2 workgroup in a grid of n1 x groups
+// (with XS x-sections per plane, "y" here is y * XS + section).  Workgroups
+// go to the 8 XCDs in turn by linear id; for n1 a multiple of 8, XCD x takes
+// the contiguous tiles [x n1/8, (x+1) n1/8), so that the cache lines that
+// neighbouring tiles share at the ends of their rows are fetched through one
+// L2 instead of two.  The set of tiles in flight is unchanged.
 __device__ __forceinline__ void plane_tile(int& y, int& g) {
   const int ny = int(gridDim.x);
   if (ny % 8 == 0) {
@@ -402,47 +403,53 @@ __device__ __forceinline__ void plane_tile(int& y, int& g) {
   }
 }
 
-// One workgroup takes the same y-plane of PQ consecutive pairs: the kernel
-// values of the plane are loaded once and, with PF, the next pair's plane is
-// in flight while the current one is transformed.
-template <typename T, int N0, int N1, int N2, int NT, bool G0, bool EX, int PQ, bool PF>
+// One workgroup takes the same tile of a y-plane of PQ consecutive pairs:
+// the kernel values of the tile are loaded once and, with PF, the next pair's
+// tile is in flight while the current one is transformed.  A tile is x-section
+// xs of XS: the NX = N0/XS z-lines x in [xs NX, (xs+1) NX) of the plane (XS > 1
+// gives more, smaller workgroups per CU).  Energy partials go to slot
+// y * XS + xs of the pair (N1 * XS slots per pair).
+template <typename T, int N0, int N1, int N2, int NT, bool G0, bool EX, int PQ, bool PF, int XS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
-    lds_waves_per_simd(N2 * (N0 + 1) * int(sizeof(cpx<T>)) + 1024, NT, pass2_wave_cap<T, N2>()))))
+    lds_waves_per_simd(N2 * (N0 / XS + 1) * int(sizeof(cpx<T>)) + 1024, NT, pass2_wave_cap<T, N2>()))))
 void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
+  static_assert(N0 % XS == 0, "x-sections must divide the plane");
+  constexpr int NX = N0 / XS;
   const ChunkArgs a = chunk_args(a0, tasks);
   // pairs q in [qbeg, qend) of the chunk; pair q owns slot pair_slot(a, q)
   const int np = chunk_pairs(a);
-  int y, grp;
-  plane_tile(y, grp);
+  int yt, grp;
+  plane_tile(yt, grp);
+  const int y = yt / XS, xs = yt % XS, x0 = xs * NX;
   const int qbeg = grp * PQ;
   if (qbeg >= np) return;
   const int qend = qbeg + PQ < np ? qbeg + PQ : np;
-  constexpr int P0 = N0 + 1;
+  constexpr int P0 = NX + 1;
   // energy partials: as the G = 0 sums of pass 1 (EL: per thread in LDS, one
   // wave per sum), else a wave reduction in every wave
   constexpr int NW = NT / 64, NE = G0 ? 2 : 1;
-  constexpr bool EL = EX && NT % 64 == 0 && ex_lds_fits<T, N0, N2, NT, G0>();
+  constexpr bool EL = EX && NT % 64 == 0 && ex_lds_fits<T, NX, N2, NT, G0>();
   __shared__ cpx<T> lds[N2 * P0];
   __shared__ cpx<T> tw2[N2];
   __shared__ double red[EL ? 1 : 2][NW];
   __shared__ double epart[EL ? NE * NT : 1];
-  using GZ = Lines<N2, N0, 1, P0, true>;  // plane [z][x], lines along z
+  using GZ = Lines<N2, NX, 1, P0, true>;  // tile [z][x], lines along z
   constexpr int NS = Plan<N2>::nst;
   using F0 = StageOf<N2, 0, false>;
   using FL = StageOf<N2, NS - 1, false>;
   using I0 = StageOf<N2, 0, true>;
   using IL = StageOf<N2, NS - 1, true>;
   static_assert(I0::R == FL::R, "inverse must start with the forward's last radix");
-  constexpr int NB0 = N0 * (N2 / F0::R), BPT0 = (NB0 + NT - 1) / NT;
-  constexpr int NBL = N0 * (N2 / FL::R), BPTL = (NBL + NT - 1) / NT;
-  constexpr int NBI = N0 * (N2 / IL::R), BPTI = (NBI + NT - 1) / NT;
+  constexpr int NB0 = NX * (N2 / F0::R), BPT0 = (NB0 + NT - 1) / NT;
+  constexpr int NBL = NX * (N2 / FL::R), BPTL = (NBL + NT - 1) / NT;
+  constexpr int NBI = NX * (N2 / IL::R), BPTI = (NBI + NT - 1) / NT;
 
   const size_t slab = size_t(N0) * N1;
-  cpx<T>* const buf0 = reinterpret_cast<cpx<T>*>(a.t) + size_t(y) * N0;
+  cpx<T>* const buf0 = reinterpret_cast<cpx<T>*>(a.t) + size_t(y) * N0 + x0;
   // kernel values: the FP32 copy in the FP32 form (G = 0 comes from kern)
   using KT = typename std::conditional<G0, float, double>::type;
   const KT* kern = (G0 ? reinterpret_cast<const KT*>(a.kern32) : reinterpret_cast<const KT*>(a.kern)) +
-                   size_t(y) * N0;
+                   size_t(y) * N0 + x0;
   const int tid = threadIdx.x;
 
   // global loads first: the first plane (at stage-0 positions) and the kernel
@@ -513,7 +520,7 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
         const int kz = j + r * (N2 / FL::R);
         const double kg = kv[k][r];
         cpx<T> c = v[k][r];
-        if (G0 && y == 0 && line == 0 && kz == 0) {
+        if (G0 && y == 0 && x0 + line == 0 && kz == 0) {
           const double k0 = gld(a.kern);
           // G = 0 from the FP64 slab sums of pass 1
           double s0 = 0.0, s1 = 0.0;
@@ -576,7 +583,7 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
     // sum c is added by wave c mod NW, which reads the partials before it
     // reaches the next barrier; the G = 0 term lives in thread 0
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    double* e = G0 ? a.expart + (size_t(p) * N1 + y) * 3 : a.expart + size_t(p) * N1 + y;
+    double* e = G0 ? a.expart + (size_t(p) * N1 * XS + yt) * 3 : a.expart + size_t(p) * N1 * XS + yt;
 #pragma unroll
     for (int c = 0; c < NE; ++c) {
       if (w == c % NW) {
@@ -598,12 +605,12 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
         if (G0) s3 += red[1][w];
       }
       if constexpr (G0) {
-        double* e = a.expart + (size_t(p) * N1 + y) * 3;
+        double* e = a.expart + (size_t(p) * N1 * XS + yt) * 3;
         gst(e, s2);
         gst(e + 1, s3);
         gst(e + 2, s4);
       } else {
-        gst(a.expart + size_t(p) * N1 + y, s2);
+        gst(a.expart + size_t(p) * N1 * XS + yt, s2);
       }
     }
   }
@@ -639,11 +646,11 @@ template <typename T, int N> constexpr bool psi_prefetch3_for() {
 // PP as in pass 1.
 // SV: symmetric mode, keep N_g v_ij in the pair slab for pass 4 (a compile-time
 // switch, so that the loop has the same stores on every path).
-template <typename T, int N0, int N1, int NT, bool PF, bool SV>
+template <typename T, int N0, int N1, int NT, bool PF, bool SV, bool PP>
 __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const ChunkArgs* tasks) {
+  static_assert(!PP || pingpong_fits<T, N0, N1>(), "two slabs do not fit in LDS");
   const ChunkArgs a = chunk_args(a0, tasks);
   if (int(blockIdx.y) >= a.ic) return;
-  constexpr bool PP = pingpong_fits<T, N0, N1>();
   constexpr int P0 = N0 + 1;
   constexpr int SL = N1 * P0;
   __shared__ cpx<T> lds[PP ? 2 * SL : SL];
@@ -825,6 +832,212 @@ __global__ __launch_bounds__(NT) void pass3_inv_xy_acc(ChunkArgs a0, const Chunk
   }
 }
 
+// ============================================================== pass 3, staged form
+// A workgroup barrier that waits only for this wave's LDS accesses: global ->
+// LDS transfers in flight stay in flight across it.  (The fence of
+// __syncthreads would wait for every outstanding vector memory operation,
+// those transfers included.)  The signal fences keep the compiler from moving
+// memory accesses across it.
+__device__ __forceinline__ void lds_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0); vmcnt and expcnt not waited for
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// A workgroup barrier after all of this wave's memory operations, global ->
+// LDS transfers included (vmcnt(0) lgkmcnt(0)).
+__device__ __forceinline__ void dma_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0070);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Copies BYTES contiguous bytes (a multiple of 16) from global memory into LDS
+// with 16-byte global -> LDS transfers: wave w moves the 1 KiB pieces w,
+// w + NW, ..., lane l bytes [16 l, 16 l + 16) of each (the LDS destination of
+// a transfer is wave-uniform, its lanes fill consecutive 16-byte slots).
+template <int BYTES, int NT>
+__device__ __forceinline__ void dma_to_lds(const void* src, void* dst) {
+  static_assert(BYTES % 16 == 0, "16-byte pieces");
+  constexpr int NW = NT / 64, NCH = (BYTES + 1023) / 1024;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int lane = int(threadIdx.x) & 63;
+  const char PX_GLOBAL* g = (const char PX_GLOBAL*)(src);
+  char __attribute__((address_space(3)))* l = (char __attribute__((address_space(3)))*)(dst);
+#pragma unroll
+  for (int q0 = 0; q0 < NCH; q0 += NW) {
+    const int q = q0 + w;
+    const int off = q * 1024 + lane * 16;
+    // whole pieces for every wave: no branch (the same transfers on every path)
+    if (NCH % NW == 0 && BYTES % 1024 == 0 ? true : (q < NCH && off < BYTES))
+      __builtin_amdgcn_global_load_lds((const void PX_GLOBAL*)(g + off),
+                                       (void __attribute__((address_space(3)))*)(l + q * 1024), 16, 0,
+                                       0);
+  }
+}
+
+// One in-place LDS stage like stage_lds, with lds_sync barriers.
+template <typename T, class G, int R, int NS, bool INV, int NT>
+__device__ __forceinline__ void stage_inplace(cpx<T>* lds, const cpx<T>* tw) {
+  constexpr int NB = G::nl * (G::n / R);
+  constexpr int BPT = (NB + NT - 1) / NT;
+  cpx<T> v[BPT][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int b = tid + k * NT;
+    if (NB % NT == 0 || b < NB) {
+      int line, j;
+      decode<G, R>(b, line, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k][r] = lds[line * G::ls + (j + r * (G::n / R)) * G::es];
+    }
+  }
+  lds_sync();
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int b = tid + k * NT;
+    if (NB % NT == 0 || b < NB) {
+      int line, j;
+      decode<G, R>(b, line, j);
+      twiddle<T, G::n, R, NS, INV>(v[k], j, tw);
+      dft<T, R, INV>(v[k]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[line * G::ls + out_pos<R, NS>(j, r) * G::es] = v[k][r];
+    }
+  }
+  lds_sync();
+}
+
+// Pass 3 with the pair slab staged through LDS (FP32): one working slab A
+// (padded rows, stages in place) and one staging slab S (the pair slab as
+// stored).  While pair jj is transformed, the next pair's slab moves into S by
+// global -> LDS transfers, so neither the registers of a second slab (which at
+// 96^3 would cost the occupancy of the 12-wave workgroup) nor a wait at the
+// start of each pair are needed.  The psi_j slab of the pair is requested at
+// the start of the pair, before the transfer, so that waiting for it never
+// waits for the transfer.  Same arithmetic and results as pass3_inv_xy_acc.
+template <typename T, int N0, int N1, int NT, bool SV>
+__global__ __launch_bounds__(NT) void pass3_staged(ChunkArgs a0, const ChunkArgs* tasks) {
+  const ChunkArgs a = chunk_args(a0, tasks);
+  if (int(blockIdx.y) >= a.ic) return;
+  constexpr int P0 = N0 + 1;
+  constexpr int SL = N1 * P0;
+  constexpr int SLAB_BYTES = N0 * N1 * int(sizeof(cpx<T>));
+  __shared__ cpx<T> lds[SL];
+  __shared__ __attribute__((aligned(16))) cpx<T> sbuf[N0 * N1];
+  __shared__ cpx<T> tw0[N0];
+  __shared__ cpx<T> tw1[N1];
+  using GX = Lines<N0, N1, P0, 1, false>;
+  using GY = Lines<N1, N0, 1, P0, true>;
+  constexpr int NSX = Plan<N0>::nst, NSY = Plan<N1>::nst;
+  static_assert(NSX == 2 && NSY == 2, "staged pass 3 assumes two-stage plans");
+  using X0 = StageOf<N0, 0, true>;
+  using X1 = StageOf<N0, 1, true>;
+  constexpr int RF = StageOf<N1, NSY - 1, false>::R, RR = StageOf<N1, NSY - 1, true>::R;
+  constexpr bool YREV = sizeof(T) == 8 ||
+                        (N0 * (N1 / RR) + NT - 1) / NT <= (N0 * (N1 / RF) + NT - 1) / NT;
+  using Y0 = StageOf<N1, 0, YREV>;
+  using YL = StageOf<N1, NSY - 1, YREV>;
+  constexpr int NB0 = N1 * (N0 / X0::R), BPT0 = (NB0 + NT - 1) / NT;
+  constexpr int NBL = N0 * (N1 / YL::R), BPTL = (NBL + NT - 1) / NT;
+
+  fill_twiddles<T, N0, NT>(tw0);
+  fill_twiddles<T, N1, NT>(tw1);
+  const int z = blockIdx.x, ii = blockIdx.y;
+  const int jend = a.tri ? ii + 1 : a.jc;  // pairs jj < jend of row ii
+  const size_t slab = size_t(N0) * N1;
+  const size_t ng = slab * a.n2;
+  const int tid = threadIdx.x;
+  const cpx<T>* t0 = reinterpret_cast<const cpx<T>*>(a.t) + size_t(ii * a.jc) * ng + z * slab;
+  const cpx<T>* psi0 = reinterpret_cast<const cpx<T>*>(a.psi) + size_t(a.j0) * ng + z * slab;
+  auto pload = [](const cpx<T>* base) {
+    return [base](int line, int e) { return ldc(base + unsigned(line + e * N0)); };
+  };
+  cpx<T>* const outz = reinterpret_cast<cpx<T>*>(a.out) + size_t(a.i0 + ii) * ng + z * slab;
+  cpx<T> acc[BPTL][YL::R];
+#pragma unroll
+  for (int k = 0; k < BPTL; ++k)
+#pragma unroll
+    for (int r = 0; r < YL::R; ++r) acc[k][r] = {T(0), T(0)};
+
+  dma_to_lds<SLAB_BYTES, NT>(t0, sbuf);
+  dma_sync();
+  for (int jj = 0; jj < jend; ++jj) {
+    // the weight is uniform: a scalar load (counted with the LDS operations,
+    // so that waiting for it never waits for the slab transfer)
+    const T wj = T(*(const __attribute__((address_space(4))) double*)(a.occ + a.j0 + jj) * a.inv_ng);
+    cpx<T> pc[BPTL][YL::R];
+    gather<T, GY, YL::R, NT>(pc, pload(psi0 + size_t(jj) * ng));
+    // first inverse x stage: staging slab -> registers -> working slab
+#pragma unroll
+    for (int k = 0; k < BPT0; ++k) {
+      const int b = tid + k * NT;
+      if (NB0 % NT == 0 || b < NB0) {
+        int line, j;
+        decode<GX, X0::R>(b, line, j);
+        cpx<T> v[X0::R];
+#pragma unroll
+        for (int r = 0; r < X0::R; ++r) v[r] = sbuf[line * N0 + j + r * (N0 / X0::R)];
+        dft<T, X0::R, true>(v);
+#pragma unroll
+        for (int r = 0; r < X0::R; ++r) lds[line * P0 + out_pos<X0::R, 1>(j, r)] = v[r];
+      }
+    }
+    lds_sync();  // the staging slab has been read by every thread
+    // the next pair's slab (the last pair moves its own slab again: the same
+    // transfers on every pair, so that the compiler's wait for the psi_j slab
+    // counts them and does not wait for them)
+    dma_to_lds<SLAB_BYTES, NT>(t0 + size_t(jj + 1 < jend ? jj + 1 : jj) * ng, sbuf);
+    stage_inplace<T, GX, X1::R, X1::NS, true, NT>(lds, tw0);
+    stage_inplace<T, GY, Y0::R, Y0::NS, true, NT>(lds, tw1);
+    // last stage: registers, psi_j-weighted accumulation, kept v_ij (SV)
+    cpx<T>* tv = reinterpret_cast<cpx<T>*>(a.t) + size_t(ii * a.jc + jj) * ng + z * slab;
+#pragma unroll
+    for (int k = 0; k < BPTL; ++k) {
+      int b = tid + k * NT;
+      if (NBL % NT != 0) b = b < NBL ? b : NBL - 1;
+      int line, j;
+      decode<GY, YL::R>(b, line, j);
+      cpx<T> v[YL::R];
+#pragma unroll
+      for (int r = 0; r < YL::R; ++r) v[r] = lds[line + (j + r * (N1 / YL::R)) * P0];
+      twiddle<T, N1, YL::R, YL::NS, true>(v, j, tw1);
+      dft<T, YL::R, true>(v);
+#pragma unroll
+      for (int r = 0; r < YL::R; ++r) {
+        cpx<T> t = cmul(pc[k][r], v[r]);
+        acc[k][r].x += wj * t.x;
+        acc[k][r].y += wj * t.y;
+      }
+      if constexpr (SV) {
+#pragma unroll
+        for (int r = 0; r < YL::R; ++r) stn(tv + unsigned(line + (j + r * (N1 / YL::R)) * N0), v[r]);
+      }
+    }
+    // the next pair's slab has arrived and the working slab is free
+    dma_sync();
+  }
+  // one read-modify-write of the output slab, all loads issued before the
+  // first store
+  cpx<T> po[BPTL][YL::R];
+  if (!a.first) gather<T, GY, YL::R, NT>(po, pload(outz));
+#pragma unroll
+  for (int k = 0; k < BPTL; ++k) {
+    const int b = tid + k * NT;
+    if (NBL % NT == 0 || b < NBL) {
+      int line, j;
+      decode<GY, YL::R>(b, line, j);
+#pragma unroll
+      for (int r = 0; r < YL::R; ++r) {
+        const cpx<T> prev = a.first ? cpx<T>{T(0), T(0)} : po[k][r];
+        stg(outz + unsigned(line + (j + r * (N1 / YL::R)) * N0), csub(prev, acc[k][r]));
+      }
+    }
+  }
+}
+
 // ============================================================== host launcher
 // Threads per workgroup: close to the butterfly count of each stage of a slab
 // (N * N / R), so that most stages take one butterfly per thread.
@@ -832,21 +1045,80 @@ template <int N> constexpr int threads_for() {
   return N == 16 ? 64 : N == 24 ? 192 : N == 32 ? 256 : N == 40 ? 320 : N == 48 ? 384
        : N == 60 ? 640 : N == 64 ? 512 : N == 72 ? 704 : N == 80 ? 832 : 768;
 }
-// Prefetch across pair iterations where the doubled register set fits
-// without spilling (checked with the compiler's resource report).
+// Per-pass configuration of passes 1 and 3: threads per workgroup, the
+// ping-pong form (two LDS slabs, one barrier per stage) or one slab updated in
+// place, and prefetch across pair iterations where the doubled register set
+// fits without spilling (checked with the compiler's resource report).  The
+// defaults were chosen by measurement; a build may override them for one grid
+// size, PX_P13_N, to time alternatives (PX_P1_NT32, PX_P1_PP32, PX_P1_PF32,
+// PX_P3_NT32, PX_P3_PP32, PX_P3_PF32 and the same with 64 for FP64).
+#if defined(PX_P13_N)
+#define PX_OVR(M32, M64)                                    \
+  if (sizeof(T) == 4 && N == PX_P13_N) return M32;          \
+  if (sizeof(T) == 8 && N == PX_P13_N) return M64;
+#endif
+template <typename T, int N> constexpr int pass1_threads() {
+#if defined(PX_P13_N) && defined(PX_P1_NT32) && defined(PX_P1_NT64)
+  PX_OVR(PX_P1_NT32, PX_P1_NT64)
+#endif
+  return threads_for<N>();
+}
+template <typename T, int N> constexpr int pass3_threads() {
+#if defined(PX_P13_N) && defined(PX_P3_NT32) && defined(PX_P3_NT64)
+  PX_OVR(PX_P3_NT32, PX_P3_NT64)
+#endif
+  return threads_for<N>();
+}
+template <typename T, int N> constexpr bool pass1_pingpong() {
+#if defined(PX_P13_N) && defined(PX_P1_PP32) && defined(PX_P1_PP64)
+  PX_OVR(bool(PX_P1_PP32), bool(PX_P1_PP64))
+#endif
+  return pingpong_fits<T, N, N>();
+}
+template <typename T, int N> constexpr bool pass3_pingpong() {
+#if defined(PX_P13_N) && defined(PX_P3_PP32) && defined(PX_P3_PP64)
+  PX_OVR(bool(PX_P3_PP32), bool(PX_P3_PP64))
+#endif
+  return pingpong_fits<T, N, N>();
+}
 template <typename T, int N> constexpr bool prefetch1_for() {
+#if defined(PX_P13_N) && defined(PX_P1_PF32) && defined(PX_P1_PF64)
+  PX_OVR(bool(PX_P1_PF32), bool(PX_P1_PF64))
+#endif
   return sizeof(T) == 4 ? true : (N <= 72 && N != 60);  // FP32 at 96^3: -21 % with it
 }
+// Pass 3 in the staged form (pass3_staged) instead of pass3_inv_xy_acc: FP32
+// at 96^3, where the 12-wave workgroup has no registers for a second slab
+// (3.52 -> 3.14 ms per 1,024-pair launch, same box).
+template <typename T, int N> constexpr bool pass3_staged_for() {
+#if defined(PX_P13_N) && defined(PX_P3_STG32)
+  if (sizeof(T) == 4 && N == PX_P13_N) return bool(PX_P3_STG32);
+#endif
+  return sizeof(T) == 4 && N == 96;
+}
 template <typename T, int N> constexpr bool prefetch3_for() {
+#if defined(PX_P13_N) && defined(PX_P3_PF32) && defined(PX_P3_PF64)
+  PX_OVR(bool(PX_P3_PF32), bool(PX_P3_PF64))
+#endif
   return sizeof(T) == 4 ? N <= 72 : N <= 48;
 }
 
 // Threads of a pass-2 workgroup.  FP32 at 72^3: 512 (two butterflies per
-// thread in each stage) lets three workgroups share a CU instead of two; at
-// 96^3: 384 (two or three per thread), two workgroups of 6 waves instead of
-// one of 12 (measured on the same box).
+// thread in each stage) lets three workgroups share a CU instead of two.  At
+// 96^3 (two x-sections per plane, see pass2_sections): 192 in both forms
+// (2-3 butterflies per thread; FP32 four workgroups per CU; measured against
+// 128-384 threads and one to four sections on the same box).
+template <typename T, int N> constexpr int pass2_threads_default() {
+  return N == 96 ? 192 : sizeof(T) == 4 && N == 72 ? 512 : threads_for<N>();
+}
 template <typename T, int N> constexpr int pass2_threads_for() {
-  return sizeof(T) == 4 && N == 72 ? 512 : sizeof(T) == 4 && N == 96 ? 384 : threads_for<N>();
+#if defined(PX_P2_N) && defined(PX_P2_NT32)
+  if (sizeof(T) == 4 && N == PX_P2_N) return PX_P2_NT32;
+#endif
+#if defined(PX_P2_N) && defined(PX_P2_NT64)
+  if (sizeof(T) == 8 && N == PX_P2_N) return PX_P2_NT64;
+#endif
+  return pass2_threads_default<T, N>();
 }
 
 // Pairs per pass-2 workgroup, with prefetch of the next plane: FP64 at 72^3,
@@ -866,38 +1138,50 @@ template <int N>
 hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, bool store_v,
                           hipStream_t s, hipEvent_t* ev, const ChunkArgs* tasks, int ntasks,
                           int max_ic) {
-  constexpr int NT = threads_for<N>();
   if (!tasks) {
     ntasks = 1;
     max_ic = a.ic;
   }
   constexpr int Q32 = pass2_pairs_per_wg<float, N>(), Q64 = pass2_pairs_per_wg<double, N>();
+  constexpr int X32 = pass2_sections(true, N), X64 = pass2_sections(false, N);
   const int pq = fp32 ? Q32 : Q64;
-  dim3 g1(N, max_ic, ntasks), g2(N, (npairs + pq - 1) / pq, ntasks), g3(N, max_ic, ntasks);
+  dim3 g1(N, max_ic, ntasks), g2(N * (fp32 ? X32 : X64), (npairs + pq - 1) / pq, ntasks),
+      g3(N, max_ic, ntasks);
   if (ev) (void)hipEventRecord(ev[0], s);
+  constexpr int NT1F = pass1_threads<float, N>(), NT1D = pass1_threads<double, N>();
   if (fp32)
-    hipLaunchKernelGGL((pass1_fwd_xy<float, N, N, NT, true, prefetch1_for<float, N>()>), g1, dim3(NT), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass1_fwd_xy<float, N, N, NT1F, true, prefetch1_for<float, N>(), pass1_pingpong<float, N>()>),
+                       g1, dim3(NT1F), 0, s, a, tasks);
   else
-    hipLaunchKernelGGL((pass1_fwd_xy<double, N, N, NT, false, prefetch1_for<double, N>()>), g1, dim3(NT), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass1_fwd_xy<double, N, N, NT1D, false, prefetch1_for<double, N>(), pass1_pingpong<double, N>()>),
+                       g1, dim3(NT1D), 0, s, a, tasks);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (fp32) {
     constexpr int NT2 = pass2_threads_for<float, N>();
-    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT2, true, true, Q32, (Q32 > 1)>), g2, dim3(NT2), 0, s, a, tasks);
-    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT2, true, false, Q32, (Q32 > 1)>), g2, dim3(NT2), 0, s, a, tasks);
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT2, true, true, Q32, (Q32 > 1), X32>), g2, dim3(NT2), 0, s, a, tasks);
+    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT2, true, false, Q32, (Q32 > 1), X32>), g2, dim3(NT2), 0, s, a, tasks);
   } else {
-    if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, true, Q64, (Q64 > 1)>), g2, dim3(NT), 0, s, a, tasks);
-    else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT, false, false, Q64, (Q64 > 1)>), g2, dim3(NT), 0, s, a, tasks);
+    constexpr int NT2 = pass2_threads_for<double, N>();
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT2, false, true, Q64, (Q64 > 1), X64>), g2, dim3(NT2), 0, s, a, tasks);
+    else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT2, false, false, Q64, (Q64 > 1), X64>), g2, dim3(NT2), 0, s, a, tasks);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
   constexpr bool P32 = prefetch3_for<float, N>(), P64 = prefetch3_for<double, N>();
-  if (fp32 && store_v)
-    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT, P32, true>), g3, dim3(NT), 0, s, a, tasks);
+  constexpr bool Q3F = pass3_pingpong<float, N>(), Q3D = pass3_pingpong<double, N>();
+  constexpr int NT3F = pass3_threads<float, N>(), NT3D = pass3_threads<double, N>();
+  constexpr bool S3F = pass3_staged_for<float, N>();
+  if (fp32 && S3F && store_v)
+    hipLaunchKernelGGL((pass3_staged<float, N, N, NT3F, true>), g3, dim3(NT3F), 0, s, a, tasks);
+  else if (fp32 && S3F)
+    hipLaunchKernelGGL((pass3_staged<float, N, N, NT3F, false>), g3, dim3(NT3F), 0, s, a, tasks);
+  else if (fp32 && store_v)
+    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT3F, P32, true, Q3F>), g3, dim3(NT3F), 0, s, a, tasks);
   else if (fp32)
-    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT, P32, false>), g3, dim3(NT), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N, N, NT3F, P32, false, Q3F>), g3, dim3(NT3F), 0, s, a, tasks);
   else if (store_v)
-    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT, P64, true>), g3, dim3(NT), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT3D, P64, true, Q3D>), g3, dim3(NT3D), 0, s, a, tasks);
   else
-    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT, P64, false>), g3, dim3(NT), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N, N, NT3D, P64, false, Q3D>), g3, dim3(NT3D), 0, s, a, tasks);
   if (ev) (void)hipEventRecord(ev[3], s);
   return hipGetLastError();
 }

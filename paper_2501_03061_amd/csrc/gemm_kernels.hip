@@ -74,13 +74,27 @@ constexpr int XC_KU = 4;       // k-steps of 4 per group in xc (16 a)
 // 32x32 sub-block (w&1, w>>1) as 2x2 MFMA tiles.  Occupancy target of two
 // waves per SIMD: the three accumulator sets fit in 256 registers without
 // spills, where the default allocation (FP64) left one wave per SIMD.
+// tri > 0 (a Hermitian result, na = nb): only the tiles (ta, tb) with ta <= tb
+// of the tri x tri tile grid are computed, blockIdx.x enumerating them row by
+// row; the reduction mirrors the others.
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_xhy_k(int na, int nb, size_t ng, const cpx<T>* X,
-                                                  const cpx<T>* Y, double* part, size_t kchunk) {
+                                                  const cpx<T>* Y, double* part, size_t kchunk,
+                                                  int tri) {
   using A = typename Acc<T>::t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int a_base = blockIdx.x * 64 + (w & 1) * 32;
-  const int b_base = blockIdx.y * 64 + (w >> 1) * 32;
+  int ta = blockIdx.x, tb = blockIdx.y;
+  if (tri > 0) {  // wave-uniform decode of the upper-triangle tile index
+    int k = blockIdx.x;
+    ta = 0;
+    while (k >= tri - ta) {
+      k -= tri - ta;
+      ++ta;
+    }
+    tb = ta + k;
+  }
+  const int a_base = ta * 64 + (w & 1) * 32;
+  const int b_base = tb * 64 + (w >> 1) * 32;
   const size_t r_begin = size_t(blockIdx.z) * kchunk;
   const size_t r_end = (r_begin + kchunk < ng) ? r_begin + kchunk : ng;
   const int q = lane >> 4, m = lane & 15;
@@ -220,16 +234,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 }
 
 __global__ void xhy_reduce_k(int na, int nb, const double* part, int nsplit, double scale,
-                             double* M, int ldm, float* M32) {
+                             double* M, int ldm, float* M32, int herm) {
   const size_t n = size_t(na) * nb;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
        e += size_t(gridDim.x) * blockDim.x) {
+    const size_t a = e / nb, b = e % nb;
+    // a Hermitian result keeps only the tiles on and above the diagonal:
+    // entries below it are the conjugates of their mirror images
+    const bool mirror = herm && (a / 64) > (b / 64);
+    const size_t src = mirror ? b * nb + a : e;
     double re = 0.0, im = 0.0;
     for (int s = 0; s < nsplit; ++s) {
-      re += part[(size_t(s) * n + e) * 2];
-      im += part[(size_t(s) * n + e) * 2 + 1];
+      re += part[(size_t(s) * n + src) * 2];
+      im += part[(size_t(s) * n + src) * 2 + 1];
     }
-    const size_t a = e / nb, b = e % nb;
+    if (mirror) im = -im;
     M[(a * ldm + b) * 2] = scale * re;
     M[(a * ldm + b) * 2 + 1] = scale * im;
     if (M32) {  // the same, rounded to FP32 (operand of an FP32 contraction)
@@ -265,26 +284,40 @@ int gemm_xhy_splits(int na, int nb, size_t ng, int max_split) {
   return nsplit;
 }
 
-hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, const void* Y,
-                           double scale, double* M, int ldm, double* part, int nsplit_avail,
-                           float* M32, hipStream_t s) {
+static hipError_t xhy_launch(bool fp32, int na, int nb, size_t ng, const void* X, const void* Y,
+                             double scale, double* M, int ldm, double* part, int nsplit_avail,
+                             float* M32, bool herm, hipStream_t s) {
   int nsplit;
   const size_t kchunk = xhy_kchunk(na, nb, ng, nsplit_avail, &nsplit);
-  if (nsplit > nsplit_avail) return hipErrorInvalidValue;
-  dim3 grid((na + 63) / 64, (nb + 63) / 64, nsplit);
+  if (nsplit > nsplit_avail || (herm && na != nb)) return hipErrorInvalidValue;
+  const int ta = (na + 63) / 64, tb = (nb + 63) / 64;
+  const int tri = herm ? ta : 0;
+  dim3 grid(herm ? ta * (ta + 1) / 2 : ta, herm ? 1 : tb, nsplit);
   if (fp32)
     hipLaunchKernelGGL(gemm_xhy_k<float>, grid, dim3(256), 0, s, na, nb, ng,
                        static_cast<const cpx<float>*>(X), static_cast<const cpx<float>*>(Y), part,
-                       kchunk);
+                       kchunk, tri);
   else
     hipLaunchKernelGGL(gemm_xhy_k<double>, grid, dim3(256), 0, s, na, nb, ng,
                        static_cast<const cpx<double>*>(X), static_cast<const cpx<double>*>(Y),
-                       part, kchunk);
+                       part, kchunk, tri);
   const size_t n = size_t(na) * nb;
   const int blocks = int((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
   hipLaunchKernelGGL(xhy_reduce_k, dim3(blocks), dim3(256), 0, s, na, nb, part, nsplit, scale, M,
-                     ldm, M32);
+                     ldm, M32, int(herm));
   return hipGetLastError();
+}
+
+hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, const void* Y,
+                           double scale, double* M, int ldm, double* part, int nsplit_avail,
+                           float* M32, hipStream_t s) {
+  return xhy_launch(fp32, na, nb, ng, X, Y, scale, M, ldm, part, nsplit_avail, M32, false, s);
+}
+
+hipError_t launch_gemm_xhy_herm(bool fp32, int n, size_t ng, const void* X, const void* Y,
+                                double scale, double* M, double* part, int nsplit_avail,
+                                hipStream_t s) {
+  return xhy_launch(fp32, n, n, ng, X, Y, scale, M, n, part, nsplit_avail, nullptr, true, s);
 }
 
 // ---------------------------------------------------------------- xc

@@ -133,7 +133,8 @@ ExLayout ex_layout(const px_cell* cell, px_precision prec, int n_psi, int n_phi,
   l.expart = off;
   l.S = off;
   if (energy) {
-    off = align_up(off + pairs * cell->n[1] * 8 * (prec == PX_PREC_FP32 ? 3 : 1));
+    const size_t slots = size_t(cell->n[1]) * px::pass2_sections(prec == PX_PREC_FP32, cell->n[0]);
+    off = align_up(off + pairs * slots * 8 * (prec == PX_PREC_FP32 ? 3 : 1));
     l.S = off;
     off = align_up(off + size_t(n_phi) * n_psi * 8);
   }
@@ -406,7 +407,8 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       }
       ++nchunks;
       if (energy) {
-        st = hip_check(c, px::launch_expart_reduce(a.expart, fp32 ? a.g0 : nullptr, cell->n[1],
+        st = hip_check(c, px::launch_expart_reduce(a.expart, fp32 ? a.g0 : nullptr,
+                                                   cell->n[1] * px::pass2_sections(fp32, cell->n[0]),
                                                    cell->n[2], double(ng), i0, a.ic, j0, a.jc, S,
                                                    n_psi, a.store_v != 0, a.tri != 0, s),
                        "energy partials");
@@ -645,8 +647,8 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   px::gemm_xhy_part_elems(n, n, ng, &nsplit);
   if (ctx->profiling) (void)hipEventRecord(ev[1], stream);
   // M = dV Psi^H W, Hermitised; -M = L L^H; U = L^{-H}; xi = W U
-  st = hip_check(ctx, px::launch_gemm_xhy(fp32, n, n, ng, psi, W, dV, Mw, n, part, nsplit, nullptr,
-                                          stream),
+  // M is Hermitian up to rounding: the tiles above the diagonal are mirrored
+  st = hip_check(ctx, px::launch_gemm_xhy_herm(fp32, n, ng, psi, W, dV, Mw, part, nsplit, stream),
                  "M = dV Psi^H W");
   if (st != PX_OK) return st;
   if (ctx->profiling) (void)hipEventRecord(ev[2], stream);
@@ -973,6 +975,10 @@ px_status px_ptim_step(px_context* ctx, const px_cell* cell, px_precision prec, 
                                      nullptr, stream), "S = dV mid^H mid")) != PX_OK) return st;
     if ((st = ok(px::launch_gemm_xhy(fp32, n_phi, n_phi, ng, mid, w + l.Y, dV, D(l.Hm), n_phi, D(l.part2),
                                      ns2, nullptr, stream), "Hm = dV mid^H Y")) != PX_OK) return st;
+    // Phi^* H Phi is Hermitian (V_ACE is): Hermitise the computed one (its defect is
+    // the contractions' rounding, 1e-7 relative in the FP32 form), so that the
+    // commutator keeps sigma Hermitian to FP64 rounding
+    if ((st = ok(px::launch_hermitize(D(l.Hm), n_phi, stream), "hermitize Hm")) != PX_OK) return st;
     // X = S^{-1} Hm in FP64: S = L L^H (the Cholesky of -(-S)), U = L^{-H}, X = U (U^H Hm)
     if ((st = ok(px::launch_scale(size_t(2) * n_phi * n_phi, D(l.S), -1.0, D(l.Mneg), stream), "-S")) != PX_OK)
       return st;
@@ -1105,7 +1111,8 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
     const size_t ng = size_t(nsz) * nsz * nsz;
     const size_t cap = std::max(min_pairs, c->batch_cap_bytes / (ng * b));
     t_bytes = std::max(t_bytes, cap * ng * b);
-    side_pairs = std::max(side_pairs, cap * size_t(nsz));
+    // per pair: n2 slab sums (g0) and n1 * XS energy-partial slots
+    side_pairs = std::max(side_pairs, cap * size_t(nsz) * px::pass2_sections(fp32, nsz));
     for (int d = 0; d < max_nb; ++d) {
       std::vector<Chunk> diag;
       for (int k = 0; k < n_inst; ++k) {
@@ -1206,7 +1213,8 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         const int k = int(reinterpret_cast<size_t>(a.S));
         a.t = ws + P.t_off + pofs * ng * b;
         a.g0 = reinterpret_cast<px::G0Part*>(ws + P.g0_off + pofs * w.n * sizeof(px::G0Part));
-        a.expart = reinterpret_cast<double*>(ws + P.ex_off + pofs * w.n * 8 * (fp32 ? 3 : 1));
+        a.expart = reinterpret_cast<double*>(ws + P.ex_off + pofs * w.n * px::pass2_sections(fp32, w.n) *
+                                             8 * (fp32 ? 3 : 1));
         a.S = reinterpret_cast<double*>(ws + P.S_off[k]);
         a.out = ace ? static_cast<void*>(ws + P.W_off[k]) : in[k].out;
         if (fp32) a.kern32 = reinterpret_cast<const float*>(ws + P.K32_off[k]);
@@ -1267,8 +1275,9 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
                      "batched transposed accumulation");
       if (st != PX_OK) return st;
     }
-    st = hip_check(c, px::launch_expart_reduce_tasks(fp32, dt + w.first, w.count, w.max_pairs, w.n,
-                                                     w.n, double(ng), s),
+    st = hip_check(c, px::launch_expart_reduce_tasks(fp32, dt + w.first, w.count, w.max_pairs,
+                                                     w.n * px::pass2_sections(fp32, w.n), w.n,
+                                                     double(ng), s),
                    "batched energy partials");
     if (st != PX_OK) return st;
   }
@@ -1289,9 +1298,9 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
     double* Mw = x.M ? x.M : reinterpret_cast<double*>(ws + P.M_off);
     int nsplit = 0;
     px::gemm_xhy_part_elems(x.n, x.n, ng, &nsplit);
-    st = hip_check(c, px::launch_gemm_xhy(fp32, x.n, x.n, ng, x.psi, W, dV, Mw, x.n,
-                                          reinterpret_cast<double*>(ws + P.part_off), nsplit,
-                                          nullptr, s),
+    st = hip_check(c, px::launch_gemm_xhy_herm(fp32, x.n, ng, x.psi, W, dV, Mw,
+                                               reinterpret_cast<double*>(ws + P.part_off), nsplit,
+                                               s),
                    "batched M");
     if (st != PX_OK) return st;
     st = hip_check(c, px::launch_hermitize(Mw, x.n, s), "batched hermitize");

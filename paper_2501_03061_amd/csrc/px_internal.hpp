@@ -97,6 +97,25 @@ __device__ __forceinline__ ChunkArgs chunk_args(const ChunkArgs& a0, const Chunk
 #endif
 
 bool grid_supported(int n0, int n1, int n2);
+
+// x-sections per y-plane tile of pass 2 (the z transforms, kernel multiply and
+// the exchange-energy partials): a pass-2 workgroup takes N0/XS of the plane's
+// N0 z-lines, and a pair has N1 * XS energy-partial slots.  Chosen per grid
+// size and form by measurement: at 96^3 two sections of 48 lines (37 KB of LDS
+// in FP32, four workgroups of 192 threads per CU instead of two of 384) take
+// pass 2 from 3.67 to 2.62 ms per 1,024-pair launch in FP32 and from 5.47 to
+// 5.11 ms in FP64; at 72^3 sections were slower in both forms.  The build may
+// override the choice for one size (PX_P2_N with PX_P2_XS32 / PX_P2_XS64).
+constexpr int pass2_sections(bool fp32, int n) {
+#if defined(PX_P2_N) && defined(PX_P2_XS32)
+  if (fp32 && n == PX_P2_N) return PX_P2_XS32;
+#endif
+#if defined(PX_P2_N) && defined(PX_P2_XS64)
+  if (!fp32 && n == PX_P2_N) return PX_P2_XS64;
+#endif
+  (void)fp32;
+  return n == 96 ? 2 : 1;
+}
 // Launches pass 1, 2, 3 of one chunk; ev (nullable) = 4 events recorded
 // before pass 1, between the passes and after pass 3.
 hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
@@ -164,6 +183,14 @@ hipError_t launch_eig_hermitian(const double* sigma, int n, double* Q, double* d
 hipError_t launch_gemm_xhy(bool fp32, int na, int nb, size_t ng, const void* X, const void* Y,
                            double scale, double* M, int ldm, double* part, int nsplit,
                            float* M32, hipStream_t s);
+// The same for a result known to be Hermitian (n x n, ldm = n, e.g. M = dV
+// Psi^H W of the ACE construction): only the 64 x 64 tiles on and above the
+// diagonal are contracted (about half the flops); each tile below the diagonal
+// is the conjugate transpose of its mirror.  The diagonal tiles are computed in
+// full, so they keep their (rounding-level) non-Hermitian part.
+hipError_t launch_gemm_xhy_herm(bool fp32, int n, size_t ng, const void* X, const void* Y,
+                                double scale, double* M, double* part, int nsplit,
+                                hipStream_t s);
 size_t gemm_xhy_part_elems(int na, int nb, size_t ng, int* nsplit);
 // Splits launch_gemm_xhy uses when at most max_split are available (fewer,
 // longer splits than the default when max_split is below it).

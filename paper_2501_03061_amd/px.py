@@ -99,6 +99,9 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libpx.so not found at {path}: run __graft_entry__.build() "
                           "(or python -m paper_2501_03061_amd.csrc.build) first")
+    # PyTorch brings its own HIP runtime; load it before libpx so that both use
+    # the same one (a second runtime loaded first does not see the GPU)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
