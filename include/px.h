@@ -120,7 +120,8 @@ px_status px_set_workspace(px_context* ctx, void* dev_ptr, size_t bytes);
 
 /* Pair-chunk tuning: a chunk is ic output orbitals x jc density orbitals whose
  * pair slabs are in flight together (Sec. III-B(b) batches 16 pairs on its
- * GPU).  0 restores the default.  Changes px_workspace_bytes. */
+ * GPU).  0 restores the default.  Changes px_workspace_bytes.  The pass-2
+ * configuration that px_autotune chose for the grid is kept. */
 px_status px_set_tuning(px_context* ctx, const px_cell* cell, px_precision prec, int32_t ic,
                         int32_t jc);
 
@@ -354,10 +355,14 @@ px_status px_set_batch_capacity(px_context* ctx, size_t pair_buffer_bytes);
 px_status px_set_graph(px_context* ctx, int32_t enable);
 
 /* Autotuner: times the Hermitian-pair pipeline on this instance (Phi = Psi)
- * for square pair blocks B in {8, 16, 24, 32, 48, 64} that fit the attached
- * workspace, keeps the fastest as the context's tuning for this grid and
- * precision, writes it to *best_block (nullable) and appends a JSON line to
- * cache_path (nullable).  Synchronises `stream`; `out` receives Vx psi. */
+ * for square pair blocks B in {16, 24, 32, 48, 64, 96, 128} (up to the first
+ * B >= n) that fit the attached workspace, each with both compiled
+ * configurations of pass 2 (the z transforms: its workgroup shape, x-sections
+ * per plane and threads, fixed per grid size at compile time), keeps the
+ * fastest pair as the context's tuning for this grid and precision, writes B
+ * to *best_block (nullable) and appends a JSON line (block, "p2"
+ * configuration, per-candidate times) to cache_path (nullable).
+ * Synchronises `stream`; `out` receives Vx psi. */
 px_status px_autotune(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
                       const void* psi, const double* occ, const double* kernel_G, void* out,
                       const char* cache_path, int32_t* best_block, hipStream_t stream);

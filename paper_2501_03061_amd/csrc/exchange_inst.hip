@@ -7,6 +7,6 @@
 #endif
 
 namespace px {
-template hipError_t launch_chunk_n<PX_N>(bool, const ChunkArgs&, int, bool, bool, hipStream_t,
+template hipError_t launch_chunk_n<PX_N>(bool, const ChunkArgs&, int, bool, bool, int, hipStream_t,
                                          hipEvent_t*, const ChunkArgs*, int, int);
 }

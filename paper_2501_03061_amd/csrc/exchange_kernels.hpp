@@ -1121,6 +1121,20 @@ template <typename T, int N> constexpr int pass2_threads_for() {
   return pass2_threads_default<T, N>();
 }
 
+// Threads of pass-2 configuration CFG (see pass2_sections_cfg): the default,
+// or for the alternative with two sections half the default (a multiple of
+// 64), with one section the single-section counts.
+template <typename T, int N, int CFG> constexpr int pass2_threads_cfg() {
+  if constexpr (CFG == 0) {
+    return pass2_threads_for<T, N>();
+  } else if constexpr (pass2_sections_cfg(sizeof(T) == 4, N, 1) == 2) {
+    constexpr int t = (pass2_threads_for<T, N>() / 2 + 63) / 64 * 64;
+    return t < 64 ? 64 : t;
+  } else {
+    return sizeof(T) == 4 && N == 72 ? 512 : sizeof(T) == 4 && N == 96 ? 384 : threads_for<N>();
+  }
+}
+
 // Pairs per pass-2 workgroup, with prefetch of the next plane: FP64 at 72^3,
 // where the plane's LDS already limits a CU to one workgroup and the loop
 // fits the registers.  Elsewhere two workgroups per CU overlap better than one
@@ -1134,19 +1148,34 @@ template <typename T, int N> constexpr int pass2_pairs_per_wg() {
 // blockIdx.z (max_ic / max_pairs: the largest chunk of the table).  The FP32
 // form always takes the G = 0 coefficient from FP64 slab sums.
 // ev (optional, 4 events) brackets the passes: ev[0] | pass 1 | ev[1] | pass 2 | ev[2] | pass 3 | ev[3].
+// Pass 2 of one chunk or task table in configuration CFG.
+template <int N, int CFG>
+void launch_pass2(bool fp32, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
+                  const ChunkArgs* tasks, int ntasks) {
+  constexpr int Q32 = pass2_pairs_per_wg<float, N>(), Q64 = pass2_pairs_per_wg<double, N>();
+  constexpr int X32 = pass2_sections_cfg(true, N, CFG), X64 = pass2_sections_cfg(false, N, CFG);
+  const int pq = fp32 ? Q32 : Q64;
+  const dim3 g2(N * (fp32 ? X32 : X64), (npairs + pq - 1) / pq, ntasks);
+  if (fp32) {
+    constexpr int NT2 = pass2_threads_cfg<float, N, CFG>();
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT2, true, true, Q32, (Q32 > 1), X32>), g2, dim3(NT2), 0, s, a, tasks);
+    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT2, true, false, Q32, (Q32 > 1), X32>), g2, dim3(NT2), 0, s, a, tasks);
+  } else {
+    constexpr int NT2 = pass2_threads_cfg<double, N, CFG>();
+    if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT2, false, true, Q64, (Q64 > 1), X64>), g2, dim3(NT2), 0, s, a, tasks);
+    else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT2, false, false, Q64, (Q64 > 1), X64>), g2, dim3(NT2), 0, s, a, tasks);
+  }
+}
+
 template <int N>
 hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, bool store_v,
-                          hipStream_t s, hipEvent_t* ev, const ChunkArgs* tasks, int ntasks,
-                          int max_ic) {
+                          int p2cfg, hipStream_t s, hipEvent_t* ev, const ChunkArgs* tasks,
+                          int ntasks, int max_ic) {
   if (!tasks) {
     ntasks = 1;
     max_ic = a.ic;
   }
-  constexpr int Q32 = pass2_pairs_per_wg<float, N>(), Q64 = pass2_pairs_per_wg<double, N>();
-  constexpr int X32 = pass2_sections(true, N), X64 = pass2_sections(false, N);
-  const int pq = fp32 ? Q32 : Q64;
-  dim3 g1(N, max_ic, ntasks), g2(N * (fp32 ? X32 : X64), (npairs + pq - 1) / pq, ntasks),
-      g3(N, max_ic, ntasks);
+  dim3 g1(N, max_ic, ntasks), g3(N, max_ic, ntasks);
   if (ev) (void)hipEventRecord(ev[0], s);
   constexpr int NT1F = pass1_threads<float, N>(), NT1D = pass1_threads<double, N>();
   if (fp32)
@@ -1156,15 +1185,8 @@ hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, bo
     hipLaunchKernelGGL((pass1_fwd_xy<double, N, N, NT1D, false, prefetch1_for<double, N>(), pass1_pingpong<double, N>()>),
                        g1, dim3(NT1D), 0, s, a, tasks);
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (fp32) {
-    constexpr int NT2 = pass2_threads_for<float, N>();
-    if (ex) hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT2, true, true, Q32, (Q32 > 1), X32>), g2, dim3(NT2), 0, s, a, tasks);
-    else hipLaunchKernelGGL((pass2_z_kernel<float, N, N, N, NT2, true, false, Q32, (Q32 > 1), X32>), g2, dim3(NT2), 0, s, a, tasks);
-  } else {
-    constexpr int NT2 = pass2_threads_for<double, N>();
-    if (ex) hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT2, false, true, Q64, (Q64 > 1), X64>), g2, dim3(NT2), 0, s, a, tasks);
-    else hipLaunchKernelGGL((pass2_z_kernel<double, N, N, N, NT2, false, false, Q64, (Q64 > 1), X64>), g2, dim3(NT2), 0, s, a, tasks);
-  }
+  if (p2cfg == 0) launch_pass2<N, 0>(fp32, a, npairs, ex, s, tasks, ntasks);
+  else launch_pass2<N, 1>(fp32, a, npairs, ex, s, tasks, ntasks);
   if (ev) (void)hipEventRecord(ev[2], s);
   constexpr bool P32 = prefetch3_for<float, N>(), P64 = prefetch3_for<double, N>();
   constexpr bool Q3F = pass3_pingpong<float, N>(), Q3D = pass3_pingpong<double, N>();

@@ -28,7 +28,8 @@ struct px_context {
   // or no convergence of the occupation-matrix diagonalisation)
   std::vector<std::pair<int32_t*, px_status>> last_status;
   int latched = PX_OK;
-  std::map<std::tuple<int, int, int, int>, std::pair<int, int>> tuning;  // (n0,n1,n2,prec) -> (ic, jc)
+  // (n0,n1,n2,prec) -> pair chunk ic x jc and the pass-2 configuration (0, 1)
+  std::map<std::tuple<int, int, int, int>, std::tuple<int, int, int>> tuning;
   // measurement mode: HIP events around each pass of each chunk
   bool profiling = false;
   std::vector<hipEvent_t> events;
@@ -105,13 +106,16 @@ void default_tuning(const px_cell* cell, px_precision prec, int* ic, int* jc) {
   *jc = 16;
 }
 
-void tuning_for(const px_context* c, const px_cell* cell, px_precision prec, int* ic, int* jc) {
+void tuning_for(const px_context* c, const px_cell* cell, px_precision prec, int* ic, int* jc,
+                int* p2 = nullptr) {
   auto it = c->tuning.find({cell->n[0], cell->n[1], cell->n[2], int(prec)});
   if (it != c->tuning.end()) {
-    *ic = it->second.first;
-    *jc = it->second.second;
+    *ic = std::get<0>(it->second);
+    *jc = std::get<1>(it->second);
+    if (p2) *p2 = std::get<2>(it->second);
   } else {
     default_tuning(cell, prec, ic, jc);
+    if (p2) *p2 = 0;
   }
 }
 
@@ -121,7 +125,7 @@ struct ExLayout {
 };
 
 ExLayout ex_layout(const px_cell* cell, px_precision prec, int n_psi, int n_phi, int ic, int jc,
-                   bool energy) {
+                   bool energy, int p2 = 0) {
   ExLayout l{};
   const int icc = ic < n_phi ? ic : n_phi, jcc = jc < n_psi ? jc : n_psi;
   const size_t pairs = size_t(icc) * jcc;
@@ -133,7 +137,7 @@ ExLayout ex_layout(const px_cell* cell, px_precision prec, int n_psi, int n_phi,
   l.expart = off;
   l.S = off;
   if (energy) {
-    const size_t slots = size_t(cell->n[1]) * px::pass2_sections(prec == PX_PREC_FP32, cell->n[0]);
+    const size_t slots = size_t(cell->n[1]) * px::pass2_sections_cfg(prec == PX_PREC_FP32, cell->n[0], p2);
     off = align_up(off + pairs * slots * 8 * (prec == PX_PREC_FP32 ? 3 : 1));
     l.S = off;
     off = align_up(off + size_t(n_phi) * n_psi * 8);
@@ -150,10 +154,10 @@ struct AceLayout {
 };
 
 AceLayout ace_layout(const px_cell* cell, px_precision prec, int n, int ic, int jc,
-                     bool symmetric) {
+                     bool symmetric, int p2 = 0) {
   AceLayout a{};
   if (symmetric) ic = jc = (ic > jc ? ic : jc);
-  a.ex = ex_layout(cell, prec, n, n, ic, jc, true);
+  a.ex = ex_layout(cell, prec, n, n, ic, jc, true, p2);
   size_t off = a.ex.end;
   a.W = off;
   off = align_up(off + size_t(n) * ngrid(cell) * elem_bytes(prec));
@@ -330,7 +334,7 @@ px_status need_ws(px_context* c, size_t bytes) {
 px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, int n_psi,
                        const void* psi, const double* occ, int n_phi, const void* phi,
                        const double* kern, void* out, const ExLayout& l, bool energy, int ic,
-                       int jc, bool symmetric, hipStream_t s) {
+                       int jc, bool symmetric, hipStream_t s, int p2 = 0) {
   const bool fp32 = prec == PX_PREC_FP32;
   const size_t ng = ngrid(cell);
   px::ChunkArgs a{};
@@ -379,7 +383,7 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       const int npairs = px::chunk_pairs(a);
       hipEvent_t* ev = c->profiling ? &c->events[5 * nchunks] : nullptr;
       px_status st = hip_check(
-          c, px::launch_chunk(fp32, cell->n[0], a, npairs, energy, s, ev), "pair pipeline");
+          c, px::launch_chunk(fp32, cell->n[0], a, npairs, energy, p2, s, ev), "pair pipeline");
       if (st != PX_OK) return st;
       if (a.store_v) {
         st = hip_check(c, px::launch_pass4(fp32, a, ng, s), "transposed accumulation");
@@ -408,7 +412,7 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       ++nchunks;
       if (energy) {
         st = hip_check(c, px::launch_expart_reduce(a.expart, fp32 ? a.g0 : nullptr,
-                                                   cell->n[1] * px::pass2_sections(fp32, cell->n[0]),
+                                                   cell->n[1] * px::pass2_sections_cfg(fp32, cell->n[0], p2),
                                                    cell->n[2], double(ng), i0, a.ic, j0, a.jc, S,
                                                    n_psi, a.store_v != 0, a.tri != 0, s),
                        "energy partials");
@@ -475,14 +479,14 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
   const bool gemm_grid = prec == PX_PREC_FP64 || ngrid(cell) % 2 == 0;
   const bool fft_op = op == PX_OP_EXCHANGE || op == PX_OP_ACE_BUILD || op == PX_OP_EXCHANGE_SIGMA;
   if (fft_op ? !fft_grid : !gemm_grid) return 0;
-  int ic, jc;
-  tuning_for(ctx, cell, prec, &ic, &jc);
+  int ic, jc, p2;
+  tuning_for(ctx, cell, prec, &ic, &jc, &p2);
   switch (op) {
     case PX_OP_EXCHANGE:
       if (n_phi <= 0) return 0;
-      return ex_layout(cell, prec, n_psi, n_phi, ic, jc, true).end;
+      return ex_layout(cell, prec, n_psi, n_phi, ic, jc, true, p2).end;
     case PX_OP_ACE_BUILD:
-      return ace_layout(cell, prec, n_psi, ic, jc, ctx->symmetric_ace).end;
+      return ace_layout(cell, prec, n_psi, ic, jc, ctx->symmetric_ace, p2).end;
     case PX_OP_ACE_APPLY:
       if (n_phi <= 0) return 0;
       return apply_layout(cell, n_psi, n_phi).end;
@@ -491,7 +495,7 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
       return loop_layout(cell, prec, n_psi, n_phi).end;
     case PX_OP_EXCHANGE_SIGMA: {
       if (n_phi <= 0) return 0;
-      const ExLayout ex = ex_layout(cell, prec, n_psi, n_phi, ic, jc, false);
+      const ExLayout ex = ex_layout(cell, prec, n_psi, n_phi, ic, jc, false, p2);
       return sigma_layout(ex.end, cell, prec, n_psi, false).end;
     }
     case PX_OP_SIGMA_DIAG:
@@ -520,8 +524,10 @@ px_status px_set_tuning(px_context* ctx, const px_cell* cell, px_precision prec,
   if (!cell_ok(cell) || ic < 0 || jc < 0 || ic > 4096 || jc > 4096)
     return fail(ctx, PX_ERR_INVALID_ARG, "tuning: need a valid cell and 0 <= ic, jc <= 4096");
   auto key = std::make_tuple(cell->n[0], cell->n[1], cell->n[2], int(prec));
+  auto it = ctx->tuning.find(key);
+  const int p2 = it != ctx->tuning.end() ? std::get<2>(it->second) : 0;  // kept from px_autotune
   if (ic == 0 || jc == 0) ctx->tuning.erase(key);
-  else ctx->tuning[key] = {ic, jc};
+  else ctx->tuning[key] = {ic, jc, p2};
   return PX_OK;
 }
 
@@ -574,15 +580,15 @@ px_status px_exchange_apply(px_context* ctx, const px_cell* cell, px_precision p
     return fail(ctx, PX_ERR_INVALID_ARG, "exchange_apply: orbital blocks must be 16-byte aligned");
   if (e_x && (phi != psi || n_phi != n_psi))
     return fail(ctx, PX_ERR_INVALID_ARG, "exchange_apply: e_x requires phi == psi and n_phi == n_psi");
-  int ic, jc;
-  tuning_for(ctx, cell, prec, &ic, &jc);
-  const ExLayout l = ex_layout(cell, prec, n_psi, n_phi, ic, jc, e_x != nullptr);
+  int ic, jc, p2;
+  tuning_for(ctx, cell, prec, &ic, &jc, &p2);
+  const ExLayout l = ex_layout(cell, prec, n_psi, n_phi, ic, jc, e_x != nullptr, p2);
   st = need_ws(ctx, l.end);
   if (st != PX_OK) return st;
   hipError_t he = hipSetDevice(ctx->device);
   if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
   st = run_exchange(ctx, cell, prec, n_psi, psi, occ, n_phi, phi, kernel_G, vx_phi, l,
-                    e_x != nullptr, ic, jc, false, stream);
+                    e_x != nullptr, ic, jc, false, stream, p2);
   if (st != PX_OK) return st;
   if (e_x) {
     const double ng = double(ngrid(cell));
@@ -609,9 +615,9 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   if (xi == psi) return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: xi must not alias psi");
   if (misaligned(psi) || misaligned(xi))
     return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: orbital blocks must be 16-byte aligned");
-  int ic, jc;
-  tuning_for(ctx, cell, prec, &ic, &jc);
-  const AceLayout l = ace_layout(cell, prec, n, ic, jc, ctx->symmetric_ace);
+  int ic, jc, p2;
+  tuning_for(ctx, cell, prec, &ic, &jc, &p2);
+  const AceLayout l = ace_layout(cell, prec, n, ic, jc, ctx->symmetric_ace, p2);
   st = need_ws(ctx, l.end);
   if (st != PX_OK) return st;
   hipError_t he = hipSetDevice(ctx->device);
@@ -634,7 +640,7 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   double* part = reinterpret_cast<double*>(ctx->ws + l.part);
   // W = Vx Psi (pair pipeline) and the energy sums
   st = run_exchange(ctx, cell, prec, n, psi, occ, n, psi, kernel_G, W, l.ex, true, ic, jc,
-                    ctx->symmetric_ace, stream);
+                    ctx->symmetric_ace, stream, p2);
   if (st != PX_OK) return st;
   if (e_x) {
     st = hip_check(ctx,
@@ -853,9 +859,9 @@ px_status px_exchange_apply_sigma(px_context* ctx, const px_cell* cell, px_preci
   if (misaligned(phi_basis) || misaligned(tgt) || misaligned(vx_tgt) || misaligned(sigma))
     return fail(ctx, PX_ERR_INVALID_ARG,
                 "exchange_apply_sigma: orbital blocks and sigma must be 16-byte aligned");
-  int ic, jc;
-  tuning_for(ctx, cell, prec, &ic, &jc);
-  const ExLayout ex = ex_layout(cell, prec, n, n_tgt, ic, jc, false);
+  int ic, jc, p2;
+  tuning_for(ctx, cell, prec, &ic, &jc, &p2);
+  const ExLayout ex = ex_layout(cell, prec, n, n_tgt, ic, jc, false, p2);
   const SigmaLayout sl = sigma_layout(ex.end, cell, prec, n, false);
   st = need_ws(ctx, sl.end);
   if (st != PX_OK) return st;
@@ -865,7 +871,7 @@ px_status px_exchange_apply_sigma(px_context* ctx, const px_cell* cell, px_preci
   if (st != PX_OK) return st;
   // Eq. 13 on (phi, d): the double loop over the rotated orbitals
   st = run_exchange(ctx, cell, prec, n, ctx->ws + sl.phi, reinterpret_cast<double*>(ctx->ws + sl.d),
-                    n_tgt, tgt, kernel_G, vx_tgt, ex, false, ic, jc, false, stream);
+                    n_tgt, tgt, kernel_G, vx_tgt, ex, false, ic, jc, false, stream, p2);
   if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED});
   return st;
 }
@@ -1055,6 +1061,7 @@ namespace {
 
 struct BatchWave {
   int n;            // cubic grid size of the wave's instances
+  int p2;           // pass-2 configuration of that size
   int first, count; // tasks [first, first + count)
   int max_ic, max_jc, max_pairs;
   bool any_v;       // its tasks keep v_ij for pass 4 (a wave holds one block diagonal, so
@@ -1073,6 +1080,11 @@ int block_for(const px_context* c, const px_cell* cell, px_precision prec) {
   int ic, jc;
   tuning_for(c, cell, prec, &ic, &jc);
   return ic > jc ? ic : jc;
+}
+int pass2_cfg_for(const px_context* c, const px_cell* cell, px_precision prec) {
+  int ic, jc, p2;
+  tuning_for(c, cell, prec, &ic, &jc, &p2);
+  return p2;
 }
 
 // Plan of one batched call.  Instances are grouped by grid size; within a
@@ -1112,7 +1124,10 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
     const size_t cap = std::max(min_pairs, c->batch_cap_bytes / (ng * b));
     t_bytes = std::max(t_bytes, cap * ng * b);
     // per pair: n2 slab sums (g0) and n1 * XS energy-partial slots
-    side_pairs = std::max(side_pairs, cap * size_t(nsz) * px::pass2_sections(fp32, nsz));
+    int p2 = 0;  // the tuning of the size (every instance of a size shares it)
+    for (int k = 0; k < n_inst; ++k)
+      if (in[k].cell.n[0] == nsz) p2 = pass2_cfg_for(c, &in[k].cell, prec);
+    side_pairs = std::max(side_pairs, cap * size_t(nsz) * px::pass2_sections_cfg(fp32, nsz, p2));
     for (int d = 0; d < max_nb; ++d) {
       std::vector<Chunk> diag;
       for (int k = 0; k < n_inst; ++k) {
@@ -1127,7 +1142,7 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         const int icc = std::min(ch.B, n - ch.I * ch.B), jcc = std::min(ch.B, n - ch.J * ch.B);
         const size_t pairs = size_t(icc) * jcc;
         if (used + pairs > cap) {
-          P.waves.push_back({nsz, int(P.tasks.size()), 0, 0, 0, 0, false});
+          P.waves.push_back({nsz, p2, int(P.tasks.size()), 0, 0, 0, 0, false});
           used = 0;
         }
         BatchWave& w = P.waves.back();
@@ -1213,8 +1228,9 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         const int k = int(reinterpret_cast<size_t>(a.S));
         a.t = ws + P.t_off + pofs * ng * b;
         a.g0 = reinterpret_cast<px::G0Part*>(ws + P.g0_off + pofs * w.n * sizeof(px::G0Part));
-        a.expart = reinterpret_cast<double*>(ws + P.ex_off + pofs * w.n * px::pass2_sections(fp32, w.n) *
-                                             8 * (fp32 ? 3 : 1));
+        a.expart = reinterpret_cast<double*>(ws + P.ex_off + pofs * w.n *
+                                             px::pass2_sections_cfg(fp32, w.n, w.p2) * 8 *
+                                             (fp32 ? 3 : 1));
         a.S = reinterpret_cast<double*>(ws + P.S_off[k]);
         a.out = ace ? static_cast<void*>(ws + P.W_off[k]) : in[k].out;
         if (fp32) a.kern32 = reinterpret_cast<const float*>(ws + P.K32_off[k]);
@@ -1267,7 +1283,7 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
   for (const BatchWave& w : P.waves) {
     const size_t ng = size_t(w.n) * w.n * w.n;
     st = hip_check(c, px::launch_chunk_tasks(fp32, w.n, dt + w.first, w.count, w.max_ic,
-                                             w.max_pairs, true, w.any_v, s),
+                                             w.max_pairs, true, w.any_v, w.p2, s),
                    "batched pair pipeline");
     if (st != PX_OK) return st;
     if (w.any_v) {
@@ -1276,7 +1292,7 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
       if (st != PX_OK) return st;
     }
     st = hip_check(c, px::launch_expart_reduce_tasks(fp32, dt + w.first, w.count, w.max_pairs,
-                                                     w.n * px::pass2_sections(fp32, w.n), w.n,
+                                                     w.n * px::pass2_sections_cfg(fp32, w.n, w.p2), w.n,
                                                      double(ng), s),
                    "batched energy partials");
     if (st != PX_OK) return st;
@@ -1342,8 +1358,9 @@ std::vector<unsigned char> batch_key(const px_context* c, int n_inst, const px_i
   put(&c->batch_cap_bytes, sizeof c->batch_cap_bytes);
   for (int k = 0; k < n_inst; ++k) {
     put(&in[k], sizeof(px_instance));
-    const int B = block_for(c, &in[k].cell, prec);
+    const int B = block_for(c, &in[k].cell, prec), p2 = pass2_cfg_for(c, &in[k].cell, prec);
     put(&B, sizeof B);
+    put(&p2, sizeof p2);
   }
   return key;
 }
@@ -1455,44 +1472,53 @@ px_status px_autotune(px_context* ctx, const px_cell* cell, px_precision prec, i
                 "autotune: need n > 0 and valid, non-aliased, 16-byte aligned arrays");
   hipError_t he = hipSetDevice(ctx->device);
   if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
-  const int cand[] = {8, 16, 24, 32, 48, 64};
+  // square pair blocks B (the Hermitian-pair mode's chunks are B x B) and the
+  // two compiled pass-2 configurations; candidates whose pair buffer does not
+  // fit the attached workspace are skipped
+  const int cand[] = {16, 24, 32, 48, 64, 96, 128};
   const auto key = std::make_tuple(cell->n[0], cell->n[1], cell->n[2], int(prec));
-  const auto saved = ctx->tuning.count(key) ? ctx->tuning[key] : std::make_pair(0, 0);
   const bool had = ctx->tuning.count(key) != 0;
+  const auto saved = had ? ctx->tuning[key] : std::make_tuple(0, 0, 0);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(ctx, PX_ERR_DEVICE, "hipEventCreate failed");
   double best = 1e300;
-  int bestB = 0;
+  int bestB = 0, bestP2 = 0;
   std::string trials;
+  bool covered = false;  // a candidate B >= n has been timed (larger ones are the same chunking)
   for (int B : cand) {
-    if (B > n && B != cand[0]) break;
-    const ExLayout l = ex_layout(cell, prec, n, n, B, B, false);
-    if (ctx->ws == nullptr || ctx->ws_bytes < l.end) continue;
-    float ms = 0.f, best_ms = 1e30f;
-    for (int rep = 0; rep < 3; ++rep) {
-      (void)hipEventRecord(e0, stream);
-      st = run_exchange(ctx, cell, prec, n, psi, occ, n, psi, kernel_G, out, l, false, B, B, true,
-                        stream);
-      (void)hipEventRecord(e1, stream);
-      if (st != PX_OK) break;
-      he = hipEventSynchronize(e1);
-      if (he != hipSuccess) {
-        st = hip_check(ctx, he, "autotune sync");
-        break;
+    if (covered) break;
+    covered = B >= n;
+    for (int p2 = 0; p2 < 2 && st == PX_OK; ++p2) {
+      const ExLayout l = ex_layout(cell, prec, n, n, B, B, false, p2);
+      if (ctx->ws == nullptr || ctx->ws_bytes < l.end) continue;
+      float ms = 0.f, best_ms = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        (void)hipEventRecord(e0, stream);
+        st = run_exchange(ctx, cell, prec, n, psi, occ, n, psi, kernel_G, out, l, false, B, B, true,
+                          stream, p2);
+        (void)hipEventRecord(e1, stream);
+        if (st != PX_OK) break;
+        he = hipEventSynchronize(e1);
+        if (he != hipSuccess) {
+          st = hip_check(ctx, he, "autotune sync");
+          break;
+        }
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) best_ms = std::min(best_ms, ms);  // first run warms up
       }
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (rep > 0) best_ms = std::min(best_ms, ms);  // first run warms up
+      if (st != PX_OK) break;
+      const double us_pair = 1e3 * best_ms / (double(n) * n);
+      char buf[64];
+      snprintf(buf, sizeof buf, "%s\"%d/%d\": %.4f", trials.empty() ? "" : ", ", B, p2, us_pair);
+      trials += buf;
+      if (us_pair < best) {
+        best = us_pair;
+        bestB = B;
+        bestP2 = p2;
+      }
     }
     if (st != PX_OK) break;
-    const double us_pair = 1e3 * best_ms / (double(n) * n);
-    char buf[64];
-    snprintf(buf, sizeof buf, "%s\"%d\": %.4f", trials.empty() ? "" : ", ", B, us_pair);
-    trials += buf;
-    if (us_pair < best) {
-      best = us_pair;
-      bestB = B;
-    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1501,16 +1527,16 @@ px_status px_autotune(px_context* ctx, const px_cell* cell, px_precision prec, i
     if (had) ctx->tuning[key] = saved;
     return fail(ctx, PX_ERR_WORKSPACE, "autotune: workspace too small for every candidate block");
   }
-  ctx->tuning[key] = {bestB, bestB};
+  ctx->tuning[key] = {bestB, bestB, bestP2};
   if (best_block) *best_block = bestB;
   if (cache_path && cache_path[0]) {
     FILE* f = fopen(cache_path, "a");
     if (!f) return fail(ctx, PX_ERR_INVALID_ARG, "autotune: cannot open %s", cache_path);
     fprintf(f,
             "{\"arch\": \"gfx950\", \"n\": [%d, %d, %d], \"prec\": \"%s\", \"n_orb\": %d, "
-            "\"block\": %d, \"us_per_pair\": %.4f, \"trials_us_per_pair\": {%s}}\n",
+            "\"block\": %d, \"p2\": %d, \"us_per_pair\": %.4f, \"trials_us_per_pair\": {%s}}\n",
             cell->n[0], cell->n[1], cell->n[2], prec == PX_PREC_FP32 ? "fp32" : "fp64", n, bestB,
-            best, trials.c_str());
+            bestP2, best, trials.c_str());
     fclose(f);
   }
   return PX_OK;
@@ -1535,7 +1561,10 @@ px_status px_load_tuning(px_context* ctx, const char* cache_path, int32_t* appli
     if (sscanf(pp, "\"prec\": \"%4[a-z0-9]\"", prec) != 1) continue;
     if (sscanf(pb, "\"block\": %d", &blk) != 1 || blk <= 0 || blk > 4096) continue;
     const int pr = strcmp(prec, "fp32") == 0 ? int(PX_PREC_FP32) : int(PX_PREC_FP64);
-    ctx->tuning[std::make_tuple(n0, n1, n2, pr)] = {blk, blk};
+    int p2 = 0;  // pass-2 configuration (absent in older lines: the default)
+    const char* pq = strstr(line, "\"p2\": ");
+    if (pq && (sscanf(pq, "\"p2\": %d", &p2) != 1 || p2 < 0 || p2 > 1)) p2 = 0;
+    ctx->tuning[std::make_tuple(n0, n1, n2, pr)] = {blk, blk, p2};
     ++count;
   }
   fclose(f);

@@ -116,16 +116,21 @@ constexpr int pass2_sections(bool fp32, int n) {
   (void)fp32;
   return n == 96 ? 2 : 1;
 }
+// Pass-2 configuration cfg: 0 the measured default, 1 the alternative that the
+// autotuner times as well (one section where the default has two, else two).
+constexpr int pass2_sections_cfg(bool fp32, int n, int cfg) {
+  return cfg == 0 ? pass2_sections(fp32, n) : (pass2_sections(fp32, n) == 1 ? 2 : 1);
+}
 // Launches pass 1, 2, 3 of one chunk; ev (nullable) = 4 events recorded
 // before pass 1, between the passes and after pass 3.
-hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool ex, hipStream_t s,
-                        hipEvent_t* ev);
+hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool ex, int p2cfg,
+                        hipStream_t s, hipEvent_t* ev);
 
 // The same passes over a task table in device memory (ntasks chunks of one
 // grid size, all with ic <= max_ic and ic*jc <= max_pairs, and all with the
 // given store_v), one launch each.
 hipError_t launch_chunk_tasks(bool fp32, int n, const ChunkArgs* tasks, int ntasks, int max_ic,
-                              int max_pairs, bool ex, bool store_v, hipStream_t s);
+                              int max_pairs, bool ex, bool store_v, int p2cfg, hipStream_t s);
 // Pass 4 over a task table (tasks without kept v_ij are skipped).
 hipError_t launch_pass4_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_jc, size_t ng,
                               hipStream_t s);

@@ -212,6 +212,19 @@ def test_load_tuning_cache(lib, ctx, tmp_path):
     tuned = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c), 1, 512, 512)
     assert tuned < base                       # 8 x 8 pair block instead of the default
     assert lib.px_load_tuning(ctx, b"/nonexistent/file", None) == px.PX_ERR_INVALID_ARG
+    # the pass-2 configuration of a line: at 96^3 the default has two x-sections per
+    # plane (twice the energy-partial slots of configuration 1)
+    c96 = _cell(96, 27.0)
+    path.write_text('{"n": [96, 96, 96], "prec": "fp32", "block": 32, "p2": 0}\n')
+    assert lib.px_load_tuning(ctx, str(path).encode(), None) == px.PX_OK
+    w0 = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c96), 1, 64, 64)
+    path.write_text('{"n": [96, 96, 96], "prec": "fp32", "block": 32, "p2": 1}\n')
+    assert lib.px_load_tuning(ctx, str(path).encode(), None) == px.PX_OK
+    w1 = lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c96), 1, 64, 64)
+    assert w1 < w0
+    # px_set_tuning keeps the configuration
+    assert lib.px_set_tuning(ctx, ctypes.byref(c96), 1, 32, 32) == px.PX_OK
+    assert lib.px_workspace_bytes(ctx, px.PX_OP_EXCHANGE, ctypes.byref(c96), 1, 64, 64) == w1
 
 
 def test_sigma_and_density_validation(lib, ctx):

@@ -219,12 +219,15 @@ def test_exchange_single_orbital_and_zero_occupation(px_ctx):
 
 @pytest.mark.parametrize("n", [16, 24, 32, 40, 48, 60, 64, 72, 80, 96])
 @pytest.mark.parametrize("fp32", [False, True])
-def test_exchange_energy_sizes_ragged_chunks(px_ctx, n, fp32):
-    """E_x (Phi = Psi) on every compiled grid with ragged pair chunks.  The
-    slab sums of pass 1 and the energy partials of pass 2 are added per wave
-    or staged through LDS depending on each size's LDS budget; both paths
+@pytest.mark.parametrize("p2", [0, 1])
+def test_exchange_energy_sizes_ragged_chunks(px_ctx, n, fp32, p2, tmp_path):
+    """E_x (Phi = Psi) on every compiled grid with ragged pair chunks, in both
+    compiled pass-2 configurations (p2 = 1 is the alternative the autotuner
+    times: x-sections per plane where the default has none, and the reverse).
+    The slab sums of pass 1 and the energy partials of pass 2 are added per
+    wave or staged through LDS depending on each size's LDS budget; all paths
     against the oracle's energy, band-limited orbitals, fractional f."""
-    banner(f"exchange energy n={n} fp32={fp32}")
+    banner(f"exchange energy n={n} fp32={fp32} p2={p2}")
     inst = inputs.make_instance(n, 0.28 * n, 7, 0.05, seed=300 + n)
     cell = _cell(inst)
     K = oracle.kernel_hse(inst.n, inst.L, 0.106)
@@ -232,12 +235,15 @@ def test_exchange_energy_sizes_ragged_chunks(px_ctx, n, fp32):
     vx = oracle.exchange_apply(inst.psi, inst.occ, inst.psi, K)
     ex = oracle.exchange_energy_real(inst.psi, inst.occ, vx, dv)
     prec = px.PX_PREC_FP32 if fp32 else px.PX_PREC_FP64
-    px_ctx.set_tuning(cell, prec, 3, 3)      # chunks of 3, 3, 1 orbitals in both directions
+    # chunks of 3, 3, 1 orbitals in both directions, in pass-2 configuration p2
+    tune = tmp_path / "tune.jsonl"
+    tune.write_text(f'{{"n": [{n}, {n}, {n}], "prec": "{"fp32" if fp32 else "fp64"}", "block": 3, "p2": {p2}}}\n')
+    assert px_ctx.px_load_tuning(str(tune)) == 1
     try:
         out, e = _run(px_ctx, cell, inst.psi, inst.occ, inst.psi, to_dev(K), fp32=fp32, energy=True)
     finally:
         px_ctx.set_tuning(cell, prec, 0, 0)
     err, eerr = relerr(out, vx), abs(e - ex) / abs(ex)
-    print(f"n={n} fp32={fp32}: Vx err {err:.3e}, E_x err {eerr:.3e} (E_x = {ex:.10f})")
+    print(f"n={n} fp32={fp32} p2={p2}: Vx err {err:.3e}, E_x err {eerr:.3e} (E_x = {ex:.10f})")
     assert err < (FP32_TOL if fp32 else FP64_TOL)
     assert eerr < (FP32_EX_TOL if fp32 else FP64_TOL)
