@@ -1088,13 +1088,15 @@ template <typename T, int N> constexpr bool prefetch1_for() {
   return sizeof(T) == 4 ? true : (N <= 72 && N != 60);  // FP32 at 96^3: -21 % with it
 }
 // Pass 3 in the staged form (pass3_staged) instead of pass3_inv_xy_acc: FP32
-// at 96^3, where the 12-wave workgroup has no registers for a second slab
-// (3.52 -> 3.14 ms per 1,024-pair launch, same box).
+// at 72^3 to 96^3 (per 1,024-pair launch, same box: 96^3 3.52 -> 3.14 ms,
+// where the 12-wave workgroup has no registers for a second slab; 80^3 2.11 ->
+// 1.78 ms; 72^3 1.51 -> 1.36 ms).  Pass 4 then runs 4-9 % slower, so at 64^3
+// and below, where pass 3 gained nothing, the register form stays.
 template <typename T, int N> constexpr bool pass3_staged_for() {
 #if defined(PX_P13_N) && defined(PX_P3_STG32)
   if (sizeof(T) == 4 && N == PX_P13_N) return bool(PX_P3_STG32);
 #endif
-  return sizeof(T) == 4 && N == 96;
+  return sizeof(T) == 4 && (N == 72 || N == 80 || N == 96);
 }
 template <typename T, int N> constexpr bool prefetch3_for() {
 #if defined(PX_P13_N) && defined(PX_P3_PF32) && defined(PX_P3_PF64)
@@ -1104,12 +1106,17 @@ template <typename T, int N> constexpr bool prefetch3_for() {
 }
 
 // Threads of a pass-2 workgroup.  FP32 at 72^3: 512 (two butterflies per
-// thread in each stage) lets three workgroups share a CU instead of two.  At
-// 96^3 (two x-sections per plane, see pass2_sections): 192 in both forms
+// thread in each stage) lets three workgroups share a CU instead of two.  With
+// two x-sections per plane (see pass2_sections): 192 at 96^3 in both forms
 // (2-3 butterflies per thread; FP32 four workgroups per CU; measured against
-// 128-384 threads and one to four sections on the same box).
+// 128-384 threads and one to four sections on the same box), FP32 256 at
+// 64^3 and 320 at 80^3 (half the single-section counts).
 template <typename T, int N> constexpr int pass2_threads_default() {
-  return N == 96 ? 192 : sizeof(T) == 4 && N == 72 ? 512 : threads_for<N>();
+  return N == 96 ? 192
+       : sizeof(T) == 4 && N == 72 ? 512
+       : sizeof(T) == 4 && N == 64 ? 256
+       : sizeof(T) == 4 && N == 80 ? 320
+       : threads_for<N>();
 }
 template <typename T, int N> constexpr int pass2_threads_for() {
 #if defined(PX_P2_N) && defined(PX_P2_NT32)

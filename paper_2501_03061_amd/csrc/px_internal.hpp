@@ -101,11 +101,13 @@ bool grid_supported(int n0, int n1, int n2);
 // x-sections per y-plane tile of pass 2 (the z transforms, kernel multiply and
 // the exchange-energy partials): a pass-2 workgroup takes N0/XS of the plane's
 // N0 z-lines, and a pair has N1 * XS energy-partial slots.  Chosen per grid
-// size and form by measurement: at 96^3 two sections of 48 lines (37 KB of LDS
-// in FP32, four workgroups of 192 threads per CU instead of two of 384) take
-// pass 2 from 3.67 to 2.62 ms per 1,024-pair launch in FP32 and from 5.47 to
-// 5.11 ms in FP64; at 72^3 sections were slower in both forms.  The build may
-// override the choice for one size (PX_P2_N with PX_P2_XS32 / PX_P2_XS64).
+// size and form by measurement (per 1,024-pair launch, same box): at 96^3 two
+// sections of 48 lines (37 KB of LDS in FP32, four workgroups of 192 threads
+// per CU instead of two of 384) take FP32 pass 2 from 3.67 to 2.62 ms and FP64
+// from 5.47 to 5.11 ms; FP32 at 80^3 2.13 -> 1.74 ms, at 64^3 0.76 -> 0.68 ms;
+// at 48^3 and 72^3, and FP64 below 96^3, sections were slower or no faster.
+// The build may override the choice for one size (PX_P2_N with PX_P2_XS32 /
+// PX_P2_XS64).
 constexpr int pass2_sections(bool fp32, int n) {
 #if defined(PX_P2_N) && defined(PX_P2_XS32)
   if (fp32 && n == PX_P2_N) return PX_P2_XS32;
@@ -113,8 +115,7 @@ constexpr int pass2_sections(bool fp32, int n) {
 #if defined(PX_P2_N) && defined(PX_P2_XS64)
   if (!fp32 && n == PX_P2_N) return PX_P2_XS64;
 #endif
-  (void)fp32;
-  return n == 96 ? 2 : 1;
+  return n == 96 || (fp32 && (n == 64 || n == 80)) ? 2 : 1;
 }
 // Pass-2 configuration cfg: 0 the measured default, 1 the alternative that the
 // autotuner times as well (one section where the default has two, else two).
