@@ -857,6 +857,11 @@ __device__ __forceinline__ void dma_sync() {
 // with 16-byte global -> LDS transfers: wave w moves the 1 KiB pieces w,
 // w + NW, ..., lane l bytes [16 l, 16 l + 16) of each (the LDS destination of
 // a transfer is wave-uniform, its lanes fill consecutive 16-byte slots).
+// Cache-policy bits of the slab transfers (a build may set PX_DMA_AUX to time
+// alternatives).
+#ifndef PX_DMA_AUX
+#define PX_DMA_AUX 0
+#endif
 template <int BYTES, int NT>
 __device__ __forceinline__ void dma_to_lds(const void* src, void* dst) {
   static_assert(BYTES % 16 == 0, "16-byte pieces");
@@ -873,7 +878,7 @@ __device__ __forceinline__ void dma_to_lds(const void* src, void* dst) {
     if (NCH % NW == 0 && BYTES % 1024 == 0 ? true : (q < NCH && off < BYTES))
       __builtin_amdgcn_global_load_lds((const void PX_GLOBAL*)(g + off),
                                        (void __attribute__((address_space(3)))*)(l + q * 1024), 16, 0,
-                                       0);
+                                       PX_DMA_AUX);
   }
 }
 

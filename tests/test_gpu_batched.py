@@ -131,7 +131,7 @@ def test_autotune_and_cache(px_ctx, tmp_path):
     lines = open(path).read().strip().splitlines()
     assert len(lines) == 1 and f'"block": {best}' in lines[0]
     assert '"p2": 0' in lines[0] or '"p2": 1' in lines[0]
-    assert '"40/1"' in lines[0]        # both pass-2 configurations were timed, up to B >= n
+    assert '"48/1"' in lines[0]        # both pass-2 configurations, blocks up to the first B >= n
     # results with the tuned block equal the untuned ones to FP32 tolerance
     tuned = to_host(px_ctx.px_exchange_apply(d["cell"], d["psi"], d["occ"], d["psi"], d["kern"]))
     px_ctx.set_tuning(d["cell"], px.PX_PREC_FP32, 0, 0)
