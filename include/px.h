@@ -340,11 +340,17 @@ size_t px_workspace_bytes_batched(const px_context* ctx, int32_t n_inst, const p
  * must be real and even, K(G) = K(-G); square blocks from the tuning) are
  * grouped by grid size and scheduled by block diagonal, so each pass runs as
  * one launch over a task table for many chunks of many instances; then the
- * per-instance energies and, with ace != 0, the ACE construction.  The whole
- * call is captured once into a HIP graph and replayed while the instance
- * descriptors, the workspace and the tuning stay the same (rebuilding it
- * synchronises `stream` once).  Results equal those of per-instance
- * px_exchange_apply / px_ace_build calls up to summation order. */
+ * per-instance energies and, with ace != 0, the ACE construction.  In ACE
+ * mode the instances whose last chunk ran in one wave form a group whose
+ * tail (Gram matrices, one factorisation launch sequence for the whole
+ * group, xi) runs on one of two side streams of the context while `stream`
+ * goes on with the next waves; `stream` waits for both before the call's
+ * work ends.  The whole call is captured once into a HIP graph and replayed
+ * while the instance descriptors, the workspace and the tuning stay the same
+ * (rebuilding it synchronises `stream` once).  Results equal those of
+ * per-instance px_exchange_apply / px_ace_build calls up to summation order.
+ * Calls on one context must not overlap (they share the side streams and the
+ * workspace). */
 px_status px_exchange_apply_batched(px_context* ctx, int32_t n_inst, const px_instance* inst,
                                     px_precision prec, int32_t ace, hipStream_t stream);
 
@@ -355,8 +361,9 @@ px_status px_set_batch_capacity(px_context* ctx, size_t pair_buffer_bytes);
 px_status px_set_graph(px_context* ctx, int32_t enable);
 
 /* Autotuner: times the Hermitian-pair pipeline on this instance (Phi = Psi)
- * for square pair blocks B in {16, 24, 32, 48, 64, 96, 128} (up to the first
- * B >= n) that fit the attached workspace, each with both compiled
+ * for square pair blocks B in {16, 24, 32, 48, 64, 96, 128, 192, 256} (up to
+ * the first B >= n, which solves the instance as one triangular block) that
+ * fit the attached workspace, each with both compiled
  * configurations of pass 2 (the z transforms: its workgroup shape, x-sections
  * per plane and threads, fixed per grid size at compile time), keeps the
  * fastest pair as the context's tuning for this grid and precision, writes B

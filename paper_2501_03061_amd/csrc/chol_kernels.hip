@@ -12,14 +12,23 @@
 
 namespace px {
 
-__global__ void hermitize_k(double* M, int n) {
+// The factorisation of a launch: the argument, or entry blockIdx.z of a job
+// table in device memory (a group shares one launch per step).
+__device__ __forceinline__ CholJob chol_job(const CholJob& j0, const CholJob* jobs) {
+  return jobs ? jobs[blockIdx.z] : j0;
+}
+
+__global__ void hermitize_k(CholJob j0, const CholJob* jobs) {
+  const CholJob j = chol_job(j0, jobs);
+  double* const M = j.M;
+  const int n = j.n;
   const size_t total = size_t(n) * n;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += size_t(gridDim.x) * blockDim.x) {
-    const int i = int(e / n), j = int(e % n);
-    if (j < i) continue;
-    double* a = M + (size_t(i) * n + j) * 2;
-    double* b = M + (size_t(j) * n + i) * 2;
+    const int i = int(e / n), c = int(e % n);
+    if (c < i) continue;
+    double* a = M + (size_t(i) * n + c) * 2;
+    double* b = M + (size_t(c) * n + i) * 2;
     const double re = 0.5 * (a[0] + b[0]);
     const double im = 0.5 * (a[1] - b[1]);
     a[0] = re;
@@ -29,10 +38,19 @@ __global__ void hermitize_k(double* M, int n) {
   }
 }
 
-hipError_t launch_hermitize(double* M, int n, hipStream_t s) {
+namespace {
+int elementwise_blocks(int n) {
   const size_t total = size_t(n) * n;
-  const int blocks = int((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
-  hipLaunchKernelGGL(hermitize_k, dim3(blocks), dim3(256), 0, s, M, n);
+  return int((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+}
+}  // namespace
+
+hipError_t launch_hermitize(double* M, int n, hipStream_t s) {
+  CholJob j{};
+  j.M = M;
+  j.n = n;
+  hipLaunchKernelGGL(hermitize_k, dim3(elementwise_blocks(n)), dim3(256), 0, s, j,
+                     static_cast<const CholJob*>(nullptr));
   return hipGetLastError();
 }
 
@@ -43,26 +61,32 @@ hipError_t launch_hermitize(double* M, int n, hipStream_t s) {
 // The working matrix L starts as -M and ends as the lower factor with a
 // zeroed strict upper triangle.  A non-positive pivot stops the factorisation:
 // status = 1-based global column, and every later kernel returns at once.
+// In a group every job runs the steps of the largest n; a step past a job's
+// own size returns at once.
 constexpr int KB = 32;
 
-__global__ void chol_init_k(const double* M, int n, double* L, int32_t* status) {
-  const size_t total = size_t(n) * n;
+__global__ void chol_init_k(CholJob j0, const CholJob* jobs) {
+  const CholJob j = chol_job(j0, jobs);
+  const size_t total = size_t(j.n) * j.n;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += size_t(gridDim.x) * blockDim.x) {
-    L[2 * e] = -M[2 * e];
-    L[2 * e + 1] = -M[2 * e + 1];
+    j.L[2 * e] = -j.M[2 * e];
+    j.L[2 * e + 1] = -j.M[2 * e + 1];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) status[0] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) j.status[0] = 0;
 }
 
 // Factor the diagonal block at k0 (size kb <= KB) in LDS; write L_kk back and
-// inv(L_kk) into Dinv (KB x KB, row-major complex).
-__global__ __launch_bounds__(256) void chol_diag_k(double* L, int n, int k0, double* Dinv,
-                                                   int32_t* status) {
+// inv(L_kk) into the job's dinv (KB x KB per block, row-major complex).
+__global__ __launch_bounds__(256) void chol_diag_k(CholJob j0, const CholJob* jobs, int k0) {
   __shared__ double a[KB][KB][2];
   __shared__ double x[KB][KB][2];
   __shared__ int bad;
-  if (status[0] != 0) return;
+  const CholJob j = chol_job(j0, jobs);
+  const int n = j.n;
+  if (k0 >= n || j.status[0] != 0) return;
+  double* const L = j.L;
+  double* const Dinv = j.dinv + size_t(k0 / KB) * KB * KB * 2;
   const int kb = (n - k0) < KB ? (n - k0) : KB;
   const int t = threadIdx.x;
   for (int e = t; e < KB * KB; e += 256) {
@@ -101,7 +125,7 @@ __global__ __launch_bounds__(256) void chol_diag_k(double* L, int n, int k0, dou
     __syncthreads();
   }
   if (bad) {
-    if (t == 0) status[0] = bad;
+    if (t == 0) j.status[0] = bad;
     return;
   }
   // inverse of the lower factor: column c by forward substitution (thread c)
@@ -136,10 +160,18 @@ __global__ __launch_bounds__(256) void chol_diag_k(double* L, int n, int k0, dou
 
 // Panel: for rows i >= k0 + kb, L[i][k0:k0+kb] = A[i][k0:k0+kb] * inv(L_kk)^H,
 // and zero the block above the diagonal (L[k0..][i] for the same columns).
-__global__ __launch_bounds__(64) void chol_panel_k(double* L, int n, int k0, const double* Dinv,
-                                                   const int32_t* status) {
-  if (status[0] != 0) return;
+// inv(L_kk) is staged in LDS (every lane then reads the same entry).
+__global__ __launch_bounds__(64) void chol_panel_k(CholJob j0, const CholJob* jobs, int k0) {
+  __shared__ double dl[KB * KB * 2];
+  const CholJob j = chol_job(j0, jobs);
+  const int n = j.n;
+  if (k0 >= n || j.status[0] != 0) return;
   const int kb = (n - k0) < KB ? (n - k0) : KB;
+  if (k0 + kb + int(blockIdx.x) * 64 >= n) return;  // no row of this job in the workgroup
+  const double* const Dinv = j.dinv + size_t(k0 / KB) * KB * KB * 2;
+  for (int e = threadIdx.x; e < KB * KB * 2; e += 64) dl[e] = Dinv[e];
+  __syncthreads();
+  double* const L = j.L;
   const int i = k0 + kb + blockIdx.x * 64 + threadIdx.x;
   if (i >= n) return;
   double ar[KB], ai[KB];
@@ -152,7 +184,7 @@ __global__ __launch_bounds__(64) void chol_panel_k(double* L, int n, int k0, con
   for (int c = 0; c < kb; ++c) {
     double sr = 0.0, si = 0.0;
     for (int p = 0; p <= c; ++p) {
-      const double dr = Dinv[(c * KB + p) * 2], di = Dinv[(c * KB + p) * 2 + 1];
+      const double dr = dl[(c * KB + p) * 2], di = dl[(c * KB + p) * 2 + 1];
       sr += ar[p] * dr + ai[p] * di;
       si += ai[p] * dr - ar[p] * di;
     }
@@ -166,16 +198,19 @@ __global__ __launch_bounds__(64) void chol_panel_k(double* L, int n, int k0, con
 
 // Trailing update of the lower triangle: tile (bi, bj) of 32 x 32 with
 // bi >= bj over rows/columns >= k0 + kb.
-__global__ __launch_bounds__(256) void chol_update_k(double* L, int n, int k0,
-                                                     const int32_t* status) {
+__global__ __launch_bounds__(256) void chol_update_k(CholJob j0, const CholJob* jobs, int k0) {
   __shared__ double pi_[KB][KB + 1][2];
   __shared__ double pj_[KB][KB + 1][2];
-  if (status[0] != 0) return;
+  const CholJob j = chol_job(j0, jobs);
+  const int n = j.n;
+  if (k0 >= n || j.status[0] != 0) return;
   const int kb = (n - k0) < KB ? (n - k0) : KB;
   const int base = k0 + kb;
   const int bi = blockIdx.x, bj = blockIdx.y;
   if (bj > bi) return;
   const int r0 = base + bi * KB, c0 = base + bj * KB;
+  if (r0 >= n) return;
+  double* const L = j.L;
   const int t = threadIdx.x;
   for (int e = t; e < KB * KB; e += 256) {
     const int r = e / KB, p = e % KB;
@@ -203,7 +238,7 @@ __global__ __launch_bounds__(256) void chol_update_k(double* L, int n, int k0,
 }
 
 // U = L^{-H} from the blocked inverse X = L^{-1}, by block wavefronts.  The
-// factorisation leaves inv(L_kk) of every diagonal block in Dinv
+// factorisation leaves inv(L_kk) of every diagonal block in dinv
 // (nb x KB x KB).  Wavefront d = 0 sets X_cc = inv(L_cc); wavefront d >= 1
 // computes, for every block column c with r = c + d < nb,
 //   X_rc = -inv(L_rr) * sum_{p=c}^{r-1} L_rp X_pc,
@@ -211,18 +246,23 @@ __global__ __launch_bounds__(256) void chol_update_k(double* L, int n, int k0,
 // to U as U[c0 + j][r0 + i] = conj(X_rc[i][j]), and later wavefronts read X_pc
 // back from there (a launch boundary orders the store before the load).
 // The strict lower triangle of U is zeroed first; after a breakdown U stays 0.
-__global__ void tri_zero_k(double* U, int n) {
-  const size_t total = size_t(n) * n * 2;
+__global__ void tri_zero_k(CholJob j0, const CholJob* jobs) {
+  const CholJob j = chol_job(j0, jobs);
+  const size_t total = size_t(j.n) * j.n * 2;
   for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += size_t(gridDim.x) * blockDim.x)
-    U[e] = 0.0;
+    j.U[e] = 0.0;
 }
 
-__global__ __launch_bounds__(256) void tri_wave_k(const double* L, int n, const double* Dinv,
-                                                  double* U, int d, const int32_t* status) {
+__global__ __launch_bounds__(256) void tri_wave_k(CholJob j0, const CholJob* jobs, int d) {
   __shared__ double ls[KB][KB + 1][2];
   __shared__ double xs[KB][KB + 1][2];
-  if (status[0] != 0) return;
+  const CholJob jb = chol_job(j0, jobs);
+  if (jb.status[0] != 0) return;
+  const int n = jb.n;
+  const double* const L = jb.L;
+  const double* const Dinv = jb.dinv;
+  double* const U = jb.U;
   const int nb = (n + KB - 1) / KB;
   const int c = blockIdx.x, r = c + d;
   if (r >= nb) return;
@@ -248,13 +288,13 @@ __global__ __launch_bounds__(256) void tri_wave_k(const double* L, int n, const 
         ls[i][q][0] = in ? L[(size_t(r0 + i) * n + p0 + q) * 2] : 0.0;
         ls[i][q][1] = in ? L[(size_t(r0 + i) * n + p0 + q) * 2 + 1] : 0.0;
         // X_pc[q][j] with j = e / KB, q = e % KB (contiguous reads of U row c0 + j)
-        const int j = e / KB, qq = e % KB;
+        const int jj = e / KB, qq = e % KB;
         if (p == c) {
-          xs[qq][j][0] = dp[(qq * KB + j) * 2];
-          xs[qq][j][1] = dp[(qq * KB + j) * 2 + 1];
+          xs[qq][jj][0] = dp[(qq * KB + jj) * 2];
+          xs[qq][jj][1] = dp[(qq * KB + jj) * 2 + 1];
         } else {
-          xs[qq][j][0] = U[(size_t(c0 + j) * n + p0 + qq) * 2];
-          xs[qq][j][1] = -U[(size_t(c0 + j) * n + p0 + qq) * 2 + 1];
+          xs[qq][jj][0] = U[(size_t(c0 + jj) * n + p0 + qq) * 2];
+          xs[qq][jj][1] = -U[(size_t(c0 + jj) * n + p0 + qq) * 2 + 1];
         }
       }
       __syncthreads();
@@ -295,39 +335,60 @@ __global__ __launch_bounds__(256) void tri_wave_k(const double* L, int n, const 
   }
   if (row < rb) {
     for (int k = 0; k < 4; ++k) {
-      const int j = col + 8 * k;
-      if (c0 + j >= n) continue;
-      U[(size_t(c0 + j) * n + r0 + row) * 2] = ar[k];
-      U[(size_t(c0 + j) * n + r0 + row) * 2 + 1] = -ai[k];
+      const int jc = col + 8 * k;
+      if (c0 + jc >= n) continue;
+      U[(size_t(c0 + jc) * n + r0 + row) * 2] = ar[k];
+      U[(size_t(c0 + jc) * n + r0 + row) * 2 + 1] = -ai[k];
     }
   }
+}
+
+namespace {
+// Every step of the factorisation and the inverse for one job (jobs ==
+// nullptr) or a table of njobs (steps and grids of the largest size n).
+hipError_t chol_steps(const CholJob& j0, const CholJob* jobs, int njobs, int n, hipStream_t s) {
+  const int blocks = elementwise_blocks(n);
+  hipLaunchKernelGGL(chol_init_k, dim3(blocks, 1, njobs), dim3(256), 0, s, j0, jobs);
+  for (int k0 = 0; k0 < n; k0 += KB) {
+    hipLaunchKernelGGL(chol_diag_k, dim3(1, 1, njobs), dim3(256), 0, s, j0, jobs, k0);
+    const int kb = (n - k0) < KB ? (n - k0) : KB;
+    const int rest = n - k0 - kb;
+    if (rest > 0) {
+      hipLaunchKernelGGL(chol_panel_k, dim3((rest + 63) / 64, 1, njobs), dim3(64), 0, s, j0, jobs,
+                         k0);
+      const int nt = (rest + KB - 1) / KB;
+      hipLaunchKernelGGL(chol_update_k, dim3(nt, nt, njobs), dim3(256), 0, s, j0, jobs, k0);
+    }
+  }
+  hipLaunchKernelGGL(tri_zero_k, dim3(blocks, 1, njobs), dim3(256), 0, s, j0, jobs);
+  const int nb = (n + KB - 1) / KB;
+  for (int d = 0; d < nb; ++d)
+    hipLaunchKernelGGL(tri_wave_k, dim3(nb - d, 1, njobs), dim3(256), 0, s, j0, jobs, d);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t* status,
+                           double* dinv, hipStream_t s) {
+  CholJob j{};
+  j.M = const_cast<double*>(M);  // read only by these kernels
+  j.L = L;
+  j.U = U;
+  j.dinv = dinv;
+  j.status = status;
+  j.n = n;
+  return chol_steps(j, nullptr, 1, n, s);
+}
+
+hipError_t launch_chol_inv_group(const CholJob* jobs, int njobs, int max_n, hipStream_t s) {
+  const CholJob none{};
+  hipLaunchKernelGGL(hermitize_k, dim3(elementwise_blocks(max_n), 1, njobs), dim3(256), 0, s, none,
+                     jobs);
+  return chol_steps(none, jobs, njobs, max_n, s);
 }
 
 size_t chol_dinv_bytes(int n) { return size_t((n + KB - 1) / KB) * KB * KB * 16; }
 
-hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t* status,
-                           double* dinv, hipStream_t s) {
-  const size_t total = size_t(n) * n;
-  const int blocks = int((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
-  hipLaunchKernelGGL(chol_init_k, dim3(blocks), dim3(256), 0, s, M, n, L, status);
-  for (int k0 = 0; k0 < n; k0 += KB) {
-    double* dk = dinv + size_t(k0 / KB) * KB * KB * 2;
-    hipLaunchKernelGGL(chol_diag_k, dim3(1), dim3(256), 0, s, L, n, k0, dk, status);
-    const int kb = (n - k0) < KB ? (n - k0) : KB;
-    const int rest = n - k0 - kb;
-    if (rest > 0) {
-      hipLaunchKernelGGL(chol_panel_k, dim3((rest + 63) / 64), dim3(64), 0, s, L, n, k0, dk,
-                         status);
-      const int nt = (rest + KB - 1) / KB;
-      hipLaunchKernelGGL(chol_update_k, dim3(nt, nt), dim3(256), 0, s, L, n, k0, status);
-    }
-  }
-  hipLaunchKernelGGL(tri_zero_k, dim3(blocks), dim3(256), 0, s, U, n);
-  const int nb = (n + KB - 1) / KB;
-  for (int d = 0; d < nb; ++d)
-    hipLaunchKernelGGL(tri_wave_k, dim3(nb - d), dim3(256), 0, s, L, n, dinv, U, d, status);
-  return hipGetLastError();
-}
 
 }  // namespace px
 

@@ -71,6 +71,16 @@ template <typename T> __device__ __forceinline__ void stn(cpx<T>* p, cpx<T> a) {
   __builtin_nontemporal_store(v, (PX_GLOBAL V*)p);
 }
 
+// Pair-slab loads of pass 2 (each element is read once; a build may set
+// PX_P2_NT to time the streaming form).
+#ifndef PX_P2_NT
+#define PX_P2_NT 0
+#endif
+template <typename T> __device__ __forceinline__ cpx<T> ld_pair2(const cpx<T>* p) {
+  if constexpr (PX_P2_NT != 0) return ldg(p);
+  else return ldc(p);
+}
+
 // Twiddle table: tw[m] = exp(-2 pi i m / N) from the compile-time roots
 // (FP64, about one ulp) rounded to T; copied into LDS by each workgroup.
 template <typename T, int N, int NT> __device__ __forceinline__ void fill_twiddles(cpx<T>* tw) {
@@ -456,7 +466,7 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
   // values at the positions the last forward stage produces
   cpx<T> nx[BPT0][F0::R];
   gather_live<T, GZ, F0::R, NT>(nx, [&](int line, int e) {
-    return ldc(buf0 + size_t(pair_slot(a, qbeg)) * slab * N2 + unsigned(e * int(slab) + line));
+    return ld_pair2(buf0 + size_t(pair_slot(a, qbeg)) * slab * N2 + unsigned(e * int(slab) + line));
   });
   KT kv[BPTL][FL::R];
   const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
@@ -481,11 +491,11 @@ void pass2_z_kernel(ChunkArgs a0, const ChunkArgs* tasks) {
 #pragma unroll
       for (int r = 0; r < F0::R; ++r) v0[k][r] = nx[k][r];
   } else {
-    gather_live<T, GZ, F0::R, NT>(v0, [&](int line, int e) { return ldc(buf + unsigned(e * int(slab) + line)); });
+    gather_live<T, GZ, F0::R, NT>(v0, [&](int line, int e) { return ld_pair2(buf + unsigned(e * int(slab) + line)); });
   }
   if (PF && q + 1 < qend) {
     cpx<T>* const bn = buf0 + size_t(pair_slot(a, q + 1)) * slab * N2;
-    gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) { return ldc(bn + unsigned(e * int(slab) + line)); });
+    gather<T, GZ, F0::R, NT>(nx, [&](int line, int e) { return ld_pair2(bn + unsigned(e * int(slab) + line)); });
   }
   if (q > qbeg) __syncthreads();  // the previous pair's last stage has read LDS
 #pragma unroll
@@ -860,7 +870,7 @@ __device__ __forceinline__ void dma_sync() {
 // Cache-policy bits of the slab transfers (a build may set PX_DMA_AUX to time
 // alternatives).
 #ifndef PX_DMA_AUX
-#define PX_DMA_AUX 0
+#define PX_DMA_AUX 2
 #endif
 template <int BYTES, int NT>
 __device__ __forceinline__ void dma_to_lds(const void* src, void* dst) {

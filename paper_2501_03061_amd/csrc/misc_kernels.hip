@@ -178,9 +178,9 @@ __global__ __launch_bounds__(256) void expart_reduce_tasks_k(const ChunkArgs* ta
   }
 }
 
-hipError_t launch_expart_reduce_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_pairs,
+hipError_t launch_expart_reduce_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_slots,
                                       int n1, int n2, double ng, hipStream_t s) {
-  hipLaunchKernelGGL(expart_reduce_tasks_k, dim3((max_pairs + 3) / 4, ntasks), dim3(256), 0, s,
+  hipLaunchKernelGGL(expart_reduce_tasks_k, dim3((max_slots + 3) / 4, ntasks), dim3(256), 0, s,
                      tasks, int(fp32), n1, n2, ng);
   return hipGetLastError();
 }

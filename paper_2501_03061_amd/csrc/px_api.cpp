@@ -50,8 +50,14 @@ struct px_context {
   std::vector<unsigned char> graph_key;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;
-  void* pinned_tasks = nullptr;  // host copy of the task table (page-locked)
+  void* pinned_tasks = nullptr;  // host copy of the task and job tables (page-locked)
   size_t pinned_bytes = 0;
+  // ACE tails of the batched form (Gram matrix, factorisation, xi) run on
+  // side streams beside the later pair-pipeline waves
+  static constexpr int kTailLanes = 2;
+  hipStream_t lanes[kTailLanes] = {nullptr, nullptr};
+  hipEvent_t lane_done[kTailLanes] = {nullptr, nullptr};
+  std::vector<hipEvent_t> fork_events;
   ~px_context() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     for (hipEvent_t e : ace_events)
@@ -59,6 +65,11 @@ struct px_context {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (pinned_tasks) (void)hipHostFree(pinned_tasks);
+    for (int l = 0; l < kTailLanes; ++l) {
+      if (lanes[l]) (void)hipStreamDestroy(lanes[l]);
+      if (lane_done[l]) (void)hipEventDestroy(lane_done[l]);
+    }
+    for (hipEvent_t e : fork_events) (void)hipEventDestroy(e);
   }
 };
 
@@ -1063,17 +1074,30 @@ struct BatchWave {
   int n;            // cubic grid size of the wave's instances
   int p2;           // pass-2 configuration of that size
   int first, count; // tasks [first, first + count)
-  int max_ic, max_jc, max_pairs;
+  int max_ic, max_jc, max_pairs, max_slots;  // max_pairs: solved pairs; max_slots: ic * jc
   bool any_v;       // its tasks keep v_ij for pass 4 (a wave holds one block diagonal, so
                     // all of its tasks or none)
 };
 
+// The ACE tail of the instances whose last chunk is in wave after_wave: their
+// Gram matrices, one grouped factorisation (jobs [first_job, first_job +
+// count) of the job table) and their xi, on side stream lane.
+struct TailGroup {
+  int after_wave, lane, first_job, count, max_n;
+};
+
 struct BatchPlan {
-  size_t tasks_off = 0, t_off = 0, g0_off = 0, ex_off = 0;
+  size_t tasks_off = 0, jobs_off = 0, table_end = 0, t_off = 0, g0_off = 0, ex_off = 0;
   std::vector<size_t> S_off, W_off, K32_off;
-  size_t M_off = 0, L_off = 0, U_off = 0, dinv_off = 0, part_off = 0, end = 0;
+  // ACE: per instance M (unless the caller's), L (FP32: then U in complex64),
+  // U and the diagonal-block inverses; per lane the Gram split partials
+  std::vector<size_t> M_off, L_off, U_off, dinv_off, part_off;
+  size_t end = 0;
   std::vector<px::ChunkArgs> tasks;
+  std::vector<px::CholJob> jobs;   // instance order of the tail groups
+  std::vector<int> job_inst;       // instance of each job
   std::vector<BatchWave> waves;
+  std::vector<TailGroup> groups;
 };
 
 int block_for(const px_context* c, const px_cell* cell, px_precision prec) {
@@ -1099,12 +1123,6 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
   BatchPlan P;
   const bool fp32 = prec == PX_PREC_FP32;
   const size_t b = elem_bytes(prec);
-  int max_n = 0;
-  for (int k = 0; k < n_inst; ++k) max_n = std::max(max_n, int(in[k].n));
-  // pair-buffer capacity per grid size: batch_cap_bytes, at least one block
-  int max_block = 1;
-  for (int k = 0; k < n_inst; ++k) max_block = std::max(max_block, block_for(c, &in[k].cell, prec));
-  const size_t min_pairs = size_t(max_block) * max_block;
   size_t t_bytes = 0, side_pairs = 0;  // sizes of the pair buffer and of the per-plane partials
   // schedule
   std::vector<int> sizes;
@@ -1114,11 +1132,15 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
   std::sort(sizes.begin(), sizes.end());
   struct Chunk { int inst, I, J, B; };
   for (int nsz : sizes) {
+    // pair-buffer capacity of the size: batch_cap_bytes, at least its largest chunk
     int max_nb = 0;
+    size_t min_pairs = 1;
     for (int k = 0; k < n_inst; ++k)
       if (in[k].cell.n[0] == nsz) {
         const int B = block_for(c, &in[k].cell, prec);
         max_nb = std::max(max_nb, (int(in[k].n) + B - 1) / B);
+        const size_t e = size_t(std::min(B, int(in[k].n)));
+        min_pairs = std::max(min_pairs, e * e);
       }
     const size_t ng = size_t(nsz) * nsz * nsz;
     const size_t cap = std::max(min_pairs, c->batch_cap_bytes / (ng * b));
@@ -1142,7 +1164,7 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         const int icc = std::min(ch.B, n - ch.I * ch.B), jcc = std::min(ch.B, n - ch.J * ch.B);
         const size_t pairs = size_t(icc) * jcc;
         if (used + pairs > cap) {
-          P.waves.push_back({nsz, p2, int(P.tasks.size()), 0, 0, 0, 0, false});
+          P.waves.push_back({nsz, p2, int(P.tasks.size()), 0, 0, 0, 0, 0, false});
           used = 0;
         }
         BatchWave& w = P.waves.back();
@@ -1168,16 +1190,41 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         w.count++;
         w.max_ic = std::max(w.max_ic, icc);
         w.max_jc = std::max(w.max_jc, jcc);
-        w.max_pairs = std::max(w.max_pairs, int(pairs));
+        // launch grids cover the solved pairs (the lower triangle of a
+        // triangular block), not the block's pair slots
+        w.max_pairs = std::max(w.max_pairs, px::chunk_pairs(a));
+        w.max_slots = std::max(w.max_slots, int(pairs));
         w.any_v = w.any_v || a.store_v;
         used += pairs;
       }
     }
   }
+  // ACE tails: an instance's tail may start once the last wave holding one of
+  // its chunks has run; the instances completed by one wave form a group
+  if (ace) {
+    std::vector<int> last(n_inst, -1);
+    for (int w = 0; w < int(P.waves.size()); ++w)
+      for (int t = P.waves[w].first; t < P.waves[w].first + P.waves[w].count; ++t)
+        last[int(reinterpret_cast<size_t>(P.tasks[t].S))] = w;
+    for (int w = 0; w < int(P.waves.size()); ++w) {
+      TailGroup g{w, int(P.groups.size()) % px_context::kTailLanes, int(P.job_inst.size()), 0, 0};
+      for (int k = 0; k < n_inst; ++k)
+        if (last[k] == w) {
+          P.job_inst.push_back(k);
+          g.count++;
+          g.max_n = std::max(g.max_n, int(in[k].n));
+        }
+      if (g.count) P.groups.push_back(g);
+    }
+    P.jobs.resize(P.job_inst.size());
+  }
   // layout
   size_t off = 0;
   P.tasks_off = off;
   off = align_up(off + P.tasks.size() * sizeof(px::ChunkArgs));
+  P.jobs_off = off;
+  off = align_up(off + P.jobs.size() * sizeof(px::CholJob));
+  P.table_end = off;
   P.t_off = off;
   off = align_up(off + t_bytes);
   P.g0_off = off;
@@ -1198,25 +1245,33 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
     }
   }
   if (ace) {
+    P.M_off.resize(n_inst);
+    P.L_off.resize(n_inst);
+    P.U_off.resize(n_inst);
+    P.dinv_off.resize(n_inst);
     for (int k = 0; k < n_inst; ++k) {
+      const size_t nn = size_t(in[k].n) * in[k].n * 16;
       P.W_off[k] = off;
       off = align_up(off + size_t(in[k].n) * ngrid(&in[k].cell) * b);
+      P.M_off[k] = off;
+      off = align_up(off + nn);
+      P.L_off[k] = off;
+      off = align_up(off + nn);
+      P.U_off[k] = off;
+      off = align_up(off + nn);
+      P.dinv_off[k] = off;
+      off = align_up(off + px::chol_dinv_bytes(in[k].n));
     }
-    P.M_off = off;
-    off = align_up(off + size_t(max_n) * max_n * 16);
-    P.L_off = off;
-    off = align_up(off + size_t(max_n) * max_n * 16);
-    P.U_off = off;
-    off = align_up(off + size_t(max_n) * max_n * 16);
-    P.dinv_off = off;
-    off = align_up(off + px::chol_dinv_bytes(max_n));
     size_t part = 0;
     for (int k = 0; k < n_inst; ++k) {
       int ns = 0;
       part = std::max(part, px::gemm_xhy_part_elems(in[k].n, in[k].n, ngrid(&in[k].cell), &ns));
     }
-    P.part_off = off;
-    off = align_up(off + part * 16);
+    P.part_off.resize(px_context::kTailLanes);
+    for (int l = 0; l < px_context::kTailLanes; ++l) {
+      P.part_off[l] = off;
+      off = align_up(off + part * 16);
+    }
   }
   P.end = off;
   if (ws) {
@@ -1236,8 +1291,28 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         if (fp32) a.kern32 = reinterpret_cast<const float*>(ws + P.K32_off[k]);
       }
     }
+    for (size_t q = 0; q < P.jobs.size(); ++q) {
+      const int k = P.job_inst[q];
+      px::CholJob& j = P.jobs[q];
+      j.M = in[k].M ? in[k].M : reinterpret_cast<double*>(ws + P.M_off[k]);
+      j.L = reinterpret_cast<double*>(ws + P.L_off[k]);
+      j.U = reinterpret_cast<double*>(ws + P.U_off[k]);
+      j.dinv = reinterpret_cast<double*>(ws + P.dinv_off[k]);
+      j.status = in[k].status;
+      j.n = int(in[k].n);
+    }
   }
   return P;
+}
+
+// The host image of the task and job tables, laid out as in the workspace
+// from tasks_off.
+void table_image(const BatchPlan& P, std::vector<unsigned char>& img) {
+  img.assign(P.table_end - P.tasks_off, 0);
+  std::memcpy(img.data(), P.tasks.data(), P.tasks.size() * sizeof(px::ChunkArgs));
+  if (!P.jobs.empty())
+    std::memcpy(img.data() + (P.jobs_off - P.tasks_off), P.jobs.data(),
+                P.jobs.size() * sizeof(px::CholJob));
 }
 
 px_status check_instances(px_context* c, int n_inst, const px_instance* in, px_precision prec,
@@ -1261,17 +1336,88 @@ px_status check_instances(px_context* c, int n_inst, const px_instance* in, px_p
   return PX_OK;
 }
 
-// Everything of one batched call, stream ordered on s.
+// The ACE tail of one group on stream ls: Gram matrices (and energies), one
+// grouped factorisation, xi.
+px_status enqueue_tail(px_context* c, const BatchPlan& P, const TailGroup& g, const px_instance* in,
+                       px_precision prec, hipStream_t ls) {
+  const bool fp32 = prec == PX_PREC_FP32;
+  char* ws = c->ws;
+  double* part = reinterpret_cast<double*>(ws + P.part_off[g.lane]);
+  px_status st = PX_OK;
+  for (int q = g.first_job; q < g.first_job + g.count; ++q) {
+    const int k = P.job_inst[q];
+    const px_instance& x = in[k];
+    const size_t ng = ngrid(&x.cell);
+    const double omega = x.cell.L[0] * x.cell.L[1] * x.cell.L[2];
+    if (x.e_x) {
+      st = hip_check(c, px::launch_energy(reinterpret_cast<const double*>(ws + P.S_off[k]), x.occ,
+                                          x.n, -0.5 * omega / (double(ng) * double(ng)), x.e_x, ls),
+                     "batched energy");
+      if (st != PX_OK) return st;
+    }
+    int nsplit = 0;
+    px::gemm_xhy_part_elems(x.n, x.n, ng, &nsplit);
+    st = hip_check(c, px::launch_gemm_xhy_herm(fp32, x.n, ng, x.psi, ws + P.W_off[k],
+                                               omega / double(ng), P.jobs[q].M, part, nsplit, ls),
+                   "batched M");
+    if (st != PX_OK) return st;
+  }
+  const px::CholJob* dj = reinterpret_cast<const px::CholJob*>(ws + P.jobs_off) + g.first_job;
+  st = hip_check(c, px::launch_chol_inv_group(dj, g.count, g.max_n, ls), "batched cholesky");
+  if (st != PX_OK) return st;
+  for (int q = g.first_job; q < g.first_job + g.count; ++q) {
+    const int k = P.job_inst[q];
+    const px_instance& x = in[k];
+    const size_t ng = ngrid(&x.cell);
+    // FP32 form: U rounded to complex64 into L's place (L is not read again)
+    const void* Uc = P.jobs[q].U;
+    if (fp32) {
+      st = hip_check(c, px::launch_convert_f64_f32(size_t(2) * x.n * x.n, P.jobs[q].U,
+                                                   reinterpret_cast<float*>(P.jobs[q].L), ls),
+                     "batched U to FP32");
+      if (st != PX_OK) return st;
+      Uc = P.jobs[q].L;
+    }
+    st = hip_check(c, px::launch_gemm_xc(fp32, x.n, x.n, ng, ws + P.W_off[k], Uc, x.n, 1.0, x.out,
+                                         true, ls),
+                   "batched xi");
+    if (st != PX_OK) return st;
+  }
+  return PX_OK;
+}
+
+// Side streams and events of the ACE tails (created once per context).
+px_status ensure_lanes(px_context* c, size_t n_fork) {
+  for (int l = 0; l < px_context::kTailLanes; ++l) {
+    if (!c->lanes[l] && hipStreamCreateWithFlags(&c->lanes[l], hipStreamNonBlocking) != hipSuccess)
+      return fail(c, PX_ERR_DEVICE, "hipStreamCreate (tail lane) failed");
+    if (!c->lane_done[l] &&
+        hipEventCreateWithFlags(&c->lane_done[l], hipEventDisableTiming) != hipSuccess)
+      return fail(c, PX_ERR_DEVICE, "hipEventCreate failed");
+  }
+  while (c->fork_events.size() < n_fork) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return fail(c, PX_ERR_DEVICE, "hipEventCreate failed");
+    c->fork_events.push_back(e);
+  }
+  return PX_OK;
+}
+
+// Everything of one batched call, stream ordered on s: the pair-pipeline
+// waves on s; in ACE mode each tail group on its lane once its wave has run,
+// and s waits for every lane at the end (also after an error, so that a
+// capture is always joined).
 px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_instance* in,
-                        px_precision prec, bool ace, const void* host_tasks, hipStream_t s) {
+                        px_precision prec, bool ace, const void* host_table, hipStream_t s) {
   const bool fp32 = prec == PX_PREC_FP32;
   char* ws = c->ws;
   const px::ChunkArgs* dt = reinterpret_cast<const px::ChunkArgs*>(ws + P.tasks_off);
-  px_status st = hip_check(c, hipMemcpyAsync(ws + P.tasks_off, host_tasks,
-                                             P.tasks.size() * sizeof(px::ChunkArgs),
+  px_status st = hip_check(c, hipMemcpyAsync(ws + P.tasks_off, host_table, P.table_end - P.tasks_off,
                                              hipMemcpyHostToDevice, s),
                            "task table upload");
   if (st != PX_OK) return st;
+  if (ace && (st = ensure_lanes(c, P.waves.size())) != PX_OK) return st;
   if (fp32) {
     for (int k = 0; k < n_inst; ++k) {
       st = hip_check(c, px::launch_convert_f64_f32(ngrid(&in[k].cell), in[k].kernel_G,
@@ -1280,64 +1426,52 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
       if (st != PX_OK) return st;
     }
   }
-  for (const BatchWave& w : P.waves) {
+  bool used[px_context::kTailLanes] = {false, false};
+  size_t gi = 0;
+  for (int wi = 0; wi < int(P.waves.size()) && st == PX_OK; ++wi) {
+    const BatchWave& w = P.waves[wi];
     const size_t ng = size_t(w.n) * w.n * w.n;
     st = hip_check(c, px::launch_chunk_tasks(fp32, w.n, dt + w.first, w.count, w.max_ic,
                                              w.max_pairs, true, w.any_v, w.p2, s),
                    "batched pair pipeline");
-    if (st != PX_OK) return st;
+    if (st != PX_OK) break;
     if (w.any_v) {
       st = hip_check(c, px::launch_pass4_tasks(fp32, dt + w.first, w.count, w.max_jc, ng, s),
                      "batched transposed accumulation");
-      if (st != PX_OK) return st;
+      if (st != PX_OK) break;
     }
-    st = hip_check(c, px::launch_expart_reduce_tasks(fp32, dt + w.first, w.count, w.max_pairs,
+    st = hip_check(c, px::launch_expart_reduce_tasks(fp32, dt + w.first, w.count, w.max_slots,
                                                      w.n * px::pass2_sections_cfg(fp32, w.n, w.p2), w.n,
                                                      double(ng), s),
                    "batched energy partials");
-    if (st != PX_OK) return st;
+    if (st != PX_OK) break;
+    if (gi < P.groups.size() && P.groups[gi].after_wave == wi) {
+      hipEvent_t e = c->fork_events[wi];
+      st = hip_check(c, hipEventRecord(e, s), "fork event");
+      while (st == PX_OK && gi < P.groups.size() && P.groups[gi].after_wave == wi) {
+        const TailGroup& g = P.groups[gi++];
+        st = hip_check(c, hipStreamWaitEvent(c->lanes[g.lane], e, 0), "tail lane wait");
+        if (st != PX_OK) break;
+        used[g.lane] = true;
+        st = enqueue_tail(c, P, g, in, prec, c->lanes[g.lane]);
+      }
+    }
   }
+  for (int l = 0; l < px_context::kTailLanes; ++l) {
+    if (!used[l]) continue;
+    px_status sj = hip_check(c, hipEventRecord(c->lane_done[l], c->lanes[l]), "lane event");
+    if (sj == PX_OK) sj = hip_check(c, hipStreamWaitEvent(s, c->lane_done[l], 0), "lane join");
+    if (st == PX_OK) st = sj;
+  }
+  if (st != PX_OK || ace) return st;
   for (int k = 0; k < n_inst; ++k) {
     const px_instance& x = in[k];
+    if (!x.e_x) continue;
     const size_t ng = ngrid(&x.cell);
     const double omega = x.cell.L[0] * x.cell.L[1] * x.cell.L[2];
-    const double* S = reinterpret_cast<const double*>(ws + P.S_off[k]);
-    if (x.e_x) {
-      st = hip_check(c, px::launch_energy(S, x.occ, x.n, -0.5 * omega / (double(ng) * double(ng)),
-                                          x.e_x, s),
-                     "batched energy");
-      if (st != PX_OK) return st;
-    }
-    if (!ace) continue;
-    const double dV = omega / double(ng);
-    void* W = ws + P.W_off[k];
-    double* Mw = x.M ? x.M : reinterpret_cast<double*>(ws + P.M_off);
-    int nsplit = 0;
-    px::gemm_xhy_part_elems(x.n, x.n, ng, &nsplit);
-    st = hip_check(c, px::launch_gemm_xhy_herm(fp32, x.n, ng, x.psi, W, dV, Mw,
-                                               reinterpret_cast<double*>(ws + P.part_off), nsplit,
-                                               s),
-                   "batched M");
-    if (st != PX_OK) return st;
-    st = hip_check(c, px::launch_hermitize(Mw, x.n, s), "batched hermitize");
-    if (st != PX_OK) return st;
-    st = hip_check(c, px::launch_chol_inv(Mw, x.n, reinterpret_cast<double*>(ws + P.L_off),
-                                          reinterpret_cast<double*>(ws + P.U_off), x.status,
-                                          reinterpret_cast<double*>(ws + P.dinv_off), s),
-                   "batched cholesky");
-    if (st != PX_OK) return st;
-    // FP32 form: U rounded to complex64 into L's place (L is not read again)
-    const void* Uc = ws + P.U_off;
-    if (fp32) {
-      st = hip_check(c, px::launch_convert_f64_f32(size_t(2) * x.n * x.n,
-                                                   reinterpret_cast<double*>(ws + P.U_off),
-                                                   reinterpret_cast<float*>(ws + P.L_off), s),
-                     "batched U to FP32");
-      if (st != PX_OK) return st;
-      Uc = ws + P.L_off;
-    }
-    st = hip_check(c, px::launch_gemm_xc(fp32, x.n, x.n, ng, W, Uc, x.n, 1.0, x.out, true, s),
-                   "batched xi");
+    st = hip_check(c, px::launch_energy(reinterpret_cast<const double*>(ws + P.S_off[k]), x.occ, x.n,
+                                        -0.5 * omega / (double(ng) * double(ng)), x.e_x, s),
+                   "batched energy");
     if (st != PX_OK) return st;
   }
   return PX_OK;
@@ -1402,7 +1536,9 @@ px_status px_exchange_apply_batched(px_context* ctx, int32_t n_inst, const px_in
   hipError_t he = hipSetDevice(ctx->device);
   if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
   P = plan_batch(ctx, n_inst, inst, prec, ace != 0, ctx->ws);
-  const size_t tbytes = P.tasks.size() * sizeof(px::ChunkArgs);
+  std::vector<unsigned char> img;
+  table_image(P, img);
+  const size_t tbytes = img.size();
   if (ace) {
     ctx->last_status.clear();
     for (int k = 0; k < n_inst; ++k)
@@ -1425,7 +1561,7 @@ px_status px_exchange_apply_batched(px_context* ctx, int32_t n_inst, const px_in
     if (he != hipSuccess) return hip_check(ctx, he, "hipHostMalloc (task table)");
     ctx->pinned_bytes = tbytes;
   }
-  std::memcpy(ctx->pinned_tasks, P.tasks.data(), tbytes);
+  std::memcpy(ctx->pinned_tasks, img.data(), tbytes);
   if (!ctx->use_graph) return enqueue_batch(ctx, P, n_inst, inst, prec, ace != 0, ctx->pinned_tasks, stream);
   if (!ctx->cap_stream) {
     he = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
@@ -1475,7 +1611,7 @@ px_status px_autotune(px_context* ctx, const px_cell* cell, px_precision prec, i
   // square pair blocks B (the Hermitian-pair mode's chunks are B x B) and the
   // two compiled pass-2 configurations; candidates whose pair buffer does not
   // fit the attached workspace are skipped
-  const int cand[] = {16, 24, 32, 48, 64, 96, 128};
+  const int cand[] = {16, 24, 32, 48, 64, 96, 128, 192, 256};
   const auto key = std::make_tuple(cell->n[0], cell->n[1], cell->n[2], int(prec));
   const bool had = ctx->tuning.count(key) != 0;
   const auto saved = had ? ctx->tuning[key] : std::make_tuple(0, 0, 0);

@@ -128,15 +128,16 @@ hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool e
                         hipStream_t s, hipEvent_t* ev);
 
 // The same passes over a task table in device memory (ntasks chunks of one
-// grid size, all with ic <= max_ic and ic*jc <= max_pairs, and all with the
-// given store_v), one launch each.
+// grid size, all with ic <= max_ic and at most max_pairs solved pairs
+// (chunk_pairs), and all with the given store_v), one launch each.
 hipError_t launch_chunk_tasks(bool fp32, int n, const ChunkArgs* tasks, int ntasks, int max_ic,
                               int max_pairs, bool ex, bool store_v, int p2cfg, hipStream_t s);
 // Pass 4 over a task table (tasks without kept v_ij are skipped).
 hipError_t launch_pass4_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_jc, size_t ng,
                               hipStream_t s);
 // Energy partials -> S for every task of a table (see launch_expart_reduce).
-hipError_t launch_expart_reduce_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_pairs,
+// max_slots: the largest ic * jc of the table.
+hipError_t launch_expart_reduce_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_slots,
                                       int n1, int n2, double ng, hipStream_t s);
 
 // Pass 4 (symmetric mode): out[j] -= sum_i f_i/N_g psi_i conj(v_ij) from the
@@ -214,6 +215,19 @@ hipError_t launch_hermitize(double* M, int n, hipStream_t s);
 size_t chol_dinv_bytes(int n);
 hipError_t launch_chol_inv(const double* M, int n, double* L, double* U, int32_t* status,
                            double* dinv, hipStream_t s);
+// One factorisation of a group: its matrices and status word (M is hermitized in place).
+struct CholJob {
+  double* M;
+  double* L;
+  double* U;
+  double* dinv;
+  int32_t* status;
+  int n;
+  int pad;
+};
+// hermitize + launch_chol_inv for every job of a device-resident table, one
+// launch per step for the whole group (blockIdx.z = job); max_n >= every n.
+hipError_t launch_chol_inv_group(const CholJob* jobs, int njobs, int max_n, hipStream_t s);
 // C = op(A) B, n x n complex128 row-major, op(A) = A^H when ah
 hipError_t launch_zgemm(bool ah, int n, const double* A, const double* B, double* C, hipStream_t s);
 // dst = alpha * src, n real FP64 values

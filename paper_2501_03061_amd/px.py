@@ -482,11 +482,11 @@ class Context:
         if out is None:
             out = torch.empty_like(psi)
         need = max(self.workspace_bytes(PX_OP_EXCHANGE, cell, prec, psi.shape[0], psi.shape[0]), 1)
-        # room for the largest candidate block (128 x 128 pair slabs, or as
-        # many as 24 GiB hold; larger candidates are skipped)
+        # room for the largest candidate block (256 x 256 pair slabs, or as
+        # many as 64 GiB hold; larger candidates are skipped)
         b = psi.element_size()
-        blk = min(128, psi.shape[0])
-        need = max(need, min(blk * blk * cell.ng * b, 24 << 30) + (256 << 20))
+        blk = min(256, psi.shape[0])
+        need = max(need, min(blk * blk * cell.ng * b, 64 << 30) + (256 << 20))
         self.ensure_workspace(need)
         best = ctypes.c_int32(0)
         self._check(self.lib.px_autotune(self.h, ctypes.byref(cell.c()), prec, psi.shape[0],

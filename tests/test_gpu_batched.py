@@ -96,18 +96,29 @@ def test_batched_graph_replay_is_deterministic(px_ctx):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("blk", [0, 8])
 @pytest.mark.parametrize("fp32", [False, True])
-def test_batched_ace_matches_single_builds(px_ctx, fp32):
-    banner(f"batched ace fp32={fp32}")
+def test_batched_ace_matches_oracle(px_ctx, fp32, blk):
+    """ACE tails: with the default blocks every instance completes in its
+    size's first wave (one tail group per size); with 8 x 8 blocks instances
+    complete in different waves, so several groups of different sizes run on
+    both side streams while later waves are still in flight."""
+    banner(f"batched ace fp32={fp32} blk={blk}")
     import torch
     insts = _make(SPECS, fp32, px_ctx)
+    prec = px.PX_PREC_FP32 if fp32 else px.PX_PREC_FP64
     args = []
     for d in insts:
         n = d["inst"].n_orb
         d["M"] = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
         args.append(dict(cell=d["cell"], psi=d["psi"], occ=d["occ"], kern=d["kern"], e_x=d["e_x"], M=d["M"]))
-    xis, stats = px_ctx.px_exchange_apply_batched(args, ace=True)
-    px_ctx.px_sync()
+        px_ctx.set_tuning(d["cell"], prec, blk, blk)
+    try:
+        xis, stats = px_ctx.px_exchange_apply_batched(args, ace=True)
+        px_ctx.px_sync()
+    finally:
+        for d in insts:
+            px_ctx.set_tuning(d["cell"], prec, 0, 0)
     tol = FP32_TOL if fp32 else FP64_TOL
     for d, xi, st in zip(insts, xis, stats):
         inst = d["inst"]
@@ -119,6 +130,8 @@ def test_batched_ace_matches_single_builds(px_ctx, fp32):
               f"xi {relerr(to_host(xi), r['xi']):.2e}")
         assert relerr(to_host(d["M"]), r["M"]) < tol
         assert relerr(to_host(xi), r["xi"]) < tol
+        ex = oracle.exchange_energy_gspace(inst.psi, inst.occ, K, inst.omega)
+        assert abs(float(d["e_x"].item()) - ex) / abs(ex) < (FP32_EX_TOL if fp32 else FP64_TOL)
 
 
 def test_autotune_and_cache(px_ctx, tmp_path):
@@ -127,7 +140,7 @@ def test_autotune_and_cache(px_ctx, tmp_path):
     d = _make([(32, 40, 0.02, 9)], True, px_ctx)[0]
     path = str(tmp_path / "tune.jsonl")
     best = px_ctx.px_autotune(d["cell"], d["psi"], d["occ"], d["kern"], cache_path=path)
-    assert best in (16, 24, 32, 48, 64, 96, 128)
+    assert best in (16, 24, 32, 48, 64, 96, 128, 192, 256)
     lines = open(path).read().strip().splitlines()
     assert len(lines) == 1 and f'"block": {best}' in lines[0]
     assert '"p2": 0' in lines[0] or '"p2": 1' in lines[0]
