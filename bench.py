@@ -285,6 +285,11 @@ def bench_single(args, workload):
     dom, roof, pipeline, passes, stages = roofline_fields(prof, ace, args.steps, pairs_phys, ng, 8,
                                                           copy["copy_GBps"])
     roof["traffic"] = profsum.measured_traffic(workload, PASS_NAMES[dom])
+    if roof["traffic"] is not None:
+        # the same launch priced by its counter-measured HBM bytes
+        avg_s = prof[dom]["ms"] * 1e-3 / max(1, prof[dom]["launches"])
+        roof["measured_GBps"] = roof["traffic"] / avg_s / 1e9
+        roof["measured_frac"] = roof["measured_GBps"] / HBM_PEAK_GBPS
     ace_s = [a * 1e-3 for a, _ in ev32]
     extra = dict(
         logical_pair_solves_per_step=pairs, physical_pair_solves_per_step=pairs_phys,

@@ -164,7 +164,8 @@ px_status px_exchange_apply(px_context* ctx, const px_cell* cell, px_precision p
  * pair is solved once and v_ji = conj(v_ij) is used for the other; that holds
  * only for a real kernel with K(G) = K(-G) (true of px_kernel_hse and of any
  * radial interaction).  For another kernel turn the mode off: with it on, the
- * results are those of the kernel's even real part on the pairs j < i. */
+ * pairs (i, j) with j <= i use K(G) and the transposed pairs (j, i) use
+ * conj(K(-G)) instead (they reuse conj(v_ij)). */
 px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
                        const void* psi, const double* occ, const double* kernel_G, void* xi,
                        double* M, double* e_x, int32_t* status, hipStream_t stream);
