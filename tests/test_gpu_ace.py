@@ -210,7 +210,7 @@ def test_ace_build_non_even_kernel(px_ctx, sym):
     iz, iy, ix = np.meshgrid(*(np.arange(m) for m in inst.n[::-1]), indexing="ij")
     K = K0 * (1.0 + 0.3 * np.sin(2 * np.pi * (ix / inst.n[0] + 2 * iy / inst.n[1] + 3 * iz / inst.n[2])))
     Kref = K[(-iz) % inst.n[2], (-iy) % inst.n[1], (-ix) % inst.n[0]]
-    assert np.abs(K - Kref).max() > 0.1 * np.abs(K).max()
+    assert np.abs(K - Kref).max() > 0.01 * np.abs(K).max()      # K(0) = pi / mu^2 dominates the max
     dV = inst.omega / inst.ng
     if sym:
         W = np.empty_like(inst.psi)

@@ -96,6 +96,52 @@ def test_batched_graph_replay_is_deterministic(px_ctx):
         assert torch.equal(a, b)
 
 
+def test_batched_ace_streams_and_replays_bitwise(px_ctx):
+    """ACE mode with the grid sizes on one or on two pipeline streams and the
+    tails on the side streams: graph replays (eager work in between) and
+    direct enqueue give bitwise the same xi, M and e_x as the first call with
+    one stream (same kernels and task order per size, fixed-order sums)."""
+    banner("batched ace streams and replays")
+    import torch
+    insts = _make(SPECS, True, px_ctx)
+    args = []
+    for d in insts:
+        n = d["inst"].n_orb
+        d["M"] = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+        args.append(dict(cell=d["cell"], psi=d["psi"], occ=d["occ"], kern=d["kern"], e_x=d["e_x"], M=d["M"],
+                         out=torch.empty_like(d["psi"])))
+        px_ctx.set_tuning(d["cell"], px.PX_PREC_FP32, 8, 8)
+
+    def run():
+        for a in args:
+            a["out"].zero_()
+            a["M"].zero_()
+        _, stats = px_ctx.px_exchange_apply_batched(args, ace=True)
+        px_ctx.px_sync()
+        assert all(int(st.item()) == 0 for st in stats)
+        return [(a["out"].clone(), a["M"].clone(), float(a["e_x"].item())) for a in args]
+
+    try:
+        px_ctx.px_set_batch_streams(1)
+        ref = run()
+        px_ctx.px_set_batch_streams(2)
+        for rep in range(3):
+            junk = torch.randn(1 << 20, device="cuda").sum()      # eager work between replays
+            got = run()
+            del junk
+            for (x, m, e), (x0, m0, e0) in zip(got, ref):
+                assert torch.equal(x, x0) and torch.equal(m, m0) and e == e0, f"replay {rep} differs"
+        px_ctx.px_set_graph(False)
+        got = run()
+        for (x, m, e), (x0, m0, e0) in zip(got, ref):
+            assert torch.equal(x, x0) and torch.equal(m, m0) and e == e0
+    finally:
+        px_ctx.px_set_graph(True)
+        px_ctx.px_set_batch_streams(2)
+        for d in insts:
+            px_ctx.set_tuning(d["cell"], px.PX_PREC_FP32, 0, 0)
+
+
 @pytest.mark.parametrize("blk", [0, 8])
 @pytest.mark.parametrize("fp32", [False, True])
 def test_batched_ace_matches_oracle(px_ctx, fp32, blk):
