@@ -358,12 +358,6 @@ px_status px_exchange_apply_batched(px_context* ctx, int32_t n_inst, const px_in
 /* Pair-buffer bytes of one wave of the batched form (0 = default 4 GiB). */
 px_status px_set_batch_capacity(px_context* ctx, size_t pair_buffer_bytes);
 
-/* Pipeline streams of the batched form: 2 (default) splits the grid sizes
- * over the caller's stream and a second stream of the context (by estimated
- * work), so that waves of different sizes run side by side; 1 runs every
- * wave on the caller's stream.  Other values: PX_ERR_INVALID_ARG. */
-px_status px_set_batch_streams(px_context* ctx, int32_t n);
-
 /* Graph capture of the batched form on (default) or off (direct enqueue). */
 px_status px_set_graph(px_context* ctx, int32_t enable);
 

@@ -47,7 +47,6 @@ struct px_context {
   // signature (instances, pointers, workspace) stays the same
   bool use_graph = true;
   size_t batch_cap_bytes = size_t(4) << 30;  // pair buffer of one wave
-  int batch_lanes = 2;                        // pipeline streams of the batched form
   std::vector<unsigned char> graph_key;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -59,10 +58,6 @@ struct px_context {
   hipStream_t lanes[kTailLanes] = {nullptr, nullptr};
   hipEvent_t lane_done[kTailLanes] = {nullptr, nullptr};
   std::vector<hipEvent_t> fork_events;
-  // second pipeline stream of the batched form (grid sizes split over two
-  // streams) and its fork / join events
-  hipStream_t pipe2 = nullptr;
-  hipEvent_t pipe_fork = nullptr, pipe_done = nullptr;
   ~px_context() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     for (hipEvent_t e : ace_events)
@@ -75,9 +70,6 @@ struct px_context {
       if (lane_done[l]) (void)hipEventDestroy(lane_done[l]);
     }
     for (hipEvent_t e : fork_events) (void)hipEventDestroy(e);
-    if (pipe2) (void)hipStreamDestroy(pipe2);
-    if (pipe_fork) (void)hipEventDestroy(pipe_fork);
-    if (pipe_done) (void)hipEventDestroy(pipe_done);
   }
 };
 
@@ -1081,7 +1073,6 @@ namespace {
 struct BatchWave {
   int n;            // cubic grid size of the wave's instances
   int p2;           // pass-2 configuration of that size
-  int lane;         // pipeline stream (0: the caller's, 1: the second one)
   int first, count; // tasks [first, first + count)
   int max_ic, max_jc, max_pairs, max_slots;  // max_pairs: solved pairs; max_slots: ic * jc
   bool any_v;       // its tasks keep v_ij for pass 4 (a wave holds one block diagonal, so
@@ -1096,10 +1087,7 @@ struct TailGroup {
 };
 
 struct BatchPlan {
-  size_t tasks_off = 0, jobs_off = 0, table_end = 0;
-  // per pipeline lane: pair buffer, slab sums, energy partials
-  size_t t_off[2] = {0, 0}, g0_off[2] = {0, 0}, ex_off[2] = {0, 0};
-  bool two_lanes = false;
+  size_t tasks_off = 0, jobs_off = 0, table_end = 0, t_off = 0, g0_off = 0, ex_off = 0;
   std::vector<size_t> S_off, W_off, K32_off;
   // ACE: per instance M (unless the caller's), L (FP32: then U in complex64),
   // U and the diagonal-block inverses; per lane the Gram split partials
@@ -1135,42 +1123,15 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
   BatchPlan P;
   const bool fp32 = prec == PX_PREC_FP32;
   const size_t b = elem_bytes(prec);
-  // per lane: sizes of the pair buffer and of the per-plane partials
-  size_t t_bytes[2] = {0, 0}, side_pairs[2] = {0, 0};
+  size_t t_bytes = 0, side_pairs = 0;  // sizes of the pair buffer and of the per-plane partials
   // schedule
   std::vector<int> sizes;
   for (int k = 0; k < n_inst; ++k)
     if (std::find(sizes.begin(), sizes.end(), in[k].cell.n[0]) == sizes.end())
       sizes.push_back(in[k].cell.n[0]);
   std::sort(sizes.begin(), sizes.end());
-  // instances of different grid sizes share no buffer, so the sizes are split
-  // over two pipeline streams that run side by side (one size's compute-bound
-  // forward transforms beside another's memory-bound passes, and no launch
-  // drains the GPU alone): by estimated work (solved pairs x N_g), heaviest
-  // size first, each to the lighter lane
-  std::map<int, int> lane_of;
-  {
-    std::vector<std::pair<double, int>> work;
-    for (int nsz : sizes) {
-      double w = 0.0;
-      for (int k = 0; k < n_inst; ++k)
-        if (in[k].cell.n[0] == nsz) w += 0.5 * double(in[k].n) * (in[k].n + 1) * ngrid(&in[k].cell);
-      work.push_back({w, nsz});
-    }
-    std::sort(work.rbegin(), work.rend());
-    double load[2] = {0.0, 0.0};
-    for (const auto& x : work) {
-      const int l = load[1] < load[0] ? 1 : 0;
-      lane_of[x.second] = l;
-      load[l] += x.first;
-    }
-    P.two_lanes = sizes.size() > 1 && c->batch_lanes > 1;
-    if (!P.two_lanes)
-      for (auto& x : lane_of) x.second = 0;
-  }
   struct Chunk { int inst, I, J, B; };
   for (int nsz : sizes) {
-    const int lane = lane_of[nsz];
     // pair-buffer capacity of the size: batch_cap_bytes, at least its largest chunk
     int max_nb = 0;
     size_t min_pairs = 1;
@@ -1183,12 +1144,12 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
       }
     const size_t ng = size_t(nsz) * nsz * nsz;
     const size_t cap = std::max(min_pairs, c->batch_cap_bytes / (ng * b));
-    t_bytes[lane] = std::max(t_bytes[lane], cap * ng * b);
+    t_bytes = std::max(t_bytes, cap * ng * b);
     // per pair: n2 slab sums (g0) and n1 * XS energy-partial slots
     int p2 = 0;  // the tuning of the size (every instance of a size shares it)
     for (int k = 0; k < n_inst; ++k)
       if (in[k].cell.n[0] == nsz) p2 = pass2_cfg_for(c, &in[k].cell, prec);
-    side_pairs[lane] = std::max(side_pairs[lane], cap * size_t(nsz) * px::pass2_sections_cfg(fp32, nsz, p2));
+    side_pairs = std::max(side_pairs, cap * size_t(nsz) * px::pass2_sections_cfg(fp32, nsz, p2));
     for (int d = 0; d < max_nb; ++d) {
       std::vector<Chunk> diag;
       for (int k = 0; k < n_inst; ++k) {
@@ -1203,12 +1164,7 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         const int icc = std::min(ch.B, n - ch.I * ch.B), jcc = std::min(ch.B, n - ch.J * ch.B);
         const size_t pairs = size_t(icc) * jcc;
         if (used + pairs > cap) {
-          BatchWave nw{};
-          nw.n = nsz;
-          nw.p2 = p2;
-          nw.lane = lane;
-          nw.first = int(P.tasks.size());
-          P.waves.push_back(nw);
+          P.waves.push_back({nsz, p2, int(P.tasks.size()), 0, 0, 0, 0, 0, false});
           used = 0;
         }
         BatchWave& w = P.waves.back();
@@ -1269,14 +1225,12 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
   P.jobs_off = off;
   off = align_up(off + P.jobs.size() * sizeof(px::CholJob));
   P.table_end = off;
-  for (int l = 0; l < 2; ++l) {
-    P.t_off[l] = off;
-    off = align_up(off + t_bytes[l]);
-    P.g0_off[l] = off;
-    if (fp32) off = align_up(off + side_pairs[l] * sizeof(px::G0Part));
-    P.ex_off[l] = off;
-    off = align_up(off + side_pairs[l] * 8 * (fp32 ? 3 : 1));
-  }
+  P.t_off = off;
+  off = align_up(off + t_bytes);
+  P.g0_off = off;
+  if (fp32) off = align_up(off + side_pairs * sizeof(px::G0Part));
+  P.ex_off = off;
+  off = align_up(off + side_pairs * 8 * (fp32 ? 3 : 1));
   P.S_off.resize(n_inst);
   P.W_off.resize(n_inst);
   P.K32_off.resize(n_inst);
@@ -1327,9 +1281,9 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         px::ChunkArgs& a = P.tasks[t];
         const size_t pofs = reinterpret_cast<size_t>(a.t);
         const int k = int(reinterpret_cast<size_t>(a.S));
-        a.t = ws + P.t_off[w.lane] + pofs * ng * b;
-        a.g0 = reinterpret_cast<px::G0Part*>(ws + P.g0_off[w.lane] + pofs * w.n * sizeof(px::G0Part));
-        a.expart = reinterpret_cast<double*>(ws + P.ex_off[w.lane] + pofs * w.n *
+        a.t = ws + P.t_off + pofs * ng * b;
+        a.g0 = reinterpret_cast<px::G0Part*>(ws + P.g0_off + pofs * w.n * sizeof(px::G0Part));
+        a.expart = reinterpret_cast<double*>(ws + P.ex_off + pofs * w.n *
                                              px::pass2_sections_cfg(fp32, w.n, w.p2) * 8 *
                                              (fp32 ? 3 : 1));
         a.S = reinterpret_cast<double*>(ws + P.S_off[k]);
@@ -1432,8 +1386,7 @@ px_status enqueue_tail(px_context* c, const BatchPlan& P, const TailGroup& g, co
   return PX_OK;
 }
 
-// Side streams and events of the batched form: the ACE tail lanes and the
-// second pipeline stream (created once per context).
+// Side streams and events of the ACE tails (created once per context).
 px_status ensure_lanes(px_context* c, size_t n_fork) {
   for (int l = 0; l < px_context::kTailLanes; ++l) {
     if (!c->lanes[l] && hipStreamCreateWithFlags(&c->lanes[l], hipStreamNonBlocking) != hipSuccess)
@@ -1442,11 +1395,6 @@ px_status ensure_lanes(px_context* c, size_t n_fork) {
         hipEventCreateWithFlags(&c->lane_done[l], hipEventDisableTiming) != hipSuccess)
       return fail(c, PX_ERR_DEVICE, "hipEventCreate failed");
   }
-  if (!c->pipe2 && hipStreamCreateWithFlags(&c->pipe2, hipStreamNonBlocking) != hipSuccess)
-    return fail(c, PX_ERR_DEVICE, "hipStreamCreate (pipeline lane) failed");
-  for (hipEvent_t* e : {&c->pipe_fork, &c->pipe_done})
-    if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
-      return fail(c, PX_ERR_DEVICE, "hipEventCreate failed");
   while (c->fork_events.size() < n_fork) {
     hipEvent_t e;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
@@ -1457,10 +1405,9 @@ px_status ensure_lanes(px_context* c, size_t n_fork) {
 }
 
 // Everything of one batched call, stream ordered on s: the pair-pipeline
-// waves on s or, for the grid sizes of lane 1, on the second pipeline stream
-// (forked from s after the uploads); in ACE mode each tail group on its lane
-// once its wave has run; s waits for every stream at the end (also after an
-// error, so that a capture is always joined).
+// waves on s; in ACE mode each tail group on its lane once its wave has run,
+// and s waits for every lane at the end (also after an error, so that a
+// capture is always joined).
 px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_instance* in,
                         px_precision prec, bool ace, const void* host_table, hipStream_t s) {
   const bool fp32 = prec == PX_PREC_FP32;
@@ -1470,7 +1417,7 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
                                              hipMemcpyHostToDevice, s),
                            "task table upload");
   if (st != PX_OK) return st;
-  if ((ace || P.two_lanes) && (st = ensure_lanes(c, P.waves.size())) != PX_OK) return st;
+  if (ace && (st = ensure_lanes(c, P.waves.size())) != PX_OK) return st;
   if (fp32) {
     for (int k = 0; k < n_inst; ++k) {
       st = hip_check(c, px::launch_convert_f64_f32(ngrid(&in[k].cell), in[k].kernel_G,
@@ -1480,35 +1427,27 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
     }
   }
   bool used[px_context::kTailLanes] = {false, false};
-  const hipStream_t ps[2] = {s, P.two_lanes ? c->pipe2 : s};
-  bool forked = false;
-  if (P.two_lanes) {
-    st = hip_check(c, hipEventRecord(c->pipe_fork, s), "pipeline fork");
-    if (st == PX_OK) st = hip_check(c, hipStreamWaitEvent(c->pipe2, c->pipe_fork, 0), "pipeline fork");
-    forked = st == PX_OK;
-  }
   size_t gi = 0;
   for (int wi = 0; wi < int(P.waves.size()) && st == PX_OK; ++wi) {
     const BatchWave& w = P.waves[wi];
-    const hipStream_t ws_ = ps[w.lane];
     const size_t ng = size_t(w.n) * w.n * w.n;
     st = hip_check(c, px::launch_chunk_tasks(fp32, w.n, dt + w.first, w.count, w.max_ic,
-                                             w.max_pairs, true, w.any_v, w.p2, ws_),
+                                             w.max_pairs, true, w.any_v, w.p2, s),
                    "batched pair pipeline");
     if (st != PX_OK) break;
     if (w.any_v) {
-      st = hip_check(c, px::launch_pass4_tasks(fp32, dt + w.first, w.count, w.max_jc, ng, ws_),
+      st = hip_check(c, px::launch_pass4_tasks(fp32, dt + w.first, w.count, w.max_jc, ng, s),
                      "batched transposed accumulation");
       if (st != PX_OK) break;
     }
     st = hip_check(c, px::launch_expart_reduce_tasks(fp32, dt + w.first, w.count, w.max_slots,
                                                      w.n * px::pass2_sections_cfg(fp32, w.n, w.p2), w.n,
-                                                     double(ng), ws_),
+                                                     double(ng), s),
                    "batched energy partials");
     if (st != PX_OK) break;
     if (gi < P.groups.size() && P.groups[gi].after_wave == wi) {
       hipEvent_t e = c->fork_events[wi];
-      st = hip_check(c, hipEventRecord(e, ws_), "fork event");
+      st = hip_check(c, hipEventRecord(e, s), "fork event");
       while (st == PX_OK && gi < P.groups.size() && P.groups[gi].after_wave == wi) {
         const TailGroup& g = P.groups[gi++];
         st = hip_check(c, hipStreamWaitEvent(c->lanes[g.lane], e, 0), "tail lane wait");
@@ -1522,11 +1461,6 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
     if (!used[l]) continue;
     px_status sj = hip_check(c, hipEventRecord(c->lane_done[l], c->lanes[l]), "lane event");
     if (sj == PX_OK) sj = hip_check(c, hipStreamWaitEvent(s, c->lane_done[l], 0), "lane join");
-    if (st == PX_OK) st = sj;
-  }
-  if (forked) {
-    px_status sj = hip_check(c, hipEventRecord(c->pipe_done, c->pipe2), "pipeline event");
-    if (sj == PX_OK) sj = hip_check(c, hipStreamWaitEvent(s, c->pipe_done, 0), "pipeline join");
     if (st == PX_OK) st = sj;
   }
   if (st != PX_OK || ace) return st;
@@ -1556,7 +1490,6 @@ std::vector<unsigned char> batch_key(const px_context* c, int n_inst, const px_i
   put(&c->ws, sizeof c->ws);
   put(&c->ws_bytes, sizeof c->ws_bytes);
   put(&c->batch_cap_bytes, sizeof c->batch_cap_bytes);
-  put(&c->batch_lanes, sizeof c->batch_lanes);
   for (int k = 0; k < n_inst; ++k) {
     put(&in[k], sizeof(px_instance));
     const int B = block_for(c, &in[k].cell, prec), p2 = pass2_cfg_for(c, &in[k].cell, prec);
@@ -1583,13 +1516,6 @@ size_t px_workspace_bytes_batched(const px_context* ctx, int32_t n_inst, const p
 px_status px_set_batch_capacity(px_context* ctx, size_t pair_buffer_bytes) {
   if (!ctx) return PX_ERR_INVALID_ARG;
   ctx->batch_cap_bytes = pair_buffer_bytes ? pair_buffer_bytes : (size_t(4) << 30);
-  return PX_OK;
-}
-
-px_status px_set_batch_streams(px_context* ctx, int32_t n) {
-  if (!ctx) return PX_ERR_INVALID_ARG;
-  if (n != 1 && n != 2) return fail(ctx, PX_ERR_INVALID_ARG, "batch streams: 1 or 2, not %d", int(n));
-  ctx->batch_lanes = n;
   return PX_OK;
 }
 

@@ -74,7 +74,6 @@ SIGNATURES = {
     "px_workspace_bytes_batched": (_sz, [_vp, _i32, _instp, _i32, _i32]),
     "px_exchange_apply_batched": (_i32, [_vp, _i32, _instp, _i32, _i32, _vp]),
     "px_set_batch_capacity": (_i32, [_vp, _sz]),
-    "px_set_batch_streams": (_i32, [_vp, _i32]),
     "px_set_graph": (_i32, [_vp, _i32]),
     "px_autotune": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.c_char_p,
                            ctypes.POINTER(_i32), _vp]),
@@ -473,9 +472,6 @@ class Context:
 
     def px_set_batch_capacity(self, nbytes: int):
         self._check(self.lib.px_set_batch_capacity(self.h, int(nbytes)))
-
-    def px_set_batch_streams(self, n: int):
-        self._check(self.lib.px_set_batch_streams(self.h, int(n)))
 
     def px_autotune(self, cell: Cell, psi, occ, kern, out=None, cache_path=None, stream=None):
         """Returns the fastest square pair block for this grid and precision

@@ -195,13 +195,6 @@ def test_batched_validation(lib, ctx):
     assert lib.px_workspace_bytes_batched(ctx, 2, bad, 0, 0) == 0
     with_ace = (px.PxInstance * 2)(_inst(status=FAKE), _inst(32, status=FAKE))
     assert lib.px_workspace_bytes_batched(ctx, 2, with_ace, 0, 1) > need
-    # one or two pipeline streams; two sizes on two streams need a second pair buffer
-    assert lib.px_set_batch_streams(ctx, 0) == px.PX_ERR_INVALID_ARG
-    assert lib.px_set_batch_streams(ctx, 3) == px.PX_ERR_INVALID_ARG
-    assert lib.px_set_batch_streams(ctx, 1) == px.PX_OK
-    one = lib.px_workspace_bytes_batched(ctx, 2, arr, 0, 0)
-    assert lib.px_set_batch_streams(ctx, 2) == px.PX_OK
-    assert one < need
 
 
 def test_load_tuning_cache(lib, ctx, tmp_path):

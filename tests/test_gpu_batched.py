@@ -96,12 +96,11 @@ def test_batched_graph_replay_is_deterministic(px_ctx):
         assert torch.equal(a, b)
 
 
-def test_batched_ace_streams_and_replays_bitwise(px_ctx):
-    """ACE mode with the grid sizes on one or on two pipeline streams and the
-    tails on the side streams: graph replays (eager work in between) and
-    direct enqueue give bitwise the same xi, M and e_x as the first call with
-    one stream (same kernels and task order per size, fixed-order sums)."""
-    banner("batched ace streams and replays")
+def test_batched_ace_replays_bitwise(px_ctx):
+    """ACE mode with the tails on the side streams: graph replays (eager work
+    in between) and direct enqueue give bitwise the same xi, M and e_x as the
+    first call (same kernels and task order, fixed-order sums)."""
+    banner("batched ace replays")
     import torch
     insts = _make(SPECS, True, px_ctx)
     args = []
@@ -122,9 +121,7 @@ def test_batched_ace_streams_and_replays_bitwise(px_ctx):
         return [(a["out"].clone(), a["M"].clone(), float(a["e_x"].item())) for a in args]
 
     try:
-        px_ctx.px_set_batch_streams(1)
         ref = run()
-        px_ctx.px_set_batch_streams(2)
         for rep in range(3):
             junk = torch.randn(1 << 20, device="cuda").sum()      # eager work between replays
             got = run()
@@ -137,7 +134,6 @@ def test_batched_ace_streams_and_replays_bitwise(px_ctx):
             assert torch.equal(x, x0) and torch.equal(m, m0) and e == e0
     finally:
         px_ctx.px_set_graph(True)
-        px_ctx.px_set_batch_streams(2)
         for d in insts:
             px_ctx.set_tuning(d["cell"], px.PX_PREC_FP32, 0, 0)
 
