@@ -4,6 +4,7 @@ Measurement harness beside bench.py (not part of the library):
 
     python profsum.py --workload W --trace DIR --fetch DIR --write DIR \
         --copy-fetch DIR --copy-write DIR --bench-json FILE --out profiles
+    python profsum.py --workload W --trace DIR --bench-json FILE --out profiles
     python profsum.py --workload W --mfma DIR --out profiles
     python profsum.py --workload W --sq DIR DIR DIR --out profiles
 
@@ -80,12 +81,19 @@ def _per_kernel(d):
 
 
 def _short(name):
-    # "void px::pass3_inv_xy_acc<float, 72, ...>(...)" -> "pass3_inv_xy_acc"
+    # "void px::pass3_inv_xy_acc<float, 72, ...>(...)" -> "pass3_inv_xy_acc"; the staged
+    # form of pass 3 (FP32 at 72^3-96^3) counts as pass 3
     base = name.split("(")[0].split("<")[0]
-    return base.split("::")[-1].replace("void ", "").strip()
+    short = base.split("::")[-1].replace("void ", "").strip()
+    return "pass3_inv_xy_acc" if short == "pass3_staged" else short
 
 
 def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, commands, workload):
+    summarize_trace(trace, bench_json, out, commands, workload)
+    summarize_hbm(fetch, write, copy_fetch, copy_write, out, commands, workload)
+
+
+def summarize_trace(trace, bench_json, out, commands, workload):
     os.makedirs(out, exist_ok=True)
     rec = json.loads(open(bench_json).read().strip().splitlines()[-1])
     stats = _csv(trace, "kernel_stats.csv")
@@ -123,6 +131,8 @@ def summarize(trace, fetch, write, copy_fetch, copy_write, bench_json, out, comm
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
     open(os.path.join(out, f"pair_pipeline_{workload}_kernel_trace.md"), "w").write("\n".join(lines) + "\n")
 
+
+def summarize_hbm(fetch, write, copy_fetch, copy_write, out, commands, workload):
     fc, wc = _per_kernel(copy_fetch), _per_kernel(copy_write)
     ck = [k for k in fc if "stream_copy" in k][0]
     f_copy = sum(fc[ck]) / len(fc[ck])
@@ -307,8 +317,11 @@ def main():
                                (400, "FETCH_SIZE", "pmc_fetch_bench", f"{one} --no-fp64 --no-cpu"),
                                (400, "WRITE_SIZE", "pmc_write_bench", f"{one} --no-fp64 --no-cpu"))],
     }
-    summarize(args.trace, args.fetch, args.write, args.copy_fetch, args.copy_write, args.bench_json,
-              args.out, commands, w)
+    if args.fetch:
+        summarize(args.trace, args.fetch, args.write, args.copy_fetch, args.copy_write, args.bench_json,
+                  args.out, commands, w)
+    else:  # kernel trace only
+        summarize_trace(args.trace, args.bench_json, args.out, commands, w)
 
 
 if __name__ == "__main__":
