@@ -19,6 +19,9 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libpx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SIZES = (16, 24, 32, 40, 48, 60, 64, 72, 80, 96)
+# non-cubic grids (x, y, z): the wavefunction grids of the paper's 768- and
+# 1536-atom cells
+SHAPES = ((60, 60, 90), (60, 90, 120))
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", HERE,
@@ -37,6 +40,9 @@ def _units():
     units = []
     for n in SIZES:
         units.append(("exchange_inst.hip", f"exchange_n{n}.o", [f"-DPX_N={n}"]))
+    for n0, n1, n2 in SHAPES:
+        units.append(("exchange_shape.hip", f"exchange_s{n0}x{n1}x{n2}.o",
+                      [f"-DPX_S0={n0}", f"-DPX_S1={n1}", f"-DPX_S2={n2}"]))
     for src in ("exchange_dispatch.cpp", "pair_transpose.hip", "misc_kernels.hip", "gemm_kernels.hip",
                 "chol_kernels.hip", "eig_kernels.hip", "px_api.cpp"):
         units.append((src, os.path.splitext(src)[0] + ".o", []))

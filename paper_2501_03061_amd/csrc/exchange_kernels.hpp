@@ -1232,4 +1232,68 @@ hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, bo
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- other grids
+// Grids whose three lengths differ (the wavefunction grids of the paper's
+// 768- and 1536-atom cells, 60 x 60 x 90 and 60 x 90 x 120): configurations
+// derived from the plans alone, without the per-size tuning of the cubic
+// grids.  Threads = the largest stage's butterfly count rounded up to whole
+// waves, halved while above 768 (12 waves leave 170 registers per thread at
+// one workgroup per CU: the 960-thread form of pass 3 at 60 x 90 spilled);
+// ping-pong slabs where two fit; no cross-pair prefetch; one x-section per
+// pass-2 plane and one pair per workgroup.
+constexpr int wave_threads(int butterflies) {
+  int t = (butterflies + 63) / 64 * 64;
+  while (t > 768) t = (t / 2 + 63) / 64 * 64;
+  return t;
+}
+template <int N0, int N1> constexpr int slab_threads() {
+  int m = 0;
+  for (int s = 0; s < Plan<N0>::nst; ++s) m = m > N1 * (N0 / Plan<N0>::rad[s]) ? m : N1 * (N0 / Plan<N0>::rad[s]);
+  for (int s = 0; s < Plan<N1>::nst; ++s) m = m > N0 * (N1 / Plan<N1>::rad[s]) ? m : N0 * (N1 / Plan<N1>::rad[s]);
+  return wave_threads(m);
+}
+template <int N0, int N2> constexpr int plane_threads() {
+  int m = 0;
+  for (int s = 0; s < Plan<N2>::nst; ++s) m = m > N0 * (N2 / Plan<N2>::rad[s]) ? m : N0 * (N2 / Plan<N2>::rad[s]);
+  return wave_threads(m);
+}
+
+template <int N0, int N1, int N2>
+hipError_t launch_chunk_shape(bool fp32, const ChunkArgs& a, int npairs, bool ex, bool store_v,
+                              hipStream_t s, hipEvent_t* ev, const ChunkArgs* tasks, int ntasks,
+                              int max_ic) {
+  if (!tasks) {
+    ntasks = 1;
+    max_ic = a.ic;
+  }
+  constexpr int NT1 = slab_threads<N0, N1>(), NT2 = plane_threads<N0, N2>();
+  constexpr bool PPF = pingpong_fits<float, N0, N1>(), PPD = pingpong_fits<double, N0, N1>();
+  const dim3 g1(N2, max_ic, ntasks), g2(N1, npairs, ntasks);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  if (fp32)
+    hipLaunchKernelGGL((pass1_fwd_xy<float, N0, N1, NT1, true, false, PPF>), g1, dim3(NT1), 0, s, a, tasks);
+  else
+    hipLaunchKernelGGL((pass1_fwd_xy<double, N0, N1, NT1, false, false, PPD>), g1, dim3(NT1), 0, s, a, tasks);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  if (fp32 && ex)
+    hipLaunchKernelGGL((pass2_z_kernel<float, N0, N1, N2, NT2, true, true, 1, false, 1>), g2, dim3(NT2), 0, s, a, tasks);
+  else if (fp32)
+    hipLaunchKernelGGL((pass2_z_kernel<float, N0, N1, N2, NT2, true, false, 1, false, 1>), g2, dim3(NT2), 0, s, a, tasks);
+  else if (ex)
+    hipLaunchKernelGGL((pass2_z_kernel<double, N0, N1, N2, NT2, false, true, 1, false, 1>), g2, dim3(NT2), 0, s, a, tasks);
+  else
+    hipLaunchKernelGGL((pass2_z_kernel<double, N0, N1, N2, NT2, false, false, 1, false, 1>), g2, dim3(NT2), 0, s, a, tasks);
+  if (ev) (void)hipEventRecord(ev[2], s);
+  if (fp32 && store_v)
+    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N0, N1, NT1, false, true, PPF>), g1, dim3(NT1), 0, s, a, tasks);
+  else if (fp32)
+    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N0, N1, NT1, false, false, PPF>), g1, dim3(NT1), 0, s, a, tasks);
+  else if (store_v)
+    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N0, N1, NT1, false, true, PPD>), g1, dim3(NT1), 0, s, a, tasks);
+  else
+    hipLaunchKernelGGL((pass3_inv_xy_acc<double, N0, N1, NT1, false, false, PPD>), g1, dim3(NT1), 0, s, a, tasks);
+  if (ev) (void)hipEventRecord(ev[3], s);
+  return hipGetLastError();
+}
+
 }  // namespace px

@@ -234,7 +234,9 @@ PX_PLAN(60, 2, 6, 10, 1)
 PX_PLAN(64, 2, 8, 8, 1)
 PX_PLAN(72, 2, 8, 9, 1)
 PX_PLAN(80, 2, 8, 10, 1)
+PX_PLAN(90, 2, 9, 10, 1)
 PX_PLAN(96, 2, 8, 12, 1)
+PX_PLAN(120, 2, 10, 12, 1)
 #undef PX_PLAN
 
 // Radix and span of stage S of the plan's radix sequence (INV = false) or of

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <string>
@@ -148,7 +149,7 @@ ExLayout ex_layout(const px_cell* cell, px_precision prec, int n_psi, int n_phi,
   l.expart = off;
   l.S = off;
   if (energy) {
-    const size_t slots = size_t(cell->n[1]) * px::pass2_sections_cfg(prec == PX_PREC_FP32, cell->n[0], p2);
+    const size_t slots = size_t(cell->n[1]) * px::pass2_sections_grid(prec == PX_PREC_FP32, cell->n, p2);
     off = align_up(off + pairs * slots * 8 * (prec == PX_PREC_FP32 ? 3 : 1));
     l.S = off;
     off = align_up(off + size_t(n_phi) * n_psi * 8);
@@ -309,7 +310,8 @@ px_status check_grid(px_context* c, const px_cell* cell) {
     return fail(c, PX_ERR_INVALID_ARG, "cell: edge lengths must be > 0 and grid sizes > 0");
   if (!px::grid_supported(cell->n[0], cell->n[1], cell->n[2]))
     return fail(c, PX_ERR_UNSUPPORTED_GRID,
-                "grid %dx%dx%d has no compiled FFT plan (cubic n in {16,24,32,40,48,60,64,72,80,96})",
+                "grid %dx%dx%d has no compiled FFT plan (cubic n in {16,24,32,40,48,60,64,72,80,96}, "
+                "or 60x60x90, 60x90x120)",
                 cell->n[0], cell->n[1], cell->n[2]);
   return PX_OK;
 }
@@ -394,7 +396,7 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       const int npairs = px::chunk_pairs(a);
       hipEvent_t* ev = c->profiling ? &c->events[5 * nchunks] : nullptr;
       px_status st = hip_check(
-          c, px::launch_chunk(fp32, cell->n[0], a, npairs, energy, p2, s, ev), "pair pipeline");
+          c, px::launch_chunk(fp32, cell->n, a, npairs, energy, p2, s, ev), "pair pipeline");
       if (st != PX_OK) return st;
       if (a.store_v) {
         st = hip_check(c, px::launch_pass4(fp32, a, ng, s), "transposed accumulation");
@@ -423,7 +425,7 @@ px_status run_exchange(px_context* c, const px_cell* cell, px_precision prec, in
       ++nchunks;
       if (energy) {
         st = hip_check(c, px::launch_expart_reduce(a.expart, fp32 ? a.g0 : nullptr,
-                                                   cell->n[1] * px::pass2_sections_cfg(fp32, cell->n[0], p2),
+                                                   cell->n[1] * px::pass2_sections_grid(fp32, cell->n, p2),
                                                    cell->n[2], double(ng), i0, a.ic, j0, a.jc, S,
                                                    n_psi, a.store_v != 0, a.tri != 0, s),
                        "energy partials");
@@ -1071,7 +1073,7 @@ px_status px_profile_read_ace(px_context* ctx, double* ms, int64_t* calls, int32
 namespace {
 
 struct BatchWave {
-  int n;            // cubic grid size of the wave's instances
+  int g[3];         // grid of the wave's instances
   int p2;           // pass-2 configuration of that size
   int first, count; // tasks [first, first + count)
   int max_ic, max_jc, max_pairs, max_slots;  // max_pairs: solved pairs; max_slots: ic * jc
@@ -1124,36 +1126,42 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
   const bool fp32 = prec == PX_PREC_FP32;
   const size_t b = elem_bytes(prec);
   size_t t_bytes = 0, side_pairs = 0;  // sizes of the pair buffer and of the per-plane partials
-  // schedule
-  std::vector<int> sizes;
+  // schedule: grids in order of size
+  using Grid = std::array<int, 3>;
+  auto grid_of = [&](int k) { return Grid{in[k].cell.n[0], in[k].cell.n[1], in[k].cell.n[2]}; };
+  std::vector<Grid> grids;
   for (int k = 0; k < n_inst; ++k)
-    if (std::find(sizes.begin(), sizes.end(), in[k].cell.n[0]) == sizes.end())
-      sizes.push_back(in[k].cell.n[0]);
-  std::sort(sizes.begin(), sizes.end());
+    if (std::find(grids.begin(), grids.end(), grid_of(k)) == grids.end()) grids.push_back(grid_of(k));
+  std::sort(grids.begin(), grids.end(), [](const Grid& x, const Grid& y) {
+    const size_t nx = size_t(x[0]) * x[1] * x[2], ny = size_t(y[0]) * y[1] * y[2];
+    return nx != ny ? nx < ny : x < y;
+  });
   struct Chunk { int inst, I, J, B; };
-  for (int nsz : sizes) {
-    // pair-buffer capacity of the size: batch_cap_bytes, at least its largest chunk
+  for (const Grid& gr : grids) {
+    // pair-buffer capacity of the grid: batch_cap_bytes, at least its largest chunk
     int max_nb = 0;
     size_t min_pairs = 1;
     for (int k = 0; k < n_inst; ++k)
-      if (in[k].cell.n[0] == nsz) {
+      if (grid_of(k) == gr) {
         const int B = block_for(c, &in[k].cell, prec);
         max_nb = std::max(max_nb, (int(in[k].n) + B - 1) / B);
         const size_t e = size_t(std::min(B, int(in[k].n)));
         min_pairs = std::max(min_pairs, e * e);
       }
-    const size_t ng = size_t(nsz) * nsz * nsz;
+    const size_t ng = size_t(gr[0]) * gr[1] * gr[2];
     const size_t cap = std::max(min_pairs, c->batch_cap_bytes / (ng * b));
     t_bytes = std::max(t_bytes, cap * ng * b);
     // per pair: n2 slab sums (g0) and n1 * XS energy-partial slots
-    int p2 = 0;  // the tuning of the size (every instance of a size shares it)
+    int p2 = 0;  // the tuning of the grid (every instance of a grid shares it)
     for (int k = 0; k < n_inst; ++k)
-      if (in[k].cell.n[0] == nsz) p2 = pass2_cfg_for(c, &in[k].cell, prec);
-    side_pairs = std::max(side_pairs, cap * size_t(nsz) * px::pass2_sections_cfg(fp32, nsz, p2));
+      if (grid_of(k) == gr) p2 = pass2_cfg_for(c, &in[k].cell, prec);
+    const size_t per_pair = std::max(size_t(gr[1]) * px::pass2_sections_grid(fp32, gr.data(), p2),
+                                     size_t(gr[2]));
+    side_pairs = std::max(side_pairs, cap * per_pair);
     for (int d = 0; d < max_nb; ++d) {
       std::vector<Chunk> diag;
       for (int k = 0; k < n_inst; ++k) {
-        if (in[k].cell.n[0] != nsz) continue;
+        if (grid_of(k) != gr) continue;
         const int B = block_for(c, &in[k].cell, prec);
         const int nb = (int(in[k].n) + B - 1) / B;
         for (int J = 0; J + d < nb; ++J) diag.push_back({k, J + d, J, B});
@@ -1164,7 +1172,7 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         const int icc = std::min(ch.B, n - ch.I * ch.B), jcc = std::min(ch.B, n - ch.J * ch.B);
         const size_t pairs = size_t(icc) * jcc;
         if (used + pairs > cap) {
-          P.waves.push_back({nsz, p2, int(P.tasks.size()), 0, 0, 0, 0, 0, false});
+          P.waves.push_back({{gr[0], gr[1], gr[2]}, p2, int(P.tasks.size()), 0, 0, 0, 0, 0, false});
           used = 0;
         }
         BatchWave& w = P.waves.back();
@@ -1176,7 +1184,7 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
         a.first = d == 0;
         a.tri = d == 0 && c->tri_diag && icc == jcc;
         a.store_v = d > 0 || a.tri;
-        a.n2 = nsz;
+        a.n2 = gr[2];
         a.inv_ng = 1.0 / double(ng);
         a.s_ld = n;
         // pointers are filled below once the layout is known; keep the
@@ -1276,15 +1284,15 @@ BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_
   P.end = off;
   if (ws) {
     for (const BatchWave& w : P.waves) {
-      const size_t ng = size_t(w.n) * w.n * w.n;
+      const size_t ng = size_t(w.g[0]) * w.g[1] * w.g[2];
       for (int t = w.first; t < w.first + w.count; ++t) {
         px::ChunkArgs& a = P.tasks[t];
         const size_t pofs = reinterpret_cast<size_t>(a.t);
         const int k = int(reinterpret_cast<size_t>(a.S));
         a.t = ws + P.t_off + pofs * ng * b;
-        a.g0 = reinterpret_cast<px::G0Part*>(ws + P.g0_off + pofs * w.n * sizeof(px::G0Part));
-        a.expart = reinterpret_cast<double*>(ws + P.ex_off + pofs * w.n *
-                                             px::pass2_sections_cfg(fp32, w.n, w.p2) * 8 *
+        a.g0 = reinterpret_cast<px::G0Part*>(ws + P.g0_off + pofs * w.g[2] * sizeof(px::G0Part));
+        a.expart = reinterpret_cast<double*>(ws + P.ex_off + pofs * w.g[1] *
+                                             px::pass2_sections_grid(fp32, w.g, w.p2) * 8 *
                                              (fp32 ? 3 : 1));
         a.S = reinterpret_cast<double*>(ws + P.S_off[k]);
         a.out = ace ? static_cast<void*>(ws + P.W_off[k]) : in[k].out;
@@ -1430,8 +1438,8 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
   size_t gi = 0;
   for (int wi = 0; wi < int(P.waves.size()) && st == PX_OK; ++wi) {
     const BatchWave& w = P.waves[wi];
-    const size_t ng = size_t(w.n) * w.n * w.n;
-    st = hip_check(c, px::launch_chunk_tasks(fp32, w.n, dt + w.first, w.count, w.max_ic,
+    const size_t ng = size_t(w.g[0]) * w.g[1] * w.g[2];
+    st = hip_check(c, px::launch_chunk_tasks(fp32, w.g, dt + w.first, w.count, w.max_ic,
                                              w.max_pairs, true, w.any_v, w.p2, s),
                    "batched pair pipeline");
     if (st != PX_OK) break;
@@ -1441,7 +1449,7 @@ px_status enqueue_batch(px_context* c, const BatchPlan& P, int n_inst, const px_
       if (st != PX_OK) break;
     }
     st = hip_check(c, px::launch_expart_reduce_tasks(fp32, dt + w.first, w.count, w.max_slots,
-                                                     w.n * px::pass2_sections_cfg(fp32, w.n, w.p2), w.n,
+                                                     w.g[1] * px::pass2_sections_grid(fp32, w.g, w.p2), w.g[2],
                                                      double(ng), s),
                    "batched energy partials");
     if (st != PX_OK) break;
@@ -1625,7 +1633,7 @@ px_status px_autotune(px_context* ctx, const px_cell* cell, px_precision prec, i
   for (int B : cand) {
     if (covered) break;
     covered = B >= n;
-    for (int p2 = 0; p2 < 2 && st == PX_OK; ++p2) {
+    for (int p2 = 0; p2 < px::pass2_configs(cell->n) && st == PX_OK; ++p2) {
       const ExLayout l = ex_layout(cell, prec, n, n, B, B, false, p2);
       if (ctx->ws == nullptr || ctx->ws_bytes < l.end) continue;
       float ms = 0.f, best_ms = 1e30f;
@@ -1699,7 +1707,8 @@ px_status px_load_tuning(px_context* ctx, const char* cache_path, int32_t* appli
     const int pr = strcmp(prec, "fp32") == 0 ? int(PX_PREC_FP32) : int(PX_PREC_FP64);
     int p2 = 0;  // pass-2 configuration (absent in older lines: the default)
     const char* pq = strstr(line, "\"p2\": ");
-    if (pq && (sscanf(pq, "\"p2\": %d", &p2) != 1 || p2 < 0 || p2 > 1)) p2 = 0;
+    const int grid[3] = {n0, n1, n2};
+    if (pq && (sscanf(pq, "\"p2\": %d", &p2) != 1 || p2 < 0 || p2 >= px::pass2_configs(grid))) p2 = 0;
     ctx->tuning[std::make_tuple(n0, n1, n2, pr)] = {blk, blk, p2};
     ++count;
   }

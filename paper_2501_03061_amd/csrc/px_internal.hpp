@@ -96,7 +96,9 @@ __device__ __forceinline__ ChunkArgs chunk_args(const ChunkArgs& a0, const Chunk
 }
 #endif
 
+// Grids with compiled pipelines: the cubic sizes and the non-cubic shapes.
 bool grid_supported(int n0, int n1, int n2);
+bool grid_cubic(int n0, int n1, int n2);
 
 // x-sections per y-plane tile of pass 2 (the z transforms, kernel multiply and
 // the exchange-energy partials): a pass-2 workgroup takes N0/XS of the plane's
@@ -122,15 +124,22 @@ constexpr int pass2_sections(bool fp32, int n) {
 constexpr int pass2_sections_cfg(bool fp32, int n, int cfg) {
   return cfg == 0 ? pass2_sections(fp32, n) : (pass2_sections(fp32, n) == 1 ? 2 : 1);
 }
-// Launches pass 1, 2, 3 of one chunk; ev (nullable) = 4 events recorded
-// before pass 1, between the passes and after pass 3.
-hipError_t launch_chunk(bool fp32, int n, const ChunkArgs& a, int npairs, bool ex, int p2cfg,
+// The same for any grid n[3]: non-cubic grids have one configuration, with one
+// section.
+inline int pass2_sections_grid(bool fp32, const int* n, int cfg) {
+  return grid_cubic(n[0], n[1], n[2]) ? pass2_sections_cfg(fp32, n[0], cfg) : 1;
+}
+// Pass-2 configurations the autotuner can choose from on grid n[3].
+inline int pass2_configs(const int* n) { return grid_cubic(n[0], n[1], n[2]) ? 2 : 1; }
+// Launches pass 1, 2, 3 of one chunk on grid n[3]; ev (nullable) = 4 events
+// recorded before pass 1, between the passes and after pass 3.
+hipError_t launch_chunk(bool fp32, const int* n, const ChunkArgs& a, int npairs, bool ex, int p2cfg,
                         hipStream_t s, hipEvent_t* ev);
 
 // The same passes over a task table in device memory (ntasks chunks of one
-// grid size, all with ic <= max_ic and at most max_pairs solved pairs
+// grid, all with ic <= max_ic and at most max_pairs solved pairs
 // (chunk_pairs), and all with the given store_v), one launch each.
-hipError_t launch_chunk_tasks(bool fp32, int n, const ChunkArgs* tasks, int ntasks, int max_ic,
+hipError_t launch_chunk_tasks(bool fp32, const int* n, const ChunkArgs* tasks, int ntasks, int max_ic,
                               int max_pairs, bool ex, bool store_v, int p2cfg, hipStream_t s);
 // Pass 4 over a task table (tasks without kept v_ij are skipped).
 hipError_t launch_pass4_tasks(bool fp32, const ChunkArgs* tasks, int ntasks, int max_jc, size_t ng,

@@ -64,6 +64,11 @@ def test_grid_support(lib):
         assert lib.px_grid_supported(ctypes.byref(_cell(n)), 0) == 0
     noncubic = px.Cell((1.0, 1.0, 1.0), (24, 24, 32)).c()
     assert lib.px_grid_supported(ctypes.byref(noncubic), 0) == 0
+    # the non-cubic grids with compiled pipelines (x, y, z), and not their transposes
+    for n in ((60, 60, 90), (60, 90, 120)):
+        assert lib.px_grid_supported(ctypes.byref(px.Cell((1.0, 1.0, 1.0), n).c()), 0) == 1
+    for n in ((90, 60, 60), (120, 90, 60), (60, 120, 90)):
+        assert lib.px_grid_supported(ctypes.byref(px.Cell((1.0, 1.0, 1.0), n).c()), 0) == 0
 
 
 def test_create_rejects_negative_device(lib):

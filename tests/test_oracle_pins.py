@@ -158,6 +158,29 @@ def test_p4_plane_wave_closed_form():
     assert _relerr(out, lam * phi) < 1e-13
 
 
+def test_p4_plane_wave_closed_form_orthorhombic():
+    """P4 on an orthorhombic cell with three different edge lengths and grid
+    lengths: each momentum component must meet its own edge, so a kernel table
+    that pairs an axis with another edge length or array axis gives other
+    K(G) values and fails."""
+    n, L, mu = (6, 8, 10), (3.0, 5.0, 7.0), 0.3
+    ms = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, -3, 4)]
+    occ = np.array([0.9, 0.8, 0.6, 0.4, 0.2])
+    psi = inputs.plane_wave_orbitals(n, L, ms)
+    K = oracle.kernel_hse(n, L, mu)
+    omega = L[0] * L[1] * L[2]
+    mk = (-2, 3, 4)
+    phi = inputs.plane_wave_orbitals(n, L, [mk])
+    lam = 0.0
+    for j, mj in enumerate(ms):
+        q = [int(_wrap(mk[a] - mj[a], n[a])) for a in range(3)]
+        g2 = sum((2 * math.pi * q[a] / L[a]) ** 2 for a in range(3))
+        kq = math.pi / mu ** 2 if g2 == 0 else 4 * math.pi * (1 - math.exp(-g2 / (4 * mu ** 2))) / g2
+        lam -= occ[j] * kq / omega
+    out = oracle.exchange_apply(psi, occ, phi, K)
+    assert _relerr(out, lam * phi) < 1e-13
+
+
 def test_p5_plane_wave_energy_and_ace():
     n, L, mu = 16, 8.0, 0.2
     ms = [(0, 0, 0), (1, 0, 0), (0, -2, 1), (3, 1, -1), (-8, 2, 0)]
