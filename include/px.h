@@ -104,7 +104,11 @@ void px_destroy(px_context* ctx);
 const char* px_last_error(const px_context* ctx);
 
 /* Whether the grid of `cell` has compiled FFT plans in precision `prec`
- * (1 = yes).  Supported: cubic n in {16,24,32,40,48,60,64,72,80,96}. */
+ * (1 = yes).  Supported: cubic n in {16,24,32,40,48,60,64,72,80,96}, and the
+ * non-cubic (n[0], n[1], n[2]) = (60, 60, 90) and (60, 90, 120), the
+ * wavefunction grids of the 768- and 1536-atom cells of Sec. VI (their
+ * pipelines use configurations derived from the FFT plans, without per-size
+ * tuning). */
 int32_t px_grid_supported(const px_cell* cell, px_precision prec);
 
 /* Bytes of workspace that `op` needs for this problem with the context's
@@ -366,7 +370,8 @@ px_status px_set_graph(px_context* ctx, int32_t enable);
  * the first B >= n, which solves the instance as one triangular block) that
  * fit the attached workspace, each with both compiled
  * configurations of pass 2 (the z transforms: its workgroup shape, x-sections
- * per plane and threads, fixed per grid size at compile time), keeps the
+ * per plane and threads, fixed per grid size at compile time; one
+ * configuration on the non-cubic grids), keeps the
  * fastest pair as the context's tuning for this grid and precision, writes B
  * to *best_block (nullable) and appends a JSON line (block, "p2"
  * configuration, per-candidate times) to cache_path (nullable).

@@ -10,7 +10,9 @@ include the first orbital (its W comes almost entirely from the transposed
 accumulation of the pairs j < i), both sides of a block edge, the orbital
 nearest the Fermi level and the last one.  Over the whole block the FP32 form
 is compared with the FP64 GPU path: M, exchange energy, and the 4-iteration
-PT-IM-style loop on Phi = Psi + 1e-3 Z.
+PT-IM-style loop on Phi = Psi + 1e-3 Z; and E_x, summed from the pair energies
+in G space, against 1/2 sum_i f_i M_ii from the contraction (two paths to the
+same energy over all pairs).
 """
 import numpy as np
 import pytest
@@ -92,6 +94,11 @@ def test_large96_ace_vs_oracle_fp32_vs_fp64_and_loop(px_ctx, large):
     print(f"large96 FP64 ACE columns vs oracle {ey:.2e}, M columns {em:.2e}", flush=True)
     assert ey < FP64_TOL
     assert em < FP64_TOL
+    # E_x from the pair energies of pass 2 (G space) against the same energy
+    # from the contraction, 1/2 sum_i f_i M_ii (every pair of the full block)
+    e_m = 0.5 * float(np.sum(inst.occ * np.real(np.diag(to_host(M64)))))
+    print(f"large96 FP64 E_x {e64:.12f} vs 1/2 sum f_i M_ii {e_m:.12f}", flush=True)
+    assert abs(e64 - e_m) < FP64_TOL * abs(e_m)
 
     banner("large96: FP32 ACE build")
     psi32 = px_ctx.px_convert_c128_to_c64(psi64)
@@ -108,6 +115,7 @@ def test_large96_ace_vs_oracle_fp32_vs_fp64_and_loop(px_ctx, large):
     assert em32 < FP32_TOL
     assert emf < FP32_TOL
     assert ee < FP32_EX_TOL
+    assert abs(e32 - e_m) < FP32_EX_TOL * abs(e_m)
 
     banner("large96: PT-IM-style loops")
     z = inputs.noise_block(inst.n, inst.L, n, seed=1001)

@@ -75,6 +75,10 @@ def test_mid72_ace_builds_vs_oracle_and_fp32_vs_fp64(px_ctx, mid):
 
     for k, c in enumerate(COLS):   # column by column as well
         assert relerr(y64[k], ref[k]) < FP64_TOL, c
+    # E_x from the pair energies (G space) against 1/2 sum_i f_i M_ii from the
+    # contraction: two paths to the same energy over all pairs
+    e_m = 0.5 * float(np.sum(inst.occ * np.real(np.diag(to_host(M64)))))
+    assert abs(e64 - e_m) < FP64_TOL * abs(e_m)
 
     banner("mid72: FP32 ACE build")
     psi32 = px_ctx.px_convert_c128_to_c64(psi64)
