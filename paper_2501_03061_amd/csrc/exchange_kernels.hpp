@@ -130,7 +130,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 // 40^3 and 64^3 gains from it (-22 %, -7 %; cap 6 keeps it free of spills);
 // elsewhere it did not help (32^3 got slower) and the cap is 1 (no target).
 template <typename T, int N> constexpr int pass2_wave_cap() {
-  return sizeof(T) == 4 && (N == 40 || N == 64) ? 6 : 1;
+#if defined(PX_SH_CAP2)
+  if (N == 90 || N == 120) return PX_SH_CAP2;
+#endif
+  // 90 and 120 occur as z lengths of the non-cubic grids only: FP32 pass 2 at
+  // 60 x 90 x 120 with two 768-thread workgroups per CU instead of one,
+  // 3.42 -> 2.88 ms per 1,024-pair launch
+  return sizeof(T) == 4 && (N == 40 || N == 64 || N == 90 || N == 120) ? 6 : 1;
 }
 constexpr int lds_waves_per_simd(int lds_bytes, int nt, int cap) {
   const int waves = (nt + 63) / 64;
@@ -401,14 +407,25 @@ __global__ __launch_bounds__(NT) void pass1_fwd_xy(ChunkArgs a0, const ChunkArgs
 // go to the 8 XCDs in turn by linear id; for n1 a multiple of 8, XCD x takes
 // the contiguous tiles [x n1/8, (x+1) n1/8), so that the cache lines that
 // neighbouring tiles share at the ends of their rows are fetched through one
-// L2 instead of two.  The set of tiles in flight is unchanged.
+// L2 instead of two.  The set of tiles in flight is unchanged.  Otherwise,
+// when n1 x groups is a multiple of 8, XCD x takes the contiguous eighth
+// [x T, (x+1) T) of the tiles in pair-major order (T = n1 x groups / 8): every
+// pair's planes then go through one L2, and the XCDs work on different pairs.
+#ifndef PX_PLANE_MAP
+#define PX_PLANE_MAP 1
+#endif
 __device__ __forceinline__ void plane_tile(int& y, int& g) {
   const int ny = int(gridDim.x);
+  const int b = int(blockIdx.x) + ny * int(blockIdx.y);
   if (ny % 8 == 0) {
-    const int b = int(blockIdx.x) + ny * int(blockIdx.y);
     const int k = b >> 3, per = ny >> 3;
     y = (b & 7) * per + k % per;
     g = k / per;
+  } else if (PX_PLANE_MAP && (ny * int(gridDim.y)) % 8 == 0) {
+    const int t = (ny * int(gridDim.y)) >> 3;
+    const int idx = (b & 7) * t + (b >> 3);
+    y = idx % ny;
+    g = idx / ny;
   } else {
     y = blockIdx.x;
     g = blockIdx.y;
@@ -1235,27 +1252,38 @@ hipError_t launch_chunk_n(bool fp32, const ChunkArgs& a, int npairs, bool ex, bo
 // ---------------------------------------------------------------- other grids
 // Grids whose three lengths differ (the wavefunction grids of the paper's
 // 768- and 1536-atom cells, 60 x 60 x 90 and 60 x 90 x 120): configurations
-// derived from the plans alone, without the per-size tuning of the cubic
-// grids.  Threads = the largest stage's butterfly count rounded up to whole
-// waves, halved while above 768 (12 waves leave 170 registers per thread at
-// one workgroup per CU: the 960-thread form of pass 3 at 60 x 90 spilled);
-// ping-pong slabs where two fit; no cross-pair prefetch; one x-section per
-// pass-2 plane and one pair per workgroup.
-constexpr int wave_threads(int butterflies) {
-  int t = (butterflies + 63) / 64 * 64;
-  while (t > 768) t = (t / 2 + 63) / 64 * 64;
-  return t;
+// derived from the plans plus a few choices measured at 60 x 90 x 120 (FP32,
+// per 1,024-pair launch, same box).  Slab kernels (passes 1, 3): threads = the
+// largest stage's butterfly count rounded up to whole waves, at most 768 (12
+// waves leave 170 registers per thread at one workgroup per CU; 960 threads
+// spilled in pass 3, 512 were 25 % slower); ping-pong slabs where two fit; the
+// FP32 form prefetches the next density orbital in pass 1 (2.27 -> 1.90 ms) and
+// runs pass 3 staged through LDS (3.55 -> 2.23 ms).  Pass 2: see
+// shape_sections; one pair per workgroup.  A build may override these for
+// timing (PX_SH_* below).
+#ifndef PX_SH_NT_CAP
+#define PX_SH_NT_CAP 768
+#endif
+#ifndef PX_SH_PF1
+#define PX_SH_PF1 1
+#endif
+#ifndef PX_SH_STG3
+#define PX_SH_STG3 1
+#endif
+constexpr int wave_threads(int butterflies, int cap) {
+  const int t = (butterflies + 63) / 64 * 64;
+  return t < cap ? t : cap;
 }
 template <int N0, int N1> constexpr int slab_threads() {
   int m = 0;
   for (int s = 0; s < Plan<N0>::nst; ++s) m = m > N1 * (N0 / Plan<N0>::rad[s]) ? m : N1 * (N0 / Plan<N0>::rad[s]);
   for (int s = 0; s < Plan<N1>::nst; ++s) m = m > N0 * (N1 / Plan<N1>::rad[s]) ? m : N0 * (N1 / Plan<N1>::rad[s]);
-  return wave_threads(m);
+  return wave_threads(m, PX_SH_NT_CAP);
 }
-template <int N0, int N2> constexpr int plane_threads() {
+template <int NX, int N2> constexpr int plane_threads() {
   int m = 0;
-  for (int s = 0; s < Plan<N2>::nst; ++s) m = m > N0 * (N2 / Plan<N2>::rad[s]) ? m : N0 * (N2 / Plan<N2>::rad[s]);
-  return wave_threads(m);
+  for (int s = 0; s < Plan<N2>::nst; ++s) m = m > NX * (N2 / Plan<N2>::rad[s]) ? m : NX * (N2 / Plan<N2>::rad[s]);
+  return wave_threads(m, 1024);
 }
 
 template <int N0, int N1, int N2>
@@ -1266,29 +1294,39 @@ hipError_t launch_chunk_shape(bool fp32, const ChunkArgs& a, int npairs, bool ex
     ntasks = 1;
     max_ic = a.ic;
   }
-  constexpr int NT1 = slab_threads<N0, N1>(), NT2 = plane_threads<N0, N2>();
+  constexpr int NT1 = slab_threads<N0, N1>();
   constexpr bool PPF = pingpong_fits<float, N0, N1>(), PPD = pingpong_fits<double, N0, N1>();
-  const dim3 g1(N2, max_ic, ntasks), g2(N1, npairs, ntasks);
+  constexpr int XF = shape_sections(true, N0, N2), XD = shape_sections(false, N0, N2);
+  constexpr int NT2F = plane_threads<N0 / XF, N2>(), NT2D = plane_threads<N0 / XD, N2>();
+  const dim3 g1(N2, max_ic, ntasks), g2f(N1 * XF, npairs, ntasks), g2d(N1 * XD, npairs, ntasks);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (fp32)
-    hipLaunchKernelGGL((pass1_fwd_xy<float, N0, N1, NT1, true, false, PPF>), g1, dim3(NT1), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass1_fwd_xy<float, N0, N1, NT1, true, bool(PX_SH_PF1), PPF>), g1, dim3(NT1), 0, s, a, tasks);
   else
     hipLaunchKernelGGL((pass1_fwd_xy<double, N0, N1, NT1, false, false, PPD>), g1, dim3(NT1), 0, s, a, tasks);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (fp32 && ex)
-    hipLaunchKernelGGL((pass2_z_kernel<float, N0, N1, N2, NT2, true, true, 1, false, 1>), g2, dim3(NT2), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass2_z_kernel<float, N0, N1, N2, NT2F, true, true, 1, false, XF>), g2f, dim3(NT2F), 0, s, a, tasks);
   else if (fp32)
-    hipLaunchKernelGGL((pass2_z_kernel<float, N0, N1, N2, NT2, true, false, 1, false, 1>), g2, dim3(NT2), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass2_z_kernel<float, N0, N1, N2, NT2F, true, false, 1, false, XF>), g2f, dim3(NT2F), 0, s, a, tasks);
   else if (ex)
-    hipLaunchKernelGGL((pass2_z_kernel<double, N0, N1, N2, NT2, false, true, 1, false, 1>), g2, dim3(NT2), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass2_z_kernel<double, N0, N1, N2, NT2D, false, true, 1, false, XD>), g2d, dim3(NT2D), 0, s, a, tasks);
   else
-    hipLaunchKernelGGL((pass2_z_kernel<double, N0, N1, N2, NT2, false, false, 1, false, 1>), g2, dim3(NT2), 0, s, a, tasks);
+    hipLaunchKernelGGL((pass2_z_kernel<double, N0, N1, N2, NT2D, false, false, 1, false, XD>), g2d, dim3(NT2D), 0, s, a, tasks);
   if (ev) (void)hipEventRecord(ev[2], s);
-  if (fp32 && store_v)
-    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N0, N1, NT1, false, true, PPF>), g1, dim3(NT1), 0, s, a, tasks);
-  else if (fp32)
-    hipLaunchKernelGGL((pass3_inv_xy_acc<float, N0, N1, NT1, false, false, PPF>), g1, dim3(NT1), 0, s, a, tasks);
-  else if (store_v)
+  if (fp32) {
+    if constexpr (PX_SH_STG3 != 0) {
+      if (store_v)
+        hipLaunchKernelGGL((pass3_staged<float, N0, N1, NT1, true>), g1, dim3(NT1), 0, s, a, tasks);
+      else
+        hipLaunchKernelGGL((pass3_staged<float, N0, N1, NT1, false>), g1, dim3(NT1), 0, s, a, tasks);
+    } else {
+      if (store_v)
+        hipLaunchKernelGGL((pass3_inv_xy_acc<float, N0, N1, NT1, false, true, PPF>), g1, dim3(NT1), 0, s, a, tasks);
+      else
+        hipLaunchKernelGGL((pass3_inv_xy_acc<float, N0, N1, NT1, false, false, PPF>), g1, dim3(NT1), 0, s, a, tasks);
+    }
+  } else if (store_v)
     hipLaunchKernelGGL((pass3_inv_xy_acc<double, N0, N1, NT1, false, true, PPD>), g1, dim3(NT1), 0, s, a, tasks);
   else
     hipLaunchKernelGGL((pass3_inv_xy_acc<double, N0, N1, NT1, false, false, PPD>), g1, dim3(NT1), 0, s, a, tasks);

@@ -124,10 +124,27 @@ constexpr int pass2_sections(bool fp32, int n) {
 constexpr int pass2_sections_cfg(bool fp32, int n, int cfg) {
   return cfg == 0 ? pass2_sections(fp32, n) : (pass2_sections(fp32, n) == 1 ? 2 : 1);
 }
-// The same for any grid n[3]: non-cubic grids have one configuration, with one
-// section.
+// Non-cubic grids: the fewest x-sections (a divisor of n0) that keep a pass-2
+// tile (n2 lines of n0/XS + 1 padded values) within 64 KB of LDS in the FP32
+// form (two 768-thread workgroups per CU) and within 40 KB in FP64.  Measured
+// at 60 x 90 x 120 per 1,024-pair launch: FP32 one section 2.88 ms against
+// 3.03 with two; FP64 three sections 4.28 ms against 4.82 with one and 6.00
+// with two.  PX_SH_XS32 / PX_SH_XS64 override for timing.
+constexpr int shape_sections(bool fp32, int n0, int n2) {
+#if defined(PX_SH_XS32)
+  if (fp32) return PX_SH_XS32;
+#endif
+#if defined(PX_SH_XS64)
+  if (!fp32) return PX_SH_XS64;
+#endif
+  for (int xs = 1; xs <= n0; ++xs)
+    if (n0 % xs == 0 && n2 * (n0 / xs + 1) * (fp32 ? 8 : 16) <= (fp32 ? 64 : 40) * 1024) return xs;
+  return n0;
+}
+// The same for any grid n[3]: non-cubic grids have one configuration.
 inline int pass2_sections_grid(bool fp32, const int* n, int cfg) {
-  return grid_cubic(n[0], n[1], n[2]) ? pass2_sections_cfg(fp32, n[0], cfg) : 1;
+  return grid_cubic(n[0], n[1], n[2]) ? pass2_sections_cfg(fp32, n[0], cfg)
+                                      : shape_sections(fp32, n[0], n[2]);
 }
 // Pass-2 configurations the autotuner can choose from on grid n[3].
 inline int pass2_configs(const int* n) { return grid_cubic(n[0], n[1], n[2]) ? 2 : 1; }
