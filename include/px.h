@@ -343,7 +343,7 @@ size_t px_workspace_bytes_batched(const px_context* ctx, int32_t n_inst, const p
 /* Batched form (Sec. III-B(b) batches pairs to fill the GPU): all block pairs
  * of all instances (Hermitian-pair mode, always on here, so every kernel_G
  * must be real and even, K(G) = K(-G); square blocks from the tuning) are
- * grouped by grid size and scheduled by block diagonal, so each pass runs as
+ * grouped by grid and scheduled by block diagonal, so each pass runs as
  * one launch over a task table for many chunks of many instances; then the
  * per-instance energies and, with ace != 0, the ACE construction.  In ACE
  * mode the instances whose last chunk ran in one wave form a group whose

@@ -1113,12 +1113,13 @@ int pass2_cfg_for(const px_context* c, const px_cell* cell, px_precision prec) {
   return p2;
 }
 
-// Plan of one batched call.  Instances are grouped by grid size; within a
-// size the block pairs (I, J <= I) of every instance are scheduled by block
-// diagonal d = I - J, so that one launch never has two chunks writing the
-// same output block (pass 3 writes block I, pass 4 block J): d = 0 first
-// (those chunks initialise the output), then d = 1, 2, ...  A diagonal's
-// chunks are packed into waves that fit the pair buffer.  ws == nullptr:
+// Plan of one batched call.  Instances are grouped by grid (all three
+// lengths); within a grid the block pairs (I, J <= I) of every instance are
+// scheduled by block diagonal d = I - J, so that one launch never has two
+// chunks writing the same output block (pass 3 writes block I, pass 4 block
+// J): d = 0 first (those chunks initialise the output), then d = 1, 2, ...  A
+// diagonal's chunks are packed into waves that fit the pair buffer.  In ACE
+// mode the instances completed by a wave form a tail group.  ws == nullptr:
 // sizes only.
 BatchPlan plan_batch(const px_context* c, int n_inst, const px_instance* in, px_precision prec,
                      bool ace, char* ws) {
