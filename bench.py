@@ -322,6 +322,7 @@ def bench_single(args, workload):
             fp64_pair_solves_per_s=pairs / (ms64 * 1e-3),
             fp64_physical_pair_solves_per_s=pairs_phys / (ms64 * 1e-3),
             fp64_ms_per_step=ms64, fp64_steps=args.fp64_steps,
+            fp64_step_ms_all=[s for _, s in ev64],
             ace_build_s_fp64=statistics.median(ace64),
             speedup_fp32_vs_fp64=ms64 / ms_step,
             speedup_fp32_vs_fp64_ace_build=statistics.median(ace64) / statistics.median(ace_s),
@@ -423,7 +424,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
