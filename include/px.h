@@ -79,7 +79,8 @@ typedef enum {
   PX_OP_EXCHANGE_SIGMA = 4,  /* n_psi = n (Phi and sigma), n_phi = n_tgt */
   PX_OP_SIGMA_DIAG = 5,      /* n_psi = n; n_phi ignored                 */
   PX_OP_DENSITY_SIGMA = 6,   /* n_psi = n; n_phi ignored                 */
-  PX_OP_PTIM_STEP = 7        /* n_psi = n (rank of xi), n_phi            */
+  PX_OP_PTIM_STEP = 7,       /* n_psi = n (rank of xi), n_phi            */
+  PX_OP_ACE_BUILD_SIGMA = 8  /* n_psi = n (Phi and sigma); n_phi ignored */
 } px_op;
 
 /* Orthorhombic cell: edge lengths in bohr and the real-space grid, n[0] = x. */
@@ -218,7 +219,7 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
  * the eigenvalues in ascending order.  Eigenvectors are unique up to a phase
  * (and a rotation within a degenerate eigenspace); Q D Q^H is unique.
  * status (device int32, required): 0 when the off-diagonal Frobenius norm fell
- * below 64 eps sqrt(n) ||sigma||_F within 16 sweeps, else the sweeps made
+ * below 64 eps sqrt(n) ||sigma||_F within 40 sweeps, else the sweeps made
  * (Q, d then approximate; px_sync returns PX_ERR_NOT_CONVERGED).  Workspace:
  * px_workspace_bytes(PX_OP_SIGMA_DIAG, cell (any), FP64, n, 0). */
 px_status px_sigma_diagonalize(px_context* ctx, int32_t n, const double* sigma, double* Q, double* d,
@@ -256,18 +257,39 @@ px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision pr
                            const void* phi_basis, const double* sigma, double* rho, int32_t* status,
                            hipStream_t stream);
 
+/* ACE construction for a full occupation matrix (Eq. 10 compressed as in
+ * Eq. 14, evaluated through Eq. 11-13): sigma = Q D Q^H, phi = Phi Q, then
+ * the construction of px_ace_build on (phi, d).  phi spans the space of Phi,
+ * so V_ACE = -xi xi^H reproduces Vx[sigma] on every vector of span(Phi).
+ * Phi [n][N_g] (element type of prec), sigma complex128 [n][n] (Hermitian;
+ * its eigenvalues are the occupations d, normally in [0, 1]), kernel_G as in
+ * px_exchange_apply.  Outputs: xi [n][N_g]; M (nullable) complex128 [n][n],
+ * dV phi^H W in the eigenbasis of sigma (it depends on the phases chosen for
+ * Q; xi xi^H does not); e_x (nullable) = (1/2) Tr(sigma Phi^H Vx[sigma] Phi) dV,
+ * the exchange energy of Eq. 10.  status (device int32 [2], required):
+ * status[0] as in px_sigma_diagonalize, status[1] as the status of
+ * px_ace_build; px_sync reports either.  Workspace: PX_OP_ACE_BUILD_SIGMA with
+ * n.  Kernel evenness as for px_ace_build (the Hermitian-pair mode applies). */
+px_status px_ace_build_sigma(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                             const void* phi_basis, const double* sigma, const double* kernel_G,
+                             void* xi, double* M, double* e_x, int32_t* status,
+                             hipStream_t stream);
+
 /* Exchange-only PT-IM step with the projector and the occupation matrix
  * (Sec. II-A: the scheme of Eq. 6 at the midpoints of Eq. 4 with the
  * projector P~ of Eq. 5, H reduced to alpha * V_ACE (Eq. 8, Eq. 14), iterated
  * as the fixed point x = T(x) of Eq. 7 from x^(0) = (Phi_n, sigma_n)):
  *   Phi_mid = (Phi_n + Phi^(k))/2,  sigma_mid = (sigma_n + sigma^(k))/2,
  *   Y = V_ACE Phi_mid,  S = dV Phi_mid^H Phi_mid,  Hm = dV Phi_mid^H Y
- *   (Hermitised: Phi^* H Phi is Hermitian, the computed one only to rounding),
+ *   (with V_ACE = -xi dV xi^H, Hm = -C^H C for C = dV xi^H Phi_mid, which
+ *   the application of V_ACE forms anyway: Hm costs an n_phi x n_phi product
+ *   over n instead of a contraction over the grid, and is Hermitian),
  *   Phi^(k+1)   = Phi_n   - i dt_alpha (Y - Phi_mid S^{-1} Hm),
  *   sigma^(k+1) = sigma_n - i dt_alpha (Hm sigma_mid - sigma_mid Hm),
  * for k = 0 .. n_iter-1 (n_iter <= 64), dt_alpha = dt * alpha.  Orbital
- * contractions in the form's precision; S^{-1} Hm (Cholesky of S, U = L^{-H},
- * X = U U^H Hm), the sigma algebra and the residuals in FP64.
+ * contractions in the form's precision (C and S with FP64 results); Hm,
+ * S^{-1} Hm (Cholesky of S, U = L^{-H}, X = U U^H Hm), the sigma algebra and
+ * the residuals in FP64.
  * xi [n][N_g], phi_n and phi_out [n_phi][N_g] (element type of prec);
  * sigma_n, sigma_out complex128 [n_phi][n_phi]; residuals float64
  * [2][n_iter]: R_Phi,k = ||Phi^(k+1) - Phi^(k)||_F / ||Phi^(k+1)||_F in

@@ -395,27 +395,32 @@ size_t chol_dinv_bytes(int n) { return size_t((n + KB - 1) / KB) * KB * KB * 16;
 // ---------------------------------------------------------------- small FP64 products
 namespace px {
 
-// C = op(A) B for n x n complex128 row-major matrices, op(A) = A or A^H:
-// 16 x 16 tiles of C per workgroup, 16 x 16 tiles of op(A) and B staged in
-// LDS, one entry of C per thread.  Used for the occupation-matrix algebra of
-// the PT-IM step (N_phi x N_phi), where the FP64 vector rate is ample.
+// C = alpha op(A) B for complex128 row-major matrices: op(A) is m x k (A
+// itself, or A^H with A stored k x m), B is k x n, C is m x n, with leading
+// dimensions lda, ldb, ldc in elements.  16 x 16 tiles of C per workgroup,
+// 16 x 16 tiles of op(A) and B staged in LDS, one entry of C per thread.
+// Used for the small matrix algebra of the PT-IM step (N_phi x N_phi, and
+// N_phi x N_phi products over the rank of xi), where the FP64 vector rate is
+// ample.
 template <bool AH>
-__global__ __launch_bounds__(256) void zgemm_k(int n, const double* A, const double* B, double* C) {
+__global__ __launch_bounds__(256) void zgemm_k(int m, int n, int kd, const double* A, int lda,
+                                               const double* B, int ldb, double* C, int ldc,
+                                               double alpha) {
   __shared__ double2 sa[16][17], sb[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
   double cr = 0.0, ci = 0.0;
-  for (int k0 = 0; k0 < n; k0 += 16) {
+  for (int k0 = 0; k0 < kd; k0 += 16) {
     // op(A)[row][k0 + tx]: A[row][k] or conj(A[k][row])
     {
       const int k = k0 + tx;
       double2 v = make_double2(0.0, 0.0);
-      if (row < n && k < n) {
+      if (row < m && k < kd) {
         if (AH) {
-          const double* p = A + (size_t(k) * n + row) * 2;
+          const double* p = A + (size_t(k) * lda + row) * 2;
           v = make_double2(p[0], -p[1]);
         } else {
-          const double* p = A + (size_t(row) * n + k) * 2;
+          const double* p = A + (size_t(row) * lda + k) * 2;
           v = make_double2(p[0], p[1]);
         }
       }
@@ -424,8 +429,8 @@ __global__ __launch_bounds__(256) void zgemm_k(int n, const double* A, const dou
     {
       const int k = k0 + ty;
       double2 v = make_double2(0.0, 0.0);
-      if (k < n && col < n) {
-        const double* p = B + (size_t(k) * n + col) * 2;
+      if (k < kd && col < n) {
+        const double* p = B + (size_t(k) * ldb + col) * 2;
         v = make_double2(p[0], p[1]);
       }
       sb[ty][tx] = v;
@@ -439,19 +444,25 @@ __global__ __launch_bounds__(256) void zgemm_k(int n, const double* A, const dou
     }
     __syncthreads();
   }
-  if (row < n && col < n) {
-    C[(size_t(row) * n + col) * 2] = cr;
-    C[(size_t(row) * n + col) * 2 + 1] = ci;
+  if (row < m && col < n) {
+    C[(size_t(row) * ldc + col) * 2] = alpha * cr;
+    C[(size_t(row) * ldc + col) * 2 + 1] = alpha * ci;
   }
 }
 
-hipError_t launch_zgemm(bool ah, int n, const double* A, const double* B, double* C, hipStream_t s) {
-  const dim3 g((n + 15) / 16, (n + 15) / 16);
+hipError_t launch_zgemm_gen(bool ah, int m, int n, int k, const double* A, int lda, const double* B,
+                            int ldb, double* C, int ldc, double alpha, hipStream_t s) {
+  if (m <= 0 || n <= 0 || k <= 0) return hipErrorInvalidValue;
+  const dim3 g((n + 15) / 16, (m + 15) / 16);
   if (ah)
-    hipLaunchKernelGGL(zgemm_k<true>, g, dim3(256), 0, s, n, A, B, C);
+    hipLaunchKernelGGL(zgemm_k<true>, g, dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, alpha);
   else
-    hipLaunchKernelGGL(zgemm_k<false>, g, dim3(256), 0, s, n, A, B, C);
+    hipLaunchKernelGGL(zgemm_k<false>, g, dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, alpha);
   return hipGetLastError();
+}
+
+hipError_t launch_zgemm(bool ah, int n, const double* A, const double* B, double* C, hipStream_t s) {
+  return launch_zgemm_gen(ah, n, n, n, A, n, B, n, C, n, 1.0, s);
 }
 
 // dst = alpha * src over n real values

@@ -1,22 +1,27 @@
 // FP64 Hermitian eigendecomposition of the occupation matrix, sigma = Q D Q^H
-// (Sec. IV-A-1, Eq. 11), by the cyclic Jacobi method in a parallel ordering.
+// (Sec. IV-A-1, Eq. 11), by the cyclic Jacobi method in a blocked parallel
+// ordering.
 //
-// A sweep visits every index pair (p, q) once, in n' - 1 rounds of n'/2
-// disjoint pairs (n' = n rounded up to even; the circle method: index n' - 1
-// stays put, the others rotate, and a pair with the padding index n is
-// skipped).  In a round, each pair gets the unitary G = P J that zeroes its
-// off-diagonal entry: with A_pq = |A_pq| e^{i theta}, P = diag(1, e^{-i theta})
-// makes the 2 x 2 block real symmetric and J is the real Jacobi rotation of
-// that block (tangent t = sgn(tau)/(|tau| + sqrt(1 + tau^2)),
-// tau = (A_qq - A_pp)/(2 |A_pq|), the smaller of the two angles).  The
-// rotations of a round are disjoint, so A <- G^H A G and V <- V G split into
-// independent 2 x 2 blocks: one thread per block updates A in place (every
-// rotation was formed from the diagonal blocks before any update) and one per
-// (row, pair) updates V.  After each sweep one workgroup forms the off-diagonal
-// Frobenius norm; below 64 eps sqrt(n) ||A||_F a device flag makes the
-// remaining launches return at once, so the host enqueues a fixed number of
-// sweeps without waiting for the device.  Finally d = diag(A) in ascending
-// order, Q the matching columns of V.
+// The indices are cut into blocks of BJ = 16 (nb blocks, rounded up to even;
+// indices past n are absent).  A sweep visits every pair of blocks once, in
+// nb - 1 rounds of nb/2 disjoint block pairs (the circle method: block nb - 1
+// stays put, the others rotate).  In a round, one workgroup per block pair
+// takes the 32 x 32 Hermitian submatrix of its 32 indices into LDS and runs
+// one sweep of scalar cyclic Jacobi on it (31 rounds of 16 disjoint index
+// pairs in the same circle ordering; each pair gets the unitary G = P J that
+// zeroes its off-diagonal entry: with A_pq = |A_pq| e^{i theta},
+// P = diag(1, e^{-i theta}) makes the 2 x 2 block real symmetric and J is its
+// real Jacobi rotation, tangent t = sgn(tau)/(|tau| + sqrt(1 + tau^2)),
+// tau = (A_qq - A_pp)/(2 |A_pq|), the smaller angle), accumulating the 32 x 32
+// unitary U of the pair.  The U of a round act on disjoint index sets, so
+// A <- G^H A G splits into 32 x 32 tiles A_PS <- U_P^H A_PS U_S and V <- V G
+// into 32-row tiles V_rS <- V_rS U_S, one workgroup per tile.  Compared with
+// rotating single index pairs, a sweep reads and writes A and V nb - 1 times
+// instead of n - 1 times, which is what bounds the method at these sizes.
+// After each sweep one workgroup forms the off-diagonal Frobenius norm; below
+// 64 eps sqrt(n) ||A||_F a device flag makes the remaining launches return at
+// once, so the host enqueues a fixed number of sweeps without waiting for the
+// device.  Finally d = diag(A) in ascending order, Q the matching columns of V.
 #include <float.h>
 
 #include "px_internal.hpp"
@@ -93,87 +98,166 @@ __global__ void eig_init_k(const double* sigma, int n, double* A, double* V, int
   }
 }
 
-// The rotations of round k, one thread per pair.
-__global__ void eig_rot_k(const double* A, int n, int np, int k, Rot* rot, const int* flags) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= np / 2 || flags[0]) return;
-  int p, q;
-  round_pair(np, k, slot, p, q);
+constexpr int BJ = 16;        // indices per block
+constexpr int BJ2 = 2 * BJ;   // size of a block pair's subproblem
+
+// Index t (0 <= t < 32) of block pair `slot` in block round k: block I's 16
+// indices, then block J's.
+__device__ __forceinline__ int bj_index(int nb, int k, int slot, int t) {
+  int I, J;
+  round_pair(nb, k, slot, I, J);
+  return t < BJ ? I * BJ + t : J * BJ + (t - BJ);
+}
+
+// Rotation of indices (p, q) of the 2 x 2 diagonal block (app, aqq real, apq).
+__device__ __forceinline__ Rot make_rot(double app, double aqq, double2 apq, int p, int q) {
   Rot r;
   r.p = p;
-  r.q = q < n ? q : -1;
+  r.q = q;
   r.id = 1;
   r.pad = 0;
   r.c = 1.0;
   r.s = 0.0;
   r.er = 1.0;
   r.ei = 0.0;
-  if (q < n) {
-    const double app = ld2(A, n, p, p).x, aqq = ld2(A, n, q, q).x;
-    const double2 apq = ld2(A, n, p, q);
-    const double m = hypot(apq.x, apq.y);
-    if (m > 0.0) {
-      const double tau = (aqq - app) / (2.0 * m);
-      const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-      r.c = 1.0 / sqrt(1.0 + t * t);
-      r.s = t * r.c;
-      r.er = apq.x / m;   // e^{-i theta} = conj(A_pq)/|A_pq|
-      r.ei = -apq.y / m;
-      r.id = 0;
-    }
+  const double m = hypot(apq.x, apq.y);
+  if (m > 0.0) {
+    const double tau = (aqq - app) / (2.0 * m);
+    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    r.c = 1.0 / sqrt(1.0 + t * t);
+    r.s = t * r.c;
+    r.er = apq.x / m;  // e^{-i theta} = conj(A_pq)/|A_pq|
+    r.ei = -apq.y / m;
+    r.id = 0;
   }
-  rot[slot] = r;
+  return r;
 }
 
-// A <- G^H A G on the 2 x 2 blocks (pair P, pair S) (blockIdx.y = 0), and
-// V <- V G on the (row, pair) pieces (blockIdx.y = 1).
-__global__ void eig_apply_k(double* A, double* V, int n, int np, const Rot* rot, const int* flags) {
+// One inner sweep on the 32 x 32 subproblem of each block pair of round k
+// (one workgroup per pair): U_P (32 x 32, row-major) into Ug[P].
+__global__ __launch_bounds__(256) void bj_solve_k(const double* A, int n, int nb, int k, double* Ug,
+                                                  const int* flags) {
   if (flags[0]) return;
-  const int half = np / 2;
-  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (blockIdx.y == 0) {
-    if (e >= size_t(half) * half) return;
-    const int P = int(e / half), S = int(e % half);
-    const Rot rp = rot[P], rs = rot[S];
-    if (rp.id && rs.id) return;  // both identities: the block keeps its values
-    double2 gp[2][2], gs[2][2];
-    rot_matrix(rp, gp);
-    rot_matrix(rs, gs);
-    // rows of pair P, columns of pair S (-1: the padding index, left out;
-    // the partner of an identity pair takes part with a unit rotation)
-    const int ip[2] = {rp.p, rp.q}, is[2] = {rs.p, rs.q};
-    double2 b[2][2];
+  __shared__ double2 S[BJ2][BJ2 + 1];
+  __shared__ double2 U[BJ2][BJ2 + 1];
+  __shared__ Rot rot[BJ];
+  __shared__ int gi[BJ2];
+  const int P = blockIdx.x, tid = threadIdx.x;
+  if (tid < BJ2) gi[tid] = bj_index(nb, k, P, tid);
+  __syncthreads();
+  for (int e = tid; e < BJ2 * BJ2; e += 256) {
+    const int i = e / BJ2, j = e % BJ2;
+    S[i][j] = (gi[i] < n && gi[j] < n) ? ld2(A, n, gi[i], gi[j]) : make_double2(0.0, 0.0);
+    U[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int kk = 0; kk < BJ2 - 1; ++kk) {
+    if (tid < BJ) {
+      int p, q;
+      round_pair(BJ2, kk, tid, p, q);
+      rot[tid] = make_rot(S[p][p].x, S[q][q].x, S[p][q], p, q);
+    }
+    __syncthreads();
+    {  // S <- G^H S G on the 2 x 2 blocks (pair x, pair y): 16 x 16 = 256 blocks
+      const Rot rp = rot[tid / BJ], rs = rot[tid % BJ];
+      if (!(rp.id && rs.id)) {
+        double2 gp[2][2], gs[2][2], b[2][2], t[2][2];
+        rot_matrix(rp, gp);
+        rot_matrix(rs, gs);
+        const int ip[2] = {rp.p, rp.q}, is[2] = {rs.p, rs.q};
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
-        b[x][y] = (ip[x] >= 0 && is[y] >= 0) ? ld2(A, n, ip[x], is[y]) : make_double2(0.0, 0.0);
-    // T = B G_S, A' = G_P^H T
-    double2 t[2][2], o[2][2];
+          for (int y = 0; y < 2; ++y) b[x][y] = S[ip[x]][is[y]];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) t[x][y] = cadd2(cmul2(b[x][0], gs[0][y]), cmul2(b[x][1], gs[1][y]));
+          for (int y = 0; y < 2; ++y) t[x][y] = cadd2(cmul2(b[x][0], gs[0][y]), cmul2(b[x][1], gs[1][y]));
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
-        o[x][y] = cadd2(cmul2(cconj2(gp[0][x]), t[0][y]), cmul2(cconj2(gp[1][x]), t[1][y]));
+          for (int y = 0; y < 2; ++y)
+            S[ip[x]][is[y]] = cadd2(cmul2(cconj2(gp[0][x]), t[0][y]), cmul2(cconj2(gp[1][x]), t[1][y]));
+      }
+    }
+    for (int e = tid; e < BJ2 * BJ; e += 256) {  // U <- U G: (row, pair) pieces
+      const int r = e / BJ;
+      const Rot rs = rot[e % BJ];
+      if (rs.id) continue;
+      double2 g[2][2];
+      rot_matrix(rs, g);
+      const double2 v0 = U[r][rs.p], v1 = U[r][rs.q];
+      U[r][rs.p] = cadd2(cmul2(v0, g[0][0]), cmul2(v1, g[1][0]));
+      U[r][rs.q] = cadd2(cmul2(v0, g[0][1]), cmul2(v1, g[1][1]));
+    }
+    __syncthreads();
+  }
+  double2* out = reinterpret_cast<double2*>(Ug) + size_t(P) * BJ2 * BJ2;
+  for (int e = tid; e < BJ2 * BJ2; e += 256) out[e] = U[e / BJ2][e % BJ2];
+}
+
+// The block rotations of round k: A_PS <- U_P^H A_PS U_S for every pair of
+// block pairs (blockIdx.y = 0, blockIdx.x = P * m + S), V_rS <- V_rS U_S for
+// every 32-row tile r and block pair S (blockIdx.y = 1, blockIdx.x = r * m + S).
+// Each tile is read and written by its own workgroup only.
+__global__ __launch_bounds__(256) void bj_apply_k(double* A, double* V, int n, int nb, int k,
+                                                  const double* Ug, const int* flags) {
+  if (flags[0]) return;
+  const int m = nb / 2, tid = threadIdx.x;
+  const int rows = (n + BJ2 - 1) / BJ2;
+  const bool is_a = blockIdx.y == 0;
+  if (blockIdx.x >= unsigned(is_a ? m * m : rows * m)) return;
+  __shared__ double2 X[BJ2][BJ2 + 1];
+  __shared__ double2 W[BJ2][BJ2 + 1];
+  __shared__ int ri[BJ2], ci[BJ2];
+  const int P = blockIdx.x / m, Sx = blockIdx.x % m;
+  if (tid < BJ2) {
+    ri[tid] = is_a ? bj_index(nb, k, P, tid) : P * BJ2 + tid;
+    ci[tid] = bj_index(nb, k, Sx, tid);
+  }
+  __syncthreads();
+  double* M = is_a ? A : V;
+  const double2* us = reinterpret_cast<const double2*>(Ug) + size_t(Sx) * BJ2 * BJ2;
+  for (int e = tid; e < BJ2 * BJ2; e += 256) {
+    const int i = e / BJ2, j = e % BJ2;
+    X[i][j] = (ri[i] < n && ci[j] < n) ? ld2(M, n, ri[i], ci[j]) : make_double2(0.0, 0.0);
+    W[i][j] = us[e];
+  }
+  __syncthreads();
+  // T = X U_S: four entries per thread
+  double2 t[4];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q, i = e / BJ2, j = e % BJ2;
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 8
+    for (int l = 0; l < BJ2; ++l) acc = cadd2(acc, cmul2(X[i][l], W[l][j]));
+    t[q] = acc;
+  }
+  if (is_a) {
+    // out = U_P^H T
+    __syncthreads();
+    const double2* up = reinterpret_cast<const double2*>(Ug) + size_t(P) * BJ2 * BJ2;
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
-        if (ip[x] >= 0 && is[y] >= 0) st2(A, n, ip[x], is[y], o[x][y]);
-  } else {
-    if (e >= size_t(n) * half) return;
-    const int r = int(e / half), S = int(e % half);
-    const Rot rs = rot[S];
-    if (rs.id) return;
-    double2 g[2][2];
-    rot_matrix(rs, g);
-    const double2 v0 = ld2(V, n, r, rs.p), v1 = ld2(V, n, r, rs.q);
-    st2(V, n, r, rs.p, cadd2(cmul2(v0, g[0][0]), cmul2(v1, g[1][0])));
-    st2(V, n, r, rs.q, cadd2(cmul2(v0, g[0][1]), cmul2(v1, g[1][1])));
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      X[e / BJ2][e % BJ2] = t[q];
+    }
+    for (int e = tid; e < BJ2 * BJ2; e += 256) W[e / BJ2][e % BJ2] = up[e];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q, i = e / BJ2, j = e % BJ2;
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 8
+      for (int l = 0; l < BJ2; ++l) acc = cadd2(acc, cmul2(cconj2(W[l][i]), X[l][j]));
+      t[q] = acc;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q, i = e / BJ2, j = e % BJ2;
+    if (ri[i] < n && ci[j] < n) st2(M, n, ri[i], ci[j], t[q]);
   }
 }
 
@@ -242,15 +326,20 @@ int grid_for(size_t total) {
 
 }  // namespace
 
+int eig_blocks(int n) {
+  const int nb = (n + BJ - 1) / BJ;
+  return nb + (nb & 1) < 2 ? 2 : nb + (nb & 1);
+}
+
 size_t eig_work_bytes(int n) {
-  const int np = n + (n & 1);
   const size_t mat = size_t(n) * n * 16;
-  return 2 * mat + size_t(np / 2) * sizeof(Rot) + size_t(n) * sizeof(int) + 4 * sizeof(int) + 4 * 256;
+  const size_t ug = size_t(eig_blocks(n) / 2) * BJ2 * BJ2 * 16;
+  return 2 * mat + ug + size_t(n) * sizeof(int) + 4 * sizeof(int) + 4 * 256;
 }
 
 hipError_t launch_eig_hermitian(const double* sigma, int n, double* Q, double* d, int32_t* status,
                                 void* work, int max_sweeps, hipStream_t s) {
-  const int np = n + (n & 1);
+  const int nb = eig_blocks(n), m = nb / 2;
   char* w = static_cast<char*>(work);
   auto carve = [&w](size_t bytes) {
     char* p = w;
@@ -259,21 +348,18 @@ hipError_t launch_eig_hermitian(const double* sigma, int n, double* Q, double* d
   };
   double* A = reinterpret_cast<double*>(carve(size_t(n) * n * 16));
   double* V = reinterpret_cast<double*>(carve(size_t(n) * n * 16));
-  Rot* rot = reinterpret_cast<Rot*>(carve(size_t(np / 2) * sizeof(Rot)));
+  double* Ug = reinterpret_cast<double*>(carve(size_t(m) * BJ2 * BJ2 * 16));
   int* rank = reinterpret_cast<int*>(carve(size_t(n) * sizeof(int)));
   int* flags = reinterpret_cast<int*>(carve(4 * sizeof(int)));
   const size_t total = size_t(n) * n;
   hipLaunchKernelGGL(eig_init_k, dim3(grid_for(total)), dim3(256), 0, s, sigma, n, A, V, flags);
   if (n > 1) {
-    const int half = np / 2;
-    const size_t work_a = size_t(half) * half, work_v = size_t(n) * half;
-    const size_t most = work_a > work_v ? work_a : work_v;
-    const dim3 ga(unsigned((most + 255) / 256), 2);
+    const int rows = (n + BJ2 - 1) / BJ2;
+    const int tiles = m * m > rows * m ? m * m : rows * m;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-      for (int k = 0; k < np - 1; ++k) {
-        hipLaunchKernelGGL(eig_rot_k, dim3((half + 255) / 256), dim3(256), 0, s, A, n, np, k, rot,
-                           flags);
-        hipLaunchKernelGGL(eig_apply_k, ga, dim3(256), 0, s, A, V, n, np, rot, flags);
+      for (int k = 0; k < nb - 1; ++k) {
+        hipLaunchKernelGGL(bj_solve_k, dim3(m), dim3(256), 0, s, A, n, nb, k, Ug, flags);
+        hipLaunchKernelGGL(bj_apply_k, dim3(tiles, 2), dim3(256), 0, s, A, V, n, nb, k, Ug, flags);
       }
       hipLaunchKernelGGL(eig_conv_k, dim3(1), dim3(1024), 0, s, A, n, flags);
     }

@@ -230,10 +230,13 @@ LoopLayout loop_layout(const px_cell* cell, px_precision prec, int n, int n_phi)
   return l;
 }
 
-// Maximum Jacobi sweeps of the occupation-matrix diagonalisation (the method
-// converges quadratically; a few sweeps past ten are rare for n in the
-// thousands).
-constexpr int kEigSweeps = 16;
+// Maximum Jacobi sweeps of the occupation-matrix diagonalisation.  The
+// method converges quadratically only once the off-diagonal norm is below the
+// gaps between distinct eigenvalues; Fermi-Dirac spectra hold eigenvalues
+// exponentially close to 0 and 1, and then the off-diagonal norm first falls
+// by a factor of only 2-3 per sweep (n = 512 at kT = 0.02 Ha: 21 sweeps).
+// Sweeps after convergence cost one no-op launch pair per round.
+constexpr int kEigSweeps = 40;
 // Most fixed-point iterations of one px_ptim_step call.
 constexpr int kStepMaxIter = 64;
 
@@ -490,7 +493,8 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
   if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32) return 0;
   const bool fft_grid = px::grid_supported(cell->n[0], cell->n[1], cell->n[2]);
   const bool gemm_grid = prec == PX_PREC_FP64 || ngrid(cell) % 2 == 0;
-  const bool fft_op = op == PX_OP_EXCHANGE || op == PX_OP_ACE_BUILD || op == PX_OP_EXCHANGE_SIGMA;
+  const bool fft_op = op == PX_OP_EXCHANGE || op == PX_OP_ACE_BUILD || op == PX_OP_EXCHANGE_SIGMA ||
+                      op == PX_OP_ACE_BUILD_SIGMA;
   if (fft_op ? !fft_grid : !gemm_grid) return 0;
   int ic, jc, p2;
   tuning_for(ctx, cell, prec, &ic, &jc, &p2);
@@ -518,6 +522,10 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
     case PX_OP_PTIM_STEP:
       if (n_phi <= 0) return 0;
       return step_layout(cell, prec, n_psi, n_phi, kStepMaxIter).end;
+    case PX_OP_ACE_BUILD_SIGMA: {
+      const AceLayout a = ace_layout(cell, prec, n_psi, ic, jc, ctx->symmetric_ace, p2);
+      return sigma_layout(a.end, cell, prec, n_psi, false).end;
+    }
   }
   return 0;
 }
@@ -614,27 +622,20 @@ px_status px_exchange_apply(px_context* ctx, const px_cell* cell, px_precision p
   return st;
 }
 
-px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
-                       const void* psi, const double* occ, const double* kernel_G, void* xi,
-                       double* M, double* e_x, int32_t* status, hipStream_t stream) {
-  if (!ctx) return PX_ERR_INVALID_ARG;
-  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
-    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
-  px_status st = check_grid(ctx, cell);
-  if (st != PX_OK) return st;
-  if (n <= 0) return fail(ctx, PX_ERR_INVALID_ARG, "n must be > 0 (got %d)", n);
-  if (!psi || !occ || !kernel_G || !xi || !status)
-    return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: null array argument");
-  if (xi == psi) return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: xi must not alias psi");
-  if (misaligned(psi) || misaligned(xi))
-    return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: orbital blocks must be 16-byte aligned");
-  int ic, jc, p2;
-  tuning_for(ctx, cell, prec, &ic, &jc, &p2);
-  const AceLayout l = ace_layout(cell, prec, n, ic, jc, ctx->symmetric_ace, p2);
-  st = need_ws(ctx, l.end);
-  if (st != PX_OK) return st;
-  hipError_t he = hipSetDevice(ctx->device);
-  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+}  // extern "C"
+
+namespace {
+
+// The ACE construction of Eq. 14 from orbitals psi with occupations occ, in
+// the workspace layout l (validated arguments, device set): W = Vx psi through
+// the pair pipeline, M = dV psi^H W, -M = L L^H, U = L^-H, xi = W U; the
+// Cholesky breakdown column goes to *status.
+px_status ace_build_run(px_context* ctx, const px_cell* cell, px_precision prec, int n,
+                        const void* psi, const double* occ, const double* kernel_G, void* xi,
+                        double* M, double* e_x, int32_t* status, const AceLayout& l, int ic,
+                        int jc, int p2, hipStream_t stream) {
+  px_status st = PX_OK;
+  hipError_t he = hipSuccess;
   const bool fp32 = prec == PX_PREC_FP32;
   const size_t ng = ngrid(cell);
   const double omega = cell->L[0] * cell->L[1] * cell->L[2];
@@ -691,7 +692,6 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   st = hip_check(ctx, px::launch_gemm_xc(fp32, n, n, ng, W, Uc, n, 1.0, xi, true, stream),
                  "xi = W L^-H");
   if (st != PX_OK) return st;
-  ctx->last_status.assign(1, {status, PX_ERR_NOT_POSITIVE_DEFINITE});
   if (ctx->profiling) {
     (void)hipEventRecord(ev[4], stream);
     he = hipEventSynchronize(ev[4]);
@@ -706,6 +706,36 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
     ctx->ace_calls += 1;
   }
   return PX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                       const void* psi, const double* occ, const double* kernel_G, void* xi,
+                       double* M, double* e_x, int32_t* status, hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  px_status st = check_grid(ctx, cell);
+  if (st != PX_OK) return st;
+  if (n <= 0) return fail(ctx, PX_ERR_INVALID_ARG, "n must be > 0 (got %d)", n);
+  if (!psi || !occ || !kernel_G || !xi || !status)
+    return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: null array argument");
+  if (xi == psi) return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: xi must not alias psi");
+  if (misaligned(psi) || misaligned(xi))
+    return fail(ctx, PX_ERR_INVALID_ARG, "ace_build: orbital blocks must be 16-byte aligned");
+  int ic, jc, p2;
+  tuning_for(ctx, cell, prec, &ic, &jc, &p2);
+  const AceLayout l = ace_layout(cell, prec, n, ic, jc, ctx->symmetric_ace, p2);
+  st = need_ws(ctx, l.end);
+  if (st != PX_OK) return st;
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  st = ace_build_run(ctx, cell, prec, n, psi, occ, kernel_G, xi, M, e_x, status, l, ic, jc, p2, stream);
+  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_POSITIVE_DEFINITE});
+  return st;
 }
 
 px_status px_ace_apply(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
@@ -934,6 +964,41 @@ px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision pr
   return st;
 }
 
+px_status px_ace_build_sigma(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                             const void* phi_basis, const double* sigma, const double* kernel_G,
+                             void* xi, double* M, double* e_x, int32_t* status,
+                             hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  px_status st = check_grid(ctx, cell);
+  if (st != PX_OK) return st;
+  if (n <= 0) return fail(ctx, PX_ERR_INVALID_ARG, "n must be > 0 (got %d)", n);
+  if (!phi_basis || !sigma || !kernel_G || !xi || !status)
+    return fail(ctx, PX_ERR_INVALID_ARG, "ace_build_sigma: null array argument");
+  if (xi == phi_basis) return fail(ctx, PX_ERR_INVALID_ARG, "ace_build_sigma: xi must not alias Phi");
+  if (misaligned(phi_basis) || misaligned(xi) || misaligned(sigma))
+    return fail(ctx, PX_ERR_INVALID_ARG,
+                "ace_build_sigma: orbital blocks and sigma must be 16-byte aligned");
+  int ic, jc, p2;
+  tuning_for(ctx, cell, prec, &ic, &jc, &p2);
+  const AceLayout l = ace_layout(cell, prec, n, ic, jc, ctx->symmetric_ace, p2);
+  const SigmaLayout sl = sigma_layout(l.end, cell, prec, n, false);
+  st = need_ws(ctx, sl.end);
+  if (st != PX_OK) return st;
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  // sigma = Q D Q^H and phi = Phi Q (Eq. 11); then Eq. 14 on (phi, d), which
+  // span the same space as Phi, so V_ACE is exact on span(Phi)
+  st = rotate_orbitals(ctx, sl, cell, prec, n, phi_basis, sigma, status, stream);
+  if (st != PX_OK) return st;
+  st = ace_build_run(ctx, cell, prec, n, ctx->ws + sl.phi, reinterpret_cast<double*>(ctx->ws + sl.d),
+                     kernel_G, xi, M, e_x, status + 1, l, ic, jc, p2, stream);
+  if (st == PX_OK)
+    ctx->last_status = {{status, PX_ERR_NOT_CONVERGED}, {status + 1, PX_ERR_NOT_POSITIVE_DEFINITE}};
+  return st;
+}
+
 px_status px_ptim_step(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
                        const void* xi, int32_t n_phi, const void* phi_n, const double* sigma_n,
                        int32_t n_iter, double dt_alpha, void* phi_out, double* sigma_out,
@@ -989,14 +1054,15 @@ px_status px_ptim_step(px_context* ctx, const px_cell* cell, px_precision prec, 
                                      stream), "C = dV xi^H mid")) != PX_OK) return st;
     if ((st = ok(px::launch_gemm_xc(fp32, n, n_phi, ng, xi, Cc, n_phi, -1.0, w + l.Y, false, stream),
                  "Y = -xi C")) != PX_OK) return st;
-    // S = dV mid^H mid, Hm = dV mid^H Y (Eq. 5 and Eq. 6's Phi^* H Phi)
-    if ((st = ok(px::launch_gemm_xhy(fp32, n_phi, n_phi, ng, mid, mid, dV, D(l.S), n_phi, D(l.part2), ns2,
-                                     nullptr, stream), "S = dV mid^H mid")) != PX_OK) return st;
-    if ((st = ok(px::launch_gemm_xhy(fp32, n_phi, n_phi, ng, mid, w + l.Y, dV, D(l.Hm), n_phi, D(l.part2),
-                                     ns2, nullptr, stream), "Hm = dV mid^H Y")) != PX_OK) return st;
-    // Phi^* H Phi is Hermitian (V_ACE is): Hermitise the computed one (its defect is
-    // the contractions' rounding, 1e-7 relative in the FP32 form), so that the
-    // commutator keeps sigma Hermitian to FP64 rounding
+    // S = dV mid^H mid (Eq. 5; Hermitian: upper tiles, mirrored).  Eq. 6's
+    // Phi^* H Phi with H = V_ACE: dV mid^H Y = -dV mid^H xi C = -C^H C, an
+    // n_phi x n_phi product over the rank of xi from the FP64 C already formed
+    // (exactly Hermitian; Hermitised anyway so that the commutator keeps sigma
+    // Hermitian to the last bit)
+    if ((st = ok(px::launch_gemm_xhy_herm(fp32, n_phi, ng, mid, mid, dV, D(l.S), D(l.part2), ns2, stream),
+                 "S = dV mid^H mid")) != PX_OK) return st;
+    if ((st = ok(px::launch_zgemm_gen(true, n_phi, n_phi, n, C, n_phi, C, n_phi, D(l.Hm), n_phi, -1.0,
+                                      stream), "Hm = -C^H C")) != PX_OK) return st;
     if ((st = ok(px::launch_hermitize(D(l.Hm), n_phi, stream), "hermitize Hm")) != PX_OK) return st;
     // X = S^{-1} Hm in FP64: S = L L^H (the Cholesky of -(-S)), U = L^{-H}, X = U (U^H Hm)
     if ((st = ok(px::launch_scale(size_t(2) * n_phi * n_phi, D(l.S), -1.0, D(l.Mneg), stream), "-S")) != PX_OK)
@@ -1735,7 +1801,7 @@ px_status px_sync(px_context* ctx, hipStream_t stream) {
       ctx->latched = kind;
       if (kind == PX_ERR_NOT_POSITIVE_DEFINITE)
         fail(ctx, kind,
-             "ace_build (instance %zu): -M is not positive definite (Cholesky breakdown at column %d)",
+             "ace_build (status word %zu): -M is not positive definite (Cholesky breakdown at column %d)",
              k, s);
       else
         fail(ctx, kind, "sigma diagonalisation: Jacobi sweeps did not converge (%d sweeps)", s);

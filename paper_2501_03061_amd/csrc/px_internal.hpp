@@ -256,6 +256,10 @@ struct CholJob {
 hipError_t launch_chol_inv_group(const CholJob* jobs, int njobs, int max_n, hipStream_t s);
 // C = op(A) B, n x n complex128 row-major, op(A) = A^H when ah
 hipError_t launch_zgemm(bool ah, int n, const double* A, const double* B, double* C, hipStream_t s);
+// C = alpha op(A) B: op(A) m x k (A^H of a k x m A when ah), B k x n, C m x n,
+// complex128 row-major with leading dimensions lda, ldb, ldc (elements)
+hipError_t launch_zgemm_gen(bool ah, int m, int n, int k, const double* A, int lda, const double* B,
+                            int ldb, double* C, int ldc, double alpha, hipStream_t s);
 // dst = alpha * src, n real FP64 values
 hipError_t launch_scale(size_t n, const double* src, double alpha, double* dst, hipStream_t s);
 // nxt = sigma_n - i c (A1 - A2) (n x n complex128); *res = ||nxt - cur|| / ||nxt|| (FP64)

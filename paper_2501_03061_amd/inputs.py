@@ -34,7 +34,7 @@ from scipy.special import expit
 __all__ = [
     "Instance", "signed_freq", "sphere_indices", "random_orbitals",
     "fermi_dirac", "make_instance", "plane_wave_orbitals", "noise_block",
-    "batch_recipe", "CONFIGS",
+    "batch_recipe", "occupation_matrix", "CONFIGS",
 ]
 
 
@@ -183,6 +183,23 @@ def batch_recipe(n_inst=48, seed=0, sizes=(32, 40, 48, 64), n_range=(32, 256),
         kT = float(rng.uniform(*kT_range))
         out.append(dict(n=n, L=spacing * n, n_orb=n_orb, kT=kT, seed=s))
     return out
+
+
+def occupation_matrix(occ, seed, mix=0.1) -> np.ndarray:
+    """A full Hermitian occupation matrix with the spectrum occ, standing for
+    sigma some time steps into a run (it starts diagonal and develops
+    coherences): sigma = V diag(occ) V^H with V the unitary factor of the QR of
+    I + mix * (A + iB) / sqrt(2 n), A and B standard normal from one generator
+    (column phases fixed so that diag(R) > 0).  complex128 [n][n]."""
+    occ = np.asarray(occ, dtype=np.float64)
+    n = occ.shape[0]
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    q, r = np.linalg.qr(np.eye(n) + mix * g / math.sqrt(2.0 * n))
+    d = np.diag(r)
+    q = q * (d / np.abs(d))
+    sigma = (q * occ) @ q.conj().T
+    return (sigma + sigma.conj().T) / 2
 
 
 # The five workloads: grids, cells, orbital counts and temperatures.

@@ -20,6 +20,7 @@ PX_OK, PX_ERR_INVALID_ARG, PX_ERR_UNSUPPORTED_GRID, PX_ERR_WORKSPACE, PX_ERR_DEV
 PX_PREC_FP64, PX_PREC_FP32 = 0, 1
 PX_OP_EXCHANGE, PX_OP_ACE_BUILD, PX_OP_ACE_APPLY, PX_OP_PTIM_LOOP = 0, 1, 2, 3
 PX_OP_EXCHANGE_SIGMA, PX_OP_SIGMA_DIAG, PX_OP_DENSITY_SIGMA, PX_OP_PTIM_STEP = 4, 5, 6, 7
+PX_OP_ACE_BUILD_SIGMA = 8
 
 STATUS_NAMES = {0: "PX_OK", 1: "PX_ERR_INVALID_ARG", 2: "PX_ERR_UNSUPPORTED_GRID",
                 3: "PX_ERR_WORKSPACE", 4: "PX_ERR_DEVICE", 5: "PX_ERR_NOT_POSITIVE_DEFINITE",
@@ -66,6 +67,7 @@ SIGNATURES = {
     "px_density_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "px_ptim_step": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _dbl, _vp, _vp, _vp,
                             _vp, _vp]),
+    "px_ace_build_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "px_set_symmetry": (_i32, [_vp, _i32]),
     "px_set_profiling": (_i32, [_vp, _i32]),
     "px_profile_read_ace": (_i32, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(ctypes.c_int64), _i32]),
@@ -388,6 +390,27 @@ class Context:
         self._check(self.lib.px_density_sigma(self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis),
                                               _ptr(sigma), _ptr(rho), _ptr(status), _stream(stream)))
         return rho, status
+
+    def px_ace_build_sigma(self, cell: Cell, phi_basis, sigma, kern, xi=None, M=None, e_x=None,
+                           status=None, stream=None):
+        """ACE operator of Vx[Phi sigma Phi^H] (Eq. 14 on (Phi Q, d)); returns
+        (xi, status [2]: diagonalisation, Cholesky)."""
+        import torch
+        prec = _prec(phi_basis.dtype)
+        _check_block("phi_basis", phi_basis, cell)
+        n = phi_basis.shape[0]
+        self._sigma(sigma, n)
+        if xi is None:
+            xi = torch.empty_like(phi_basis)
+        if status is None:
+            status = torch.zeros(2, dtype=torch.int32, device=phi_basis.device)
+        elif status.numel() < 2 or status.dtype != torch.int32:
+            raise ValueError("status must hold two int32 words")
+        self.ensure_workspace(self.workspace_bytes(PX_OP_ACE_BUILD_SIGMA, cell, prec, n))
+        self._check(self.lib.px_ace_build_sigma(
+            self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis), _ptr(sigma), _ptr(kern),
+            _ptr(xi), _ptr(M), _ptr(e_x), _ptr(status), _stream(stream)))
+        return xi, status
 
     def px_ptim_step(self, cell: Cell, xi, phi_n, sigma_n, n_iter: int, dt_alpha: float,
                      phi_out=None, sigma_out=None, residuals=None, status=None, stream=None):

@@ -289,3 +289,27 @@ def test_ptim_step_validation(lib, ctx):
     wb = lib.px_workspace_bytes
     assert wb(ctx, px.PX_OP_PTIM_STEP, ctypes.byref(c), 1, 16, 8) >= 5 * 8 * 24 ** 3 * 8
     assert wb(ctx, px.PX_OP_PTIM_STEP, ctypes.byref(c), 1, 16, 0) == 0
+
+
+def test_ace_build_sigma_validation(lib, ctx):
+    c = _cell()
+    f = lib.px_ace_build_sigma
+    phi, s, kern, xi, st = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000, 0x4000, 0x5000))
+
+    def call(n=4, cell=c, **kw):
+        a = dict(phi=phi, s=s, kern=kern, xi=xi, st=st)
+        a.update(kw)
+        return f(ctx, ctypes.byref(cell), 0, n, a["phi"], a["s"], a["kern"], a["xi"], None, None,
+                 a["st"], None)
+    assert call(n=0) == px.PX_ERR_INVALID_ARG
+    assert call(st=None) == px.PX_ERR_INVALID_ARG
+    assert call(kern=None) == px.PX_ERR_INVALID_ARG
+    assert call(xi=phi) == px.PX_ERR_INVALID_ARG                  # xi aliases Phi
+    assert call(s=ctypes.c_void_p(0x2008)) == px.PX_ERR_INVALID_ARG  # sigma misaligned
+    assert call(cell=_cell(7)) == px.PX_ERR_UNSUPPORTED_GRID
+    assert call() == px.PX_ERR_WORKSPACE
+    wb = lib.px_workspace_bytes
+    ace = wb(ctx, px.PX_OP_ACE_BUILD, ctypes.byref(c), 1, 16, 0)
+    # the ACE build's workspace plus phi = Phi Q, Q and the Jacobi arrays
+    assert wb(ctx, px.PX_OP_ACE_BUILD_SIGMA, ctypes.byref(c), 1, 16, 0) >= ace + 16 * 24 ** 3 * 8 + 16 * 16 * 16
+    assert wb(ctx, px.PX_OP_ACE_BUILD_SIGMA, ctypes.byref(_cell(7)), 1, 16, 0) == 0

@@ -37,7 +37,7 @@ def _sigma(rng, n, degenerate=False):
     return U @ np.diag(d) @ U.conj().T
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 64, 201])
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 64, 201, 600])
 def test_sigma_diagonalize(px_ctx, n):
     import torch
     banner(f"sigma diagonalize n={n}")
@@ -56,6 +56,32 @@ def test_sigma_diagonalize(px_ctx, n):
     assert np.all(np.diff(dh) >= 0)
     assert np.abs(Qh.conj().T @ Qh - np.eye(n)).max() < 1e-12
     assert relerr(Qh @ np.diag(dh) @ Qh.conj().T, sigma) < 1e-12
+
+
+@pytest.mark.parametrize("n,kT", [(512, 0.02), (1536, 0.03)])
+def test_sigma_diagonalize_fermi_dirac(px_ctx, n, kT):
+    """The occupation matrices of the mixed-state workloads: Fermi-Dirac
+    spectra, whose eigenvalues crowd exponentially close to 0 and 1 (Jacobi's
+    slow case: quadratic convergence only once the off-diagonal norm is below
+    those gaps)."""
+    import torch
+    banner(f"sigma diagonalize Fermi-Dirac n={n}")
+    e = np.sort(np.random.default_rng(n).uniform(-0.5, 0.5, n))
+    sigma = inputs.occupation_matrix(inputs.fermi_dirac(e, kT), seed=n + 1)
+    Q, d, st = px_ctx.px_sigma_diagonalize(to_dev(sigma))
+    px_ctx.px_sync()
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    Qh, dh = to_host(Q), to_host(d)
+    dref, _ = oracle.sigma_eig(sigma)
+    rebuild = relerr((Qh * dh) @ Qh.conj().T, sigma)
+    print(f"n={n}: eigenvalue err {np.abs(dh - dref).max():.2e}, rebuild {rebuild:.2e}", flush=True)
+    # Jacobi stops at an off-diagonal norm of 64 eps sqrt(n) ||sigma||; Q carries
+    # the rounding of about 20 sweeps of rotations: O(n eps) after normalisation
+    tol = 20 * n * np.finfo(float).eps
+    assert np.abs(dh - dref).max() < 1e-11
+    assert np.abs(Qh.conj().T @ Qh - np.eye(n)).max() < tol
+    assert rebuild < tol
 
 
 def test_sigma_diagonalize_diagonal_and_zero(px_ctx):
@@ -145,3 +171,47 @@ def test_density(px_ctx, fp32, n, L, N):
     print(f"density fp32={fp32}: occupations {e1:.2e}, sigma {e2:.2e}", flush=True)
     assert e1 < 1e-12
     assert e2 < (FP32_TOL if fp32 else 1e-12)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_ace_build_sigma(px_ctx, fp32):
+    """ACE operator of a full occupation matrix on a 16^3 grid with 6 orbitals
+    and a random sigma with eigenvalues in [0, 1]:
+    * V_ACE Phi = Vx[sigma] Phi against the oracle's Eq. 10 triple loop
+      (exactness on span(Phi));
+    * V_ACE on vectors outside span(Phi) against the oracle's ACE built on
+      (Phi Q, d) (xi xi^H does not depend on the phases of Q);
+    * e_x against (1/2) dV Tr(sigma Phi^H Vx[sigma] Phi) from the triple loop."""
+    import torch
+    banner(f"ace build sigma fp32={fp32}")
+    rng = np.random.default_rng(11)
+    inst = inputs.make_instance(16, 6.0, 6, kT=0.05, seed=41)
+    Phi = inst.psi
+    sigma = _sigma(rng, 6)
+    K = oracle.kernel_hse(inst.n, inst.L, 0.106)
+    dV = inst.omega / inst.ng
+    vx_phi = oracle.exchange_apply_sigma(Phi, sigma, Phi, K)
+    A = dV * Phi.reshape(6, -1).conj() @ vx_phi.reshape(6, -1).T        # A_ki = dV <Phi_k|Vx Phi_i>
+    e_ref = 0.5 * float(np.trace(sigma @ A).real)
+    d, Q = oracle.sigma_eig(sigma)
+    r = oracle.ace_build(oracle.rotate(Phi, Q), d, K, dV)
+    X = inputs.noise_block(inst.n, inst.L, 3, seed=42)
+    ref_x = oracle.ace_apply(r["xi"], X, dV)
+    cell = px.Cell(inst.L, inst.n)
+    P, Xd = to_dev(Phi), to_dev(X)
+    if fp32:
+        P, Xd = px_ctx.px_convert_c128_to_c64(P), px_ctx.px_convert_c128_to_c64(Xd)
+    e_x = torch.zeros(1, dtype=torch.float64, device="cuda")
+    xi, st = px_ctx.px_ace_build_sigma(cell, P, to_dev(sigma), to_dev(K), e_x=e_x)
+    px_ctx.px_sync()
+    assert to_host(st).tolist() == [0, 0]
+    on_span = to_host(px_ctx.px_ace_apply(cell, xi, P))
+    off_span = to_host(px_ctx.px_ace_apply(cell, xi, Xd))
+    torch.cuda.synchronize()
+    e1, e2 = relerr(on_span, vx_phi), relerr(off_span, ref_x)
+    e3 = abs(float(e_x.item()) - e_ref) / abs(e_ref)
+    print(f"ace build sigma fp32={fp32}: V_ACE Phi vs Eq. 10 {e1:.2e}, outside span {e2:.2e}, "
+          f"e_x {e3:.2e}", flush=True)
+    tol = FP32_TOL if fp32 else FP64_TOL
+    assert e1 < tol and e2 < tol
+    assert e3 < (1e-7 if fp32 else FP64_TOL)
