@@ -353,71 +353,94 @@ def bench_single(args, workload):
 
 
 class MixedStep:
-    """One exchange-only finite-temperature PT-IM step with a full occupation
-    matrix, in one precision form, buffers preallocated:
-      staging of Phi_n to complex64 (FP32 form),
-      ACE build of Vx[Phi_n sigma_n Phi_n^H]: sigma_n = Q D Q^H (FP64 Jacobi),
-        phi = Phi_n Q (MFMA), then the ACE construction on (phi, d),
+    """Exchange-only finite-temperature PT-IM time steps with a full occupation
+    matrix, in one precision form, buffers preallocated.  The state is
+    (Phi, sigma) with the diagonal form (phi = Phi Q, d) of sigma = Q D Q^H;
+    one step is
+      the ACE build of Vx[Phi sigma Phi^H] on (phi, d) (pair pipeline, M,
+        Cholesky, xi),
       the PT-IM step (Eq. 4-7 with the projector and the sigma commutator,
-        n_iter fixed-point iterations, FP64 residuals),
-      the density of the new state, rho = sum_ij Phi_i sigma_ij conj(Phi_j)
-        (diagonalise, rotate, sum d_i |phi_i|^2).
-    Events on the current stream (the library's stream) bracket the stages."""
+        n_iter fixed-point iterations, FP64 residuals) -> (Phi', sigma'),
+      the diagonalisation of sigma' (FP64 blocked Jacobi) and phi' = Phi' Q',
+      the density of the new state, sum_i d'_i |phi'_i|^2,
+    so that one diagonalisation per step serves both the density of the new
+    state and the exchange operator of the next step.  Each call advances the
+    state by one step.  Events on the current stream (the library's stream)
+    bracket the stages."""
 
     def __init__(self, ctx, cell, phi64, sigma, kern, fp32, n_iter=4):
         import torch
         from paper_2501_03061_amd import px
-        self.ctx, self.cell, self.fp32, self.n_iter = ctx, cell, fp32, n_iter
-        self.phi64, self.sigma, self.kern = phi64, sigma, kern
+        self.ctx, self.cell, self.fp32, self.n_iter, self.kern = ctx, cell, fp32, n_iter, kern
         dt = torch.complex64 if fp32 else torch.complex128
         n = phi64.shape[0]
         dev = phi64.device
-        self.phi = torch.empty(phi64.shape, dtype=dt, device=dev) if fp32 else phi64
-        self.xi = torch.empty(phi64.shape, dtype=dt, device=dev)
-        self.phi_out = torch.empty(phi64.shape, dtype=dt, device=dev)
-        self.sigma_out = torch.empty_like(sigma)
+        mk = lambda: torch.empty(phi64.shape, dtype=dt, device=dev)  # noqa: E731
+        self.phi = [mk(), mk()]          # Phi of the current and the next state
+        self.rot = [mk(), mk()]          # phi = Phi Q of the current and the next state
+        self.xi = mk()
+        self.sigma = [sigma.clone(), torch.empty_like(sigma)]
+        self.Q = torch.empty_like(sigma)
+        self.d = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(2)]
         self.res = torch.zeros((2, n_iter), dtype=torch.float64, device=dev)
         self.ex = torch.zeros(1, dtype=torch.float64, device=dev)
-        self.st_ace = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.st_ace = torch.zeros(1, dtype=torch.int32, device=dev)
         self.st_step = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.st_rho = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.st_eig = torch.zeros(1, dtype=torch.int32, device=dev)
         self.rho = torch.empty((cell.n[2], cell.n[1], cell.n[0]), dtype=torch.float64, device=dev)
         prec = px.PX_PREC_FP32 if fp32 else px.PX_PREC_FP64
-        need = max(ctx.workspace_bytes(px.PX_OP_ACE_BUILD_SIGMA, cell, prec, n),
+        need = max(ctx.workspace_bytes(px.PX_OP_ACE_BUILD, cell, prec, n),
                    ctx.workspace_bytes(px.PX_OP_PTIM_STEP, cell, prec, n, n),
-                   ctx.workspace_bytes(px.PX_OP_DENSITY_SIGMA, cell, prec, n))
+                   ctx.workspace_bytes(px.PX_OP_SIGMA_DIAG, cell, prec, n),
+                   ctx.workspace_bytes(px.PX_OP_ROTATE, cell, prec, n))
         ctx.ensure_workspace(need)
+        self.cur = 0
+        # the diagonal form of the initial state (outside the steps)
+        if fp32:
+            ctx.px_convert_c128_to_c64(phi64, self.phi[0])
+        else:
+            self.phi[0].copy_(phi64)
+        ctx.px_sigma_diagonalize(self.sigma[0], Q=self.Q, d=self.d[0], status=self.st_eig)
+        ctx.px_rotate_orbitals(cell, self.phi[0], self.Q, out=self.rot[0])
         self.events = []
 
     def __call__(self, record=False):
         import torch
-        c = self.ctx
+        c, a, b = self.ctx, self.cur, 1 - self.cur
         if record:
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
             e[0].record()
-        if self.fp32:
-            c.px_convert_c128_to_c64(self.phi64, self.phi)
+        c.px_ace_build(self.cell, self.rot[a], self.d[a], self.kern, xi=self.xi, e_x=self.ex,
+                       status=self.st_ace)
         if record:
             e[1].record()
-        c.px_ace_build_sigma(self.cell, self.phi, self.sigma, self.kern, xi=self.xi, e_x=self.ex,
-                             status=self.st_ace)
-        if record:
-            e[2].record()
-        c.px_ptim_step(self.cell, self.xi, self.phi, self.sigma, self.n_iter, DT_ALPHA,
-                       phi_out=self.phi_out, sigma_out=self.sigma_out, residuals=self.res,
+        c.px_ptim_step(self.cell, self.xi, self.phi[a], self.sigma[a], self.n_iter, DT_ALPHA,
+                       phi_out=self.phi[b], sigma_out=self.sigma[b], residuals=self.res,
                        status=self.st_step)
         if record:
+            e[2].record()
+        c.px_sigma_diagonalize(self.sigma[b], Q=self.Q, d=self.d[b], status=self.st_eig)
+        if record:
             e[3].record()
-        c.px_density_sigma(self.cell, self.phi_out, self.sigma_out, rho=self.rho, status=self.st_rho)
+        c.px_rotate_orbitals(self.cell, self.phi[b], self.Q, out=self.rot[b])
         if record:
             e[4].record()
+        c.px_density(self.cell, self.rot[b], self.d[b], rho=self.rho)
+        if record:
+            e[5].record()
             self.events.append(e)
+        self.cur = b
+
+    STAGES = ("ace_build", "ptim_step", "sigma_diagonalize", "rotation", "density")
 
     def stage_times(self):
-        """Per recorded step: ms of staging, ACE build with sigma, PT-IM step, density."""
-        out = [[e[k].elapsed_time(e[k + 1]) for k in range(4)] for e in self.events]
+        """Per recorded step: ms of each stage in STAGES."""
+        out = [[e[k].elapsed_time(e[k + 1]) for k in range(5)] for e in self.events]
         self.events = []
         return out
+
+    def status(self):
+        return [int(self.st_ace.item()), int(self.st_step.item()), int(self.st_eig.item())]
 
 
 def time_call(fn, reps=3):
@@ -439,10 +462,11 @@ MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 
 
 def bench_mixed(args, workload):
-    """The occupation-matrix front end, the PT-IM step with the projector and
-    the density (the rows after the exchange/ACE path), as one finite-temperature
-    step on the resident instance of the same size as the single-instance
-    workloads, FP32 form; stage rooflines from event timings of each entry point."""
+    """The rows after the exchange/ACE path (the occupation-matrix front end,
+    the PT-IM step with the projector, the density) in exchange-only
+    finite-temperature time steps on the resident instance of the same size as
+    the single-instance workloads, FP32 form; stage rooflines from the event
+    timings of each stage inside the timed steps."""
     import numpy as np
     import torch
     from paper_2501_03061_amd import inputs, px
@@ -457,6 +481,8 @@ def bench_mixed(args, workload):
     ctx = px.Context(0)
     kern = ctx.px_kernel_hse(cell, cfg["mu"])
     step = MixedStep(ctx, cell, phi64, sigma, kern, fp32=True)
+    del phi64
+    torch.cuda.empty_cache()
     for k in range(max(1, args.warmup)):
         step()
         log(f"mixed warmup step {k + 1}")
@@ -477,16 +503,7 @@ def bench_mixed(args, workload):
     ace = ctx.px_profile_read_ace(reset=True)
     ctx.px_sync()
     stages = step.stage_times()
-    med = [statistics.median(s[k] for s in stages) for k in range(4)]
-    build_ms = ace["build"] / max(1, ace["calls"])
-    # the stages inside the two sigma entry points, each entry point alone
-    Q = torch.empty_like(sigma)
-    d = torch.empty(n, dtype=torch.float64, device="cuda")
-    st = torch.zeros(1, dtype=torch.int32, device="cuda")
-    eig_ms = time_call(lambda: ctx.px_sigma_diagonalize(sigma, Q=Q, d=d, status=st))
-    dens_ms = time_call(lambda: ctx.px_density(cell, step.phi_out, d, rho=step.rho))
-    ctx.px_sync()
-    rot_ms = med[1] - build_ms - eig_ms
+    med = {name: statistics.median(s[k] for s in stages) for k, name in enumerate(MixedStep.STAGES)}
     pairs = n * n
     pairs_phys = n * (n + 1) // 2
     dom, roof, pipeline, passes, ace_stages = roofline_fields(prof, ace, args.steps, pairs_phys, ng, 8, 0.0)
@@ -496,53 +513,53 @@ def bench_mixed(args, workload):
     # per PT-IM iteration: C = dV xi^H mid and Y = -xi C (8 n^2 N_g each), S on
     # its upper tiles (about 4 n^2 N_g), Z = -mid X (8 n^2 N_g)
     it_flops = 28.0 * n * n * ng
-    step_ms = med[2]
     dens_bytes = n * ng * 8 + ng * 8
+
+    def mfma(ms, flops, desc):
+        return dict(ms=ms, bound="mfma", flops=flops, TFLOPs=flops / (ms * 1e-3) / 1e12, peak_TFLOPs=peak,
+                    frac=flops / (ms * 1e-3) / 1e12 / peak, desc=desc)
     stage_roof = {
-        "sigma_diagonalize": dict(ms=eig_ms, bound="latency",
-                                  desc=f"FP64 cyclic Jacobi, {n} x {n}, rounds of disjoint rotations"),
-        "rotation_phi_Q": dict(ms=rot_ms, bound="mfma", flops=rot_flops,
-                               TFLOPs=rot_flops / (rot_ms * 1e-3) / 1e12 if rot_ms > 0 else None,
-                               peak_TFLOPs=peak,
-                               frac=rot_flops / (rot_ms * 1e-3) / 1e12 / peak if rot_ms > 0 else None,
-                               desc="phi = Phi Q, 8 n^2 N_g flops, FP32 MFMA"),
-        "ace_build_on_phi_d": dict(ms=build_ms, stages=ace_stages),
-        "ptim_step": dict(ms=step_ms, iterations=step.n_iter, bound="mfma",
-                          flops=it_flops * step.n_iter,
-                          TFLOPs=it_flops * step.n_iter / (step_ms * 1e-3) / 1e12, peak_TFLOPs=peak,
-                          frac=it_flops * step.n_iter / (step_ms * 1e-3) / 1e12 / peak,
-                          desc="per iteration 28 n^2 N_g flops (xi^H mid, xi C, S upper tiles, "
-                               "mid X), FP32 MFMA; Hm = -C^H C and the sigma algebra in FP64"),
-        "density": dict(ms=dens_ms, bound="hbm", bytes=dens_bytes,
-                        GBps=dens_bytes / (dens_ms * 1e-3) / 1e9,
-                        frac=dens_bytes / (dens_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                        desc="sum_i d_i |phi_i|^2: n N_g b read + 8 N_g written"),
-        "density_sigma": dict(ms=med[3], desc="diagonalise, rotate, density"),
+        "ace_build": dict(ms=med["ace_build"], stages=ace_stages,
+                          desc="ACE build on (phi, d): pair pipeline, M, Cholesky, xi"),
+        "ptim_step": dict(mfma(med["ptim_step"], it_flops * step.n_iter,
+                               "per iteration 28 n^2 N_g flops (xi^H mid, xi C, S on its upper tiles, "
+                               "mid X) on FP32 MFMA; Hm = -C^H C and the sigma algebra in FP64"),
+                          iterations=step.n_iter),
+        "sigma_diagonalize": dict(ms=med["sigma_diagonalize"], bound="latency",
+                                  desc=f"FP64 blocked cyclic Jacobi, {n} x {n}: per sweep "
+                                       f"{2 * ((n + 15) // 16 + ((n + 15) // 16) % 2) - 2} small launches"),
+        "rotation": mfma(med["rotation"], rot_flops, "phi = Phi Q, 8 n^2 N_g flops, FP32 MFMA"),
+        "density": dict(ms=med["density"], bound="hbm", bytes=dens_bytes,
+                        GBps=dens_bytes / (med["density"] * 1e-3) / 1e9,
+                        frac=dens_bytes / (med["density"] * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                        desc="sum_i d_i |phi_i|^2: n N_g b read + 8 N_g written (FP64)"),
     }
     res = step.res.cpu().numpy()
-    sig_out = step.sigma_out.cpu().numpy()
+    a = step.cur
+    sig_now = step.sigma[a].cpu().numpy()
     rho_int = float(step.rho.sum().item()) * cell.dV
-    checks = dict(trace_sigma_n=float(np.trace(sigma_h).real), trace_sigma_out=float(np.trace(sig_out).real),
-                  hermitian_defect_sigma_out=float(np.abs(sig_out - sig_out.conj().T).max()),
+    checks = dict(trace_sigma_0=float(np.trace(sigma_h).real), trace_sigma_now=float(np.trace(sig_now).real),
+                  hermitian_defect_sigma_now=float(np.abs(sig_now - sig_now.conj().T).max()),
                   integral_rho=rho_int, e_x=float(step.ex.item()),
-                  residuals_phi=[float(x) for x in res[0]], residuals_sigma=[float(x) for x in res[1]],
-                  status=[int(x) for x in step.st_ace.cpu()] + [int(step.st_step.item()), int(step.st_rho.item())])
-    log(f"mixed step {ms_step:.1f} ms: stages {[round(x, 1) for x in med]} ms; eig {eig_ms:.1f} ms, "
-        f"rotation {rot_ms:.1f} ms, density {dens_ms:.2f} ms; checks {checks}")
+                  residuals_phi_last_step=[float(x) for x in res[0]],
+                  residuals_sigma_last_step=[float(x) for x in res[1]], status=step.status(),
+                  steps_taken=max(1, args.warmup) + args.steps)
+    log(f"mixed step {ms_step:.1f} ms: stages {[round(med[k], 2) for k in MixedStep.STAGES]} ms; "
+        f"checks {checks}")
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(inst, kern.cpu().numpy(), args.cpu_seconds)
         import oracle
         t1 = time.perf_counter()
-        oracle.sigma_eig(sigma_h)
+        oracle.sigma_eig(sig_now)
         t_eig = time.perf_counter() - t1
-        phi_h = step.phi_out[:, :1].to(torch.complex128).cpu().numpy()
+        rot_h = step.rot[a][:, :1].to(torch.complex128).cpu().numpy()
         t1 = time.perf_counter()
-        oracle.density_sigma(phi_h, sig_out)
+        oracle.density(rot_h, step.d[a].cpu().numpy())
         t_rho = (time.perf_counter() - t1) * inst.n[2]
-        cpu["stage_samples"] = dict(sigma_eig_s=t_eig, density_sigma_s_scaled=t_rho,
-                                    desc="oracle sigma_eig (LAPACK) at full n; oracle density_sigma "
-                                         "on one z-plane, times the number of planes")
+        cpu["stage_samples"] = dict(sigma_eig_s=t_eig, density_s_scaled=t_rho,
+                                    desc="oracle sigma_eig (LAPACK) at full n; oracle density on one "
+                                         "z-plane, times the number of planes")
     rec = {
         "metric": METRIC, "value": pairs / (ms_step * 1e-3), "unit": "pair-solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -550,9 +567,7 @@ def bench_mixed(args, workload):
         "config": {"workload": MIXED_TEXT[workload], "grid": list(inst.n), "n_orbitals": n,
                    "pairs_per_step": pairs},
         "roofline": roof, "cpu_baseline": cpu,
-        "extra": {"stage_ms_median": dict(staging=med[0], ace_build_sigma=med[1], ptim_step=med[2],
-                                          density_sigma=med[3]),
-                  "stages": stage_roof, "pair_pipeline": pipeline, "passes": passes,
+        "extra": {"stage_ms_median": med, "stages": stage_roof, "pair_pipeline": pipeline, "passes": passes,
                   "physical_pair_solves_per_s": pairs_phys / (ms_step * 1e-3), "checks": checks,
                   "gpu": torch.cuda.get_device_name(0)},
     }
@@ -562,10 +577,11 @@ def bench_mixed(args, workload):
 
 MIXED_BASE = {"mixed72": "mid72", "mixed96": "large96"}
 MIXED_TEXT = {
-    k: f"{k}: the {v} instance (Phi_n = Psi + 1e-3 Z) with a full occupation matrix sigma_n = "
-       "V diag(f) V^H (V unitary, I + 0.1 noise); step = staging + ACE build of Vx[sigma] "
-       "(Jacobi diagonalisation, Phi Q, pair pipeline on (phi, d), M, Cholesky, xi) + PT-IM step "
-       "with projector and sigma commutator (4 iterations) + density of the new state; FP32 bulk"
+    k: f"{k}: the {v} instance (Phi_0 = Psi + 1e-3 Z) with a full occupation matrix sigma_0 = "
+       "V diag(f) V^H (V unitary, I + 0.1 noise), advanced by exchange-only PT-IM time steps; "
+       "step = ACE build of Vx[sigma] on the diagonal form (phi = Phi Q, d) + PT-IM step with "
+       "projector and sigma commutator (4 iterations) + diagonalisation of the new sigma (FP64 "
+       "Jacobi) + phi' = Phi' Q' + density of the new state; FP32 bulk"
     for k, v in MIXED_BASE.items()}
 
 

@@ -80,7 +80,8 @@ typedef enum {
   PX_OP_SIGMA_DIAG = 5,      /* n_psi = n; n_phi ignored                 */
   PX_OP_DENSITY_SIGMA = 6,   /* n_psi = n; n_phi ignored                 */
   PX_OP_PTIM_STEP = 7,       /* n_psi = n (rank of xi), n_phi            */
-  PX_OP_ACE_BUILD_SIGMA = 8  /* n_psi = n (Phi and sigma); n_phi ignored */
+  PX_OP_ACE_BUILD_SIGMA = 8, /* n_psi = n (Phi and sigma); n_phi ignored */
+  PX_OP_ROTATE = 9           /* n_psi = n; n_phi ignored                 */
 } px_op;
 
 /* Orthorhombic cell: edge lengths in bohr and the real-space grid, n[0] = x. */
@@ -256,6 +257,18 @@ px_status px_density(px_context* ctx, const px_cell* cell, px_precision prec, in
 px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
                            const void* phi_basis, const double* sigma, double* rho, int32_t* status,
                            hipStream_t stream);
+
+/* The orbitals of the diagonal form (Eq. 11): phi = Phi Q, orbital b of phi
+ * being sum_a Q[a][b] Phi_a (with Q from px_sigma_diagonalize, phi and d
+ * feed px_ace_build, px_exchange_apply and px_density, so that one
+ * diagonalisation serves both the density of a state and the exchange
+ * operator of the next step).  Phi and phi_out [n][N_g] (element type of
+ * prec, no aliasing), Q complex128 [n][n] row-major (device).  A contraction
+ * over the orbitals on the matrix cores, in the form's precision (the FP32
+ * form rounds Q to complex64 in the workspace, PX_OP_ROTATE with n; the FP64
+ * form reads Q directly and needs no workspace).  Grids as in px_ace_apply. */
+px_status px_rotate_orbitals(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                             const void* phi_basis, const double* Q, void* phi_out, hipStream_t stream);
 
 /* ACE construction for a full occupation matrix (Eq. 10 compressed as in
  * Eq. 14, evaluated through Eq. 11-13): sigma = Q D Q^H, phi = Phi Q, then

@@ -18,7 +18,8 @@
 // into 32-row tiles V_rS <- V_rS U_S, one workgroup per tile.  Compared with
 // rotating single index pairs, a sweep reads and writes A and V nb - 1 times
 // instead of n - 1 times, which is what bounds the method at these sizes.
-// After each sweep one workgroup forms the off-diagonal Frobenius norm; below
+// After each sweep the off-diagonal Frobenius norm is formed (partial sums,
+// then a fixed-order total); below
 // 64 eps sqrt(n) ||A||_F a device flag makes the remaining launches return at
 // once, so the host enqueues a fixed number of sweeps without waiting for the
 // device.  Finally d = diag(A) in ascending order, Q the matching columns of V.
@@ -261,14 +262,18 @@ __global__ __launch_bounds__(256) void bj_apply_k(double* A, double* V, int n, i
   }
 }
 
-// End of a sweep: off-diagonal and total Frobenius norms (one workgroup, fixed
-// order); sets the convergence flag.
-__global__ __launch_bounds__(1024) void eig_conv_k(const double* A, int n, int* flags) {
-  __shared__ double so[1024], st[1024];
+// End of a sweep: off-diagonal and total squared Frobenius norms, first as
+// partial sums of kConvBlocks workgroups (a strided share of the entries
+// each), then summed in fixed order by one workgroup, which sets the
+// convergence flag.
+constexpr int kConvBlocks = 256;
+
+__global__ __launch_bounds__(256) void eig_norm_part_k(const double* A, int n, double* part, const int* flags) {
+  __shared__ double so[256], st[256];
   if (flags[0]) return;
   double off = 0.0, tot = 0.0;
   const size_t total = size_t(n) * n;
-  for (size_t e = threadIdx.x; e < total; e += blockDim.x) {
+  for (size_t e = size_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += size_t(kConvBlocks) * 256) {
     const int i = int(e / n), j = int(e % n);
     const double2 a = ld2(A, n, i, j);
     const double m2 = a.x * a.x + a.y * a.y;
@@ -278,7 +283,26 @@ __global__ __launch_bounds__(1024) void eig_conv_k(const double* A, int n, int* 
   so[threadIdx.x] = off;
   st[threadIdx.x] = tot;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+      so[threadIdx.x] += so[threadIdx.x + w];
+      st[threadIdx.x] += st[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = so[0];
+    part[2 * blockIdx.x + 1] = st[0];
+  }
+}
+
+__global__ __launch_bounds__(kConvBlocks) void eig_conv_k(const double* part, int n, int* flags) {
+  __shared__ double so[kConvBlocks], st[kConvBlocks];
+  if (flags[0]) return;
+  so[threadIdx.x] = part[2 * threadIdx.x];
+  st[threadIdx.x] = part[2 * threadIdx.x + 1];
+  __syncthreads();
+  for (int w = kConvBlocks / 2; w > 0; w >>= 1) {
     if (int(threadIdx.x) < w) {
       so[threadIdx.x] += so[threadIdx.x + w];
       st[threadIdx.x] += st[threadIdx.x + w];
@@ -334,7 +358,8 @@ int eig_blocks(int n) {
 size_t eig_work_bytes(int n) {
   const size_t mat = size_t(n) * n * 16;
   const size_t ug = size_t(eig_blocks(n) / 2) * BJ2 * BJ2 * 16;
-  return 2 * mat + ug + size_t(n) * sizeof(int) + 4 * sizeof(int) + 4 * 256;
+  return 2 * mat + ug + size_t(2 * kConvBlocks) * sizeof(double) + size_t(n) * sizeof(int) + 4 * sizeof(int) +
+         5 * 256;
 }
 
 hipError_t launch_eig_hermitian(const double* sigma, int n, double* Q, double* d, int32_t* status,
@@ -349,6 +374,7 @@ hipError_t launch_eig_hermitian(const double* sigma, int n, double* Q, double* d
   double* A = reinterpret_cast<double*>(carve(size_t(n) * n * 16));
   double* V = reinterpret_cast<double*>(carve(size_t(n) * n * 16));
   double* Ug = reinterpret_cast<double*>(carve(size_t(m) * BJ2 * BJ2 * 16));
+  double* part = reinterpret_cast<double*>(carve(size_t(2 * kConvBlocks) * sizeof(double)));
   int* rank = reinterpret_cast<int*>(carve(size_t(n) * sizeof(int)));
   int* flags = reinterpret_cast<int*>(carve(4 * sizeof(int)));
   const size_t total = size_t(n) * n;
@@ -361,10 +387,12 @@ hipError_t launch_eig_hermitian(const double* sigma, int n, double* Q, double* d
         hipLaunchKernelGGL(bj_solve_k, dim3(m), dim3(256), 0, s, A, n, nb, k, Ug, flags);
         hipLaunchKernelGGL(bj_apply_k, dim3(tiles, 2), dim3(256), 0, s, A, V, n, nb, k, Ug, flags);
       }
-      hipLaunchKernelGGL(eig_conv_k, dim3(1), dim3(1024), 0, s, A, n, flags);
+      hipLaunchKernelGGL(eig_norm_part_k, dim3(kConvBlocks), dim3(256), 0, s, A, n, part, flags);
+      hipLaunchKernelGGL(eig_conv_k, dim3(1), dim3(kConvBlocks), 0, s, part, n, flags);
     }
   } else {
-    hipLaunchKernelGGL(eig_conv_k, dim3(1), dim3(1024), 0, s, A, n, flags);
+    hipLaunchKernelGGL(eig_norm_part_k, dim3(kConvBlocks), dim3(256), 0, s, A, n, part, flags);
+    hipLaunchKernelGGL(eig_conv_k, dim3(1), dim3(kConvBlocks), 0, s, part, n, flags);
   }
   hipLaunchKernelGGL(eig_rank_k, dim3((n + 255) / 256), dim3(256), 0, s, A, n, rank, d, flags, status);
   hipLaunchKernelGGL(eig_permute_k, dim3(grid_for(total)), dim3(256), 0, s, V, n, rank, Q);

@@ -522,6 +522,8 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
     case PX_OP_PTIM_STEP:
       if (n_phi <= 0) return 0;
       return step_layout(cell, prec, n_psi, n_phi, kStepMaxIter).end;
+    case PX_OP_ROTATE:  // Q in complex64 (the FP64 form does not use it)
+      return align_up(size_t(n_psi) * n_psi * 8);
     case PX_OP_ACE_BUILD_SIGMA: {
       const AceLayout a = ace_layout(cell, prec, n_psi, ic, jc, ctx->symmetric_ace, p2);
       return sigma_layout(a.end, cell, prec, n_psi, false).end;
@@ -962,6 +964,39 @@ px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision pr
                  "density");
   if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED});
   return st;
+}
+
+px_status px_rotate_orbitals(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                             const void* phi_basis, const double* Q, void* phi_out, hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  px_status st = check_gemm_grid(ctx, cell, prec);
+  if (st != PX_OK) return st;
+  if (n <= 0) return fail(ctx, PX_ERR_INVALID_ARG, "n must be > 0 (got %d)", n);
+  if (!phi_basis || !Q || !phi_out) return fail(ctx, PX_ERR_INVALID_ARG, "rotate_orbitals: null array argument");
+  if (phi_out == phi_basis)
+    return fail(ctx, PX_ERR_INVALID_ARG, "rotate_orbitals: phi_out must not alias Phi");
+  if (misaligned(phi_basis) || misaligned(Q) || misaligned(phi_out))
+    return fail(ctx, PX_ERR_INVALID_ARG, "rotate_orbitals: arrays must be 16-byte aligned");
+  const bool fp32 = prec == PX_PREC_FP32;
+  if (fp32) {
+    st = need_ws(ctx, align_up(size_t(n) * n * 8));
+    if (st != PX_OK) return st;
+  }
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  const void* Qc = Q;
+  if (fp32) {  // the FP32 contraction reads Q rounded to complex64
+    st = hip_check(ctx, px::launch_convert_f64_f32(size_t(2) * n * n, Q, reinterpret_cast<float*>(ctx->ws),
+                                                   stream),
+                   "Q to FP32");
+    if (st != PX_OK) return st;
+    Qc = ctx->ws;
+  }
+  return hip_check(ctx, px::launch_gemm_xc(fp32, n, n, ngrid(cell), phi_basis, Qc, n, 1.0, phi_out, false,
+                                           stream),
+                   "phi = Phi Q");
 }
 
 px_status px_ace_build_sigma(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,

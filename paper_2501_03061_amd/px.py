@@ -20,7 +20,7 @@ PX_OK, PX_ERR_INVALID_ARG, PX_ERR_UNSUPPORTED_GRID, PX_ERR_WORKSPACE, PX_ERR_DEV
 PX_PREC_FP64, PX_PREC_FP32 = 0, 1
 PX_OP_EXCHANGE, PX_OP_ACE_BUILD, PX_OP_ACE_APPLY, PX_OP_PTIM_LOOP = 0, 1, 2, 3
 PX_OP_EXCHANGE_SIGMA, PX_OP_SIGMA_DIAG, PX_OP_DENSITY_SIGMA, PX_OP_PTIM_STEP = 4, 5, 6, 7
-PX_OP_ACE_BUILD_SIGMA = 8
+PX_OP_ACE_BUILD_SIGMA, PX_OP_ROTATE = 8, 9
 
 STATUS_NAMES = {0: "PX_OK", 1: "PX_ERR_INVALID_ARG", 2: "PX_ERR_UNSUPPORTED_GRID",
                 3: "PX_ERR_WORKSPACE", 4: "PX_ERR_DEVICE", 5: "PX_ERR_NOT_POSITIVE_DEFINITE",
@@ -68,6 +68,7 @@ SIGNATURES = {
     "px_ptim_step": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _dbl, _vp, _vp, _vp,
                             _vp, _vp]),
     "px_ace_build_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "px_rotate_orbitals": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp]),
     "px_set_symmetry": (_i32, [_vp, _i32]),
     "px_set_profiling": (_i32, [_vp, _i32]),
     "px_profile_read_ace": (_i32, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(ctypes.c_int64), _i32]),
@@ -390,6 +391,20 @@ class Context:
         self._check(self.lib.px_density_sigma(self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis),
                                               _ptr(sigma), _ptr(rho), _ptr(status), _stream(stream)))
         return rho, status
+
+    def px_rotate_orbitals(self, cell: Cell, phi_basis, Q, out=None, stream=None):
+        """phi = Phi Q (orbital b = sum_a Q[a][b] Phi_a)."""
+        import torch
+        prec = _prec(phi_basis.dtype)
+        _check_block("phi_basis", phi_basis, cell)
+        n = phi_basis.shape[0]
+        self._sigma(Q, n)
+        if out is None:
+            out = torch.empty_like(phi_basis)
+        self.ensure_workspace(self.workspace_bytes(PX_OP_ROTATE, cell, prec, n))
+        self._check(self.lib.px_rotate_orbitals(self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis),
+                                                _ptr(Q), _ptr(out), _stream(stream)))
+        return out
 
     def px_ace_build_sigma(self, cell: Cell, phi_basis, sigma, kern, xi=None, M=None, e_x=None,
                            status=None, stream=None):

@@ -31,7 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("exchange_kernels.hpp", "fft_core.hpp", "px_internal.hpp", "exchange_inst.hip",
                   "pair_transpose.hip")
 WORKLOAD_TEXT = {"large96": "large96 workload (96^3 grid, 1536 orbitals)",
-                 "mid72": "mid72 workload (72^3 grid, 512 orbitals)"}
+                 "mid72": "mid72 workload (72^3 grid, 512 orbitals)",
+                 "mixed96": "mixed96 workload (96^3 grid, 1536 orbitals, full occupation matrix)",
+                 "mixed72": "mixed72 workload (72^3 grid, 512 orbitals, full occupation matrix)"}
 
 
 def source_digest():
@@ -130,6 +132,48 @@ def summarize_trace(trace, bench_json, out, commands, workload):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
     open(os.path.join(out, f"pair_pipeline_{workload}_kernel_trace.md"), "w").write("\n".join(lines) + "\n")
+
+
+def summarize_stages(trace, bench_json, out, command, workload):
+    """Kernel trace of the mixed-state time steps: the bench's stage times
+    (HIP events inside its timed steps) beside the trace's kernels."""
+    os.makedirs(out, exist_ok=True)
+    rec = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    stats = _csv(trace, "kernel_stats.csv")
+    ex = rec["extra"]
+    steps = ex["checks"]["steps_taken"]
+    lines = [f"# Kernel trace: mixed-state time steps, {WORKLOAD_TEXT[workload]}", "",
+             "Command ($REPO: the repository root, $OUT: the raw output folder; one MI355X):", "",
+             "```", command, "```", "",
+             f"The run inside the profiler: {steps} time steps (the first untimed) after the initial "
+             f"diagonalisation and rotation; {rec['ms_per_step']:.1f} ms per timed step.", "",
+             "Stages of the timed step (bench.py, HIP events on the library's stream):", "",
+             "| stage | ms | bound | rate | fraction of peak |", "|---|---|---|---|---|"]
+    for name, st in ex["stages"].items():
+        rate, frac = "", ""
+        if st.get("bound") == "mfma":
+            rate, frac = f"{st['TFLOPs']:.1f} TFLOP/s", f"{st['frac']:.3f} of {st['peak_TFLOPs']}"
+        elif st.get("bound") == "hbm":
+            rate, frac = f"{st['GBps']:.0f} GB/s", f"{st['frac']:.3f} of 8000"
+        lines.append(f"| {name} | {st['ms']:.2f} | {st.get('bound', 'pipeline')} | {rate} | {frac} |")
+    lines += ["", "Kernels (`kernel_stats.csv`, the whole run; the Jacobi launches include the no-op "
+              "launches after convergence, which return at once):", "",
+              "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in stats[:26]:
+        name = r["Name"] if len(r["Name"]) < 90 else r["Name"][:90] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    fam = collections.defaultdict(float)
+    for r in stats:
+        name = r["Name"].replace("(anonymous namespace)::", "")
+        short = name.split("(")[0].split("<")[0].split("::")[-1].replace("void ", "").strip()
+        fam[short] += float(r["TotalDurationNs"]) / 1e6
+    diag = (fam["bj_solve_k"] + fam["bj_apply_k"] + fam["eig_norm_part_k"] + fam["eig_conv_k"] +
+            fam["eig_init_k"] + fam["eig_rank_k"] + fam["eig_permute_k"]) / (steps + 1)
+    lines += ["", f"Per diagonalisation in the trace ({steps + 1} of them): {diag:.1f} ms "
+              f"(bench: {ex['stages']['sigma_diagonalize']['ms']:.1f} ms); density kernel "
+              f"{fam['density_k'] / steps:.2f} ms per call (bench: {ex['stages']['density']['ms']:.2f} ms)."]
+    open(os.path.join(out, f"mixed_steps_{workload}_kernel_trace.md"), "w").write("\n".join(lines) + "\n")
 
 
 def summarize_hbm(fetch, write, copy_fetch, copy_write, out, commands, workload):
@@ -287,6 +331,11 @@ def main():
     w = args.workload
     # $REPO: the repository root; $OUT: a folder for the raw rocprofv3 output
     pre = "cd /tmp && export TMPDIR=/tmp"
+    if w.startswith("mixed"):
+        summarize_stages(args.trace, args.bench_json, args.out,
+                         pre + "\nrocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace_" + w +
+                         f" -o run -- python3 $REPO/bench.py --workload {w} --steps 1 --warmup 1 --no-cpu", w)
+        return
     one = f"--workload {w} --steps 1 --warmup 0"
     if args.sq:
         groups = ["SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "

@@ -313,3 +313,17 @@ def test_ace_build_sigma_validation(lib, ctx):
     # the ACE build's workspace plus phi = Phi Q, Q and the Jacobi arrays
     assert wb(ctx, px.PX_OP_ACE_BUILD_SIGMA, ctypes.byref(c), 1, 16, 0) >= ace + 16 * 24 ** 3 * 8 + 16 * 16 * 16
     assert wb(ctx, px.PX_OP_ACE_BUILD_SIGMA, ctypes.byref(_cell(7)), 1, 16, 0) == 0
+
+
+def test_rotate_orbitals_validation(lib, ctx):
+    c = _cell()
+    f = lib.px_rotate_orbitals
+    phi, Q, out = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000))
+    assert f(ctx, ctypes.byref(c), 1, 0, phi, Q, out, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, ctypes.byref(c), 1, 4, phi, None, out, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, ctypes.byref(c), 1, 4, phi, Q, phi, None) == px.PX_ERR_INVALID_ARG      # aliasing
+    assert f(ctx, ctypes.byref(c), 1, 4, phi, ctypes.c_void_p(0x2008), out, None) == px.PX_ERR_INVALID_ARG
+    odd = px.Cell((5.0, 5.0, 5.0), (5, 5, 5)).c()
+    assert f(ctx, ctypes.byref(odd), 1, 4, phi, Q, out, None) == px.PX_ERR_UNSUPPORTED_GRID
+    assert f(ctx, ctypes.byref(c), 1, 4, phi, Q, out, None) == px.PX_ERR_WORKSPACE         # FP32: Q in complex64
+    assert lib.px_workspace_bytes(ctx, px.PX_OP_ROTATE, ctypes.byref(c), 1, 16, 0) >= 16 * 16 * 8

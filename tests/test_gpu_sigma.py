@@ -174,6 +174,35 @@ def test_density(px_ctx, fp32, n, L, N):
 
 
 @pytest.mark.parametrize("fp32", [False, True])
+def test_rotate_orbitals(px_ctx, fp32):
+    """phi = Phi Q against the oracle's rotation (Eq. 11), with Q from the
+    library's diagonalisation; the FP32 form against the oracle on the rounded
+    Phi and Q."""
+    import torch
+    banner(f"rotate orbitals fp32={fp32}")
+    rng = np.random.default_rng(12)
+    inst = inputs.make_instance(24, 10.0, 37, kT=0.05, seed=43)
+    sigma = _sigma(rng, 37)
+    cell = px.Cell(inst.L, inst.n)
+    Q, d, st = px_ctx.px_sigma_diagonalize(to_dev(sigma))
+    P = to_dev(inst.psi)
+    if fp32:
+        P = px_ctx.px_convert_c128_to_c64(P)
+    out = to_host(px_ctx.px_rotate_orbitals(cell, P, Q))
+    px_ctx.px_sync()
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    Qh = to_host(Q)
+    if fp32:
+        base, Qr = to_host(P).astype(np.complex128), Qh.astype(np.complex64).astype(np.complex128)
+    else:
+        base, Qr = inst.psi, Qh
+    err = relerr(out, oracle.rotate(base, Qr))
+    print(f"rotate fp32={fp32}: {err:.2e}", flush=True)
+    assert err < (2e-6 if fp32 else 1e-13)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
 def test_ace_build_sigma(px_ctx, fp32):
     """ACE operator of a full occupation matrix on a 16^3 grid with 6 orbitals
     and a random sigma with eigenvalues in [0, 1]:
