@@ -230,7 +230,7 @@ def summarize_mfma(mfma, out, command, workload):
     durs = collections.defaultdict(dict)
     for r in _csv(mfma, "counter_collection.csv"):
         k = r["Kernel_Name"]
-        if "gemm_" not in k:
+        if "gemm_x" not in k:   # the MFMA contractions (xhy, xc)
             continue
         rows[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
         durs[k][r["Dispatch_Id"]] = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9
@@ -331,11 +331,6 @@ def main():
     w = args.workload
     # $REPO: the repository root; $OUT: a folder for the raw rocprofv3 output
     pre = "cd /tmp && export TMPDIR=/tmp"
-    if w.startswith("mixed"):
-        summarize_stages(args.trace, args.bench_json, args.out,
-                         pre + "\nrocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace_" + w +
-                         f" -o run -- python3 $REPO/bench.py --workload {w} --steps 1 --warmup 1 --no-cpu", w)
-        return
     one = f"--workload {w} --steps 1 --warmup 0"
     if args.sq:
         groups = ["SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "
@@ -355,6 +350,11 @@ def main():
                        f"python3 $REPO/bench.py {one} --no-cpu", w)
         if not args.trace:
             return
+    if w.startswith("mixed"):
+        summarize_stages(args.trace, args.bench_json, args.out,
+                         pre + "\nrocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace_" + w +
+                         f" -o run -- python3 $REPO/bench.py --workload {w} --steps 1 --warmup 1 --no-cpu", w)
+        return
     commands = {
         "trace": pre + "\nrocprofv3 --kernel-trace --stats --output-format csv -d $OUT/trace_bench "
                        f"-o run -- python3 $REPO/bench.py --workload {w}",
