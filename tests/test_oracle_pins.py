@@ -448,6 +448,18 @@ def test_generator_sphere_size_mid72():
     assert len(inputs.sphere_indices((72, 72, 72), (20.0, 20.0, 20.0), 10.0)) == 12053
 
 
+def test_generator_occupation_matrix():
+    """The full occupation matrix of the mixed-state workloads: Hermitian, with
+    exactly the requested spectrum, and with coherences (off-diagonal entries)."""
+    occ = inputs.fermi_dirac(np.sort(np.random.default_rng(2).uniform(-0.5, 0.5, 64)), 0.02)
+    s = inputs.occupation_matrix(occ, seed=9)
+    assert np.array_equal(s, s.conj().T)
+    assert np.abs(np.linalg.eigvalsh(s) - np.sort(occ)).max() < 1e-14
+    off = np.abs(s - np.diag(np.diag(s))).max()
+    assert 1e-3 < off < 0.1
+    assert np.array_equal(s, inputs.occupation_matrix(occ, seed=9))      # seeded
+
+
 # ---------------------------------------------------------------- sigma: diagonalisation and density
 def _unitary(rng, n):
     q, r = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
