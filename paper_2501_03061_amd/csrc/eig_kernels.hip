@@ -225,39 +225,38 @@ __global__ __launch_bounds__(256) void bj_apply_k(double* A, double* V, int n, i
     W[i][j] = us[e];
   }
   __syncthreads();
-  // T = X U_S: four entries per thread
+  // T = X U_S: four entries per thread, rows i0 + 8q of one column j (each
+  // entry of U_S read once for the four)
+  const int i0 = tid / BJ2, j = tid % BJ2;
   double2 t[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + 256 * q, i = e / BJ2, j = e % BJ2;
-    double2 acc = make_double2(0.0, 0.0);
+  for (int q = 0; q < 4; ++q) t[q] = make_double2(0.0, 0.0);
 #pragma unroll 8
-    for (int l = 0; l < BJ2; ++l) acc = cadd2(acc, cmul2(X[i][l], W[l][j]));
-    t[q] = acc;
+  for (int l = 0; l < BJ2; ++l) {
+    const double2 w = W[l][j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q] = cadd2(t[q], cmul2(X[i0 + 8 * q][l], w));
   }
   if (is_a) {
     // out = U_P^H T
     __syncthreads();
     const double2* up = reinterpret_cast<const double2*>(Ug) + size_t(P) * BJ2 * BJ2;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      X[e / BJ2][e % BJ2] = t[q];
-    }
+    for (int q = 0; q < 4; ++q) X[i0 + 8 * q][j] = t[q];
     for (int e = tid; e < BJ2 * BJ2; e += 256) W[e / BJ2][e % BJ2] = up[e];
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q, i = e / BJ2, j = e % BJ2;
-      double2 acc = make_double2(0.0, 0.0);
+    for (int q = 0; q < 4; ++q) t[q] = make_double2(0.0, 0.0);
 #pragma unroll 8
-      for (int l = 0; l < BJ2; ++l) acc = cadd2(acc, cmul2(cconj2(W[l][i]), X[l][j]));
-      t[q] = acc;
+    for (int l = 0; l < BJ2; ++l) {
+      const double2 x = X[l][j];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[q] = cadd2(t[q], cmul2(cconj2(W[l][i0 + 8 * q]), x));
     }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int e = tid + 256 * q, i = e / BJ2, j = e % BJ2;
+    const int i = i0 + 8 * q;
     if (ri[i] < n && ci[j] < n) st2(M, n, ri[i], ci[j], t[q]);
   }
 }
