@@ -481,8 +481,9 @@ def bench_mixed(args, workload):
     ctx = px.Context(0)
     kern = ctx.px_kernel_hse(cell, cfg["mu"])
     step = MixedStep(ctx, cell, phi64, sigma, kern, fp32=True)
-    del phi64
-    torch.cuda.empty_cache()
+    if args.no_fp64:
+        del phi64
+        torch.cuda.empty_cache()
     for k in range(max(1, args.warmup)):
         step()
         log(f"mixed warmup step {k + 1}")
@@ -537,6 +538,8 @@ def bench_mixed(args, workload):
     res = step.res.cpu().numpy()
     a = step.cur
     sig_now = step.sigma[a].cpu().numpy()
+    rot_plane = step.rot[a][:, :1].to(torch.complex128).cpu().numpy()   # for the CPU sample
+    d_now = step.d[a].cpu().numpy()
     rho_int = float(step.rho.sum().item()) * cell.dV
     checks = dict(trace_sigma_0=float(np.trace(sigma_h).real), trace_sigma_now=float(np.trace(sig_now).real),
                   hermitian_defect_sigma_now=float(np.abs(sig_now - sig_now.conj().T).max()),
@@ -546,6 +549,47 @@ def bench_mixed(args, workload):
                   steps_taken=max(1, args.warmup) + args.steps)
     log(f"mixed step {ms_step:.1f} ms: stages {[round(med[k], 2) for k in MixedStep.STAGES]} ms; "
         f"checks {checks}")
+    fp64 = None
+    if not args.no_fp64:
+        # the plain FP64 form from the same initial state over the same number of
+        # steps: its speed, and the FP32 form's deviation from it per result
+        taken = checks["steps_taken"]
+        keep = dict(phi=step.phi[a].clone(), sigma=step.sigma[a].clone(), rho=step.rho.clone(),
+                    e_x=float(step.ex.item()))
+        step = None
+        torch.cuda.empty_cache()
+        step64 = MixedStep(ctx, cell, phi64, sigma, kern, fp32=False)
+        del phi64
+        torch.cuda.empty_cache()
+        n_timed = max(1, min(args.fp64_steps, taken - 1))
+        for k in range(taken - n_timed):
+            step64()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(n_timed):
+            step64(True)
+        torch.cuda.synchronize()
+        ms64 = 1e3 * (time.perf_counter() - t1) / n_timed
+        st64 = step64.stage_times()
+        med64 = {name: statistics.median(s[k] for s in st64) for k, name in enumerate(MixedStep.STAGES)}
+        b = step64.cur
+
+        def rel(x, y):
+            return float(torch.linalg.vector_norm((x.to(y.dtype) - y).flatten()) /
+                         torch.linalg.vector_norm(y.flatten()))
+        ex64 = float(step64.ex.item())
+        fp64 = dict(ms_per_step=ms64, steps_timed=n_timed, stage_ms_median=med64,
+                    speedup_fp32_vs_fp64=ms64 / ms_step,
+                    stage_speedup={k: med64[k] / med[k] for k in MixedStep.STAGES},
+                    err_fp32_vs_fp64=dict(phi=rel(keep["phi"], step64.phi[b]),
+                                          sigma=rel(keep["sigma"], step64.sigma[b]),
+                                          rho=rel(keep["rho"], step64.rho),
+                                          e_x=abs(keep["e_x"] - ex64) / abs(ex64)),
+                    desc=f"both forms advanced {taken} steps from the same state; errors of the "
+                         "FP32 state after them relative to the FP64 one")
+        log(f"mixed fp64 step {ms64:.1f} ms; FP32 vs FP64 {fp64['err_fp32_vs_fp64']}")
+        step64 = None
+        torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(inst, kern.cpu().numpy(), args.cpu_seconds)
@@ -553,9 +597,9 @@ def bench_mixed(args, workload):
         t1 = time.perf_counter()
         oracle.sigma_eig(sig_now)
         t_eig = time.perf_counter() - t1
-        rot_h = step.rot[a][:, :1].to(torch.complex128).cpu().numpy()
+        rot_h = rot_plane
         t1 = time.perf_counter()
-        oracle.density(rot_h, step.d[a].cpu().numpy())
+        oracle.density(rot_h, d_now)
         t_rho = (time.perf_counter() - t1) * inst.n[2]
         cpu["stage_samples"] = dict(sigma_eig_s=t_eig, density_s_scaled=t_rho,
                                     desc="oracle sigma_eig (LAPACK) at full n; oracle density on one "
@@ -569,7 +613,7 @@ def bench_mixed(args, workload):
         "roofline": roof, "cpu_baseline": cpu,
         "extra": {"stage_ms_median": med, "stages": stage_roof, "pair_pipeline": pipeline, "passes": passes,
                   "physical_pair_solves_per_s": pairs_phys / (ms_step * 1e-3), "checks": checks,
-                  "gpu": torch.cuda.get_device_name(0)},
+                  "fp64": fp64, "gpu": torch.cuda.get_device_name(0)},
     }
     ctx.close()
     return rec
