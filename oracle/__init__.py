@@ -15,8 +15,9 @@ Modules
                exchange-only PT-IM step with the projector and the occupation
                matrix (Eq. 4-7).
   sigma     -- occupation-matrix diagonalisation (Eq. 11), the rotated
-               orbitals Phi Q, and the density with a full sigma (Sec. III-C)
-               or with occupations (Eq. 12).
+               orbitals Phi Q, the density with a full sigma (Sec. III-C) or
+               with occupations (Eq. 12), and the latter on the twice-finer
+               charge-density grid (Sec. VI).
 
 Every function states the passage it follows and, where the paper is silent
 or garbled, the reading taken.  Parity pins live in tests/test_oracle_pins.py.
@@ -26,4 +27,4 @@ from .exchange import (  # noqa: F401
     exchange_energy_gspace, exchange_apply_sigma, pair_potential,
 )
 from .ace import ace_build, ace_apply, ptim_exchange_loop, ptim_step, DT_50AS, ALPHA  # noqa: F401
-from .sigma import sigma_eig, rotate, density_sigma, density  # noqa: F401
+from .sigma import sigma_eig, rotate, density_sigma, density, density_fine  # noqa: F401

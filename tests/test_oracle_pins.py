@@ -540,3 +540,45 @@ def test_density_gauge_invariance_and_diagonal_form(rng):
     c = oracle.density(oracle.rotate(Phi, Q), d)
     assert _relerr(c, a) < 1e-13
     assert np.all(a >= -1e-12 * np.abs(a).max())      # PSD sigma: non-negative density
+
+
+# ---------------------------------------------------------------- density on the charge-density grid
+def test_density_fine_keeps_the_coarse_points():
+    """Fourier interpolation reproduces the samples: the fine density at even
+    indices is the coarse one, and for band-limited orbitals its integral is
+    the coarse integral (orthorhombic grid: every axis pairing is exercised)."""
+    inst = inputs.make_instance((8, 6, 10), (5.0, 4.0, 6.0), 4, kT=0.05, seed=11, ecut=2.0)
+    rf = oracle.density_fine(inst.psi, inst.occ)
+    rc = oracle.density(inst.psi, inst.occ)
+    assert rf.shape == (20, 12, 16)
+    assert np.abs(rf[::2, ::2, ::2] - rc).max() < 1e-14 * np.abs(rc).max()
+    assert abs(rf.sum() / 8 - rc.sum()) < 1e-12 * rc.sum()
+
+
+def test_density_fine_two_plane_waves_closed_form():
+    """phi = a e^{i k1.r} + b e^{i k2.r} with frequencies below n/2 on every
+    axis: the interpolant is the same sum, so at every fine point
+    |phi|^2 = |a|^2 + |b|^2 + 2 Re(a conj(b) e^{i (k1 - k2).r})."""
+    n, L = (8, 6, 10), (5.0, 4.0, 6.0)
+    m1, m2 = (1, -2, 3), (-3, 1, 4)
+    a, b = 0.7 + 0.2j, -0.4 + 0.5j
+    pw = inputs.plane_wave_orbitals(n, L, [m1, m2]) * math.sqrt(np.prod(L))
+    phi = (a * pw[0] + b * pw[1])[None]
+    rf = oracle.density_fine(phi, [0.8])
+    z, y, x = np.meshgrid(*[np.arange(2 * n[k]) * L[k] / (2 * n[k]) for k in (2, 1, 0)], indexing="ij")
+    ph = sum(2 * math.pi * (m1[k] - m2[k]) / L[k] * c for k, c in zip((0, 1, 2), (x, y, z)))
+    ref = 0.8 * (abs(a) ** 2 + abs(b) ** 2 + 2 * (a * np.conj(b) * np.exp(1j * ph)).real)
+    assert np.abs(rf - ref).max() < 1e-13
+
+
+def test_density_fine_nyquist_split():
+    """Samples (-1)^j along x (the Nyquist frequency n0/2): with the Nyquist
+    coefficient split evenly, the interpolant along x is cos(pi n0 x / L0),
+    which vanishes at the odd fine points and is +-1 at the even ones; a
+    one-sided Nyquist term would give |phi| = 1 everywhere."""
+    n = (6, 4, 4)
+    j = np.arange(n[0])
+    phi = np.broadcast_to(((-1.0) ** j).astype(np.complex128), (n[2], n[1], n[0]))[None]
+    rf = oracle.density_fine(phi, [1.0])
+    assert np.abs(rf[:, :, 1::2]).max() < 1e-15
+    assert np.abs(rf[:, :, 0::2] - 1.0).max() < 1e-14
