@@ -362,7 +362,8 @@ class MixedStep:
       the PT-IM step (Eq. 4-7 with the projector and the sigma commutator,
         n_iter fixed-point iterations, FP64 residuals) -> (Phi', sigma'),
       the diagonalisation of sigma' (FP64 blocked Jacobi) and phi' = Phi' Q',
-      the density of the new state, sum_i d'_i |phi'_i|^2,
+      the density of the new state, sum_i d'_i |phi'_i|^2, on the wavefunction
+        grid and on the twice-finer charge-density grid,
     so that one diagonalisation per step serves both the density of the new
     state and the exchange operator of the next step.  Each call advances the
     state by one step.  Events on the current stream (the library's stream)
@@ -388,11 +389,14 @@ class MixedStep:
         self.st_step = torch.zeros(1, dtype=torch.int32, device=dev)
         self.st_eig = torch.zeros(1, dtype=torch.int32, device=dev)
         self.rho = torch.empty((cell.n[2], cell.n[1], cell.n[0]), dtype=torch.float64, device=dev)
+        self.rho_f = torch.empty((2 * cell.n[2], 2 * cell.n[1], 2 * cell.n[0]), dtype=torch.float64,
+                                 device=dev)
         prec = px.PX_PREC_FP32 if fp32 else px.PX_PREC_FP64
         need = max(ctx.workspace_bytes(px.PX_OP_ACE_BUILD, cell, prec, n),
                    ctx.workspace_bytes(px.PX_OP_PTIM_STEP, cell, prec, n, n),
                    ctx.workspace_bytes(px.PX_OP_SIGMA_DIAG, cell, prec, n),
-                   ctx.workspace_bytes(px.PX_OP_ROTATE, cell, prec, n))
+                   ctx.workspace_bytes(px.PX_OP_ROTATE, cell, prec, n),
+                   ctx.workspace_bytes(px.PX_OP_DENSITY_FINE, cell, prec, n))
         ctx.ensure_workspace(need)
         self.cur = 0
         # the diagonal form of the initial state (outside the steps)
@@ -408,7 +412,7 @@ class MixedStep:
         import torch
         c, a, b = self.ctx, self.cur, 1 - self.cur
         if record:
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
             e[0].record()
         c.px_ace_build(self.cell, self.rot[a], self.d[a], self.kern, xi=self.xi, e_x=self.ex,
                        status=self.st_ace)
@@ -428,14 +432,17 @@ class MixedStep:
         c.px_density(self.cell, self.rot[b], self.d[b], rho=self.rho)
         if record:
             e[5].record()
+        c.px_density_fine(self.cell, self.rot[b], self.d[b], rho=self.rho_f)
+        if record:
+            e[6].record()
             self.events.append(e)
         self.cur = b
 
-    STAGES = ("ace_build", "ptim_step", "sigma_diagonalize", "rotation", "density")
+    STAGES = ("ace_build", "ptim_step", "sigma_diagonalize", "rotation", "density", "density_fine")
 
     def stage_times(self):
         """Per recorded step: ms of each stage in STAGES."""
-        out = [[e[k].elapsed_time(e[k + 1]) for k in range(5)] for e in self.events]
+        out = [[e[k].elapsed_time(e[k + 1]) for k in range(len(self.STAGES))] for e in self.events]
         self.events = []
         return out
 
@@ -515,6 +522,8 @@ def bench_mixed(args, workload):
     # its upper tiles (about 4 n^2 N_g), Z = -mid X (8 n^2 N_g)
     it_flops = 28.0 * n * n * ng
     dens_bytes = n * ng * 8 + ng * 8
+    fine_flops = 4.0 * n * ng * (cell.n[0] + 2 * cell.n[1] + 4 * cell.n[2])
+    fine_bytes = 25.0 * n * ng * 8 + 2.0 * 8 * ng * 8 * ((n + 15) // 16)
 
     def mfma(ms, flops, desc):
         return dict(ms=ms, bound="mfma", flops=flops, TFLOPs=flops / (ms * 1e-3) / 1e12, peak_TFLOPs=peak,
@@ -534,6 +543,15 @@ def bench_mixed(args, workload):
                         GBps=dens_bytes / (med["density"] * 1e-3) / 1e9,
                         frac=dens_bytes / (med["density"] * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                         desc="sum_i d_i |phi_i|^2: n N_g b read + 8 N_g written (FP64)"),
+        "density_fine": dict(ms=med["density_fine"], bound="alu", flops=fine_flops, bytes=fine_bytes,
+                             TFLOPs=fine_flops / (med["density_fine"] * 1e-3) / 1e12, peak_TFLOPs=157.3,
+                             frac=fine_flops / (med["density_fine"] * 1e-3) / 1e12 / 157.3,
+                             GBps=fine_bytes / (med["density_fine"] * 1e-3) / 1e9,
+                             hbm_frac=fine_bytes / (med["density_fine"] * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                             desc="orbitals interpolated axis by axis to the 2x grid: the odd fine points of "
+                                  "each axis n MACs each, 4 flops (n0 + 2 n1 + 4 n2) N_g per orbital (x and y "
+                                  "on the FP32 vector units, z on the matrix cores); 25 N_g b of traffic per "
+                                  "orbital; squares summed in FP64; peak is the chip's FP32 vector rate"),
     }
     res = step.res.cpu().numpy()
     a = step.cur
@@ -555,7 +573,7 @@ def bench_mixed(args, workload):
         # steps: its speed, and the FP32 form's deviation from it per result
         taken = checks["steps_taken"]
         keep = dict(phi=step.phi[a].clone(), sigma=step.sigma[a].clone(), rho=step.rho.clone(),
-                    e_x=float(step.ex.item()))
+                    rho_fine=step.rho_f.clone(), e_x=float(step.ex.item()))
         step = None
         torch.cuda.empty_cache()
         step64 = MixedStep(ctx, cell, phi64, sigma, kern, fp32=False)
@@ -584,6 +602,7 @@ def bench_mixed(args, workload):
                     err_fp32_vs_fp64=dict(phi=rel(keep["phi"], step64.phi[b]),
                                           sigma=rel(keep["sigma"], step64.sigma[b]),
                                           rho=rel(keep["rho"], step64.rho),
+                                          rho_fine=rel(keep["rho_fine"], step64.rho_f),
                                           e_x=abs(keep["e_x"] - ex64) / abs(ex64)),
                     desc=f"both forms advanced {taken} steps from the same state; errors of the "
                          "FP32 state after them relative to the FP64 one")
@@ -625,7 +644,8 @@ MIXED_TEXT = {
        "V diag(f) V^H (V unitary, I + 0.1 noise), advanced by exchange-only PT-IM time steps; "
        "step = ACE build of Vx[sigma] on the diagonal form (phi = Phi Q, d) + PT-IM step with "
        "projector and sigma commutator (4 iterations) + diagonalisation of the new sigma (FP64 "
-       "Jacobi) + phi' = Phi' Q' + density of the new state; FP32 bulk"
+       "Jacobi) + phi' = Phi' Q' + density of the new state on the wavefunction grid and on the "
+       "twice-finer charge-density grid; FP32 bulk"
     for k, v in MIXED_BASE.items()}
 
 

@@ -81,7 +81,8 @@ typedef enum {
   PX_OP_DENSITY_SIGMA = 6,   /* n_psi = n; n_phi ignored                 */
   PX_OP_PTIM_STEP = 7,       /* n_psi = n (rank of xi), n_phi            */
   PX_OP_ACE_BUILD_SIGMA = 8, /* n_psi = n (Phi and sigma); n_phi ignored */
-  PX_OP_ROTATE = 9           /* n_psi = n; n_phi ignored                 */
+  PX_OP_ROTATE = 9,          /* n_psi = n; n_phi ignored                 */
+  PX_OP_DENSITY_FINE = 10    /* n_psi = n; n_phi ignored                 */
 } px_op;
 
 /* Orthorhombic cell: edge lengths in bohr and the real-space grid, n[0] = x. */
@@ -248,6 +249,20 @@ px_status px_exchange_apply_sigma(px_context* ctx, const px_cell* cell, px_preci
  * px_ace_apply. */
 px_status px_density(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
                      const void* phi, const double* occ, double* rho, hipStream_t stream);
+
+/* The density of px_density on the charge-density grid, twice as fine per
+ * axis as the wavefunction grid (Sec. VI: 120 x 180 x 240 for 60 x 90 x 120):
+ * rho_fine = sum_i occ_i |phi_i^f|^2 with phi_i^f the trigonometric
+ * interpolation of phi_i onto the fine grid (its spectrum zero-padded; the
+ * Nyquist coefficient of each axis split evenly between +n/2 and -n/2), so
+ * that rho_fine at even indices equals the density on the wavefunction grid
+ * and no product aliases.  phi [n][N_g] (element type of prec), occ float64
+ * [n], rho_fine float64 [2 n2][2 n1][2 n0].  The interpolation runs in the
+ * form's precision, the squares and sums in FP64.  Every axis must be even
+ * (PX_ERR_UNSUPPORTED_GRID otherwise).  Workspace: PX_OP_DENSITY_FINE with n
+ * (10 N_g values of the form's type for each of 16 orbitals in flight). */
+px_status px_density_fine(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                          const void* phi, const double* occ, double* rho_fine, hipStream_t stream);
 
 /* Density with a full occupation matrix (Sec. III-C:
  * rho(r) = sum_{i,j} Phi_i(r) sigma_ij conj(Phi_j(r))), evaluated as

@@ -44,7 +44,7 @@ def _units():
         units.append(("exchange_shape.hip", f"exchange_s{n0}x{n1}x{n2}.o",
                       [f"-DPX_S0={n0}", f"-DPX_S1={n1}", f"-DPX_S2={n2}"]))
     for src in ("exchange_dispatch.cpp", "pair_transpose.hip", "misc_kernels.hip", "gemm_kernels.hip",
-                "chol_kernels.hip", "eig_kernels.hip", "px_api.cpp"):
+                "chol_kernels.hip", "eig_kernels.hip", "density_fine.hip", "px_api.cpp"):
         units.append((src, os.path.splitext(src)[0] + ".o", []))
     return units
 

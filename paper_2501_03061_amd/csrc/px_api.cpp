@@ -18,6 +18,7 @@
 #include <cstdint>
 
 #include "px_internal.hpp"
+#include "density_fine.hpp"
 
 struct px_context {
   int device = 0;
@@ -524,6 +525,9 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
       return step_layout(cell, prec, n_psi, n_phi, kStepMaxIter).end;
     case PX_OP_ROTATE:  // Q in complex64 (the FP64 form does not use it)
       return align_up(size_t(n_psi) * n_psi * 8);
+    case PX_OP_DENSITY_FINE:  // even axes only
+      if (cell->n[0] % 2 || cell->n[1] % 2 || cell->n[2] % 2) return 0;
+      return align_up(px::density_fine_work_bytes(prec == PX_PREC_FP32, cell->n, n_psi));
     case PX_OP_ACE_BUILD_SIGMA: {
       const AceLayout a = ace_layout(cell, prec, n_psi, ic, jc, ctx->symmetric_ace, p2);
       return sigma_layout(a.end, cell, prec, n_psi, false).end;
@@ -936,6 +940,29 @@ px_status px_density(px_context* ctx, const px_cell* cell, px_precision prec, in
   if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
   return hip_check(ctx, px::launch_density(prec == PX_PREC_FP32, ngrid(cell), n, phi, occ, rho, stream),
                    "density");
+}
+
+px_status px_density_fine(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
+                          const void* phi, const double* occ, double* rho_fine, hipStream_t stream) {
+  if (!ctx) return PX_ERR_INVALID_ARG;
+  if (prec != PX_PREC_FP64 && prec != PX_PREC_FP32)
+    return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
+  if (!cell_ok(cell))
+    return fail(ctx, PX_ERR_INVALID_ARG, "cell: edge lengths must be > 0 and grid sizes > 0");
+  if (cell->n[0] % 2 || cell->n[1] % 2 || cell->n[2] % 2)
+    return fail(ctx, PX_ERR_UNSUPPORTED_GRID, "density_fine: grid %dx%dx%d needs even axes", cell->n[0],
+                cell->n[1], cell->n[2]);
+  if (n <= 0) return fail(ctx, PX_ERR_INVALID_ARG, "n must be > 0 (got %d)", n);
+  if (!phi || !occ || !rho_fine) return fail(ctx, PX_ERR_INVALID_ARG, "density_fine: null array argument");
+  if (misaligned(phi) || (reinterpret_cast<uintptr_t>(rho_fine) & 7) != 0)
+    return fail(ctx, PX_ERR_INVALID_ARG, "density_fine: phi must be 16-byte and rho 8-byte aligned");
+  const bool fp32 = prec == PX_PREC_FP32;
+  px_status st = need_ws(ctx, align_up(px::density_fine_work_bytes(fp32, cell->n, n)));
+  if (st != PX_OK) return st;
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
+  return hip_check(ctx, px::launch_density_fine(fp32, cell->n, n, phi, occ, rho_fine, ctx->ws, stream),
+                   "density on the fine grid");
 }
 
 px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,

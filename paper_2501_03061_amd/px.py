@@ -20,7 +20,7 @@ PX_OK, PX_ERR_INVALID_ARG, PX_ERR_UNSUPPORTED_GRID, PX_ERR_WORKSPACE, PX_ERR_DEV
 PX_PREC_FP64, PX_PREC_FP32 = 0, 1
 PX_OP_EXCHANGE, PX_OP_ACE_BUILD, PX_OP_ACE_APPLY, PX_OP_PTIM_LOOP = 0, 1, 2, 3
 PX_OP_EXCHANGE_SIGMA, PX_OP_SIGMA_DIAG, PX_OP_DENSITY_SIGMA, PX_OP_PTIM_STEP = 4, 5, 6, 7
-PX_OP_ACE_BUILD_SIGMA, PX_OP_ROTATE = 8, 9
+PX_OP_ACE_BUILD_SIGMA, PX_OP_ROTATE, PX_OP_DENSITY_FINE = 8, 9, 10
 
 STATUS_NAMES = {0: "PX_OK", 1: "PX_ERR_INVALID_ARG", 2: "PX_ERR_UNSUPPORTED_GRID",
                 3: "PX_ERR_WORKSPACE", 4: "PX_ERR_DEVICE", 5: "PX_ERR_NOT_POSITIVE_DEFINITE",
@@ -65,6 +65,7 @@ SIGNATURES = {
     "px_exchange_apply_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "px_density": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp]),
     "px_density_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "px_density_fine": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp]),
     "px_ptim_step": (_i32, [_vp, _cellp, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _dbl, _vp, _vp, _vp,
                             _vp, _vp]),
     "px_ace_build_sigma": (_i32, [_vp, _cellp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -374,6 +375,19 @@ class Context:
             rho = torch.empty((cell.n[2], cell.n[1], cell.n[0]), dtype=torch.float64, device=phi.device)
         self._check(self.lib.px_density(self.h, ctypes.byref(cell.c()), prec, phi.shape[0], _ptr(phi),
                                         _ptr(occ), _ptr(rho), _stream(stream)))
+        return rho
+
+    def px_density_fine(self, cell: Cell, phi, occ, rho=None, stream=None):
+        """rho on the grid twice as fine per axis (FP64, shape [2 n2][2 n1][2 n0])."""
+        import torch
+        prec = _prec(phi.dtype)
+        _check_block("phi", phi, cell)
+        if rho is None:
+            rho = torch.empty((2 * cell.n[2], 2 * cell.n[1], 2 * cell.n[0]), dtype=torch.float64,
+                              device=phi.device)
+        self.ensure_workspace(self.workspace_bytes(PX_OP_DENSITY_FINE, cell, prec, phi.shape[0]))
+        self._check(self.lib.px_density_fine(self.h, ctypes.byref(cell.c()), prec, phi.shape[0], _ptr(phi),
+                                             _ptr(occ), _ptr(rho), _stream(stream)))
         return rho
 
     def px_density_sigma(self, cell: Cell, phi_basis, sigma, rho=None, status=None, stream=None):

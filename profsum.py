@@ -155,6 +155,9 @@ def summarize_stages(trace, bench_json, out, command, workload):
             rate, frac = f"{st['TFLOPs']:.1f} TFLOP/s", f"{st['frac']:.3f} of {st['peak_TFLOPs']}"
         elif st.get("bound") == "hbm":
             rate, frac = f"{st['GBps']:.0f} GB/s", f"{st['frac']:.3f} of 8000"
+        elif st.get("bound") == "alu":
+            rate = f"{st['TFLOPs']:.1f} TFLOP/s, {st['GBps']:.0f} GB/s"
+            frac = f"{st['frac']:.3f} of {st['peak_TFLOPs']} (HBM {st['hbm_frac']:.3f})"
         lines.append(f"| {name} | {st['ms']:.2f} | {st.get('bound', 'pipeline')} | {rate} | {frac} |")
     lines += ["", "Kernels (`kernel_stats.csv`, the whole run; the Jacobi launches include the no-op "
               "launches after convergence, which return at once):", "",
@@ -170,9 +173,12 @@ def summarize_stages(trace, bench_json, out, command, workload):
         fam[short] += float(r["TotalDurationNs"]) / 1e6
     diag = (fam["bj_solve_k"] + fam["bj_apply_k"] + fam["eig_norm_part_k"] + fam["eig_conv_k"] +
             fam["eig_init_k"] + fam["eig_rank_k"] + fam["eig_permute_k"]) / (steps + 1)
+    fine = (fam["interp_x_k"] + fam["interp_strided_k"] + fam["density_acc_k"] + fam["interp_table_k"]) / steps
     lines += ["", f"Per diagonalisation in the trace ({steps + 1} of them): {diag:.1f} ms "
               f"(bench: {ex['stages']['sigma_diagonalize']['ms']:.1f} ms); density kernel "
-              f"{fam['density_k'] / steps:.2f} ms per call (bench: {ex['stages']['density']['ms']:.2f} ms)."]
+              f"{fam['density_k'] / steps:.2f} ms per call (bench: {ex['stages']['density']['ms']:.2f} ms); "
+              f"density on the fine grid {fine:.1f} ms per step (bench: "
+              f"{ex['stages']['density_fine']['ms']:.1f} ms)."]
     open(os.path.join(out, f"mixed_steps_{workload}_kernel_trace.md"), "w").write("\n".join(lines) + "\n")
 
 

@@ -327,3 +327,18 @@ def test_rotate_orbitals_validation(lib, ctx):
     assert f(ctx, ctypes.byref(odd), 1, 4, phi, Q, out, None) == px.PX_ERR_UNSUPPORTED_GRID
     assert f(ctx, ctypes.byref(c), 1, 4, phi, Q, out, None) == px.PX_ERR_WORKSPACE         # FP32: Q in complex64
     assert lib.px_workspace_bytes(ctx, px.PX_OP_ROTATE, ctypes.byref(c), 1, 16, 0) >= 16 * 16 * 8
+
+
+def test_density_fine_validation(lib, ctx):
+    c = _cell()
+    f = lib.px_density_fine
+    phi, occ, rho = (ctypes.c_void_p(a) for a in (0x1000, 0x2000, 0x3000))
+    assert f(ctx, ctypes.byref(c), 1, 0, phi, occ, rho, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, ctypes.byref(c), 1, 4, phi, None, rho, None) == px.PX_ERR_INVALID_ARG
+    assert f(ctx, ctypes.byref(c), 1, 4, phi, occ, ctypes.c_void_p(0x3004), None) == px.PX_ERR_INVALID_ARG
+    odd = px.Cell((5.0, 5.0, 5.0), (6, 6, 5)).c()
+    assert f(ctx, ctypes.byref(odd), 1, 4, phi, occ, rho, None) == px.PX_ERR_UNSUPPORTED_GRID
+    assert f(ctx, ctypes.byref(c), 1, 4, phi, occ, rho, None) == px.PX_ERR_WORKSPACE
+    wb = lib.px_workspace_bytes
+    assert wb(ctx, px.PX_OP_DENSITY_FINE, ctypes.byref(c), 1, 4, 0) >= 10 * 24 ** 3 * 8 * 16
+    assert wb(ctx, px.PX_OP_DENSITY_FINE, ctypes.byref(odd), 0, 4, 0) == 0
