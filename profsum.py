@@ -173,7 +173,16 @@ def summarize_stages(trace, bench_json, out, command, workload):
         fam[short] += float(r["TotalDurationNs"]) / 1e6
     diag = (fam["bj_solve_k"] + fam["bj_apply_k"] + fam["eig_norm_part_k"] + fam["eig_conv_k"] +
             fam["eig_init_k"] + fam["eig_rank_k"] + fam["eig_permute_k"]) / (steps + 1)
-    fine = (fam["interp_x_k"] + fam["interp_strided_k"] + fam["density_acc_k"] + fam["interp_table_k"]) / steps
+    # the z pass of the fine-grid density runs as xc contractions over the n2 planes of
+    # one orbital: those dispatches have ceil(n2 / 64) workgroup columns, the other xc
+    # contractions (over all orbitals) many more
+    n2 = rec["config"]["grid"][2]
+    zpass = 0.0
+    for r in _csv(trace, "kernel_trace.csv"):
+        if "gemm_xc_k" in r["Kernel_Name"] and int(r["Grid_Size_Y"]) == (n2 + 63) // 64:
+            zpass += (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e6
+    fine = (fam["interp_x_k"] + fam["interp_strided_k"] + fam["density_acc_k"] + fam["interp_table_k"] +
+            fam["interp_matrix_k"] + zpass) / steps
     lines += ["", f"Per diagonalisation in the trace ({steps + 1} of them): {diag:.1f} ms "
               f"(bench: {ex['stages']['sigma_diagonalize']['ms']:.1f} ms); density kernel "
               f"{fam['density_k'] / steps:.2f} ms per call (bench: {ex['stages']['density']['ms']:.2f} ms); "
