@@ -12,10 +12,11 @@
 // chunk of orbitals: x, then y (each pass doubles one axis; lines staged in
 // LDS, each thread computing JB consecutive odd points of one line with a
 // sliding window of h in registers), then z, the largest pass, on the matrix
-// cores: the odd z planes of an orbital are O = H^T Y with Y its [n2][4 n0 n1]
-// y-refined data and H[k][j] = h[(j - k) mod n2] (the xc contraction), the even
-// ones are Y itself; finally the weighted squares of both summed into rho_f in
-// FP64.  The interpolation runs in the form's precision.
+// cores: the odd z planes of a chunk are O = H^T Y with Y its y-refined data
+// laid out [n2][orbital][4 n0 n1] and H[k][j] = h[(j - k) mod n2] (one xc
+// contraction), the even ones are Y itself; finally the weighted squares of
+// both summed into rho_f in FP64.  The interpolation runs in the form's
+// precision.
 #include "density_fine.hpp"
 
 #include "fft_core.hpp"
@@ -97,12 +98,14 @@ __global__ __launch_bounds__(256) void interp_x_k(size_t rows, int n0, const C<T
   }
 }
 
-// A strided axis: in [outer][na][inner] -> out [outer][2 na][inner]; a
-// workgroup takes one outer index and IB consecutive inner positions.
+// A strided axis: in [outer][na][inner] -> out [outer'][2 na][inner]; a
+// workgroup takes one outer index and IB consecutive inner positions.  With
+// zdim > 0 the outer index o = b zdim + z is written at position z bdim + b
+// (orbital-major in, plane-major out).
 constexpr int IB = 32;
 template <typename T>
 __global__ __launch_bounds__(256) void interp_strided_k(int na, size_t inner, const C<T>* in, C<T>* out,
-                                                        const T* h) {
+                                                        const T* h, int zdim, int bdim) {
   extern __shared__ unsigned char smem[];
   C<T>* tile = reinterpret_cast<C<T>*>(smem);  // na x IB
   T* hs = reinterpret_cast<T*>(tile + na * IB);
@@ -116,7 +119,8 @@ __global__ __launch_bounds__(256) void interp_strided_k(int na, size_t inner, co
   }
   for (int e = threadIdx.x; e < na; e += 256) hs[e] = h[e];
   __syncthreads();
-  C<T>* dst = out + o * 2 * na * inner + i0;
+  const size_t oo = zdim > 0 ? (o % zdim) * bdim + o / zdim : o;
+  C<T>* dst = out + oo * 2 * na * inner + i0;
   for (int e = threadIdx.x; e < na * IB; e += 256) {  // even points
     const int j = e / IB, i = e % IB;
     if (i < ni) dst[size_t(2 * j) * inner + i] = tile[e];
@@ -146,7 +150,7 @@ __global__ void interp_matrix_k(int n, const T* h, C<T>* H) {
 }
 
 // rho[z_f][r] (+)= sum_i w_i |v_i|^2 in FP64 over the fine grid, v_i from the
-// even z planes (Y, the y-refined data [nb][n2][plane]) or the odd ones (O,
+// even z planes (Y, the y-refined data [n2][nb][plane]) or the odd ones (O,
 // the same layout); two points per thread (plane is even).
 template <typename T>
 __global__ __launch_bounds__(256) void density_acc_k(int n2, size_t plane, int nb, const C<T>* Y, const C<T>* O,
@@ -156,8 +160,8 @@ __global__ __launch_bounds__(256) void density_acc_k(int n2, size_t plane, int n
   if (p >= total) return;
   const size_t zf = p / plane, r = p % plane;   // p and p + 1 share zf
   const C<T>* src = (zf & 1) ? O : Y;
-  const size_t off = (zf >> 1) * plane + r;
-  const size_t per = size_t(n2) * plane;
+  const size_t off = (zf >> 1) * nb * plane + r;
+  const size_t per = plane;
   double a0 = accumulate ? rho[p] : 0.0, a1 = accumulate ? rho[p + 1] : 0.0;
   for (int i = 0; i < nb; ++i) {
     const C<T> x = src[size_t(i) * per + off], y = src[size_t(i) * per + off + 1];
@@ -198,14 +202,13 @@ hipError_t run_fine(const int* n, int norb, const void* phi_v, const double* occ
     const size_t rows = size_t(b) * n2 * n1;
     hipLaunchKernelGGL(interp_x_k<T>, dim3(unsigned((rows + RB - 1) / RB)), dim3(256),
                        RB * n0 * sizeof(C<T>) + n0 * sizeof(T), s, rows, n0, phi + size_t(c0) * ng, P, h);
-    // y: P [b n2][n1][2 n0] -> Y [b n2][2 n1][2 n0]
+    // y: P [b n2][n1][2 n0] -> Y [n2][b][2 n1][2 n0] (plane-major, for one z contraction)
     const size_t inner = size_t(2) * n0;
     hipLaunchKernelGGL(interp_strided_k<T>, dim3(unsigned((inner + IB - 1) / IB), unsigned(b * n2)), dim3(256),
-                       n1 * IB * sizeof(C<T>) + n1 * sizeof(T), s, n1, inner, P, Y, h + hstride);
-    // z, odd planes: O_i = H^T Y_i over the n2 planes of each orbital (matrix cores)
-    for (int i = 0; i < b && e == hipSuccess; ++i)
-      e = launch_gemm_xc(sizeof(T) == 4, n2, n2, plane, Y + size_t(i) * n2 * plane, H, n2, 1.0,
-                         O + size_t(i) * n2 * plane, false, s);
+                       n1 * IB * sizeof(C<T>) + n1 * sizeof(T), s, n1, inner, P, Y, h + hstride, n2, b);
+    // z, odd planes: O = H^T Y, one contraction over the n2 planes for the whole
+    // chunk (each plane row holds the b orbitals' planes side by side; matrix cores)
+    e = launch_gemm_xc(sizeof(T) == 4, n2, n2, size_t(b) * plane, Y, H, n2, 1.0, O, false, s);
     if (e != hipSuccess) break;
     const size_t half = (size_t(2) * n2 * plane) / 2;
     hipLaunchKernelGGL(density_acc_k<T>, dim3(unsigned((half + 255) / 256)), dim3(256), 0, s, n2, plane, b, Y, O,
