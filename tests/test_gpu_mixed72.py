@@ -150,3 +150,34 @@ def test_mixed72_density_sigma(px_ctx, mixed, fp32):
     print(f"mixed72 density fp32={fp32}: planes {err:.2e}, integral {ierr:.2e}", flush=True)
     assert err < (FP32_TOL if fp32 else 1e-12)
     assert ierr < (FP32_TOL if fp32 else 1e-12)
+
+
+@pytest.mark.parametrize("fp32", [True, False])
+def test_mixed72_density_fine(px_ctx, mixed, fp32):
+    """The density on the 144^3 charge-density grid at full size: over all 512
+    orbitals, the even points equal px_density bit for bit (the samples, summed
+    in the same order) and the integral equals the wavefunction-grid one (the
+    orbitals are band-limited well inside the grid); over the first 19 orbitals
+    (a full chunk and a ragged one) every fine point against the oracle."""
+    import torch
+    inst, phi, sigma, _ = mixed
+    banner(f"mixed72: density on the fine grid fp32={fp32}")
+    cell = px.Cell(inst.L, inst.n)
+    P = to_dev(phi)
+    if fp32:
+        P = px_ctx.px_convert_c128_to_c64(P)
+    occ = to_dev(inst.occ)
+    rf = to_host(px_ctx.px_density_fine(cell, P, occ))
+    rc = to_host(px_ctx.px_density(cell, P, occ))
+    sub = to_host(px_ctx.px_density_fine(cell, P[:19].contiguous(), occ[:19].contiguous()))
+    torch.cuda.synchronize()
+    base = to_host(P[:19]).astype(np.complex128) if fp32 else phi[:19]
+    del P
+    torch.cuda.empty_cache()
+    assert np.array_equal(rf[::2, ::2, ::2], rc)
+    ierr = abs(rf.sum() / 8 - rc.sum()) / rc.sum()
+    ref = oracle.density_fine(base, inst.occ[:19])
+    err = float(np.abs(sub - ref).max() / np.abs(ref).max())
+    print(f"mixed72 density fine fp32={fp32}: integral {ierr:.2e}, 19 orbitals vs oracle {err:.2e}", flush=True)
+    assert ierr < (FP32_TOL if fp32 else 1e-12)
+    assert err < (FP32_TOL if fp32 else 1e-12)
