@@ -26,9 +26,14 @@ struct px_context {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   // device status words of the last calls that report through one: the
-  // error each stands for when non-zero (Cholesky breakdown of an ACE build,
-  // or no convergence of the occupation-matrix diagonalisation)
-  std::vector<std::pair<int32_t*, px_status>> last_status;
+  // error each stands for when non-zero (a Cholesky breakdown, or no
+  // convergence of the occupation-matrix diagonalisation) and what it belongs to
+  struct StatusWord {
+    int32_t* word;
+    px_status kind;
+    std::string what;
+  };
+  std::vector<StatusWord> last_status;
   int latched = PX_OK;
   // (n0,n1,n2,prec) -> pair chunk ic x jc and the pass-2 configuration (0, 1)
   std::map<std::tuple<int, int, int, int>, std::tuple<int, int, int>> tuning;
@@ -740,7 +745,7 @@ px_status px_ace_build(px_context* ctx, const px_cell* cell, px_precision prec, 
   hipError_t he = hipSetDevice(ctx->device);
   if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
   st = ace_build_run(ctx, cell, prec, n, psi, occ, kernel_G, xi, M, e_x, status, l, ic, jc, p2, stream);
-  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_POSITIVE_DEFINITE});
+  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_POSITIVE_DEFINITE, "ace_build: -M"});
   return st;
 }
 
@@ -854,7 +859,7 @@ px_status px_sigma_diagonalize(px_context* ctx, int32_t n, const double* sigma, 
   if (he != hipSuccess) return hip_check(ctx, he, "hipSetDevice");
   st = hip_check(ctx, px::launch_eig_hermitian(sigma, n, Q, d, status, ctx->ws, kEigSweeps, stream),
                  "sigma = Q D Q^H");
-  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED});
+  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED, "sigma_diagonalize"});
   return st;
 }
 
@@ -921,7 +926,7 @@ px_status px_exchange_apply_sigma(px_context* ctx, const px_cell* cell, px_preci
   // Eq. 13 on (phi, d): the double loop over the rotated orbitals
   st = run_exchange(ctx, cell, prec, n, ctx->ws + sl.phi, reinterpret_cast<double*>(ctx->ws + sl.d),
                     n_tgt, tgt, kernel_G, vx_tgt, ex, false, ic, jc, false, stream, p2);
-  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED});
+  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED, "exchange_apply_sigma"});
   return st;
 }
 
@@ -989,7 +994,7 @@ px_status px_density_sigma(px_context* ctx, const px_cell* cell, px_precision pr
   st = hip_check(ctx, px::launch_density(prec == PX_PREC_FP32, ngrid(cell), n, ctx->ws + sl.phi,
                                          reinterpret_cast<double*>(ctx->ws + sl.d), rho, stream),
                  "density");
-  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED});
+  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_CONVERGED, "density_sigma"});
   return st;
 }
 
@@ -1057,7 +1062,8 @@ px_status px_ace_build_sigma(px_context* ctx, const px_cell* cell, px_precision 
   st = ace_build_run(ctx, cell, prec, n, ctx->ws + sl.phi, reinterpret_cast<double*>(ctx->ws + sl.d),
                      kernel_G, xi, M, e_x, status + 1, l, ic, jc, p2, stream);
   if (st == PX_OK)
-    ctx->last_status = {{status, PX_ERR_NOT_CONVERGED}, {status + 1, PX_ERR_NOT_POSITIVE_DEFINITE}};
+    ctx->last_status = {{status, PX_ERR_NOT_CONVERGED, "ace_build_sigma"},
+                        {status + 1, PX_ERR_NOT_POSITIVE_DEFINITE, "ace_build_sigma: -M"}};
   return st;
 }
 
@@ -1156,7 +1162,8 @@ px_status px_ptim_step(px_context* ctx, const px_cell* cell, px_precision prec, 
     cur_s = nxt_s;
   }
   st = ok(px::launch_status_first(sts, n_iter, status, stream), "status");
-  if (st == PX_OK) ctx->last_status.assign(1, {status, PX_ERR_NOT_POSITIVE_DEFINITE});
+  if (st == PX_OK)
+    ctx->last_status.assign(1, {status, PX_ERR_NOT_POSITIVE_DEFINITE, "ptim_step: the midpoint overlap S"});
   return st;
 }
 
@@ -1679,7 +1686,8 @@ px_status px_exchange_apply_batched(px_context* ctx, int32_t n_inst, const px_in
   if (ace) {
     ctx->last_status.clear();
     for (int k = 0; k < n_inst; ++k)
-      ctx->last_status.push_back({inst[k].status, PX_ERR_NOT_POSITIVE_DEFINITE});
+      ctx->last_status.push_back(
+          {inst[k].status, PX_ERR_NOT_POSITIVE_DEFINITE, "ace_build of instance " + std::to_string(k) + ": -M"});
   }
   std::vector<unsigned char> key = batch_key(ctx, n_inst, inst, prec, ace != 0);
   if (ctx->use_graph && ctx->graph_exec && key == ctx->graph_key)
@@ -1856,17 +1864,16 @@ px_status px_sync(px_context* ctx, hipStream_t stream) {
   if (e != hipSuccess) return hip_check(ctx, e, "hipStreamSynchronize");
   for (size_t k = 0; k < ctx->last_status.size(); ++k) {
     int32_t s = 0;
-    e = hipMemcpy(&s, ctx->last_status[k].first, sizeof s, hipMemcpyDeviceToHost);
+    e = hipMemcpy(&s, ctx->last_status[k].word, sizeof s, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_check(ctx, e, "status readback");
     if (s != 0 && ctx->latched == PX_OK) {
-      const px_status kind = ctx->last_status[k].second;
+      const px_status kind = ctx->last_status[k].kind;
+      const char* what = ctx->last_status[k].what.c_str();
       ctx->latched = kind;
       if (kind == PX_ERR_NOT_POSITIVE_DEFINITE)
-        fail(ctx, kind,
-             "ace_build (status word %zu): -M is not positive definite (Cholesky breakdown at column %d)",
-             k, s);
+        fail(ctx, kind, "%s is not positive definite (Cholesky breakdown at column %d)", what, s);
       else
-        fail(ctx, kind, "sigma diagonalisation: Jacobi sweeps did not converge (%d sweeps)", s);
+        fail(ctx, kind, "%s: the Jacobi sweeps of the diagonalisation did not converge (%d sweeps)", what, s);
     }
   }
   ctx->last_status.clear();

@@ -98,6 +98,7 @@ def test_ace_cholesky_breakdown_reported(px_ctx, toy):
     with pytest.raises(px.PxError) as ei:
         px_ctx.px_sync()
     assert ei.value.status == px.PX_ERR_NOT_POSITIVE_DEFINITE
+    assert "ace_build: -M is not positive definite (Cholesky breakdown at column 1)" in str(ei.value)
     assert int(st.item()) == 1
     # latched until cleared
     with pytest.raises(px.PxError):
