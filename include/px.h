@@ -259,7 +259,8 @@ px_status px_density(px_context* ctx, const px_cell* cell, px_precision prec, in
  * and no product aliases.  phi [n][N_g] (element type of prec), occ float64
  * [n], rho_fine float64 [2 n2][2 n1][2 n0].  The interpolation runs in the
  * form's precision, the squares and sums in FP64.  Every axis must be even
- * (PX_ERR_UNSUPPORTED_GRID otherwise).  Workspace: PX_OP_DENSITY_FINE with n
+ * and at most 120 points (PX_ERR_UNSUPPORTED_GRID otherwise; any such grid,
+ * with or without an FFT plan).  Workspace: PX_OP_DENSITY_FINE with n
  * (10 N_g values of the form's type for each of 16 orbitals in flight). */
 px_status px_density_fine(px_context* ctx, const px_cell* cell, px_precision prec, int32_t n,
                           const void* phi, const double* occ, double* rho_fine, hipStream_t stream);

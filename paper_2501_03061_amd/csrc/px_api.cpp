@@ -314,6 +314,16 @@ StepLayout step_layout(const px_cell* cell, px_precision prec, int n, int n_phi,
   return l;
 }
 
+// Grids of the fine-grid density: even axes (the interpolation splits the
+// Nyquist coefficient) of at most kFineMaxAxis points (a line tile of the
+// FP64 form, 32 lines, must stay within 64 KB of LDS).
+constexpr int kFineMaxAxis = 120;
+bool fine_grid_ok(const px_cell* cell) {
+  for (int a = 0; a < 3; ++a)
+    if (cell->n[a] % 2 || cell->n[a] > kFineMaxAxis) return false;
+  return true;
+}
+
 px_status check_grid(px_context* c, const px_cell* cell) {
   if (!cell_ok(cell))
     return fail(c, PX_ERR_INVALID_ARG, "cell: edge lengths must be > 0 and grid sizes > 0");
@@ -530,8 +540,8 @@ size_t px_workspace_bytes(const px_context* ctx, px_op op, const px_cell* cell, 
       return step_layout(cell, prec, n_psi, n_phi, kStepMaxIter).end;
     case PX_OP_ROTATE:  // Q in complex64 (the FP64 form does not use it)
       return align_up(size_t(n_psi) * n_psi * 8);
-    case PX_OP_DENSITY_FINE:  // even axes only
-      if (cell->n[0] % 2 || cell->n[1] % 2 || cell->n[2] % 2) return 0;
+    case PX_OP_DENSITY_FINE:
+      if (!fine_grid_ok(cell)) return 0;
       return align_up(px::density_fine_work_bytes(prec == PX_PREC_FP32, cell->n, n_psi));
     case PX_OP_ACE_BUILD_SIGMA: {
       const AceLayout a = ace_layout(cell, prec, n_psi, ic, jc, ctx->symmetric_ace, p2);
@@ -954,9 +964,9 @@ px_status px_density_fine(px_context* ctx, const px_cell* cell, px_precision pre
     return fail(ctx, PX_ERR_INVALID_ARG, "unknown precision %d", int(prec));
   if (!cell_ok(cell))
     return fail(ctx, PX_ERR_INVALID_ARG, "cell: edge lengths must be > 0 and grid sizes > 0");
-  if (cell->n[0] % 2 || cell->n[1] % 2 || cell->n[2] % 2)
-    return fail(ctx, PX_ERR_UNSUPPORTED_GRID, "density_fine: grid %dx%dx%d needs even axes", cell->n[0],
-                cell->n[1], cell->n[2]);
+  if (!fine_grid_ok(cell))
+    return fail(ctx, PX_ERR_UNSUPPORTED_GRID, "density_fine: grid %dx%dx%d needs even axes of at most %d",
+                cell->n[0], cell->n[1], cell->n[2], kFineMaxAxis);
   if (n <= 0) return fail(ctx, PX_ERR_INVALID_ARG, "n must be > 0 (got %d)", n);
   if (!phi || !occ || !rho_fine) return fail(ctx, PX_ERR_INVALID_ARG, "density_fine: null array argument");
   if (misaligned(phi) || (reinterpret_cast<uintptr_t>(rho_fine) & 7) != 0)

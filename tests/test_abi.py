@@ -338,6 +338,8 @@ def test_density_fine_validation(lib, ctx):
     assert f(ctx, ctypes.byref(c), 1, 4, phi, occ, ctypes.c_void_p(0x3004), None) == px.PX_ERR_INVALID_ARG
     odd = px.Cell((5.0, 5.0, 5.0), (6, 6, 5)).c()
     assert f(ctx, ctypes.byref(odd), 1, 4, phi, occ, rho, None) == px.PX_ERR_UNSUPPORTED_GRID
+    big = px.Cell((5.0, 5.0, 5.0), (8, 128, 8)).c()
+    assert f(ctx, ctypes.byref(big), 1, 4, phi, occ, rho, None) == px.PX_ERR_UNSUPPORTED_GRID
     assert f(ctx, ctypes.byref(c), 1, 4, phi, occ, rho, None) == px.PX_ERR_WORKSPACE
     wb = lib.px_workspace_bytes
     assert wb(ctx, px.PX_OP_DENSITY_FINE, ctypes.byref(c), 1, 4, 0) >= 10 * 24 ** 3 * 8 * 16
