@@ -216,7 +216,8 @@ px_status px_ptim_exchange_loop(px_context* ctx, const px_cell* cell, px_precisi
 
 /* Occupation-matrix diagonalisation (Sec. IV-A-1, Eq. 11): sigma = Q D Q^H
  * for a Hermitian sigma (the input is Hermitised as (sigma + sigma^H)/2 first),
- * in FP64 by cyclic Jacobi rotations.  sigma and Q: complex128 [n][n]
+ * in FP64 by cyclic Jacobi rotations (blocked: pairs of 16-index blocks per
+ * round, each pair's 32 x 32 subproblem rotated in LDS).  sigma and Q: complex128 [n][n]
  * row-major (device; Q[a][k] is component a of eigenvector k); d: float64 [n],
  * the eigenvalues in ascending order.  Eigenvectors are unique up to a phase
  * (and a rotation within a degenerate eigenspace); Q D Q^H is unique.
