@@ -260,10 +260,27 @@ __global__ void xhy_reduce_k(int na, int nb, const double* part, int nsplit, dou
 
 // r-span of one split: aim at ~2048 workgroups, at least 1024 values of r,
 // and at most max_split splits (the partials need max_split * na * nb
-// complex128 values of scratch).
-static size_t xhy_kchunk(int na, int nb, size_t ng, int max_split, int* nsplit) {
-  const size_t tiles = size_t((na + 63) / 64) * ((nb + 63) / 64);
-  size_t want = (2048 + tiles - 1) / tiles;
+// complex128 values of scratch).  Among 1 to 2 times the aimed split count the
+// one whose workgroups best fill whole rounds of the resident ones (two per CU
+// on 256 CUs) is taken: the workgroups of a launch all run about equally long,
+// so a last round half full idles half the chip for one workgroup's time
+// (ACE application at 96^3 x 1536: 4 -> 8 splits, about -2 %).  herm counts
+// the tiles on and above the diagonal that the Hermitian form launches.
+static size_t xhy_kchunk(int na, int nb, size_t ng, int max_split, bool herm, int* nsplit) {
+  constexpr size_t kResident = 2 * 256;
+  const size_t ta = size_t(na + 63) / 64, tb = size_t(nb + 63) / 64;
+  const size_t tiles = herm ? ta * (ta + 1) / 2 : ta * tb;
+  const size_t want0 = (2048 + tiles - 1) / tiles;
+  size_t want = want0;
+  double best = 0.0;
+  for (size_t s = want0; s <= 2 * want0; ++s) {
+    const size_t wg = tiles * s, rounds = (wg + kResident - 1) / kResident;
+    const double fill = double(wg) / double(rounds * kResident);
+    if (fill > best + 1e-9) {
+      best = fill;
+      want = s;
+    }
+  }
   size_t kchunk = (ng + want - 1) / want;
   if (kchunk < 1024) kchunk = 1024;
   if (max_split > 0 && (ng + kchunk - 1) / kchunk > size_t(max_split))
@@ -274,13 +291,13 @@ static size_t xhy_kchunk(int na, int nb, size_t ng, int max_split, int* nsplit) 
 }
 
 size_t gemm_xhy_part_elems(int na, int nb, size_t ng, int* nsplit) {
-  xhy_kchunk(na, nb, ng, 0, nsplit);
+  xhy_kchunk(na, nb, ng, 0, false, nsplit);
   return size_t(*nsplit) * na * nb;
 }
 
 int gemm_xhy_splits(int na, int nb, size_t ng, int max_split) {
   int nsplit = 0;
-  xhy_kchunk(na, nb, ng, max_split, &nsplit);
+  xhy_kchunk(na, nb, ng, max_split, false, &nsplit);
   return nsplit;
 }
 
@@ -288,7 +305,7 @@ static hipError_t xhy_launch(bool fp32, int na, int nb, size_t ng, const void* X
                              double scale, double* M, int ldm, double* part, int nsplit_avail,
                              float* M32, bool herm, hipStream_t s) {
   int nsplit;
-  const size_t kchunk = xhy_kchunk(na, nb, ng, nsplit_avail, &nsplit);
+  const size_t kchunk = xhy_kchunk(na, nb, ng, nsplit_avail, herm, &nsplit);
   if (nsplit > nsplit_avail || (herm && na != nb)) return hipErrorInvalidValue;
   const int ta = (na + 63) / 64, tb = (nb + 63) / 64;
   const int tri = herm ? ta : 0;
@@ -321,8 +338,16 @@ hipError_t launch_gemm_xhy_herm(bool fp32, int n, size_t ng, const void* X, cons
 }
 
 // ---------------------------------------------------------------- xc
-// grid (ceil(ng/64), ceil(nb/64)), 256 threads; wave w covers r-block (w&1)
-// and b-block (w>>1) of 32 each, as 2x2 MFMA tiles (i: r, j: b).  Occupancy
+// grid ceil(ng/64) * ceil(nb/64) in one dimension.  Dense C: the b tile
+// varies fastest, so the workgroups that share an r tile of X run together
+// and read it through the caches once, and each XCD (every eighth workgroup)
+// keeps a few b column blocks of C in its L2 (ACE application at 96^3 x 1536
+// -2 %, at 72^3 x 512 -6 %, against r tiles fastest).  Upper-triangular C
+// (upper): the r tile varies fastest, so the workgroups in flight share one b
+// tile and the same sum length (b-fastest mixes lengths 1 to nb/64 and was
+// 21 % slower for xi = W U at 96^3 x 1536).  256 threads; wave w covers
+// r-block (w&1) and b-block (w>>1) of 32 each, as 2x2 MFMA tiles (i: r,
+// j: b).  Occupancy
 // targets (no spills): three waves per SIMD in the FP32 form, two in FP64
 // (one by default; ACE application in FP64 -15 %).
 template <typename T>
@@ -331,12 +356,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
                                                  cpx<T>* Z, int upper) {
   using A = typename Acc<T>::t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const size_t r_base = size_t(blockIdx.x) * 64 + (w & 1) * 32;
-  const int b_base = blockIdx.y * 64 + (w >> 1) * 32;
+  const unsigned nbt = unsigned(nb + 63) / 64, nrt = unsigned((ng + 63) / 64);
+  const int bt = int(upper ? blockIdx.x / nrt : blockIdx.x % nbt);
+  const size_t rt = upper ? blockIdx.x % nrt : blockIdx.x / nbt;
+  const size_t r_base = rt * 64 + (w & 1) * 32;
+  const int b_base = bt * 64 + (w >> 1) * 32;
   const int q = lane >> 4, m = lane & 15;
   int a_end = na;
   if (upper) {
-    const int lim = blockIdx.y * 64 + 64;
+    const int lim = bt * 64 + 64;
     a_end = lim < na ? lim : na;
   }
   bool rv[2], bv[2];
@@ -429,7 +457,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 
 hipError_t launch_gemm_xc(bool fp32, int na, int nb, size_t ng, const void* X, const void* C,
                           int ldc, double alpha, void* Z, bool upper, hipStream_t s) {
-  dim3 grid(unsigned((ng + 63) / 64), (nb + 63) / 64);
+  dim3 grid(unsigned((ng + 63) / 64) * unsigned((nb + 63) / 64));
   if (fp32)
     hipLaunchKernelGGL(gemm_xc_k<float>, grid, dim3(256), 0, s, na, nb, ng,
                        static_cast<const cpx<float>*>(X), static_cast<const float*>(C), ldc,
