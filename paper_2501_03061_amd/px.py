@@ -171,6 +171,38 @@ def _check_block(name, t, cell: Cell, dtype=None):
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
 
 
+def _check_dev(name, t, dtype, numel=None, at_least=None, required=True):
+    """A contiguous device tensor of dtype holding numel (or at least at_least)
+    elements; None passes a null pointer where the argument is optional.  The
+    library reads every pointer on the device: a host tensor here would fault
+    the GPU instead of raising."""
+    if t is None:
+        if required:
+            raise ValueError(f"{name} is required")
+        return
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    if at_least is not None and t.numel() < at_least:
+        raise ValueError(f"{name} must have at least {at_least} elements, got {t.numel()}")
+
+
+def _check_inputs(cell: "Cell", n, occ=None, kern=None, e_x=None, M=None, status=None, nstatus=1):
+    """The occupations (FP64, n), the kernel table (FP64, N_g) and the optional
+    FP64 energy, complex128 n x n Gram matrix and int32 status words."""
+    import torch
+    if occ is not False:
+        _check_dev("occ", occ, torch.float64, at_least=n)
+    if kern is not False:
+        _check_dev("kern", kern, torch.float64, numel=cell.ng)
+    _check_dev("e_x", e_x, torch.float64, at_least=1, required=False)
+    _check_dev("M", M, torch.complex128, numel=n * n, required=False)
+    _check_dev("status", status, torch.int32, at_least=nstatus, required=False)
+
+
 class Context:
     """A px_context plus a caller-owned workspace tensor grown on demand."""
 
@@ -227,6 +259,7 @@ class Context:
         if out is None:
             out = torch.empty((cell.n[2], cell.n[1], cell.n[0]), dtype=torch.float64,
                               device=f"cuda:{self.device}")
+        _check_dev("out", out, torch.float64, numel=cell.ng)
         self._check(self.lib.px_kernel_hse(self.h, ctypes.byref(cell.c()), float(mu), _ptr(out),
                                            _stream(stream)))
         return out
@@ -235,8 +268,10 @@ class Context:
         import torch
         if src.dtype != torch.complex128 or not src.is_contiguous():
             raise TypeError("src must be a contiguous complex128 tensor")
+        _check_dev("src", src, torch.complex128)
         if dst is None:
             dst = torch.empty(src.shape, dtype=torch.complex64, device=src.device)
+        _check_dev("dst", dst, torch.complex64, at_least=src.numel())
         self._check(self.lib.px_convert_c128_to_c64(self.h, src.numel(), _ptr(src), _ptr(dst),
                                                     _stream(stream)))
         return dst
@@ -254,8 +289,10 @@ class Context:
         prec = _prec(psi.dtype)
         _check_block("psi", psi, cell)
         _check_block("phi", phi, cell, psi.dtype)
+        _check_inputs(cell, psi.shape[0], occ, kern, e_x)
         if out is None:
             out = torch.empty_like(phi)
+        _check_block("out", out, cell, psi.dtype)
         self.ensure_workspace(self.workspace_bytes(PX_OP_EXCHANGE, cell, prec, psi.shape[0], phi.shape[0]))
         self._check(self.lib.px_exchange_apply(
             self.h, ctypes.byref(cell.c()), prec, psi.shape[0], _ptr(psi), _ptr(occ),
@@ -272,6 +309,8 @@ class Context:
             xi = torch.empty_like(psi)
         if status is None:
             status = torch.zeros(1, dtype=torch.int32, device=dev)
+        _check_block("xi", xi, cell, psi.dtype)
+        _check_inputs(cell, psi.shape[0], occ, kern, e_x, M, status)
         self.ensure_workspace(self.workspace_bytes(PX_OP_ACE_BUILD, cell, prec, psi.shape[0]))
         self._check(self.lib.px_ace_build(
             self.h, ctypes.byref(cell.c()), prec, psi.shape[0], _ptr(psi), _ptr(occ), _ptr(kern),
@@ -285,6 +324,7 @@ class Context:
         _check_block("phi", phi, cell, xi.dtype)
         if out is None:
             out = torch.empty_like(phi)
+        _check_block("out", out, cell, xi.dtype)
         self.ensure_workspace(self.workspace_bytes(PX_OP_ACE_APPLY, cell, prec, xi.shape[0], phi.shape[0]))
         self._check(self.lib.px_ace_apply(
             self.h, ctypes.byref(cell.c()), prec, xi.shape[0], _ptr(xi), phi.shape[0], _ptr(phi),
@@ -299,6 +339,7 @@ class Context:
         _check_block("phi", phi, cell, xi.dtype)
         if out is None:
             out = torch.empty_like(phi)
+        _check_block("out", out, cell, xi.dtype)
         self._check(self.lib.px_ace_apply_noalloc(
             self.h, ctypes.byref(cell.c()), prec, xi.shape[0], _ptr(xi), phi.shape[0], _ptr(phi),
             _ptr(out), _stream(stream)))
@@ -314,6 +355,8 @@ class Context:
             out = torch.empty_like(phi_n)
         if residuals is None:
             residuals = torch.zeros(n_iter, dtype=torch.float64, device=phi_n.device)
+        _check_block("out", out, cell, xi.dtype)
+        _check_dev("residuals", residuals, torch.float64, at_least=max(int(n_iter), 0))
         self.ensure_workspace(self.workspace_bytes(PX_OP_PTIM_LOOP, cell, prec, xi.shape[0], phi_n.shape[0]))
         self._check(self.lib.px_ptim_exchange_loop(
             self.h, ctypes.byref(cell.c()), prec, xi.shape[0], _ptr(xi), phi_n.shape[0],
@@ -342,6 +385,9 @@ class Context:
         if d is None:
             d = torch.empty(n, dtype=torch.float64, device=sigma.device)
         status = self._status(status, sigma.device)
+        _check_dev("Q", Q, torch.complex128, numel=n * n)
+        _check_dev("d", d, torch.float64, at_least=n)
+        _check_dev("status", status, torch.int32, at_least=1)
         cell = Cell.cubic(16, 1.0)
         self.ensure_workspace(self.workspace_bytes(PX_OP_SIGMA_DIAG, cell, PX_PREC_FP64, n))
         self._check(self.lib.px_sigma_diagonalize(self.h, n, _ptr(sigma), _ptr(Q), _ptr(d),
@@ -360,6 +406,8 @@ class Context:
         if out is None:
             out = torch.empty_like(tgt)
         status = self._status(status, tgt.device)
+        _check_block("out", out, cell, phi_basis.dtype)
+        _check_inputs(cell, n, False, kern, status=status)
         self.ensure_workspace(self.workspace_bytes(PX_OP_EXCHANGE_SIGMA, cell, prec, n, tgt.shape[0]))
         self._check(self.lib.px_exchange_apply_sigma(
             self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis), _ptr(sigma), tgt.shape[0],
@@ -373,6 +421,8 @@ class Context:
         _check_block("phi", phi, cell)
         if rho is None:
             rho = torch.empty((cell.n[2], cell.n[1], cell.n[0]), dtype=torch.float64, device=phi.device)
+        _check_inputs(cell, phi.shape[0], occ, False)
+        _check_dev("rho", rho, torch.float64, numel=cell.ng)
         self._check(self.lib.px_density(self.h, ctypes.byref(cell.c()), prec, phi.shape[0], _ptr(phi),
                                         _ptr(occ), _ptr(rho), _stream(stream)))
         return rho
@@ -385,6 +435,8 @@ class Context:
         if rho is None:
             rho = torch.empty((2 * cell.n[2], 2 * cell.n[1], 2 * cell.n[0]), dtype=torch.float64,
                               device=phi.device)
+        _check_inputs(cell, phi.shape[0], occ, False)
+        _check_dev("rho", rho, torch.float64, numel=8 * cell.ng)
         self.ensure_workspace(self.workspace_bytes(PX_OP_DENSITY_FINE, cell, prec, phi.shape[0]))
         self._check(self.lib.px_density_fine(self.h, ctypes.byref(cell.c()), prec, phi.shape[0], _ptr(phi),
                                              _ptr(occ), _ptr(rho), _stream(stream)))
@@ -401,6 +453,8 @@ class Context:
             rho = torch.empty((cell.n[2], cell.n[1], cell.n[0]), dtype=torch.float64,
                               device=phi_basis.device)
         status = self._status(status, phi_basis.device)
+        _check_dev("rho", rho, torch.float64, numel=cell.ng)
+        _check_dev("status", status, torch.int32, at_least=1)
         self.ensure_workspace(self.workspace_bytes(PX_OP_DENSITY_SIGMA, cell, prec, n))
         self._check(self.lib.px_density_sigma(self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis),
                                               _ptr(sigma), _ptr(rho), _ptr(status), _stream(stream)))
@@ -415,6 +469,7 @@ class Context:
         self._sigma(Q, n)
         if out is None:
             out = torch.empty_like(phi_basis)
+        _check_block("out", out, cell, phi_basis.dtype)
         self.ensure_workspace(self.workspace_bytes(PX_OP_ROTATE, cell, prec, n))
         self._check(self.lib.px_rotate_orbitals(self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis),
                                                 _ptr(Q), _ptr(out), _stream(stream)))
@@ -435,6 +490,8 @@ class Context:
             status = torch.zeros(2, dtype=torch.int32, device=phi_basis.device)
         elif status.numel() < 2 or status.dtype != torch.int32:
             raise ValueError("status must hold two int32 words")
+        _check_block("xi", xi, cell, phi_basis.dtype)
+        _check_inputs(cell, n, False, kern, e_x, M, status, nstatus=2)
         self.ensure_workspace(self.workspace_bytes(PX_OP_ACE_BUILD_SIGMA, cell, prec, n))
         self._check(self.lib.px_ace_build_sigma(
             self.h, ctypes.byref(cell.c()), prec, n, _ptr(phi_basis), _ptr(sigma), _ptr(kern),
@@ -458,6 +515,10 @@ class Context:
         if residuals is None:
             residuals = torch.zeros((2, n_iter), dtype=torch.float64, device=phi_n.device)
         status = self._status(status, phi_n.device)
+        _check_block("phi_out", phi_out, cell, xi.dtype)
+        _check_dev("sigma_out", sigma_out, torch.complex128, numel=m * m)
+        _check_dev("residuals", residuals, torch.float64, at_least=2 * max(int(n_iter), 0))
+        _check_dev("status", status, torch.int32, at_least=1)
         self.ensure_workspace(self.workspace_bytes(PX_OP_PTIM_STEP, cell, prec, xi.shape[0], m))
         self._check(self.lib.px_ptim_step(
             self.h, ctypes.byref(cell.c()), prec, xi.shape[0], _ptr(xi), m, _ptr(phi_n), _ptr(sigma_n),
@@ -506,6 +567,8 @@ class Context:
             st = d.get("status")
             if ace and st is None:
                 st = torch.zeros(1, dtype=torch.int32, device=psi.device)
+            _check_block(f"instances[{k}].out", out, cell, psi.dtype)
+            _check_inputs(cell, psi.shape[0], d.get("occ"), d.get("kern"), d.get("e_x"), d.get("M"), st)
             outs.append(out)
             stats.append(st)
             arr[k] = PxInstance(cell.c(), psi.shape[0], psi.data_ptr(), d["occ"].data_ptr(),
@@ -533,6 +596,8 @@ class Context:
         _check_block("psi", psi, cell)
         if out is None:
             out = torch.empty_like(psi)
+        _check_block("out", out, cell, psi.dtype)
+        _check_inputs(cell, psi.shape[0], occ, kern)
         need = max(self.workspace_bytes(PX_OP_EXCHANGE, cell, prec, psi.shape[0], psi.shape[0]), 1)
         # room for the largest candidate block (256 x 256 pair slabs, or as
         # many as 64 GiB hold; larger candidates are skipped)

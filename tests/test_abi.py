@@ -344,3 +344,41 @@ def test_density_fine_validation(lib, ctx):
     wb = lib.px_workspace_bytes
     assert wb(ctx, px.PX_OP_DENSITY_FINE, ctypes.byref(c), 1, 4, 0) >= 10 * 24 ** 3 * 8 * 16
     assert wb(ctx, px.PX_OP_DENSITY_FINE, ctypes.byref(odd), 0, 4, 0) == 0
+
+
+class _DevTensor:
+    """Stands in for a device tensor in the binding's argument checks (no GPU here)."""
+
+    def __init__(self, dtype, numel, cuda=True, contiguous=True):
+        self.dtype, self._n, self.is_cuda, self._c = dtype, numel, cuda, contiguous
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return self._c
+
+
+def test_binding_rejects_host_and_mis_sized_arguments():
+    import torch
+    cell = px.Cell.cubic(24, 10.0)
+    ok = dict(occ=_DevTensor(torch.float64, 4), kern=_DevTensor(torch.float64, cell.ng))
+    px._check_inputs(cell, 4, **ok)
+    px._check_inputs(cell, 4, **ok, e_x=None, M=None, status=None)
+    with pytest.raises(ValueError, match="device tensor"):      # a host array would fault the GPU
+        px._check_inputs(cell, 4, occ=torch.ones(4, dtype=torch.float64), kern=ok["kern"])
+    with pytest.raises(ValueError, match="required"):
+        px._check_inputs(cell, 4, occ=None, kern=ok["kern"])
+    with pytest.raises(TypeError):
+        px._check_inputs(cell, 4, occ=_DevTensor(torch.float32, 4), kern=ok["kern"])
+    with pytest.raises(ValueError, match="at least 4"):
+        px._check_inputs(cell, 4, occ=_DevTensor(torch.float64, 3), kern=ok["kern"])
+    with pytest.raises(ValueError, match=f"{cell.ng} elements"):
+        px._check_inputs(cell, 4, occ=ok["occ"], kern=_DevTensor(torch.float64, cell.ng - 1))
+    with pytest.raises(ValueError, match="16 elements"):
+        px._check_inputs(cell, 4, **ok, M=_DevTensor(torch.complex128, 15))
+    with pytest.raises(ValueError, match="at least 2"):
+        px._check_inputs(cell, 4, **ok, status=_DevTensor(torch.int32, 1), nstatus=2)
+    with pytest.raises(ValueError, match="contiguous"):
+        px._check_dev("rho", _DevTensor(torch.float64, cell.ng, contiguous=False), torch.float64)
+    px._check_inputs(cell, 4, False, ok["kern"])                 # occupations not taken
