@@ -25,9 +25,10 @@
  *   FFT convention: forward exp(-iG.r) unnormalised, inverse exp(+iG.r) with
  *     1/N_g; for a real even kernel the result does not depend on the sign.
  *   Alignment: orbital blocks (psi, phi, xi and the outputs) must be 16-byte
- *     aligned; every orbital of a block then is too, since N_g is a multiple
- *     of 64 on the grids with FFT plans and must be even for FP32 blocks in
- *     the contraction-only entry points.  Misaligned blocks: PX_ERR_INVALID_ARG.
+ *     aligned; every orbital of a block then is too, since N_g is even on the
+ *     grids with FFT plans (all their axes are even) and must be even for FP32
+ *     blocks in the contraction-only entry points.  Misaligned blocks:
+ *     PX_ERR_INVALID_ARG.
  *   Memory: all array arguments are DEVICE pointers owned by the caller.  The
  *     library never allocates or frees device memory; scratch space comes from
  *     the workspace the caller attaches with px_set_workspace, sized by
