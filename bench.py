@@ -736,8 +736,8 @@ def main():
                     help="only run the plain copy kernel (2 GiB, 5 launches) and print its bandwidth")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the exchange shards by orbital columns; see the design notes). Use --gpus 1.",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the exchange "
+              "would shard by orbital columns, with a ring of orbital blocks). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
     from paper_2501_03061_amd import px
